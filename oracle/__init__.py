@@ -1,0 +1,281 @@
+"""CPU oracle for Ozaki-scheme multi-component GEMM (test infrastructure).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg import
+this package.  It wraps ``oracle.c`` (built by ``oracle/build.py``) and shares
+no code with the HIP library.
+
+Array conventions (the same as the product's Python binding): a matrix with
+``rows`` rows and ``cols`` columns in a c-component format is a C-contiguous
+array of shape ``(c, cols, rows)`` -- component-planar, each plane
+column-major.  So A (m x k) is ``(c, k, m)``, B (k x n) is ``(c, n, k)`` and
+C (m x n) is ``(c, n, m)``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+ZERO_EXP = -(2 ** 31)
+C_OF = {"dd": 2, "td": 3, "qd": 4, "ts": 3}
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_L = ctypes.c_long
+
+
+def lib():
+    """The loaded oracle library (built first if absent)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(LIB_PATH)
+        L.oracle_two_sum.restype = ctypes.c_double
+        L.oracle_two_sum.argtypes = [ctypes.c_double, ctypes.c_double, _P]
+        L.oracle_two_sum_f.restype = ctypes.c_float
+        L.oracle_two_sum_f.argtypes = [ctypes.c_float, ctypes.c_float, _P]
+        L.oracle_two_prod.restype = ctypes.c_double
+        L.oracle_two_prod.argtypes = [ctypes.c_double, ctypes.c_double, _P]
+        L.oracle_renorm.argtypes = [_P, _I]
+        L.oracle_renorm_f.argtypes = [_P, _I]
+        L.oracle_rho.restype = _I
+        L.oracle_rho.argtypes = [_I, _L]
+        L.oracle_split_plain.argtypes = [_I, _I, _I, _P, _L, _L, _L, _I, _I, _P, _P, _P]
+        L.oracle_split_plain_f.argtypes = [_I, _I, _I, _P, _L, _L, _L, _I, _I, _P, _P, _P]
+        L.oracle_slice_product.argtypes = [_I, _I, _I, _P, _P, _P, _P, _I, _I, _P]
+        L.oracle_gemm_exact_check.argtypes = [_I, _I, _I, _I, _I, _P, _P, _P, _I, _P, _I, _P, _P, _P]
+        L.oracle_exact_sum.argtypes = [_P, _L, _I, _I, _P]
+        L.oracle_ozaki_gemm.argtypes = [_I, _I, _I, _I, _I, _P, _P, _I, _P, _I, _P, _P]
+        L.oracle_split_int8.argtypes = [_I, _I, _I, _P, _L, _L, _L, _I, _P, _P]
+        L.oracle_int8_diag_sums.argtypes = [_I, _I, _I, _I, _P, _P, _P]
+        L.oracle_int8_combine.argtypes = [_I, _I, _I, _I, _P, _P, _P, _P]
+        L.oracle_gemm_naive.argtypes = [_I, _I, _I, _I, _I, _P, _P, _P, _I, _P]
+        L.oracle_omp_threads.restype = _I
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(status, what):
+    if status != 0:
+        raise RuntimeError(f"oracle {what} failed with status {status}")
+
+
+def threads() -> int:
+    return lib().oracle_omp_threads()
+
+
+def two_sum(a: float, b: float):
+    e = ctypes.c_double()
+    s = lib().oracle_two_sum(a, b, ctypes.byref(e))
+    return s, e.value
+
+
+def two_sum_f(a, b):
+    e = ctypes.c_float()
+    s = lib().oracle_two_sum_f(float(a), float(b), ctypes.byref(e))
+    return np.float32(s), np.float32(e.value)
+
+
+def two_prod(a: float, b: float):
+    e = ctypes.c_double()
+    p = lib().oracle_two_prod(a, b, ctypes.byref(e))
+    return p, e.value
+
+
+def renorm(x) -> np.ndarray:
+    x = np.array(x, dtype=np.float64 if np.asarray(x).dtype != np.float32 else np.float32)
+    if x.dtype == np.float32:
+        lib().oracle_renorm_f(_ptr(x), len(x))
+    else:
+        lib().oracle_renorm(_ptr(x), len(x))
+    return x
+
+
+def rho(S: int, k: int) -> int:
+    """The shift ceil((S + log2 k)/2) of Algorithm 1 (Section 3)."""
+    return lib().oracle_rho(S, k)
+
+
+def _split_axes(X, along):
+    c, cols, rows = X.shape
+    if along == "rows":  # rows of a (rows x cols) matrix: vectors are rows, length cols
+        return rows, cols, 1, rows, rows * cols
+    if along == "cols":
+        return cols, rows, rows, 1, rows * cols
+    raise ValueError(along)
+
+
+def split_plain(X: np.ndarray, D: int, along: str, *, want_resid: bool = False):
+    """Algorithm 1's split of every row (``along='rows'``, operand A) or column
+    (``along='cols'``, operand B) of X (shape ``(c, cols, rows)``).
+
+    Returns ``(slices, exps[, resid])``: slices ``(D, cols, rows)`` in X's
+    dtype, exps ``(D, nvec)`` int32 holding ceil(log2 mu) per pass (ZERO_EXP
+    when mu = 0), resid ``(c, cols, rows)`` the remainder after D passes.
+    """
+    X = np.ascontiguousarray(X)
+    c = X.shape[0]
+    nvec, ln, s_vec, s_elt, s_comp = _split_axes(X, along)
+    f32 = X.dtype == np.float32
+    S = 24 if f32 else 53
+    r = rho(S, ln)
+    slices = np.zeros((D,) + X.shape[1:], dtype=X.dtype)
+    exps = np.zeros((D, nvec), dtype=np.int32)
+    resid = np.zeros_like(X) if want_resid else None
+    fn = lib().oracle_split_plain_f if f32 else lib().oracle_split_plain
+    _check(fn(nvec, ln, c, _ptr(X), s_vec, s_elt, s_comp, D, r, _ptr(slices), _ptr(exps), _ptr(resid)), "split")
+    return (slices, exps, resid) if want_resid else (slices, exps)
+
+
+def slice_product(Aa, ea, Bb, eb, k_rho: int, S: int) -> np.ndarray:
+    """Exact C_ab = A_a B_b (Section 3): Aa ``(k, m)``, Bb ``(n, k)`` -> ``(n, m)`` float64."""
+    Aa = np.ascontiguousarray(Aa, dtype=np.float64)
+    Bb = np.ascontiguousarray(Bb, dtype=np.float64)
+    ea = np.ascontiguousarray(ea, dtype=np.int32)
+    eb = np.ascontiguousarray(eb, dtype=np.int32)
+    k, m = Aa.shape
+    n = Bb.shape[0]
+    out = np.zeros((n, m), dtype=np.float64)
+    _check(lib().oracle_slice_product(m, n, k, _ptr(Aa), _ptr(ea), _ptr(Bb), _ptr(eb), k_rho, S, _ptr(out)),
+           "slice_product")
+    return out
+
+
+def exact_check(A, B, C, rows=None):
+    """Exact comparison of ``C`` with ``A B`` for the given rows of C.
+
+    Returns ``(diff, absab, cex)``, each ``(n, nrows)`` float64: ``|C - AB|``
+    rounded once, ``sum_p |a_ip||b_pj|`` from leading components, and ``AB``
+    rounded once.
+    """
+    A = np.ascontiguousarray(A)
+    B = np.ascontiguousarray(B)
+    C = np.ascontiguousarray(C)
+    c, k, m = A.shape
+    n = B.shape[1]
+    f32 = A.dtype == np.float32
+    rows_arr = None if rows is None else np.ascontiguousarray(rows, dtype=np.int32)
+    nrows = m if rows is None else len(rows_arr)
+    ldc = C.shape[2]
+    diff = np.zeros((n, nrows))
+    absab = np.zeros((n, nrows))
+    cex = np.zeros((n, nrows))
+    _check(lib().oracle_gemm_exact_check(c, int(f32), m, n, k, _ptr(A), _ptr(B), _ptr(C), ldc, _ptr(rows_arr),
+                                         nrows, _ptr(diff), _ptr(absab), _ptr(cex)), "exact_check")
+    return diff, absab, cex
+
+
+def exact_sum(values, c: int, f32: bool = False) -> np.ndarray:
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    out = np.zeros(c)
+    _check(lib().oracle_exact_sum(_ptr(v), len(v), c, int(f32), _ptr(out)), "exact_sum")
+    return out
+
+
+def ozaki_gemm(A, B, D: int, rows=None, paper: bool = False):
+    """Ozaki product (Algorithm 1) of A ``(c, k, m)`` and B ``(c, n, k)``.
+
+    Returns ``(C_tri, C_paper)``: ``(c, n, nrows)`` float64 arrays (components
+    of TS results are binary32 values stored as float64); ``C_paper`` is None
+    unless ``paper``.
+    """
+    A = np.ascontiguousarray(A)
+    B = np.ascontiguousarray(B)
+    c, k, m = A.shape
+    n = B.shape[1]
+    f32 = A.dtype == np.float32
+    rows_arr = None if rows is None else np.ascontiguousarray(rows, dtype=np.int32)
+    nrows = m if rows is None else len(rows_arr)
+    C_tri = np.zeros((c, n, nrows))
+    C_pap = np.zeros((c, n, nrows)) if paper else None
+    _check(lib().oracle_ozaki_gemm(c, int(f32), m, n, k, _ptr(A), _ptr(B), D, _ptr(rows_arr), nrows, _ptr(C_tri),
+                                   _ptr(C_pap)), "ozaki_gemm")
+    return C_tri, C_pap
+
+
+def split_int8(X: np.ndarray, D: int, along: str):
+    """INT8 digit planes ``(D, cols, rows)`` int8 and exponents E ``(nvec,)``."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    c = X.shape[0]
+    nvec, ln, s_vec, s_elt, s_comp = _split_axes(X, along)
+    digits = np.zeros((D,) + X.shape[1:], dtype=np.int8)
+    exps = np.zeros(nvec, dtype=np.int32)
+    _check(lib().oracle_split_int8(nvec, ln, c, _ptr(X), s_vec, s_elt, s_comp, D, _ptr(digits), _ptr(exps)),
+           "split_int8")
+    return digits, exps
+
+
+def int8_diag_sums(Ad, Bd) -> np.ndarray:
+    """S_g = sum_{s+t=g+1} A_s B_t for g = 1..D: ``(D, n, m)`` int64."""
+    Ad = np.ascontiguousarray(Ad, dtype=np.int8)
+    Bd = np.ascontiguousarray(Bd, dtype=np.int8)
+    D, k, m = Ad.shape
+    n = Bd.shape[1]
+    S = np.zeros((D, n, m), dtype=np.int64)
+    _check(lib().oracle_int8_diag_sums(m, n, k, D, _ptr(Ad), _ptr(Bd), _ptr(S)), "int8_diag_sums")
+    return S
+
+
+def int8_combine(S, EA, EB, c: int) -> np.ndarray:
+    S = np.ascontiguousarray(S, dtype=np.int64)
+    EA = np.ascontiguousarray(EA, dtype=np.int32)
+    EB = np.ascontiguousarray(EB, dtype=np.int32)
+    D, n, m = S.shape
+    C = np.zeros((c, n, m))
+    _check(lib().oracle_int8_combine(m, n, D, c, _ptr(S), _ptr(EA), _ptr(EB), _ptr(C)), "int8_combine")
+    return C
+
+
+def int8_gemm(A, B, D: int):
+    """INT8-form product: split, diagonal sums, exact combination."""
+    Ad, EA = split_int8(A, D, "rows")
+    Bd, EB = split_int8(B, D, "cols")
+    S = int8_diag_sums(Ad, Bd)
+    return int8_combine(S, EA, EB, A.shape[0])
+
+
+def gemm_naive(A, B, rows=None) -> np.ndarray:
+    """The paper's simple triple-loop product in the multi-component format."""
+    A = np.ascontiguousarray(A)
+    B = np.ascontiguousarray(B)
+    c, k, m = A.shape
+    n = B.shape[1]
+    rows_arr = None if rows is None else np.ascontiguousarray(rows, dtype=np.int32)
+    nrows = m if rows is None else len(rows_arr)
+    C = np.zeros((c, n, nrows), dtype=A.dtype)
+    _check(lib().oracle_gemm_naive(c, int(A.dtype == np.float32), m, n, k, _ptr(A), _ptr(B), _ptr(rows_arr), nrows,
+                                   _ptr(C)), "gemm_naive")
+    return C
+
+
+def bound_report(diff, absab, t: int):
+    """Elementwise bound ``|C - AB| <= 2^-t (|A||B|)``.
+
+    ``absab`` is computed from leading components, so it is within a relative
+    (k + 2) 2^-52 of the true value; the check allows that slack.  Returns
+    ``(ok, worst_log2_ratio)`` where the ratio is ``diff / absab`` (an element
+    with ``absab == 0`` must have ``diff == 0``).
+    """
+    diff = np.asarray(diff)
+    absab = np.asarray(absab)
+    zero = absab == 0
+    if np.any(diff[zero] != 0):
+        return False, float("inf")
+    nz = ~zero
+    if not np.any(nz):
+        return True, float("-inf")
+    ratio = diff[nz] / absab[nz]
+    worst = float(np.max(ratio))
+    ok = bool(np.all(diff[nz] <= np.ldexp(absab[nz], -t) * (1 + 2.0 ** -30)))
+    return ok, (float(np.log2(worst)) if worst > 0 else float("-inf"))

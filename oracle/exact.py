@@ -1,0 +1,166 @@
+"""Exact pure-Python references that pin the C oracle (test infrastructure).
+
+Everything here is exact rational or integer arithmetic (``fractions`` and
+Python ``int``), or plain IEEE arithmetic on Python floats / numpy float32
+where the method itself prescribes a floating-point step.  It is written
+independently of ``oracle.c`` so the two can be compared; it is slow and meant
+for small inputs only.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+
+import numpy as np
+
+
+def value(comps) -> Fraction:
+    """Exact value of an expansion (a sequence of binary64/binary32 components)."""
+    return sum((Fraction(float(x)) for x in comps), Fraction(0))
+
+
+def matrix_values(X) -> list:
+    """Exact element values of a ``(c, cols, rows)`` array: ``V[i][p]``."""
+    c, cols, rows = X.shape
+    return [[value(X[:, p, i]) for p in range(cols)] for i in range(rows)]
+
+
+def matmul_fraction(A, B):
+    """Exact ``A B`` for ``(c, k, m)`` and ``(c, n, k)`` inputs, as ``C[i][j]`` Fractions."""
+    Av = matrix_values(A)
+    Bv = matrix_values(B)  # Bv[p][j]
+    m, k = len(Av), len(Av[0]) if Av else 0
+    n = B.shape[1]
+    return [[sum((Av[i][p] * Bv[p][j] for p in range(k)), Fraction(0)) for j in range(n)] for i in range(m)]
+
+
+def _scaled_ints(X):
+    """Every element of X as an integer times 2**q for one common q."""
+    comps = X.astype(np.float64)
+    q = None
+    nz = comps[comps != 0]
+    for v in nz.ravel():
+        m, e = math.frexp(float(v))
+        qq = e - 53
+        q = qq if q is None else min(q, qq)
+    if q is None:
+        q = 0
+    c, cols, rows = X.shape
+    ints = [[0] * cols for _ in range(rows)]
+    for i in range(rows):
+        for p in range(cols):
+            s = 0
+            for r in range(c):
+                v = float(comps[r, p, i])
+                if v != 0:
+                    s += int(Fraction(v) * (Fraction(2) ** -q))
+            ints[i][p] = s
+    return ints, q
+
+
+def matmul_exact_int(A, B):
+    """Exact ``A B`` by scaled Python integers: returns ``(Cint, q)`` with
+    ``C[i][j] = Cint[i][j] * 2**q`` (fast enough for 128^3)."""
+    Ai, qa = _scaled_ints(A)  # Ai[i][p]
+    Bi, qb = _scaled_ints(B)  # Bi[p][j] (rows of B are p)
+    m = len(Ai)
+    k = len(Ai[0]) if m else 0
+    n = B.shape[1]
+    Bt = [[Bi[p][j] for p in range(k)] for j in range(n)]
+    C = [[sum(x * y for x, y in zip(Ai[i], Bt[j])) for j in range(n)] for i in range(m)]
+    return C, qa + qb
+
+
+def rho_exact(S: int, k: int) -> int:
+    """Smallest integer r with r >= (S + log2 k)/2, i.e. 2**(2r - S) >= k (no floating point)."""
+    r = 0
+    while True:
+        if 2 * r - S >= 0 and (1 << (2 * r - S)) >= k:
+            return r
+        if 2 * r - S < 0 and k <= 0:
+            return r
+        r += 1
+
+
+def _two_sum(a, b):
+    s = a + b
+    bb = s - a
+    return s, (a - (s - bb)) + (b - bb)
+
+
+def renorm_py(x, f32: bool = False):
+    """The same written renormalization as the oracle: a bottom-up TwoSum pass,
+    then a top-down TwoSum pass that emits a term whenever its error is nonzero."""
+    t = np.float32 if f32 else float
+    x = [t(v) for v in x]
+    n = len(x)
+    e = [t(0)] * n
+    s = x[-1]
+    for i in range(n - 2, -1, -1):
+        s, e[i + 1] = _two_sum(x[i], s)
+    out = []
+    cur = s
+    for i in range(1, n):
+        cur, err = _two_sum(cur, e[i])
+        if err != 0:
+            out.append(cur)
+            cur = err
+    out.append(cur)
+    out += [t(0)] * (n - len(out))
+    return out
+
+
+def split_vector_py(vec, D: int, f32: bool = False):
+    """Algorithm 1's split of one row/column (a list of component tuples).
+
+    Returns ``(slices[D][len], exps[D], residual[len][c])`` with the same
+    readings as the C oracle (D passes, remainder dropped, mu = 0 gives a zero
+    slice and exponent None).
+    """
+    t = np.float32 if f32 else float
+    S = 24 if f32 else 53
+    ln = len(vec)
+    r = rho_exact(S, ln)
+    R = [[t(v) for v in comps] for comps in vec]
+    slices, exps = [], []
+    for _ in range(D):
+        mu = max((abs(x[0]) for x in R), default=t(0))
+        if mu == 0:
+            slices.append([t(0)] * ln)
+            exps.append(None)
+            continue
+        fr = Fraction(float(mu))
+        e = 0
+        while Fraction(2) ** e < fr:
+            e += 1
+        while Fraction(2) ** (e - 1) >= fr:
+            e -= 1
+        exps.append(e)
+        tau = t(2.0 ** (e + r))
+        row = []
+        for x in R:
+            lead = x[0]
+            sl = (lead + tau) - tau
+            row.append(sl)
+            x[0] = lead - sl
+            x[:] = renorm_py(x, f32)
+        slices.append(row)
+    return slices, exps, R
+
+
+def int8_digits_py(comps_list, D: int):
+    """INT8 digits of one row/column by Python integers: returns ``(digits[len][D], E)``."""
+    lead = [float(c[0]) for c in comps_list]
+    nz = [x for x in lead if x != 0]
+    if not nz:
+        return [[0] * D for _ in comps_list], None
+    E = max(math.frexp(x)[1] for x in nz)  # frexp exponent = ilogb + 1
+    out = []
+    for comps in comps_list:
+        v = value(comps)
+        sg = -1 if v < 0 else 1
+        N = math.floor(abs(v) * Fraction(2) ** (7 * D - E))
+        assert N < (1 << (7 * D)), "value not below 2^E"
+        digs = [sg * ((N >> (7 * (D - s))) & 127) for s in range(1, D + 1)]
+        out.append(digs)
+    return out, E

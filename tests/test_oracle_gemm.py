@@ -1,0 +1,268 @@
+"""Pins of the oracle's products and its Ozaki GEMM against exact rational /
+integer arithmetic, closed forms and special cases that reduce to a textbook
+result."""
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle.exact as X
+import workload as W
+
+T_BITS = {"dd": 100, "td": 150, "qd": 200, "ts": 66}
+
+
+def _formats():
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_formats.txt")
+    out = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            name, c, cb, L = line.split()
+            out[name] = (int(c), int(cb), int(L))
+    return out
+
+
+def test_formats_match_paper_lengths():
+    """c components of cb bits give the paper's L bits (Sections 1 and 4.4), and
+    the error-bound exponents sit below L."""
+    f = _formats()
+    for name, (c, cb, L) in f.items():
+        assert c * cb == L
+        assert T_BITS[name] < L
+        assert W.FORMATS[name][0] == c
+
+
+@pytest.mark.parametrize("fmt", ["dd", "td", "qd", "ts"])
+def test_exact_check_against_fractions(orc, fmt):
+    m, n, k = 3, 4, 6
+    A, B = W.gen_pair(fmt, m, n, k, E=16, seed=4)
+    C = np.zeros((A.shape[0], n, m), dtype=A.dtype)
+    C[0] = 1.0
+    Cf = X.matmul_fraction(A, B)
+    diff, absab, cex = orc.exact_check(A, B, C)
+    for i in range(m):
+        for j in range(n):
+            assert cex[j, i] == float(Cf[i][j])
+            assert diff[j, i] == float(abs(Fraction(1) - Cf[i][j]))
+            ab = sum(abs(Fraction(float(A[0, p, i]))) * abs(Fraction(float(B[0, j, p]))) for p in range(k))
+            assert abs(Fraction(absab[j, i]) - ab) <= ab * Fraction(2) ** -48
+
+
+def test_slice_product_exact_non_square(orc):
+    """C_ab from exact int64 dot products equals the rational product (a 5x3 times 3x7
+    shape, so a transposed operand cannot pass)."""
+    m, n, k, D = 5, 7, 3, 3
+    A, B = W.gen_pair("td", m, n, k, E=8, seed=8)
+    sa, ea = orc.split_plain(A, D, "rows")
+    sb, eb = orc.split_plain(B, D, "cols")
+    rho = orc.rho(53, k)
+    for a in range(D):
+        for b in range(D):
+            P = orc.slice_product(sa[a], ea[a], sb[b], eb[b], rho, 53)
+            for i in range(m):
+                for j in range(n):
+                    want = sum(Fraction(float(sa[a, p, i])) * Fraction(float(sb[b, j, p])) for p in range(k))
+                    assert Fraction(P[j, i]) == want
+
+
+def test_config0_dd_128_meets_bound_against_python_integers(orc):
+    """DD, m = n = k = 128, e ~ U{0..8}: the oracle's Ozaki C (D = 6) is within
+    2^-100 |A||B| of the exact product computed by Python integers."""
+    m = n = k = 128
+    A, B = W.gen_pair("dd", m, n, k, E=8, seed=0)
+    C, Cp = orc.ozaki_gemm(A, B, 6, paper=True)
+    Cint, q = X.matmul_exact_int(A, B)
+    absA = np.abs(A[0]).T  # (m, k)
+    absB = np.abs(B[0]).T  # (k, n)
+    absab = absA @ absB
+    worst = -1e9
+    for Cx in (C, Cp):
+        for i in range(0, m, 3):
+            for j in range(n):
+                exact = Fraction(Cint[i][j]) * Fraction(2) ** q
+                err = abs(X.value(Cx[:, j, i]) - exact)
+                bound = Fraction(float(absab[i, j])) * Fraction(2) ** -100 * (1 + Fraction(2) ** -30)
+                assert err <= bound, (i, j)
+                if err:
+                    worst = max(worst, float(np.log2(float(err / Fraction(float(absab[i, j]))))))
+    assert worst < -100
+    # the C exact check agrees with the Python integers on a sample
+    diff, _, cex = orc.exact_check(A, B, C, rows=[0, 77])
+    for t, i in enumerate([0, 77]):
+        for j in range(0, n, 17):
+            exact = Fraction(Cint[i][j]) * Fraction(2) ** q
+            assert cex[j, t] == float(exact)
+            assert diff[j, t] == float(abs(X.value(C[:, j, i]) - exact))
+
+
+@pytest.mark.parametrize("fmt,D", [("dd", 6), ("td", 9), ("qd", 11), ("ts", 13)])
+def test_ozaki_meets_bound_ragged(orc, fmt, D):
+    m, n, k = 33, 21, 300
+    A, B = W.gen_pair(fmt, m, n, k, E=16, seed=17)
+    C, Cp = orc.ozaki_gemm(A, B, D, paper=True)
+    for Cx in (C, Cp):
+        diff, absab, _ = orc.exact_check(A, B, Cx.astype(A.dtype))
+        ok, worst = orc.bound_report(diff, absab, T_BITS[fmt])
+        assert ok, worst
+
+
+def test_dropping_a_term_breaks_the_bound(orc):
+    """The bound has teeth: with D = 5 at k = 64 the full triangle meets
+    2^-100 |A||B|, and leaving out one of its slice products (the pair (1, D))
+    does not."""
+    m, n, k, D = 8, 8, 64, 5
+    A, B = W.gen_pair("dd", m, n, k, E=8, seed=3)
+    sa, ea = orc.split_plain(A, D, "rows")
+    sb, eb = orc.split_plain(B, D, "cols")
+    rho = orc.rho(53, k)
+    full = np.zeros((2, n, m))
+    dropped = np.zeros((2, n, m))
+    for i in range(m):
+        for j in range(n):
+            terms = {}
+            for a in range(D):
+                for b in range(D - a):
+                    terms[(a, b)] = orc.slice_product(sa[a][:, i:i + 1], ea[a][i:i + 1], sb[b][j:j + 1],
+                                                      eb[b][j:j + 1], rho, 53)[0, 0]
+            full[:, j, i] = orc.exact_sum(list(terms.values()), 2)
+            dropped[:, j, i] = orc.exact_sum([v for key, v in terms.items() if key != (0, D - 1)], 2)
+    diff, absab, _ = orc.exact_check(A, B, full)
+    assert orc.bound_report(diff, absab, 100)[0]
+    diff, absab, _ = orc.exact_check(A, B, dropped)
+    ok, worst = orc.bound_report(diff, absab, 100)
+    assert not ok and worst > -100
+
+
+def test_identity_gives_input(orc):
+    """B = I with enough slices to exhaust A: C is A's exact value (as its
+    canonical greedy expansion)."""
+    m, k = 9, 12
+    A = W.gen_matrix("dd", m, k, E=4, seed=6, operand="A")
+    B = np.zeros((2, k, k))
+    B[0] = np.eye(k)
+    C, _ = orc.ozaki_gemm(A, B, 12)
+    for i in range(m):
+        for j in range(k):
+            assert list(C[:, j, i]) == list(orc.exact_sum(list(A[:, j, i]), 2))
+
+
+def test_single_slice_is_one_exact_product(orc):
+    m, n, k = 6, 5, 40
+    A, B = W.gen_pair("qd", m, n, k, E=8, seed=2)
+    sa, ea = orc.split_plain(A, 1, "rows")
+    sb, eb = orc.split_plain(B, 1, "cols")
+    P = orc.slice_product(sa[0], ea[0], sb[0], eb[0], orc.rho(53, k), 53)
+    C, _ = orc.ozaki_gemm(A, B, 1)
+    assert np.array_equal(C[0], P) and np.all(C[1:] == 0)
+
+
+def test_zero_and_small_integers(orc):
+    m, n, k = 7, 6, 50
+    A = np.zeros((2, k, m))
+    B = W.gen_matrix("dd", k, n, seed=1, operand="B")
+    C, _ = orc.ozaki_gemm(A, B, 4)
+    assert np.all(C == 0)
+    rng = np.random.default_rng(0)
+    Ai = rng.integers(-1023, 1024, size=(m, k))
+    Bi = rng.integers(-1023, 1024, size=(k, n))
+    A = np.zeros((2, k, m))
+    B = np.zeros((2, n, k))
+    A[0] = Ai.T
+    B[0] = Bi.T
+    C, _ = orc.ozaki_gemm(A, B, 3)
+    ref = Ai @ Bi  # exact in int64
+    assert np.array_equal(C[0], ref.T.astype(np.float64)) and np.all(C[1] == 0)
+
+
+def test_power_of_two_scaling_is_exact(orc):
+    m, n, k, D = 6, 5, 33, 5
+    A, B = W.gen_pair("td", m, n, k, E=8, seed=12)
+    C, _ = orc.ozaki_gemm(A, B, D)
+    A2 = A.copy()
+    A2[:, :, 3] *= 2.0 ** 37
+    B2 = B.copy()
+    B2[:, 2, :] *= 2.0 ** -21
+    C2, _ = orc.ozaki_gemm(A2, B2, D)
+    expect = C.copy()
+    expect[:, :, 3] *= 2.0 ** 37
+    expect[:, 2, :] *= 2.0 ** -21
+    assert np.array_equal(C2, expect)
+
+
+def test_error_falls_with_D_and_saturates_on_eq1_data(orc):
+    """Paper trend (Section 4.1): on eq. (1) matrices the DD error falls as D
+    grows and stops improving around D = 6 (at the DD rounding level)."""
+    m = n = k = 64
+    A, B = W.gen_pair("dd", m, n, k, seed=1, spread="eq1")
+    errs = []
+    for D in range(2, 9):
+        C, _ = orc.ozaki_gemm(A, B, D)
+        diff, absab, cex = orc.exact_check(A, B, C)
+        rel = np.max(diff / np.maximum(np.abs(cex), 1e-300))  # the paper's max relative error
+        errs.append(np.log2(rel))
+    assert all(errs[i + 1] < errs[i] - 10 for i in range(3))  # D = 2..5 each gain > 10 bits
+    assert abs(errs[-1] - errs[-3]) < 6 and errs[-1] < -95  # D = 6..8 saturate near 2^-106
+
+
+@pytest.mark.parametrize("fmt", ["dd", "qd"])
+def test_int8_digits_against_python_integers(orc, fmt):
+    m, k, D = 4, 9, 17
+    A = W.gen_matrix(fmt, m, k, E=16, seed=31, operand="A")
+    dg, E = orc.split_int8(A, D, "rows")
+    for i in range(m):
+        want, Ew = X.int8_digits_py([tuple(A[:, p, i]) for p in range(k)], D)
+        assert E[i] == Ew
+        for p in range(k):
+            assert list(dg[:, p, i]) == want[p]
+            assert np.all(np.abs(dg[:, p, i].astype(int)) <= 127)
+            # reconstruction: a = sum_s d_s 2^(E - 7 s) + r with 0 <= r sign(a) < 2^(E - 7 D)
+            x = X.value(A[:, p, i])
+            approx = sum(Fraction(int(dg[s, p, i])) * Fraction(2) ** (int(E[i]) - 7 * (s + 1)) for s in range(D))
+            r = x - approx
+            sg = 1 if x >= 0 else -1
+            assert 0 <= r * sg < Fraction(2) ** (int(E[i]) - 7 * D)
+
+
+def test_int8_diag_sums_and_combination(orc):
+    m, n, k, D = 5, 4, 7, 6
+    A, B = W.gen_pair("dd", m, n, k, E=8, seed=5)
+    Ad, EA = orc.split_int8(A, D, "rows")
+    Bd, EB = orc.split_int8(B, D, "cols")
+    S = orc.int8_diag_sums(Ad, Bd)
+    Ai = Ad.astype(np.int64)
+    Bi = Bd.astype(np.int64)
+    for g in range(1, D + 1):
+        ref = np.zeros((n, m), dtype=np.int64)
+        for s in range(1, g + 1):
+            t = g + 1 - s
+            ref += (Ai[s - 1].T @ Bi[t - 1].T).T  # (m,k)@(k,n) -> (m,n) -> (n,m)
+        assert np.array_equal(S[g - 1], ref)
+    C = orc.int8_combine(S, EA, EB, 2)
+    for i in range(m):
+        for j in range(n):
+            v = sum(Fraction(int(S[g - 1, j, i])) * Fraction(2) ** (int(EA[i]) + int(EB[j]) - 7 * (g + 1))
+                    for g in range(1, D + 1))
+            assert C[0, j, i] == float(v) and C[1, j, i] == float(v - Fraction(C[0, j, i]))
+
+
+@pytest.mark.parametrize("fmt,D", [("dd", 17), ("td", 24), ("qd", 31)])
+def test_int8_form_meets_bound(orc, fmt, D):
+    m, n, k = 19, 13, 200
+    A, B = W.gen_pair(fmt, m, n, k, E=16, seed=23)
+    C = orc.int8_gemm(A, B, D)
+    diff, absab, _ = orc.exact_check(A, B, C)
+    ok, worst = orc.bound_report(diff, absab, T_BITS[fmt])
+    assert ok, worst
+
+
+@pytest.mark.parametrize("fmt", ["dd", "td", "qd", "ts"])
+def test_naive_loop_accuracy(orc, fmt):
+    """The paper's simple triple loop (Section 4.1) is accurate to about
+    k 2^-(L-2) |A||B| (checked exactly)."""
+    m, n, k = 6, 5, 32
+    A, B = W.gen_pair(fmt, m, n, k, E=8, seed=9)
+    C = orc.gemm_naive(A, B)
+    diff, absab, _ = orc.exact_check(A, B, C)
+    L = {"dd": 106, "td": 159, "qd": 212, "ts": 72}[fmt]
+    assert np.all(diff <= absab * k * 2.0 ** -(L - 3))
