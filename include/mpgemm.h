@@ -1,0 +1,169 @@
+/*
+ * mpgemm: Ozaki-scheme multi-component matrix multiplication on AMD MI355X
+ * (gfx950).  C-ABI of libmpgemm.so.
+ *
+ * The operation (Utsugiri & Kouya, arXiv 2301.09960, Section 3, Algorithm 1):
+ * given A (m x k) and B (k x n) whose entries are multi-component numbers
+ * (the sum of c binary64 or binary32 components), compute C := A B in the
+ * same format.  A and B are split error-free into D slices each, whose
+ * pairwise products are exact in the slice arithmetic; the slice products
+ * C_ab = A_a B_b with a + b <= D + 1 are formed on the matrix cores and added
+ * error-free into the multi-component C.
+ *
+ * Formats (Section 1 and Section 4.4):
+ *   DD  2 x binary64 (106 bits)     TD  3 x binary64 (159 bits)
+ *   QD  4 x binary64 (212 bits)     TS  3 x binary32 (72 bits)
+ *
+ * Layout (all matrices): component-planar, column-major.  For A with leading
+ * dimension lda >= max(1, m), component r of A(i, p) is A[r*lda*k + i + p*lda]
+ * (plane r starts at A + r*lda*k).  B: component r of B(p, j) is
+ * B[r*ldb*n + p + j*ldb], ldb >= max(1, k).  C: component r of C(i, j) is
+ * C[r*ldc*n + i + j*ldc], ldc >= max(1, m).  Inputs are expected to be
+ * normalized expansions (|x_{r+1}| <= ulp(x_r)/2), finite, with magnitudes in
+ * [2^-400, 2^400] (binary64 formats) or [2^-16, 2^40] (TS) or zero, so that no
+ * slice product underflows; outside that range the result may lose accuracy.
+ *
+ * Memory and streams: A, B and C are device pointers owned by the caller; A and
+ * B are only read, C is overwritten (there is no alpha/beta scaling).  Every call
+ * enqueues its work on `stream` and returns without synchronizing; the result
+ * is valid once the stream has reached the call.  Temporary device memory is
+ * taken from a workspace attached with mpgemm_set_workspace, or else allocated
+ * stream-ordered on `stream` and released at the end of the call.
+ *
+ * Return codes: 0 on success; -i when the i-th argument is invalid (1-based,
+ * as the BLAS xerbla convention: m < 0 gives -1, lda < max(1, m) gives -5, a
+ * NULL matrix pointer with a non-empty extent gives its position); a positive
+ * MPGEMM_ERR_* code on a runtime failure.  m == 0 or n == 0 returns 0 without
+ * work; k == 0 sets C to zero.  Calls are safe from several host threads on
+ * different streams; options set with mpgemm_set_* are per host thread.
+ */
+#ifndef MPGEMM_H
+#define MPGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Formats. */
+#define MPGEMM_DD 0
+#define MPGEMM_TD 1
+#define MPGEMM_QD 2
+#define MPGEMM_TS 3
+
+/* Slice forms.  FLOAT: binary64 slices on FP64 matrix cores (binary32 slices
+ * on FP32 matrix cores for TS), Algorithm 1 as written.  INT8: signed 7-bit
+ * digit slices on INT8 matrix cores with exact 32-bit integer sums (DD, TD, QD
+ * only); more slices, each product far cheaper. */
+#define MPGEMM_MODE_FLOAT 0
+#define MPGEMM_MODE_INT8 1
+
+/* Runtime failures (positive return codes). */
+#define MPGEMM_ERR_HIP 1         /* a HIP runtime call failed */
+#define MPGEMM_ERR_WORKSPACE 2   /* attached workspace too small, or allocation failed */
+#define MPGEMM_ERR_DEVICE 3      /* current device is not gfx950 */
+#define MPGEMM_ERR_UNSUPPORTED 4 /* option not available for this format */
+#define MPGEMM_ERR_TOO_LARGE 5   /* size beyond the library's limits (see below) */
+
+/* Limits: m, n, k <= 2^20 (so every packed index fits 64 bits and every slice
+ * product sum fits its accumulator); 1 <= D <= 16 (FLOAT) or 1 <= D <= 40 (INT8). */
+
+/*
+ * C := A B in DD / TD / QD (Section 3, Algorithm 1; the product set is the
+ * triangle a + b <= D + 1 and every slice product is exact).  Arguments as in
+ * the layout paragraph above.  The result satisfies, elementwise,
+ * |C - A B| <= 2^-t (|A||B|) with t = 100 (DD), 150 (TD), 200 (QD) for inputs
+ * in range when D is left at its automatic value.
+ */
+int mpgemm_dd(int m, int n, int k, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+              hipStream_t stream);
+int mpgemm_td(int m, int n, int k, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+              hipStream_t stream);
+int mpgemm_qd(int m, int n, int k, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+              hipStream_t stream);
+
+/*
+ * C := A B in TS, triple binary32 (Section 4.4: the paper's GPU format, with
+ * binary32 slices, S = 24).  Bound t = 66 with the automatic D.  FLOAT mode only.
+ */
+int mpgemm_ts(int m, int n, int k, const float *A, int lda, const float *B, int ldb, float *C, int ldc,
+              hipStream_t stream);
+
+/*
+ * Options, per host thread and per format (fmt = MPGEMM_DD .. MPGEMM_TS).
+ * mpgemm_set_mode selects the slice form (returns MPGEMM_ERR_UNSUPPORTED for
+ * INT8 with TS).  mpgemm_set_num_slices sets D for (fmt, mode); 0 restores the
+ * automatic choice (Section 3 ties the attainable accuracy to the number of
+ * divisions; the automatic D is the smallest that meets the bound above with
+ * guard bits on inputs with an exponent spread of up to 16 bits within a row or
+ * column).  mpgemm_num_slices returns the D a call with inner dimension k would
+ * use.  mpgemm_last_num_slices returns the D used by this thread's last call.
+ */
+int mpgemm_set_mode(int fmt, int mode);
+int mpgemm_get_mode(int fmt);
+int mpgemm_set_num_slices(int fmt, int mode, int D);
+int mpgemm_num_slices(int fmt, int mode, int k);
+int mpgemm_last_num_slices(void);
+
+/*
+ * Workspace.  mpgemm_workspace_bytes gives the device bytes a call of this
+ * shape needs (D = 0: automatic).  mpgemm_set_workspace attaches caller-owned
+ * device memory (at least 256-byte aligned) for this host thread's later calls;
+ * NULL detaches it.  A call that finds the attached workspace too small returns
+ * MPGEMM_ERR_WORKSPACE without enqueuing work.  Work on different streams must
+ * not share one attached workspace concurrently.
+ */
+size_t mpgemm_workspace_bytes(int fmt, int mode, int m, int n, int k, int D);
+int mpgemm_set_workspace(void *dev_ptr, size_t bytes);
+
+/*
+ * Parity hooks (used by the tests to compare intermediate results bit for bit).
+ *
+ * mpgemm_debug_split: split one operand as the GEMM does.  operand 0: the rows
+ * of A (rows = m, cols = k, X is A with ldx = lda); operand 1: the columns of B
+ * (rows = k, cols = n, X is B with ldx = ldb).  Writes D slices as planes of
+ * rows x cols, column-major with leading dimension `rows`, into `slices`
+ * (binary64 for DD/TD/QD, binary32 for TS, int8 for INT8 mode), and exponents
+ * into `exps`: FLOAT mode: D x nvec int32, exps[a*nvec + v] = ceil(log2 mu_a)
+ * of vector v in pass a (INT32_MIN when mu_a = 0), nvec = rows for operand 0,
+ * cols for operand 1; INT8 mode: nvec int32, E_v = 1 + max ilogb of the
+ * leading components (INT32_MIN for an all-zero vector).
+ *
+ * mpgemm_debug_products: FLOAT mode: the exact slice product C_ab (Section 3)
+ * for 1-based a, b, as an m x n column-major binary64 matrix (ldo >= m; for TS
+ * the values are binary32 products held in binary64).  INT8 mode: the exact
+ * integer diagonal sum S_g = sum over s + t = g + 1 of A_s B_t for g = a
+ * (b ignored), as int64 in `out` reinterpreted.  All pointers are device
+ * pointers; D = 0 takes the automatic value.
+ */
+int mpgemm_debug_split(int fmt, int mode, int operand, int rows, int cols, const void *X, int ldx, int D,
+                       void *slices, int *exps, hipStream_t stream);
+int mpgemm_debug_products(int fmt, int mode, int m, int n, int k, const void *A, int lda, const void *B, int ldb,
+                          int D, int a, int b, void *out, int ldo, hipStream_t stream);
+
+/*
+ * Stage timing (the split / multiply-and-accumulate shares that Section 4.1
+ * profiles).  mpgemm_profile_enable(1) makes this host thread's later calls
+ * record HIP events on their stream before the split, between split and GEMM,
+ * and after the GEMM kernel.  mpgemm_profile_read waits for the recorded events
+ * and returns the summed milliseconds of the split stage and of the fused
+ * slice-product GEMM kernel, and the number of calls, since the previous read;
+ * then it clears the log.  Returns 0, or MPGEMM_ERR_HIP.
+ */
+int mpgemm_profile_enable(int on);
+int mpgemm_profile_read(double *split_ms, double *gemm_ms, int *calls);
+
+/* Text for a return code. */
+const char *mpgemm_status_string(int status);
+
+/* 0 if the current device is a gfx950, else MPGEMM_ERR_DEVICE (or MPGEMM_ERR_HIP). */
+int mpgemm_check_device(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPGEMM_H */

@@ -1,0 +1,266 @@
+"""Ozaki-scheme multi-component GEMM on AMD MI355X (gfx950): Python binding.
+
+This module only marshals arguments to ``libmpgemm.so`` (the C-ABI declared
+in ``include/mpgemm.h``); every step of the computation runs in the HIP
+kernels.  PyTorch provides device memory and streams.  If the library has not
+been built, importing succeeds but every call raises ``RuntimeError`` -- there
+is no fallback path.
+
+Tensor conventions (component-planar, column-major planes):
+    A (m x k)  -> tensor of shape (c, k, m)
+    B (k x n)  -> tensor of shape (c, n, k)
+    C (m x n)  -> tensor of shape (c, n, m)
+with c = 2 (DD), 3 (TD), 4 (QD) float64 components, or 3 float32 (TS).
+Row-major users get C^T = B^T A^T by swapping operands.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpgemm.so")
+
+FORMATS = {"dd": 0, "td": 1, "qd": 2, "ts": 3}
+COMPONENTS = {"dd": 2, "td": 3, "qd": 4, "ts": 3}
+BOUND_BITS = {"dd": 100, "td": 150, "qd": 200, "ts": 66}
+MODES = {"float": 0, "int8": 1}
+ZERO_EXP = -(2 ** 31)
+
+_lib = None
+_lock = threading.Lock()
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+
+
+class MpgemmError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: status {status} ({_status_string(status)})")
+
+
+def lib():
+    """The loaded HIP library; raises if it is missing (no CPU fallback exists)."""
+    global _lib
+    if _lib is None:
+        with _lock:
+            if _lib is None:
+                if not os.path.exists(LIB_PATH):
+                    raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2301_09960_amd.build`")
+                L = ctypes.CDLL(LIB_PATH)
+                for name in ("mpgemm_dd", "mpgemm_td", "mpgemm_qd", "mpgemm_ts"):
+                    f = getattr(L, name)
+                    f.restype = _I
+                    f.argtypes = [_I, _I, _I, _P, _I, _P, _I, _P, _I, _P]
+                L.mpgemm_set_mode.argtypes = [_I, _I]
+                L.mpgemm_get_mode.argtypes = [_I]
+                L.mpgemm_set_num_slices.argtypes = [_I, _I, _I]
+                L.mpgemm_num_slices.argtypes = [_I, _I, _I]
+                L.mpgemm_workspace_bytes.restype = ctypes.c_size_t
+                L.mpgemm_workspace_bytes.argtypes = [_I, _I, _I, _I, _I, _I]
+                L.mpgemm_set_workspace.argtypes = [_P, ctypes.c_size_t]
+                L.mpgemm_debug_split.argtypes = [_I, _I, _I, _I, _I, _P, _I, _I, _P, _P, _P]
+                L.mpgemm_debug_products.argtypes = [_I, _I, _I, _I, _I, _P, _I, _P, _I, _I, _I, _I, _P, _I, _P]
+                L.mpgemm_profile_enable.argtypes = [_I]
+                L.mpgemm_profile_read.argtypes = [_P, _P, _P]
+                L.mpgemm_status_string.restype = ctypes.c_char_p
+                L.mpgemm_status_string.argtypes = [_I]
+                _lib = L
+    return _lib
+
+
+def _status_string(status: int) -> str:
+    try:
+        return lib().mpgemm_status_string(status).decode()
+    except Exception:  # library missing while formatting an error
+        return "?"
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise MpgemmError(status, what)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _fmt(fmt) -> int:
+    return FORMATS[fmt] if isinstance(fmt, str) else int(fmt)
+
+
+def _mode(mode) -> int:
+    return MODES[mode] if isinstance(mode, str) else int(mode)
+
+
+def _check_tensor(t, c, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dim() != 3 or t.shape[0] != c:
+        raise ValueError(f"{name} must have shape (c={c}, cols, rows), got {tuple(t.shape)}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def set_mode(fmt, mode):
+    _check(lib().mpgemm_set_mode(_fmt(fmt), _mode(mode)), "set_mode")
+
+
+def get_mode(fmt) -> str:
+    m = lib().mpgemm_get_mode(_fmt(fmt))
+    return {0: "float", 1: "int8"}[m]
+
+
+def set_num_slices(fmt, mode, D: int):
+    _check(lib().mpgemm_set_num_slices(_fmt(fmt), _mode(mode), int(D)), "set_num_slices")
+
+
+def num_slices(fmt, mode, k: int) -> int:
+    return lib().mpgemm_num_slices(_fmt(fmt), _mode(mode), int(k))
+
+
+def last_num_slices() -> int:
+    return lib().mpgemm_last_num_slices()
+
+
+def workspace_bytes(fmt, mode, m, n, k, D=0) -> int:
+    return lib().mpgemm_workspace_bytes(_fmt(fmt), _mode(mode), m, n, k, D)
+
+
+def set_workspace(tensor=None):
+    """Attach a caller-owned device buffer (a torch tensor) as this thread's workspace; None detaches."""
+    if tensor is None:
+        _check(lib().mpgemm_set_workspace(None, 0), "set_workspace")
+    else:
+        _check(lib().mpgemm_set_workspace(ctypes.c_void_p(tensor.data_ptr()), tensor.numel() * tensor.element_size()),
+               "set_workspace")
+
+
+def profile_enable(on: bool = True):
+    """Record stage timings (split, fused GEMM kernel) of this thread's later calls."""
+    lib().mpgemm_profile_enable(1 if on else 0)
+
+
+def profile_read():
+    """``(split_ms, gemm_ms, calls)`` summed since the previous read (waits for the events)."""
+    s = ctypes.c_double()
+    g = ctypes.c_double()
+    c = ctypes.c_int()
+    _check(lib().mpgemm_profile_read(ctypes.byref(s), ctypes.byref(g), ctypes.byref(c)), "profile_read")
+    return s.value, g.value, c.value
+
+
+def check_device() -> int:
+    return lib().mpgemm_check_device()
+
+
+class _options:
+    """Temporarily set (mode, slices) for one call on this thread."""
+
+    def __init__(self, fmt, mode, slices):
+        self.fmt, self.mode, self.slices = fmt, mode, slices
+
+    def __enter__(self):
+        L = lib()
+        self.old_mode = L.mpgemm_get_mode(self.fmt)
+        if self.mode is not None:
+            _check(L.mpgemm_set_mode(self.fmt, self.mode), "set_mode")
+        m = L.mpgemm_get_mode(self.fmt)
+        self.mode_used = m
+        if self.slices is not None:
+            _check(L.mpgemm_set_num_slices(self.fmt, m, int(self.slices)), "set_num_slices")
+        return self
+
+    def __exit__(self, *exc):
+        L = lib()
+        if self.slices is not None:
+            L.mpgemm_set_num_slices(self.fmt, self.mode_used, 0)
+        L.mpgemm_set_mode(self.fmt, self.old_mode)
+        return False
+
+
+def gemm(fmt, A, B, C=None, *, mode=None, slices=None, stream=None):
+    """C = A B (Ozaki scheme) for torch tensors in the conventions above.
+
+    ``mode``: 'float' (binary64/binary32 slices) or 'int8'; ``slices``: D
+    (None/0 = automatic).  Enqueued on ``stream`` (default: the current
+    stream); returns C without synchronizing.
+    """
+    import torch
+    f = _fmt(fmt)
+    name = [k for k, v in FORMATS.items() if v == f][0]
+    c = COMPONENTS[name]
+    dtype = torch.float32 if name == "ts" else torch.float64
+    _check_tensor(A, c, dtype, "A")
+    _check_tensor(B, c, dtype, "B")
+    k, m = A.shape[1], A.shape[2]
+    n, kb = B.shape[1], B.shape[2]
+    if kb != k:
+        raise ValueError(f"inner dimensions differ: A has k={k}, B has k={kb}")
+    if C is None:
+        C = torch.empty((c, n, m), dtype=dtype, device=A.device)
+    else:
+        _check_tensor(C, c, dtype, "C")
+        if tuple(C.shape) != (c, n, m):
+            raise ValueError(f"C must have shape {(c, n, m)}")
+    fn = getattr(lib(), "mpgemm_" + name)
+    with _options(f, None if mode is None else _mode(mode), slices):
+        st = fn(m, n, k, _P(A.data_ptr()), max(1, m), _P(B.data_ptr()), max(1, k), _P(C.data_ptr()), max(1, m),
+                _stream(stream))
+    _check(st, "mpgemm_" + name)
+    return C
+
+
+def debug_split(fmt, X, operand: int, D: int = 0, mode="float", stream=None):
+    """Slices and exponents of one operand as the GEMM computes them.
+
+    ``operand=0``: X is A ``(c, k, m)`` split by rows; ``operand=1``: X is B
+    ``(c, n, k)`` split by columns.  Returns ``(slices, exps)`` with slices
+    ``(D, cols, rows)`` (float64 / float32 / int8) and exps ``(D, nvec)`` int32
+    (FLOAT) or ``(nvec,)`` (INT8).
+    """
+    import torch
+    f = _fmt(fmt)
+    md = _mode(mode)
+    name = [k for k, v in FORMATS.items() if v == f][0]
+    c = COMPONENTS[name]
+    dtype = torch.float32 if name == "ts" else torch.float64
+    _check_tensor(X, c, dtype, "X")
+    cols, rows = X.shape[1], X.shape[2]
+    k = cols if operand == 0 else rows
+    if D == 0:
+        D = num_slices(f, md, k)
+    nvec = rows if operand == 0 else cols
+    sdt = torch.int8 if md == 1 else dtype
+    slices = torch.zeros((D, cols, rows), dtype=sdt, device=X.device)
+    exps = torch.zeros((D, nvec) if md == 0 else (nvec,), dtype=torch.int32, device=X.device)
+    _check(lib().mpgemm_debug_split(f, md, operand, rows, cols, _P(X.data_ptr()), max(1, rows), D,
+                                    _P(slices.data_ptr()), _P(exps.data_ptr()), _stream(stream)), "debug_split")
+    return slices, exps
+
+
+def debug_products(fmt, A, B, a: int, b: int = 0, D: int = 0, mode="float", stream=None):
+    """FLOAT: the exact slice product C_ab (1-based), ``(n, m)`` float64.
+    INT8: the diagonal sum S_g for g = a, ``(n, m)`` int64."""
+    import torch
+    f = _fmt(fmt)
+    md = _mode(mode)
+    name = [k for k, v in FORMATS.items() if v == f][0]
+    c = COMPONENTS[name]
+    dtype = torch.float32 if name == "ts" else torch.float64
+    _check_tensor(A, c, dtype, "A")
+    _check_tensor(B, c, dtype, "B")
+    k, m = A.shape[1], A.shape[2]
+    n = B.shape[1]
+    out = torch.zeros((n, m), dtype=torch.int64 if md == 1 else torch.float64, device=A.device)
+    _check(lib().mpgemm_debug_products(f, md, m, n, k, _P(A.data_ptr()), max(1, m), _P(B.data_ptr()), max(1, k), D,
+                                       a, b, _P(out.data_ptr()), max(1, m), _stream(stream)), "debug_products")
+    return out

@@ -1,0 +1,537 @@
+// C-ABI of libmpgemm (declared in include/mpgemm.h): argument checking, the
+// slice-count policy, workspace handling and the launch sequence
+//   split(A rows, B columns) -> fused slice-product GEMM + accumulation.
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <climits>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/mpgemm.h"
+#include "internal.h"
+#include "layout.h"
+
+using namespace mp;
+
+namespace {
+
+constexpr int kNumFmt = 4;
+constexpr int kMaxDim = 1 << 20;
+constexpr int kMaxDFloat = 16;
+constexpr int kMaxDInt8 = 40;
+constexpr int kBoundBits[kNumFmt] = {100, 150, 200, 66};  // 2^-t bound per format
+constexpr int kComps[kNumFmt] = {2, 3, 4, 3};
+
+struct ThreadOptions {
+  int mode[kNumFmt] = {MPGEMM_MODE_FLOAT, MPGEMM_MODE_FLOAT, MPGEMM_MODE_FLOAT, MPGEMM_MODE_FLOAT};
+  int slices[kNumFmt][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  int last_slices = 0;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+};
+thread_local ThreadOptions g_opt;
+
+// Per-thread stage-timing log (mpgemm_profile_*).
+struct ProfileLog {
+  bool on = false;
+  std::vector<hipEvent_t> pool;           // reusable events
+  std::vector<std::array<hipEvent_t, 3>> marks;  // (before split, before GEMM, after GEMM)
+  ~ProfileLog() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+    for (auto &m : marks)
+      for (auto e : m) (void)hipEventDestroy(e);
+  }
+  hipEvent_t take() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+thread_local ProfileLog g_prof;
+
+int ceil_log2_int(int64_t k) {
+  int r = 0;
+  while ((int64_t(1) << r) < k) ++r;
+  return r;
+}
+
+// The shift ceil((S + log2 k) / 2) of tau (Section 3, Algorithm 1).
+int rho_of(int S, int64_t k) { return k < 1 ? 0 : (S + ceil_log2_int(k) + 1) / 2; }
+
+// Automatic D.  FLOAT: each slice carries b = S - rho bits, so the dropped
+// part falls like 2^-(D b); D is the smallest count with D b >= t + g, where
+// g (guard bits) covers the gap between an element's |A||B| and the row and
+// column maxima that set the slice grids for exponent spreads up to 16 bits,
+// plus a margin; that gap shrinks as k grows.  INT8: 7 bits per digit slice,
+// D 7 >= t + 14.
+int auto_slices(int fmt, int mode, int64_t k) {
+  const int t = kBoundBits[fmt];
+  if (mode == MPGEMM_MODE_INT8) return (t + 14 + 6) / 7;
+  const int S = fmt == MPGEMM_TS ? 24 : 53;
+  const int b = S - rho_of(S, k < 1 ? 1 : k);
+  int g = 22 - (11 * ceil_log2_int(k < 1 ? 1 : k)) / 10;
+  if (g < 8) g = 8;
+  int D = (t + g + b - 1) / b;
+  if (D > kMaxDFloat) D = kMaxDFloat;
+  if (D < 1) D = 1;
+  return D;
+}
+
+int slices_for(int fmt, int mode, int64_t k) {
+  const int s = g_opt.slices[fmt][mode];
+  return s > 0 ? s : auto_slices(fmt, mode, k);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace carve-up for one call.
+struct Plan {
+  int fmt, mode, C, D, rho;
+  size_t elem;  // bytes per slice element
+  int64_t mbp, nbp, kbp;
+  size_t off_resid_a, off_resid_b, off_pack_a, off_pack_b, off_mu_a, off_mu_b, off_exp_a, off_exp_b, total;
+};
+
+Plan make_plan(int fmt, int mode, int64_t m, int64_t n, int64_t k, int D) {
+  Plan p{};
+  p.fmt = fmt;
+  p.mode = mode;
+  p.C = kComps[fmt];
+  p.D = D;
+  const bool f32 = fmt == MPGEMM_TS;
+  const size_t comp = f32 ? 4 : 8;
+  p.mbp = nblocks_padded(m);
+  p.nbp = nblocks_padded(n);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  if (mode == MPGEMM_MODE_FLOAT) {
+    p.elem = comp;
+    p.rho = rho_of(f32 ? 24 : 53, k);
+    p.kbp = kblocks_padded(k);
+    const size_t ra = D > 1 ? (size_t)p.C * m * k * comp : 0, rb = D > 1 ? (size_t)p.C * k * n * comp : 0;
+    p.off_resid_a = take(ra);
+    p.off_resid_b = take(rb);
+    p.off_pack_a = take((size_t)D * p.mbp * p.kbp * 256 * comp);
+    p.off_pack_b = take((size_t)D * p.nbp * p.kbp * 256 * comp);
+    p.off_mu_a = take((size_t)D * m * comp);
+    p.off_mu_b = take((size_t)D * n * comp);
+    p.off_exp_a = take((size_t)D * m * 4);
+    p.off_exp_b = take((size_t)D * n * 4);
+  } else {
+    p.elem = 1;
+    p.rho = 0;
+    p.kbp = kblocks8_padded(k);
+    p.off_resid_a = p.off_resid_b = take(0);
+    p.off_pack_a = take((size_t)D * p.mbp * p.kbp * 1024);
+    p.off_pack_b = take((size_t)D * p.nbp * p.kbp * 1024);
+    p.off_mu_a = take(0);
+    p.off_mu_b = take(0);
+    p.off_exp_a = take((size_t)m * 4);
+    p.off_exp_b = take((size_t)n * 4);
+  }
+  p.total = o;
+  return p;
+}
+
+// Stream-ordered workspace: the thread's attached buffer, or an allocation on
+// the stream that is released (to the device's pool) at the end of the call.
+struct Workspace {
+  char *base = nullptr;
+  bool owned = false;
+  hipStream_t st = nullptr;
+  ~Workspace() {
+    if (owned && base) (void)hipFreeAsync(base, st);
+  }
+};
+
+std::mutex g_pool_mu;
+bool g_pool_ready[64] = {};
+int g_arch_ok[64] = {};  // 0 unknown, 1 gfx950, -1 other
+
+void keep_pool_memory(int dev) {
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  if (dev < 0 || dev >= 64 || g_pool_ready[dev]) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t threshold = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold);
+  }
+  g_pool_ready[dev] = true;
+}
+
+int acquire(Workspace &ws, size_t bytes, hipStream_t st) {
+  ws.st = st;
+  if (g_opt.ws) {
+    if (g_opt.ws_bytes < bytes) return MPGEMM_ERR_WORKSPACE;
+    ws.base = static_cast<char *>(g_opt.ws);
+    return 0;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MPGEMM_ERR_HIP;
+  keep_pool_memory(dev);
+  void *p = nullptr;
+  if (hipMallocAsync(&p, bytes > 0 ? bytes : 256, st) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return MPGEMM_ERR_WORKSPACE;
+  }
+  ws.base = static_cast<char *>(p);
+  ws.owned = true;
+  return 0;
+}
+
+int check_device_cached() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MPGEMM_ERR_HIP;
+  if (dev >= 0 && dev < 64 && g_arch_ok[dev] != 0) return g_arch_ok[dev] > 0 ? 0 : MPGEMM_ERR_DEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MPGEMM_ERR_HIP;
+  const bool ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+  if (dev >= 0 && dev < 64) g_arch_ok[dev] = ok ? 1 : -1;
+  return ok ? 0 : MPGEMM_ERR_DEVICE;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? 0 : MPGEMM_ERR_HIP; }
+
+int validate(int m, int n, int k, const void *A, int lda, const void *B, int ldb, const void *C, int ldc) {
+  if (m < 0) return -1;
+  if (n < 0) return -2;
+  if (k < 0) return -3;
+  if (!A && m > 0 && k > 0) return -4;
+  if (lda < (m > 1 ? m : 1)) return -5;
+  if (!B && k > 0 && n > 0) return -6;
+  if (ldb < (k > 1 ? k : 1)) return -7;
+  if (!C && m > 0 && n > 0) return -8;
+  if (ldc < (m > 1 ? m : 1)) return -9;
+  if (m > kMaxDim || n > kMaxDim || k > kMaxDim) return MPGEMM_ERR_TOO_LARGE;
+  return 0;
+}
+
+template <typename T>
+SplitOperand<T> operand_a(const T *A, int m, int k, int lda, const Plan &p, char *base) {
+  SplitOperand<T> o{};
+  o.X = A;
+  o.comp_stride = (int64_t)lda * k;
+  o.sv = 1;
+  o.sp = lda;
+  o.nvec = m;
+  o.len = k;
+  o.orient = 0;
+  o.resid = reinterpret_cast<T *>(base + p.off_resid_a);
+  o.packed = base + p.off_pack_a;
+  o.nbp = p.mbp;
+  o.kbp = p.kbp;
+  o.mu = base + p.off_mu_a;
+  o.exps = reinterpret_cast<int *>(base + p.off_exp_a);
+  return o;
+}
+
+template <typename T>
+SplitOperand<T> operand_b(const T *B, int k, int n, int ldb, const Plan &p, char *base) {
+  SplitOperand<T> o{};
+  o.X = B;
+  o.comp_stride = (int64_t)ldb * n;
+  o.sv = ldb;
+  o.sp = 1;
+  o.nvec = n;
+  o.len = k;
+  o.orient = 1;
+  o.resid = reinterpret_cast<T *>(base + p.off_resid_b);
+  o.packed = base + p.off_pack_b;
+  o.nbp = p.nbp;
+  o.kbp = p.kbp;
+  o.mu = base + p.off_mu_b;
+  o.exps = reinterpret_cast<int *>(base + p.off_exp_b);
+  return o;
+}
+
+template <typename T, int C>
+hipError_t split_both(const SplitOperand<T> &a, const SplitOperand<T> &b, const Plan &p, hipStream_t st) {
+  if (p.mode == MPGEMM_MODE_INT8) {
+    if constexpr (sizeof(T) == 8) return launch_split_int8<C>(a, b, p.D, st);
+    return hipErrorInvalidValue;
+  }
+  return launch_split_plain<T, C>(a, b, p.D, p.rho, st);
+}
+
+template <typename T, int C>
+hipError_t gemm_launch(const Plan &p, char *base, int m, int n, int k, T *Cout, int ldc, int dbg_pair, void *dbg_out,
+                       int lddbg, hipStream_t st) {
+  if (p.mode == MPGEMM_MODE_INT8) {
+    if constexpr (sizeof(T) == 8)
+      return launch_gemm_int8<C>(base + p.off_pack_a, base + p.off_pack_b,
+                                 reinterpret_cast<const int *>(base + p.off_exp_a),
+                                 reinterpret_cast<const int *>(base + p.off_exp_b), p.mbp, p.nbp, p.kbp, k, m, n, p.D,
+                                 Cout, ldc, (int64_t)ldc * n, dbg_pair, static_cast<int64_t *>(dbg_out), lddbg, st);
+    return hipErrorInvalidValue;
+  }
+  return launch_gemm_plain<T, C>(base + p.off_pack_a, base + p.off_pack_b, p.mbp, p.nbp, p.kbp, m, n, p.D, Cout, ldc,
+                                 (int64_t)ldc * n, dbg_pair, static_cast<double *>(dbg_out), lddbg, st);
+}
+
+template <typename T, int C>
+int run(int fmt, int m, int n, int k, const T *A, int lda, const T *B, int ldb, T *Cm, int ldc, hipStream_t st) {
+  int s = validate(m, n, k, A, lda, B, ldb, Cm, ldc);
+  if (s) return s;
+  if ((s = check_device_cached())) return s;
+  const int mode = g_opt.mode[fmt];
+  const int D = slices_for(fmt, mode, k);
+  g_opt.last_slices = D;
+  if (m == 0 || n == 0) return 0;
+  if (k == 0) return hip_status(launch_zero_matrix(Cm, sizeof(T), C, m, n, ldc, (int64_t)ldc * n, st));
+  const Plan p = make_plan(fmt, mode, m, n, k, D);
+  Workspace ws;
+  if ((s = acquire(ws, p.total, st))) return s;
+  const SplitOperand<T> a = operand_a(A, m, k, lda, p, ws.base), b = operand_b(B, k, n, ldb, p, ws.base);
+  std::array<hipEvent_t, 3> ev{nullptr, nullptr, nullptr};
+  if (g_prof.on) {
+    for (auto &x : ev) x = g_prof.take();
+    if (ev[0]) (void)hipEventRecord(ev[0], st);
+  }
+  hipError_t e = split_both<T, C>(a, b, p, st);
+  if (ev[1]) (void)hipEventRecord(ev[1], st);
+  if (e == hipSuccess) e = gemm_launch<T, C>(p, ws.base, m, n, k, Cm, ldc, -1, nullptr, 0, st);
+  if (ev[2]) (void)hipEventRecord(ev[2], st);
+  if (g_prof.on) {
+    if (ev[0] && ev[1] && ev[2])
+      g_prof.marks.push_back(ev);
+    else
+      for (auto x : ev)
+        if (x) g_prof.pool.push_back(x);
+  }
+  return hip_status(e);
+}
+
+template <typename T, int C>
+int debug_split_t(int fmt, int mode, int operand, int rows, int cols, const T *X, int ldx, int D, void *slices,
+                  int *exps, hipStream_t st) {
+  if (rows < 0) return -4;
+  if (cols < 0) return -5;
+  if (!X && rows > 0 && cols > 0) return -6;
+  if (ldx < (rows > 1 ? rows : 1)) return -7;
+  if (D < 0) return -8;
+  if (!slices || !exps) return -9;
+  int s;
+  if ((s = check_device_cached())) return s;
+  const int m = operand == 0 ? rows : 0, k = operand == 0 ? cols : rows, n = operand == 0 ? 0 : cols;
+  if (D == 0) D = slices_for(fmt, mode, k);
+  if (rows == 0 || cols == 0) return 0;
+  const Plan p = make_plan(fmt, mode, m, n, k, D);
+  Workspace ws;
+  if ((s = acquire(ws, p.total, st))) return s;
+  SplitOperand<T> a = operand_a(operand == 0 ? X : (const T *)nullptr, m, k, ldx, p, ws.base);
+  SplitOperand<T> b = operand_b(operand == 1 ? X : (const T *)nullptr, k, n, ldx, p, ws.base);
+  hipError_t e = split_both<T, C>(a, b, p, st);
+  if (e != hipSuccess) return MPGEMM_ERR_HIP;
+  const int nvec = operand == 0 ? rows : cols;
+  const int64_t nbp = operand == 0 ? p.mbp : p.nbp;
+  e = launch_unpack((int)p.elem, ws.base + (operand == 0 ? p.off_pack_a : p.off_pack_b), nbp, p.kbp, D, operand, rows,
+                    cols, slices, st);
+  if (e != hipSuccess) return MPGEMM_ERR_HIP;
+  const size_t nexp = mode == MPGEMM_MODE_FLOAT ? (size_t)D * nvec : (size_t)nvec;
+  e = hipMemcpyAsync(exps, ws.base + (operand == 0 ? p.off_exp_a : p.off_exp_b), nexp * sizeof(int),
+                     hipMemcpyDeviceToDevice, st);
+  return hip_status(e);
+}
+
+template <typename T, int C>
+int debug_products_t(int fmt, int mode, int m, int n, int k, const T *A, int lda, const T *B, int ldb, int D, int a,
+                     int b, void *out, int ldo, hipStream_t st) {
+  int s = validate(m, n, k, A, lda, B, ldb, out, ldo);
+  if (s) return s < 0 ? s - 2 : s;  // shifted past (fmt, mode)
+  if ((s = check_device_cached())) return s;
+  if (D == 0) D = slices_for(fmt, mode, k);
+  if (mode == MPGEMM_MODE_FLOAT && (a < 1 || b < 1 || a + b > D + 1)) return -12;
+  if (mode == MPGEMM_MODE_INT8 && (a < 1 || a > D)) return -12;
+  if (m == 0 || n == 0 || k == 0) return 0;
+  const Plan p = make_plan(fmt, mode, m, n, k, D);
+  Workspace ws;
+  if ((s = acquire(ws, p.total, st))) return s;
+  const SplitOperand<T> sa = operand_a(A, m, k, lda, p, ws.base), sb = operand_b(B, k, n, ldb, p, ws.base);
+  hipError_t e = split_both<T, C>(sa, sb, p, st);
+  const int sel = mode == MPGEMM_MODE_FLOAT ? (a - 1) * D + (b - 1) : a;
+  if (e == hipSuccess) e = gemm_launch<T, C>(p, ws.base, m, n, k, nullptr, m, sel, out, ldo, st);
+  return hip_status(e);
+}
+
+bool fmt_ok(int fmt) { return fmt >= 0 && fmt < kNumFmt; }
+bool mode_ok(int fmt, int mode) {
+  return mode == MPGEMM_MODE_FLOAT || (mode == MPGEMM_MODE_INT8 && fmt != MPGEMM_TS);
+}
+
+__global__ void k_zero_matrix(char *C, int elem_bytes, int comps, int m, int n, int ldc, int64_t c_stride) {
+  const int64_t total = (int64_t)comps * m * n;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(t / ((int64_t)m * n));
+    const int64_t rem = t % ((int64_t)m * n);
+    const int64_t i = rem % m, j = rem / m;
+    const int64_t off = (r * c_stride + i + j * ldc) * elem_bytes;
+    if (elem_bytes == 8)
+      *reinterpret_cast<double *>(C + off) = 0.0;
+    else
+      *reinterpret_cast<float *>(C + off) = 0.0f;
+  }
+}
+
+}  // namespace
+
+namespace mp {
+hipError_t launch_zero_matrix(void *C, int elem_bytes, int comps, int m, int n, int ldc, int64_t c_stride,
+                              hipStream_t st) {
+  const int64_t total = (int64_t)comps * m * n;
+  if (total <= 0) return hipSuccess;
+  const int64_t blocks = ceil_div(total, 256);
+  hipLaunchKernelGGL(k_zero_matrix, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, st,
+                     static_cast<char *>(C), elem_bytes, comps, m, n, ldc, c_stride);
+  return hipGetLastError();
+}
+}  // namespace mp
+
+extern "C" {
+
+int mpgemm_dd(int m, int n, int k, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+              hipStream_t stream) {
+  return run<double, 2>(MPGEMM_DD, m, n, k, A, lda, B, ldb, C, ldc, stream);
+}
+int mpgemm_td(int m, int n, int k, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+              hipStream_t stream) {
+  return run<double, 3>(MPGEMM_TD, m, n, k, A, lda, B, ldb, C, ldc, stream);
+}
+int mpgemm_qd(int m, int n, int k, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+              hipStream_t stream) {
+  return run<double, 4>(MPGEMM_QD, m, n, k, A, lda, B, ldb, C, ldc, stream);
+}
+int mpgemm_ts(int m, int n, int k, const float *A, int lda, const float *B, int ldb, float *C, int ldc,
+              hipStream_t stream) {
+  return run<float, 3>(MPGEMM_TS, m, n, k, A, lda, B, ldb, C, ldc, stream);
+}
+
+int mpgemm_set_mode(int fmt, int mode) {
+  if (!fmt_ok(fmt)) return -1;
+  if (mode != MPGEMM_MODE_FLOAT && mode != MPGEMM_MODE_INT8) return -2;
+  if (!mode_ok(fmt, mode)) return MPGEMM_ERR_UNSUPPORTED;
+  g_opt.mode[fmt] = mode;
+  return 0;
+}
+int mpgemm_get_mode(int fmt) { return fmt_ok(fmt) ? g_opt.mode[fmt] : -1; }
+
+int mpgemm_set_num_slices(int fmt, int mode, int D) {
+  if (!fmt_ok(fmt)) return -1;
+  if (mode != MPGEMM_MODE_FLOAT && mode != MPGEMM_MODE_INT8) return -2;
+  if (!mode_ok(fmt, mode)) return MPGEMM_ERR_UNSUPPORTED;
+  if (D < 0 || D > (mode == MPGEMM_MODE_FLOAT ? kMaxDFloat : kMaxDInt8)) return -3;
+  g_opt.slices[fmt][mode] = D;
+  return 0;
+}
+int mpgemm_num_slices(int fmt, int mode, int k) {
+  if (!fmt_ok(fmt)) return -1;
+  if (!mode_ok(fmt, mode)) return -2;
+  if (k < 0) return -3;
+  return slices_for(fmt, mode, k);
+}
+int mpgemm_last_num_slices(void) { return g_opt.last_slices; }
+
+size_t mpgemm_workspace_bytes(int fmt, int mode, int m, int n, int k, int D) {
+  if (!fmt_ok(fmt) || !mode_ok(fmt, mode) || m < 0 || n < 0 || k < 0) return 0;
+  if (D <= 0) D = slices_for(fmt, mode, k);
+  return make_plan(fmt, mode, m, n, k, D).total;
+}
+int mpgemm_set_workspace(void *dev_ptr, size_t bytes) {
+  if (dev_ptr && (reinterpret_cast<uintptr_t>(dev_ptr) & 255)) return -1;
+  g_opt.ws = dev_ptr;
+  g_opt.ws_bytes = dev_ptr ? bytes : 0;
+  return 0;
+}
+
+int mpgemm_debug_split(int fmt, int mode, int operand, int rows, int cols, const void *X, int ldx, int D,
+                       void *slices, int *exps, hipStream_t stream) {
+  if (!fmt_ok(fmt)) return -1;
+  if (mode != MPGEMM_MODE_FLOAT && mode != MPGEMM_MODE_INT8) return -2;
+  if (!mode_ok(fmt, mode)) return MPGEMM_ERR_UNSUPPORTED;
+  if (operand != 0 && operand != 1) return -3;
+  if (D > (mode == MPGEMM_MODE_FLOAT ? kMaxDFloat : kMaxDInt8)) return -8;
+  switch (fmt) {
+    case MPGEMM_DD:
+      return debug_split_t<double, 2>(fmt, mode, operand, rows, cols, (const double *)X, ldx, D, slices, exps, stream);
+    case MPGEMM_TD:
+      return debug_split_t<double, 3>(fmt, mode, operand, rows, cols, (const double *)X, ldx, D, slices, exps, stream);
+    case MPGEMM_QD:
+      return debug_split_t<double, 4>(fmt, mode, operand, rows, cols, (const double *)X, ldx, D, slices, exps, stream);
+    default:
+      return debug_split_t<float, 3>(fmt, mode, operand, rows, cols, (const float *)X, ldx, D, slices, exps, stream);
+  }
+}
+
+int mpgemm_debug_products(int fmt, int mode, int m, int n, int k, const void *A, int lda, const void *B, int ldb,
+                          int D, int a, int b, void *out, int ldo, hipStream_t stream) {
+  if (!fmt_ok(fmt)) return -1;
+  if (mode != MPGEMM_MODE_FLOAT && mode != MPGEMM_MODE_INT8) return -2;
+  if (!mode_ok(fmt, mode)) return MPGEMM_ERR_UNSUPPORTED;
+  if (D < 0 || D > (mode == MPGEMM_MODE_FLOAT ? kMaxDFloat : kMaxDInt8)) return -10;
+  switch (fmt) {
+    case MPGEMM_DD:
+      return debug_products_t<double, 2>(fmt, mode, m, n, k, (const double *)A, lda, (const double *)B, ldb, D, a, b,
+                                         out, ldo, stream);
+    case MPGEMM_TD:
+      return debug_products_t<double, 3>(fmt, mode, m, n, k, (const double *)A, lda, (const double *)B, ldb, D, a, b,
+                                         out, ldo, stream);
+    case MPGEMM_QD:
+      return debug_products_t<double, 4>(fmt, mode, m, n, k, (const double *)A, lda, (const double *)B, ldb, D, a, b,
+                                         out, ldo, stream);
+    default:
+      return debug_products_t<float, 3>(fmt, mode, m, n, k, (const float *)A, lda, (const float *)B, ldb, D, a, b,
+                                        out, ldo, stream);
+  }
+}
+
+const char *mpgemm_status_string(int status) {
+  if (status == 0) return "success";
+  if (status < 0) return "invalid argument";
+  switch (status) {
+    case MPGEMM_ERR_HIP: return "HIP runtime error";
+    case MPGEMM_ERR_WORKSPACE: return "workspace too small or allocation failed";
+    case MPGEMM_ERR_DEVICE: return "device is not gfx950";
+    case MPGEMM_ERR_UNSUPPORTED: return "unsupported option for this format";
+    case MPGEMM_ERR_TOO_LARGE: return "size beyond library limits";
+    default: return "unknown status";
+  }
+}
+
+int mpgemm_check_device(void) { return check_device_cached(); }
+
+int mpgemm_profile_enable(int on) {
+  g_prof.on = on != 0;
+  return 0;
+}
+
+int mpgemm_profile_read(double *split_ms, double *gemm_ms, int *calls) {
+  double s = 0, g = 0;
+  int status = 0;
+  for (auto &m : g_prof.marks) {
+    float a = 0, b = 0;
+    if (hipEventSynchronize(m[2]) != hipSuccess || hipEventElapsedTime(&a, m[0], m[1]) != hipSuccess ||
+        hipEventElapsedTime(&b, m[1], m[2]) != hipSuccess)
+      status = MPGEMM_ERR_HIP;
+    s += a;
+    g += b;
+    for (auto x : m) g_prof.pool.push_back(x);
+  }
+  if (calls) *calls = (int)g_prof.marks.size();
+  g_prof.marks.clear();
+  if (split_ms) *split_ms = s;
+  if (gemm_ms) *gemm_ms = g;
+  return status;
+}
+
+}  // extern "C"

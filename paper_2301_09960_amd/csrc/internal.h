@@ -1,0 +1,64 @@
+// Internal host-side interfaces between the C-ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mp {
+
+constexpr int kZeroExp = INT32_MIN;
+
+// One operand of a split: `nvec` vectors (rows of A, or columns of B) of `len`
+// multi-component elements; component r of element (v, p) is at
+// X[r * comp_stride + v * sv + p * sp].  `orient` 0: v is the contiguous
+// index (rows of a column-major A); 1: p is (columns of a column-major B).
+template <typename T>
+struct SplitOperand {
+  const T *X;
+  int64_t comp_stride, sv, sp;
+  int nvec, len;
+  int orient;
+  // workspace
+  T *resid;              // C planes of nvec * len, same orientation, compact
+  void *packed;          // packed slices (layout.h)
+  int64_t nbp, kbp;      // padded block counts of the packed slices
+  void *mu;              // per pass: nvec maxima as IEEE bit patterns (uint64 / uint32)
+  int *exps;             // D x nvec exponents (FLOAT) or nvec (INT8)
+};
+
+// Plain split (Algorithm 1): D passes, slices written packed.  `rho` is the
+// shift ceil((S + log2 k)/2).  Both operands in one sequence of launches.
+template <typename T, int C>
+hipError_t launch_split_plain(const SplitOperand<T> &a, const SplitOperand<T> &b, int D, int rho, hipStream_t st);
+
+// INT8 digit split of both operands.
+template <int C>
+hipError_t launch_split_int8(const SplitOperand<double> &a, const SplitOperand<double> &b, int D, hipStream_t st);
+
+// Fused slice-product GEMM with error-free accumulation into C (C components).
+// single_pair >= 0 selects debug mode: only pair (a, b) = (single_pair / D,
+// single_pair % D) (0-based) is formed and written raw as binary64 into Cdbg.
+template <typename T, int C>
+hipError_t launch_gemm_plain(const void *Apk, const void *Bpk, int64_t mbp, int64_t nbp, int64_t kbp, int m, int n,
+                             int D, T *Cout, int ldc, int64_t c_stride, int single_pair, double *Cdbg, int lddbg,
+                             hipStream_t st);
+
+// INT8 form GEMM: diagonal sums and their exact combination into C.
+template <int C>
+hipError_t launch_gemm_int8(const void *Apk, const void *Bpk, const int *EA, const int *EB, int64_t mbp, int64_t nbp,
+                            int64_t kbp8, int k, int m, int n, int D, double *Cout, int ldc, int64_t c_stride,
+                            int debug_g, int64_t *Sdbg, int lddbg, hipStream_t st);
+
+// Debug: unpack D packed slices into planes of rows x cols (column-major, ld rows).
+hipError_t launch_unpack(int elem_bytes, const void *packed, int64_t nbp, int64_t kbp, int D, int orient, int rows,
+                         int cols, void *out, hipStream_t st);
+
+// Fill n 32-bit words with a value (used instead of memset so that the
+// sequence stays capturable in a graph).
+hipError_t launch_fill32(void *p, int64_t nwords, uint32_t value, hipStream_t st);
+
+// C := 0 for an m x n multi-component matrix.
+hipError_t launch_zero_matrix(void *C, int elem_bytes, int comps, int m, int n, int ldc, int64_t c_stride,
+                              hipStream_t st);
+
+}  // namespace mp

@@ -1,0 +1,62 @@
+// Packed slice layout shared by the split kernels (writers) and the
+// matrix-core GEMM kernels (readers).  Host and device.
+//
+// A slice matrix is stored as 16 x 16 blocks ("row/col block" x "k block"),
+// each block laid out in the order in which one 64-lane wavefront feeds it to
+// the 16x16x4 matrix-core instructions:
+//   lane l holds the 16-element row/column index l % 16 and, over four
+//   instructions s = 0..3, the k indices 4 s + l / 16 of the block.
+// Within a block of 256 elements the value for (lane l, step s) sits at
+//   binary64:  (s / 2) * 128 + 2 l + (s % 2)   (two 16-byte loads per lane,
+//              each contiguous across the wavefront)
+//   binary32:  4 l + s                         (one 16-byte load per lane)
+// Blocks of one row/column block are consecutive along k; a slice is
+// [nb][kb][256] with nb row/column blocks and kb k-blocks; slices follow one
+// another.  Padding (rows beyond m, k beyond k) holds zeros.
+//
+// INT8 digit slices use 16 x 64 blocks for the 16x16x64 integer instruction:
+// lane l holds index l % 16 and the 16 consecutive k values 16 (l / 16) + t,
+// t = 0..15, stored as 16 bytes at 16 l + t.
+#pragma once
+
+#include <stdint.h>
+
+namespace mp {
+
+constexpr int kBlk = 16;      // rows/cols per block
+constexpr int kKBlk = 16;     // k per block (floating-point slices)
+constexpr int kKBlk8 = 64;    // k per block (INT8 slices)
+constexpr int kTileBlocks = 4;  // GEMM tile = 4 x 4 blocks (64 x 64)
+constexpr int kKStepBlocks = 2; // GEMM k step = 2 k-blocks (32)
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Padded block counts: rows/cols padded to the GEMM tile, k to the k step.
+__host__ __device__ inline int64_t nblocks_padded(int64_t rows) {
+  return ceil_div(rows, kBlk * kTileBlocks) * kTileBlocks;
+}
+__host__ __device__ inline int64_t kblocks_padded(int64_t k) {
+  return ceil_div(k, kKBlk * kKStepBlocks) * kKStepBlocks;
+}
+__host__ __device__ inline int64_t kblocks8_padded(int64_t k) { return ceil_div(k, kKBlk8); }
+
+// Offset (in elements) of element (v, p) of slice a: v = row of A / column of B,
+// p = k index.  nbp / kbp: padded block counts.
+template <bool F64>
+__host__ __device__ inline int64_t packed_index(int64_t a, int64_t v, int64_t p, int64_t nbp, int64_t kbp) {
+  const int64_t vb = v / kBlk, vl = v % kBlk;
+  const int64_t kb = p / kKBlk, kl = p % kKBlk;
+  const int64_t lane = (kl % 4) * 16 + vl;
+  const int64_t s = kl / 4;
+  const int64_t within = F64 ? (s / 2) * 128 + 2 * lane + (s % 2) : 4 * lane + s;
+  return ((a * nbp + vb) * kbp + kb) * 256 + within;
+}
+
+__host__ __device__ inline int64_t packed_index8(int64_t a, int64_t v, int64_t p, int64_t nbp, int64_t kbp) {
+  const int64_t vb = v / kBlk, vl = v % kBlk;
+  const int64_t kb = p / kKBlk8, kl = p % kKBlk8;
+  const int64_t lane = (kl / 16) * 16 + vl;
+  return ((a * nbp + vb) * kbp + kb) * 1024 + 16 * lane + (kl % 16);
+}
+
+}  // namespace mp

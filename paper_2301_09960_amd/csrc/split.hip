@@ -1,0 +1,274 @@
+// Split kernels: Algorithm 1 (Section 3) of Utsugiri & Kouya, the loop that
+// cuts A into slices A_1..A_D row by row and B into B_1..B_D column by column.
+//
+// Pass a (0-based) of a vector (a row of A or a column of B):
+//   mu   = max |lead| over the vector          (lead: component 0 of the residual)
+//   e    = ceil(log2 mu),  tau = 2^(e + rho),   rho = ceil((S + log2 k) / 2)
+//   X_a  = (lead + tau) - tau                  (S-bit arithmetic: binary64 or binary32)
+//   lead = lead - X_a                          (exact), then renormalize the residual
+// The maximum for pass a + 1 is taken while pass a writes its residual, so the
+// D passes cost D + 1 sweeps over the operand.  mu = 0 gives a zero slice.
+// The residual after the last pass is dropped, so every slice product is exact.
+//
+// Each block handles a 64 x 64 tile of (vector, k) elements with 256 threads;
+// lanes run along the contiguous memory index (the row index of a column-major
+// A, the k index of a column-major B) so loads are coalesced.  Row maxima of A
+// are combined across the block in LDS, column maxima of B with wavefront
+// shuffles, then one integer atomic max per vector per block.
+#include "internal.h"
+#include "layout.h"
+#include "mp_device.h"
+
+namespace mp {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kTile = 64;
+constexpr int kPerThread = kTile * kTile / kThreads;  // 16
+
+struct TileCoord {
+  int v0, p0;
+};
+
+// Tile of linear index idx for an operand covering nvec_cover x len_cover.
+template <int ORIENT>
+__device__ __forceinline__ TileCoord tile_of(int idx, int nvec_cover, int len_cover) {
+  if (ORIENT == 0) {
+    const int tc = (nvec_cover + kTile - 1) / kTile;
+    return {(idx % tc) * kTile, (idx / tc) * kTile};
+  } else {
+    const int tc = (len_cover + kTile - 1) / kTile;
+    return {(idx / tc) * kTile, (idx % tc) * kTile};
+  }
+}
+
+// Element t (0..15) of this thread inside the tile.
+template <int ORIENT>
+__device__ __forceinline__ void elem_of(const TileCoord &tc, int t, int &v, int &p) {
+  const int lane = threadIdx.x % 64, ty = threadIdx.x / 64;
+  if (ORIENT == 0) {
+    v = tc.v0 + lane;
+    p = tc.p0 + ty + 4 * t;
+  } else {
+    p = tc.p0 + lane;
+    v = tc.v0 + ty + 4 * t;
+  }
+}
+
+__device__ __forceinline__ unsigned long long shfl_max(unsigned long long x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    unsigned long long y = __shfl_xor(x, off, 64);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+__device__ __forceinline__ unsigned int shfl_max(unsigned int x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    unsigned int y = __shfl_xor(x, off, 64);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+// Combine per-element maxima m[t] (bit patterns) into one atomic max per vector.
+template <int ORIENT, typename U>
+__device__ __forceinline__ void reduce_max(const TileCoord &tc, const U (&m)[kPerThread], U *mu, int nvec) {
+  const int lane = threadIdx.x % 64, ty = threadIdx.x / 64;
+  if (ORIENT == 0) {
+    // all 16 elements of a thread share v = v0 + lane
+    U best = 0;
+#pragma unroll
+    for (int t = 0; t < kPerThread; ++t) best = m[t] > best ? m[t] : best;
+    __shared__ U red[4][64];
+    red[ty][lane] = best;
+    __syncthreads();
+    if (ty == 0) {
+      U b = red[0][lane];
+#pragma unroll
+      for (int q = 1; q < 4; ++q) b = red[q][lane] > b ? red[q][lane] : b;
+      const int v = tc.v0 + lane;
+      if (v < nvec && b != 0) atomicMax(mu + v, b);
+    }
+  } else {
+    // element t of the wavefront: one vector v = v0 + ty + 4 t, lanes along k
+#pragma unroll
+    for (int t = 0; t < kPerThread; ++t) {
+      const U b = shfl_max(m[t]);
+      const int v = tc.v0 + ty + 4 * t;
+      if (lane == 0 && v < nvec && b != 0) atomicMax(mu + v, b);
+    }
+  }
+}
+
+template <typename T, int C, int ORIENT>
+__device__ void max0_body(const SplitOperand<T> &op, int idx) {
+  using U = typename bits_of<T>::type;
+  const TileCoord tc = tile_of<ORIENT>(idx, op.nvec, op.len);
+  U m[kPerThread];
+#pragma unroll
+  for (int t = 0; t < kPerThread; ++t) {
+    int v, p;
+    elem_of<ORIENT>(tc, t, v, p);
+    m[t] = (v < op.nvec && p < op.len) ? abs_bits(op.X[(int64_t)v * op.sv + (int64_t)p * op.sp]) : U(0);
+  }
+  reduce_max<ORIENT>(tc, m, static_cast<U *>(op.mu), op.nvec);
+}
+
+template <typename T, int C>
+__global__ __launch_bounds__(kThreads) void k_split_max0(SplitOperand<T> a, SplitOperand<T> b, int blocks_a) {
+  if ((int)blockIdx.x < blocks_a)
+    max0_body<T, C, 0>(a, blockIdx.x);
+  else
+    max0_body<T, C, 1>(b, blockIdx.x - blocks_a);
+}
+
+template <typename T, int C, int ORIENT>
+__device__ void pass_body(const SplitOperand<T> &op, int idx, int pass, int rho, bool first, bool last) {
+  using U = typename bits_of<T>::type;
+  const int nvec_cover = (int)(op.nbp * kBlk), len_cover = (int)(op.kbp * kKBlk);
+  const TileCoord tc = tile_of<ORIENT>(idx, nvec_cover, len_cover);
+  const U *mu_cur = static_cast<const U *>(op.mu) + (int64_t)pass * op.nvec;
+  U *mu_next = static_cast<U *>(op.mu) + (int64_t)(pass + 1) * op.nvec;
+  T *packed = static_cast<T *>(op.packed);
+  const int64_t plane = (int64_t)op.nvec * op.len;
+  // compact residual strides (same orientation as the input)
+  const int64_t rsv = ORIENT == 0 ? 1 : op.len, rsp = ORIENT == 0 ? op.nvec : 1;
+  U m[kPerThread];
+#pragma unroll
+  for (int t = 0; t < kPerThread; ++t) {
+    int v, p;
+    elem_of<ORIENT>(tc, t, v, p);
+    m[t] = 0;
+    if (v >= nvec_cover || p >= len_cover) continue;
+    const bool valid = v < op.nvec && p < op.len;
+    T sl = T(0);
+    int e = kZeroExp;
+    if (v < op.nvec) {
+      const U mub = mu_cur[v];
+      if (mub != 0) e = ceil_log2(from_bits(mub, T(0)));
+    }
+    if (valid) {
+      T R[C];
+      if (first) {
+#pragma unroll
+        for (int r = 0; r < C; ++r) R[r] = op.X[r * op.comp_stride + (int64_t)v * op.sv + (int64_t)p * op.sp];
+      } else {
+#pragma unroll
+        for (int r = 0; r < C; ++r) R[r] = op.resid[r * plane + (int64_t)v * rsv + (int64_t)p * rsp];
+      }
+      if (e != kZeroExp) {
+        const T tau = pow2(e + rho, T(0));
+        const T lead = R[0];
+        sl = (lead + tau) - tau;
+        R[0] = lead - sl;  // exact
+        renorm<T, C>(R);
+      }
+      if (!last) {
+#pragma unroll
+        for (int r = 0; r < C; ++r) op.resid[r * plane + (int64_t)v * rsv + (int64_t)p * rsp] = R[r];
+        m[t] = abs_bits(R[0]);
+      }
+    }
+    packed[packed_index<sizeof(T) == 8>(pass, v, p, op.nbp, op.kbp)] = sl;
+    // the thread holding k index 0 of vector v records the exponent of this pass
+    if (p == 0 && v < op.nvec) op.exps[(int64_t)pass * op.nvec + v] = e;
+  }
+  if (!last) reduce_max<ORIENT>(tc, m, mu_next, op.nvec);
+}
+
+template <typename T, int C>
+__global__ __launch_bounds__(kThreads) void k_split_pass(SplitOperand<T> a, SplitOperand<T> b, int blocks_a, int pass,
+                                                         int rho, int first, int last) {
+  if ((int)blockIdx.x < blocks_a)
+    pass_body<T, C, 0>(a, blockIdx.x, pass, rho, first != 0, last != 0);
+  else
+    pass_body<T, C, 1>(b, blockIdx.x - blocks_a, pass, rho, first != 0, last != 0);
+}
+
+int tiles(int64_t nvec, int64_t len) { return (int)(ceil_div(nvec, kTile) * ceil_div(len, kTile)); }
+
+__global__ void k_fill32(uint32_t *p, int64_t n, uint32_t value) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+}  // namespace
+
+hipError_t launch_fill32(void *p, int64_t nwords, uint32_t value, hipStream_t st) {
+  if (nwords <= 0) return hipSuccess;
+  const int64_t blocks = ceil_div(nwords, 256);
+  hipLaunchKernelGGL(k_fill32, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, st, (uint32_t *)p,
+                     nwords, value);
+  return hipGetLastError();
+}
+
+template <typename T, int C>
+hipError_t launch_split_plain(const SplitOperand<T> &a, const SplitOperand<T> &b, int D, int rho, hipStream_t st) {
+  using U = typename bits_of<T>::type;
+  // zero the per-pass maxima (a and b own separate arrays)
+  hipError_t err = launch_fill32(a.mu, (int64_t)D * a.nvec * sizeof(U) / 4, 0u, st);
+  if (err != hipSuccess) return err;
+  err = launch_fill32(b.mu, (int64_t)D * b.nvec * sizeof(U) / 4, 0u, st);
+  if (err != hipSuccess) return err;
+  const int ba0 = a.nvec > 0 && a.len > 0 ? tiles(a.nvec, a.len) : 0;
+  const int bb0 = b.nvec > 0 && b.len > 0 ? tiles(b.nvec, b.len) : 0;
+  if (ba0 + bb0 > 0) {
+    hipLaunchKernelGGL((k_split_max0<T, C>), dim3(ba0 + bb0), dim3(kThreads), 0, st, a, b, ba0);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
+  const int ba = a.nvec > 0 ? tiles(a.nbp * kBlk, a.kbp * kKBlk) : 0;
+  const int bb = b.nvec > 0 ? tiles(b.nbp * kBlk, b.kbp * kKBlk) : 0;
+  for (int pass = 0; pass < D; ++pass) {
+    hipLaunchKernelGGL((k_split_pass<T, C>), dim3(ba + bb), dim3(kThreads), 0, st, a, b, ba, pass, rho,
+                       pass == 0 ? 1 : 0, pass == D - 1 ? 1 : 0);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
+template hipError_t launch_split_plain<double, 2>(const SplitOperand<double> &, const SplitOperand<double> &, int, int,
+                                                  hipStream_t);
+template hipError_t launch_split_plain<double, 3>(const SplitOperand<double> &, const SplitOperand<double> &, int, int,
+                                                  hipStream_t);
+template hipError_t launch_split_plain<double, 4>(const SplitOperand<double> &, const SplitOperand<double> &, int, int,
+                                                  hipStream_t);
+template hipError_t launch_split_plain<float, 3>(const SplitOperand<float> &, const SplitOperand<float> &, int, int,
+                                                 hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Debug unpacking of packed slices.
+// ---------------------------------------------------------------------------
+namespace {
+__global__ void k_unpack(int elem_bytes, const void *packed, int64_t nbp, int64_t kbp, int D, int orient, int rows,
+                         int cols, void *out) {
+  const int64_t plane = (int64_t)rows * cols;
+  const int64_t total = plane * D;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(i / plane);
+    const int64_t rem = i % plane;
+    const int r = (int)(rem % rows), c = (int)(rem / rows);
+    // operand 0: rows = vectors (rows of A), cols = k; operand 1: rows = k, cols = vectors
+    const int64_t v = orient == 0 ? r : c, p = orient == 0 ? c : r;
+    if (elem_bytes == 8)
+      static_cast<double *>(out)[i] = static_cast<const double *>(packed)[packed_index<true>(a, v, p, nbp, kbp)];
+    else if (elem_bytes == 4)
+      static_cast<float *>(out)[i] = static_cast<const float *>(packed)[packed_index<false>(a, v, p, nbp, kbp)];
+    else
+      static_cast<int8_t *>(out)[i] = static_cast<const int8_t *>(packed)[packed_index8(a, v, p, nbp, kbp)];
+  }
+}
+}  // namespace
+
+hipError_t launch_unpack(int elem_bytes, const void *packed, int64_t nbp, int64_t kbp, int D, int orient, int rows,
+                         int cols, void *out, hipStream_t st) {
+  const int64_t total = (int64_t)rows * cols * D;
+  if (total <= 0) return hipSuccess;
+  const int64_t blocks = ceil_div(total, 256);
+  hipLaunchKernelGGL(k_unpack, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), 0, st, elem_bytes, packed,
+                     nbp, kbp, D, orient, rows, cols, out);
+  return hipGetLastError();
+}
+
+}  // namespace mp

@@ -1,0 +1,76 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every function the header declares, and its argument checks, slice policy and
+workspace sizing behave as documented."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpgemm.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2301_09960_amd as mp
+    if not os.path.exists(mp.LIB_PATH):
+        from paper_2301_09960_amd import build
+        build.build()
+    return mp.lib()
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpgemm_\w+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared()
+    assert len(names) >= 16
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_argument_codes(L):
+    P = ctypes.c_void_p
+    x = P(16)  # never dereferenced: the checks fail before any work
+    f = L.mpgemm_dd
+    assert f(-1, 4, 4, x, 4, x, 4, x, 4, None) == -1
+    assert f(4, -1, 4, x, 4, x, 4, x, 4, None) == -2
+    assert f(4, 4, -1, x, 4, x, 4, x, 4, None) == -3
+    assert f(4, 4, 4, None, 4, x, 4, x, 4, None) == -4
+    assert f(4, 4, 4, x, 3, x, 4, x, 4, None) == -5
+    assert f(4, 4, 4, x, 4, None, 4, x, 4, None) == -6
+    assert f(4, 4, 4, x, 4, x, 3, x, 4, None) == -7
+    assert f(4, 4, 4, x, 4, x, 4, None, 4, None) == -8
+    assert f(4, 4, 4, x, 4, x, 4, x, 3, None) == -9
+    assert L.mpgemm_ts(4, 4, 4, x, 4, x, 4, x, 2, None) == -9
+    assert f(1 << 21, 4, 4, x, 1 << 21, x, 4, x, 1 << 21, None) == 5  # beyond the size limit
+
+
+def test_options_and_policy(L):
+    import paper_2301_09960_amd as mp
+    # the automatic slice counts at k = 4096 (binary64 slices carry 20 bits there)
+    assert [mp.num_slices(f, "float", 4096) for f in ("dd", "td", "qd", "ts")] == [6, 8, 11, 13]
+    assert [mp.num_slices(f, "int8", 4096) for f in ("dd", "td", "qd")] == [17, 24, 31]
+    with pytest.raises(mp.MpgemmError):
+        mp.set_mode("ts", "int8")
+    mp.set_num_slices("dd", "float", 9)
+    assert mp.num_slices("dd", "float", 4096) == 9
+    mp.set_num_slices("dd", "float", 0)
+    assert mp.num_slices("dd", "float", 4096) == 6
+    with pytest.raises(mp.MpgemmError):
+        mp.set_num_slices("dd", "float", 17)
+    assert L.mpgemm_status_string(2) == b"workspace too small or allocation failed"
+
+
+def test_workspace_bytes(L):
+    import paper_2301_09960_amd as mp
+    # DD, D = 6, 4096^3: residuals 2 x 2 x 4096^2 x 8 B, packed slices 2 x 6 x 4096^2 x 8 B, plus small arrays
+    b = mp.workspace_bytes("dd", "float", 4096, 4096, 4096)
+    big = 2 * 2 * 4096 * 4096 * 8 + 2 * 6 * 4096 * 4096 * 8
+    assert big <= b <= big + 2 * 6 * 4096 * 8 * 2 + 4096
+    # ragged sizes are padded to 64 rows/columns and 32 in k
+    assert mp.workspace_bytes("ts", "float", 65, 1, 33, 1) >= 1 * 128 * 64 * 4 + 1 * 64 * 64 * 4

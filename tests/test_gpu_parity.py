@@ -1,0 +1,207 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+* slices and exponents of the split: bit-exact;
+* every slice product C_ab: bit-exact;
+* C: |C - AB| <= 2^-t (|A||B|) elementwise against the exact product, with
+  t = 100 / 150 / 200 / 66 (DD / TD / QD / TS), the log2 of the worst ratio
+  printed for every case.
+"""
+import numpy as np
+import pytest
+
+import workload as W
+
+pytestmark = pytest.mark.gpu
+
+FMTS = ["dd", "td", "qd", "ts"]
+T_BITS = {"dd": 100, "td": 150, "qd": 200, "ts": 66}
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2301_09960_amd as mp
+    mp.lib()  # must load: there is no fallback
+    assert mp.check_device() == 0, "device is not gfx950"
+    return mp
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("E", [0, 16])
+def test_split_bit_exact(mp, orc, fmt, E):
+    m, k, n = 130, 75, 70
+    A, B = W.gen_pair(fmt, m, n, k, E=E, seed=100 + E)
+    D = mp.num_slices(fmt, "float", k)
+    say(f"split {fmt} E={E} m={m} n={n} k={k} D={D}")
+    sa, ea = orc.split_plain(A, D, "rows")
+    sb, eb = orc.split_plain(B, D, "cols")
+    ga, gea = mp.debug_split(fmt, dev(A), 0, D)
+    gb, geb = mp.debug_split(fmt, dev(B), 1, D)
+    assert np.array_equal(host(ga), sa)
+    assert np.array_equal(host(gea), ea)
+    assert np.array_equal(host(gb), sb)
+    assert np.array_equal(host(geb), eb)
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_slice_products_bit_exact(mp, orc, fmt):
+    m, n, k = 70, 90, 300
+    A, B = W.gen_pair(fmt, m, n, k, E=16, seed=7)
+    D = mp.num_slices(fmt, "float", k)
+    S = 24 if fmt == "ts" else 53
+    rho = orc.rho(S, k)
+    sa, ea = orc.split_plain(A, D, "rows")
+    sb, eb = orc.split_plain(B, D, "cols")
+    dA, dB = dev(A), dev(B)
+    for a, b in sorted({(1, 1), (1, D), (D, 1), (2, 2), (1, 2), (D // 2, D // 2 + 1)}):
+        if a + b > D + 1 or a < 1 or b < 1:
+            continue
+        say(f"product {fmt} pair ({a},{b}) D={D}")
+        want = orc.slice_product(sa[a - 1], ea[a - 1], sb[b - 1], eb[b - 1], rho, S)
+        got = host(mp.debug_products(fmt, dA, dB, a, b, D))
+        assert np.array_equal(got, want), (a, b, np.max(np.abs(got - want)))
+
+
+def _check_bound(orc, fmt, A, B, C, rows=None):
+    diff, absab, _ = orc.exact_check(A, B, C, rows=rows)
+    ok, worst = orc.bound_report(diff, absab, T_BITS[fmt])
+    return ok, worst
+
+
+@pytest.mark.parametrize("fmt,m,n,k,E", [
+    ("dd", 128, 128, 128, 8),   # DD, m = n = k = 128, e ~ U{0..8}
+    ("dd", 200, 150, 333, 16),
+    ("td", 200, 150, 333, 16),
+    ("qd", 200, 150, 333, 16),
+    ("ts", 200, 150, 333, 16),
+    ("qd", 64, 64, 64, 0),
+    ("dd", 1, 1, 1, 8),
+    ("td", 1, 77, 5, 8),
+    ("qd", 77, 1, 130, 8),
+    ("ts", 65, 63, 1, 16),
+])
+def test_gemm_meets_bound(mp, orc, fmt, m, n, k, E):
+    A, B = W.gen_pair(fmt, m, n, k, E=E, seed=m + n + k)
+    say(f"gemm {fmt} m={m} n={n} k={k} E={E}")
+    C = host(mp.gemm(fmt, dev(A), dev(B)))
+    D = mp.last_num_slices()
+    ok, worst = _check_bound(orc, fmt, A, B, C)
+    say(f"  D={D} worst log2(|C-AB|/|A||B|) = {worst:.1f} (bound -{T_BITS[fmt]})")
+    assert ok
+
+
+def test_deterministic_and_identical_to_single_calls(mp):
+    import torch
+    A, B = W.gen_pair("td", 150, 130, 257, E=16, seed=3)
+    dA, dB = dev(A), dev(B)
+    C1 = host(mp.gemm("td", dA, dB))
+    C2 = host(mp.gemm("td", dA, dB))
+    assert np.array_equal(C1, C2)
+    # the same product computed on another stream
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        C3 = mp.gemm("td", dA, dB, stream=s)
+    s.synchronize()
+    assert np.array_equal(C3.cpu().numpy(), C1)
+
+
+def test_edge_cases(mp, orc):
+    import torch
+    # k = 0: C is zeroed
+    C = torch.full((2, 5, 4), 7.0, dtype=torch.float64, device="cuda")
+    A = torch.zeros((2, 0, 4), dtype=torch.float64, device="cuda")
+    B = torch.zeros((2, 5, 0), dtype=torch.float64, device="cuda")
+    mp.gemm("dd", A, B, C)
+    assert torch.all(C == 0)
+    # m = 0: no work, no error
+    A = torch.zeros((2, 3, 0), dtype=torch.float64, device="cuda")
+    B = torch.ones((2, 5, 3), dtype=torch.float64, device="cuda")
+    C = torch.zeros((2, 5, 0), dtype=torch.float64, device="cuda")
+    mp.gemm("dd", A, B, C)
+    # zero operand and zero rows
+    A, B = W.gen_pair("qd", 33, 20, 40, E=4, seed=1)
+    A[:, :, 5] = 0.0
+    B[:, 7, :] = 0.0
+    C = host(mp.gemm("qd", dev(A), dev(B)))
+    assert np.all(C[:, :, 5] == 0) and np.all(C[:, 7, :] == 0)
+    ok, worst = _check_bound(orc, "qd", A, B, C)
+    assert ok
+    Z = np.zeros_like(A)
+    C = host(mp.gemm("qd", dev(Z), dev(B)))
+    assert np.all(C == 0)
+
+
+def test_identity_gives_input(mp, orc):
+    m, k = 40, 48
+    A = W.gen_matrix("dd", m, k, E=4, seed=6, operand="A")
+    B = np.zeros((2, k, k))
+    B[0] = np.eye(k)
+    C = host(mp.gemm("dd", dev(A), dev(B), slices=12))
+    for i in range(0, m, 7):
+        for j in range(0, k, 5):
+            assert list(C[:, j, i]) == list(orc.exact_sum(list(A[:, j, i]), 2))
+
+
+def test_power_of_two_scaling_exact(mp):
+    A, B = W.gen_pair("dd", 96, 80, 100, E=8, seed=12)
+    C = host(mp.gemm("dd", dev(A), dev(B)))
+    A2 = A.copy()
+    A2[:, :, 3] *= 2.0 ** 37
+    B2 = B.copy()
+    B2[:, 2, :] *= 2.0 ** -21
+    C2 = host(mp.gemm("dd", dev(A2), dev(B2)))
+    expect = C.copy()
+    expect[:, :, 3] *= 2.0 ** 37
+    expect[:, 2, :] *= 2.0 ** -21
+    assert np.array_equal(C2, expect)
+
+
+def test_attached_workspace(mp):
+    import torch
+    A, B = W.gen_pair("dd", 100, 90, 120, E=8, seed=2)
+    dA, dB = dev(A), dev(B)
+    C1 = host(mp.gemm("dd", dA, dB))
+    need = mp.workspace_bytes("dd", "float", 100, 90, 120)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    mp.set_workspace(ws)
+    try:
+        C2 = host(mp.gemm("dd", dA, dB))
+        small = ws[: need // 2]
+        mp.set_workspace(small)
+        with pytest.raises(mp.MpgemmError) as ei:
+            mp.gemm("dd", dA, dB)
+        assert ei.value.status == 2
+    finally:
+        mp.set_workspace(None)
+    assert np.array_equal(C1, C2)
+
+
+@pytest.mark.parametrize("fmt,rows", [("dd", [0, 1111, 4095]), ("qd", [5, 2048]), ("ts", [17, 4000])])
+def test_full_size_sampled(mp, orc, fmt, rows):
+    """n = 4096 (the benchmark's size and launch path), E = 16: sampled rows of C
+    against the exact product."""
+    n = 4096
+    A, B = W.gen_pair(fmt, n, n, n, E=16, seed=4096)
+    say(f"full {fmt} n={n} rows={rows}")
+    C = host(mp.gemm(fmt, dev(A), dev(B)))
+    say(f"  D={mp.last_num_slices()}")
+    ok, worst = _check_bound(orc, fmt, A, B, np.ascontiguousarray(C), rows=rows)
+    say(f"  worst log2 ratio {worst:.1f} (bound -{T_BITS[fmt]})")
+    assert ok
