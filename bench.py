@@ -1,0 +1,221 @@
+"""Benchmark: Ozaki-scheme DD and QD GEMM at n = 4096 on one MI355X.
+
+One step = one DD and one QD product C = A B at m = n = k = 4096 (synthetic
+inputs, exponent spread e ~ U{0..16}, binary64 slices on the FP64 matrix
+cores), each a full pass of the path: split of A and B, every slice product
+of the triangle, error-free accumulation into C.  Inputs are resident in HBM
+before the timed region.  ``value`` is the whole job's effective 2 n^3 / s.
+
+Extra objects on the JSON line:
+  roofline     -- the dominant kernel (the fused slice-product GEMM of the QD
+                  call) against the FP64 matrix peak: algorithmic slice-GEMM
+                  flops per launch, D (D + 1) / 2 x 2 n^3, over its average
+                  launch time measured with HIP events on its stream.
+  cpu_baseline -- the CPU oracle's Ozaki product timed on a bounded sample.
+  stages       -- per format: split and fused-GEMM milliseconds per call.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DD/QD GEMM 2n³/s at n=4096, %MFMA peak, INT8 vs FP64 slices; served p50/p99"
+FP64_MFMA_PEAK_TFLOPS = 78.6
+FP32_MFMA_PEAK_TFLOPS = 157.3
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_plain_qd_n4096.json")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2301_09960_amd", "csrc", "gemm_fp.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--E", type=int, default=16)
+    ap.add_argument("--formats", default="dd,qd")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=0, help="rows of C in the CPU sample (0: auto)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of 1 GiB (for scaling HBM counters)")
+    return ap.parse_args()
+
+
+def source_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_for(kernel_key):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256_16") != source_hash(GEMM_SOURCE) or t.get("kernel") != kernel_key:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(n, E, rows_req):
+    """The oracle's Ozaki product (split, exact slice products, exact
+    accumulation; the CPU reference of this path) on rows 0..R-1 of the DD
+    n = 4096 product, scaled to effective 2 n^3 / s."""
+    import oracle
+    import workload as W
+    A, B = W.gen_pair("dd", n, n, n, E=E, seed=2023)
+    D = 6
+    rows = rows_req or 2 * oracle.threads()  # about 10 s of CPU work
+    t0 = time.perf_counter()
+    oracle.ozaki_gemm(A, B, D, rows=list(range(rows)))
+    dt = time.perf_counter() - t0
+    flops = 2.0 * rows * n * n
+    return {
+        "value": flops / dt / 1e9,
+        "unit": "GFLOP/s (effective 2mnk/s)",
+        "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": f"DD n={n} E~U{{0..{E}}} D={D}: full split of B, split of {rows} rows of A, exact slice products "
+                  f"and exact accumulation for {rows} x {n} entries of C ({dt:.1f} s)",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2301_09960_amd as mp
+    import workload as W
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    mp.lib()
+    torch.cuda.set_device(0)
+    n = args.n
+    fmts = args.formats.split(",")
+    log(f"generating inputs n={n} formats={fmts}")
+    inputs = {}
+    for f in fmts:
+        A, B = W.gen_pair(f, n, n, n, E=args.E, seed=4096)
+        inputs[f] = (torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda())
+        del A, B
+    outs = {f: torch.empty((W.FORMATS[f][0], n, n), dtype=inputs[f][0].dtype, device="cuda") for f in fmts}
+    slices = {f: mp.num_slices(f, "float", n) for f in fmts}
+    torch.cuda.synchronize()
+
+    for w in range(args.warmup):
+        for f in fmts:
+            mp.gemm(f, *inputs[f], outs[f])
+        torch.cuda.synchronize()
+        log(f"warmup step {w + 1}/{args.warmup} done")
+
+    mp.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        for f in fmts:
+            mp.gemm(f, *inputs[f], outs[f])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    mp.profile_enable(False)
+    split_ms, gemm_ms = mp.profile_read()
+    log(f"timed {args.steps} steps in {t1 - t0:.3f} s")
+
+    useful = 2.0 * n ** 3 * len(fmts) * args.steps
+    value = useful / (t1 - t0) / 1e9
+    stages = {}
+    for idx, f in enumerate(fmts):
+        sp = split_ms[idx::len(fmts)]
+        gm = gemm_ms[idx::len(fmts)]
+        D = slices[f]
+        slice_flops = D * (D + 1) / 2 * 2.0 * n ** 3
+        peak = FP32_MFMA_PEAK_TFLOPS if f == "ts" else FP64_MFMA_PEAK_TFLOPS
+        g_avg = float(np.mean(gm))
+        stages[f] = {
+            "D": D,
+            "split_ms": round(float(np.mean(sp)), 3),
+            "gemm_kernel_ms": round(g_avg, 3),
+            "effective_gflops": round(2.0 * n ** 3 / ((float(np.mean(sp)) + g_avg) * 1e-3) / 1e9, 1),
+            "slice_gemm_tflops": round(slice_flops / (g_avg * 1e-3) / 1e12, 2),
+            "mfma_frac": round(slice_flops / (g_avg * 1e-3) / 1e12 / peak, 4),
+        }
+    dom = max(fmts, key=lambda f: stages[f]["gemm_kernel_ms"])
+    D = slices[dom]
+    peak = FP32_MFMA_PEAK_TFLOPS if dom == "ts" else FP64_MFMA_PEAK_TFLOPS
+    achieved = D * (D + 1) / 2 * 2.0 * n ** 3 / (stages[dom]["gemm_kernel_ms"] * 1e-3) / 1e12
+    kernel_key = f"k_gemm_plain<{'float' if dom == 'ts' else 'double'},{W.FORMATS[dom][0]}> n={n}"
+    roofline = {
+        "bound": "mfma",
+        "achieved": round(achieved, 3),
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / peak, 4),
+        "traffic": traffic_for(kernel_key),
+        "kernel": kernel_key,
+    }
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration done (3 x 1 GiB device copies)")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample")
+        cpu = cpu_baseline(n, args.E, args.cpu_rows)
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GFLOP/s (effective 2n^3/s)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round((t1 - t0) * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"Ozaki GEMM {'+'.join(x.upper() for x in fmts)} m=n=k={n}, e~U{{0..{args.E}}}, "
+                        f"binary64 slices on FP64 matrix cores",
+            "n": n,
+            "formats": fmts,
+            "slices": slices,
+            "mode": "float",
+        },
+        "stages": stages,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

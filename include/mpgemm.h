@@ -148,13 +148,14 @@ int mpgemm_debug_products(int fmt, int mode, int m, int n, int k, const void *A,
  * Stage timing (the split / multiply-and-accumulate shares that Section 4.1
  * profiles).  mpgemm_profile_enable(1) makes this host thread's later calls
  * record HIP events on their stream before the split, between split and GEMM,
- * and after the GEMM kernel.  mpgemm_profile_read waits for the recorded events
- * and returns the summed milliseconds of the split stage and of the fused
- * slice-product GEMM kernel, and the number of calls, since the previous read;
- * then it clears the log.  Returns 0, or MPGEMM_ERR_HIP.
+ * and after the fused GEMM kernel.  mpgemm_profile_read waits for the recorded
+ * events of up to max_calls calls, oldest first, writes each call's split and
+ * GEMM milliseconds into split_ms[i] and gemm_ms[i] (host arrays of max_calls
+ * entries), drops those calls from the log and returns how many it wrote, or
+ * -MPGEMM_ERR_HIP on a HIP failure.
  */
 int mpgemm_profile_enable(int on);
-int mpgemm_profile_read(double *split_ms, double *gemm_ms, int *calls);
+int mpgemm_profile_read(double *split_ms, double *gemm_ms, int max_calls);
 
 /* Text for a return code. */
 const char *mpgemm_status_string(int status);

@@ -64,7 +64,7 @@ def lib():
                 L.mpgemm_debug_split.argtypes = [_I, _I, _I, _I, _I, _P, _I, _I, _P, _P, _P]
                 L.mpgemm_debug_products.argtypes = [_I, _I, _I, _I, _I, _P, _I, _P, _I, _I, _I, _I, _P, _I, _P]
                 L.mpgemm_profile_enable.argtypes = [_I]
-                L.mpgemm_profile_read.argtypes = [_P, _P, _P]
+                L.mpgemm_profile_read.argtypes = [_P, _P, _I]
                 L.mpgemm_status_string.restype = ctypes.c_char_p
                 L.mpgemm_status_string.argtypes = [_I]
                 _lib = L
@@ -149,13 +149,14 @@ def profile_enable(on: bool = True):
     lib().mpgemm_profile_enable(1 if on else 0)
 
 
-def profile_read():
-    """``(split_ms, gemm_ms, calls)`` summed since the previous read (waits for the events)."""
-    s = ctypes.c_double()
-    g = ctypes.c_double()
-    c = ctypes.c_int()
-    _check(lib().mpgemm_profile_read(ctypes.byref(s), ctypes.byref(g), ctypes.byref(c)), "profile_read")
-    return s.value, g.value, c.value
+def profile_read(max_calls: int = 4096):
+    """Per-call ``(split_ms, gemm_ms)`` lists of the recorded calls, oldest first (waits for the events)."""
+    s = (ctypes.c_double * max_calls)()
+    g = (ctypes.c_double * max_calls)()
+    n = lib().mpgemm_profile_read(s, g, max_calls)
+    if n < 0:
+        raise MpgemmError(-n, "profile_read")
+    return list(s[:n]), list(g[:n])
 
 
 def check_device() -> int:

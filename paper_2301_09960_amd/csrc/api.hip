@@ -515,23 +515,22 @@ int mpgemm_profile_enable(int on) {
   return 0;
 }
 
-int mpgemm_profile_read(double *split_ms, double *gemm_ms, int *calls) {
-  double s = 0, g = 0;
-  int status = 0;
-  for (auto &m : g_prof.marks) {
+int mpgemm_profile_read(double *split_ms, double *gemm_ms, int max_calls) {
+  int done = 0;
+  bool failed = false;
+  while (done < max_calls && done < (int)g_prof.marks.size()) {
+    auto &m = g_prof.marks[done];
     float a = 0, b = 0;
     if (hipEventSynchronize(m[2]) != hipSuccess || hipEventElapsedTime(&a, m[0], m[1]) != hipSuccess ||
         hipEventElapsedTime(&b, m[1], m[2]) != hipSuccess)
-      status = MPGEMM_ERR_HIP;
-    s += a;
-    g += b;
+      failed = true;
+    if (split_ms) split_ms[done] = a;
+    if (gemm_ms) gemm_ms[done] = b;
     for (auto x : m) g_prof.pool.push_back(x);
+    ++done;
   }
-  if (calls) *calls = (int)g_prof.marks.size();
-  g_prof.marks.clear();
-  if (split_ms) *split_ms = s;
-  if (gemm_ms) *gemm_ms = g;
-  return status;
+  g_prof.marks.erase(g_prof.marks.begin(), g_prof.marks.begin() + done);
+  return failed ? -MPGEMM_ERR_HIP : done;
 }
 
 }  // extern "C"
