@@ -149,7 +149,13 @@ def split_vector_py(vec, D: int, f32: bool = False):
 
 
 def int8_digits_py(comps_list, D: int):
-    """INT8 digits of one row/column by Python integers: returns ``(digits[len][D], E)``."""
+    """INT8 digits of one row/column with exact rationals: ``(digits[len][D], E)``.
+
+    Same written rule as the oracle: E = 1 + max ilogb of the leading
+    components; digit s is the leading component of the residual divided by
+    u_s = 2^(E - 6 - 7 (s - 1)) and rounded to nearest (ties to even); the
+    residual keeps the exact remainder and is renormalized after each digit.
+    """
     lead = [float(c[0]) for c in comps_list]
     nz = [x for x in lead if x != 0]
     if not nz:
@@ -157,10 +163,16 @@ def int8_digits_py(comps_list, D: int):
     E = max(math.frexp(x)[1] for x in nz)  # frexp exponent = ilogb + 1
     out = []
     for comps in comps_list:
-        v = value(comps)
-        sg = -1 if v < 0 else 1
-        N = math.floor(abs(v) * Fraction(2) ** (7 * D - E))
-        assert N < (1 << (7 * D)), "value not below 2^E"
-        digs = [sg * ((N >> (7 * (D - s))) & 127) for s in range(1, D + 1)]
+        R = [float(v) for v in comps]
+        digs = []
+        for s in range(1, D + 1):
+            u = Fraction(2) ** (E - 6 - 7 * (s - 1))
+            q = Fraction(R[0]) / u
+            fl = math.floor(q)
+            frac = q - fl
+            d = fl + 1 if frac > Fraction(1, 2) or (frac == Fraction(1, 2) and fl % 2 == 1) else fl
+            digs.append(d)
+            R[0] = float(Fraction(R[0]) - d * u)  # exact: the remainder is representable
+            R = renorm_py(R)
         out.append(digs)
     return out, E

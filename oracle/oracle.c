@@ -38,8 +38,10 @@
  *     is reported as INT_MIN.
  *   - ceil((S + log2 l)/2) is computed in integers as (S + ceil(log2 l) + 1)/2.
  *   - INT8 slices (not in the paper): E = 1 + max ilogb(x_0) over the row (or
- *     column); digit s (s = 1..D) of |x| is the 7-bit field of the exact |x|
- *     starting at bit E - 7 s, signed with the sign of x; the rest is dropped.
+ *     column); digit s (s = 1..D) is Algorithm 1's extraction (x + tau) - tau
+ *     on the fixed grid u_s = 2^(E - 6 - 7 (s - 1)) instead of a grid set by
+ *     the residual's maximum, i.e. the leading component rounded to nearest
+ *     on that grid; |digit| <= 64; the rest is dropped.
  *
  * Built with: gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp -shared -fPIC
  * (IEEE binary64/binary32, round to nearest, no contraction, SSE2 evaluation).
@@ -773,11 +775,14 @@ done:
 /* ------------------------------------------------------------------------- */
 
 /*
- * Split `nvec` vectors (strides as in oracle_split_plain) into D signed 7-bit
- * digit planes: E_v = 1 + max_p ilogb(x_p0) over nonzero leading components
- * (ZERO_EXP if none); digit s of element p is sign(x) * bits [E - 7 s, E - 7 s + 7)
- * of the exact |x|.  Returns ORC_ENOTEXACT if some |x| >= 2^E (input not a
- * normalized expansion).
+ * Split `nvec` vectors (strides as in oracle_split_plain) into D int8 digit
+ * planes.  E_v = 1 + max_p ilogb(x_p0) over nonzero leading components
+ * (ZERO_EXP if none), so |x_p0| < 2^E_v.  Digit s (s = 1..D) uses the unit
+ * u_s = 2^(E_v - 6 - 7 (s - 1)) and is Algorithm 1's extraction on that fixed
+ * grid: d_s = RN(lead / u_s) (nearest, ties to even), lead := lead - d_s u_s
+ * (exact), then the residual is renormalized as in the plain split.  Hence
+ * |d_s| <= 64 and x = sum_s d_s u_s + R_D with |R_D| about u_D / 2.
+ * Returns ORC_ENOTEXACT if a digit falls outside [-64, 64].
  */
 int oracle_split_int8(int nvec, int len, int c, const double *X, long s_vec, long s_elt, long s_comp, int D,
                       int8_t *digits, int *exps)
@@ -786,48 +791,34 @@ int oracle_split_int8(int nvec, int len, int c, const double *X, long s_vec, lon
         return ORC_EINVAL;
     const long plane = (long)nvec * len;
     int status = ORC_OK;
-#pragma omp parallel
-    {
-        sacc *s = malloc(sizeof(sacc));
-        sacc *mag = malloc(sizeof(sacc));
-        if (!s || !mag)
-            status = ORC_ENOMEM;
-#pragma omp for schedule(dynamic, 4)
-        for (int v = 0; v < nvec; ++v) {
-            if (!s || !mag)
-                continue;
-            int E = ZERO_EXP;
-            for (int p = 0; p < len; ++p) {
-                double x0 = X[v * s_vec + p * s_elt];
-                if (x0 != 0.0 && ilogb(x0) + 1 > E)
-                    E = ilogb(x0) + 1;
-            }
-            exps[v] = E;
-            for (int p = 0; p < len; ++p) {
-                int8_t *dst = digits + v * s_vec + p * s_elt;
-                if (E == ZERO_EXP) {
-                    for (int d = 0; d < D; ++d)
-                        dst[d * plane] = 0;
-                    continue;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int v = 0; v < nvec; ++v) {
+        int E = ZERO_EXP;
+        for (int p = 0; p < len; ++p) {
+            double x0 = X[v * s_vec + p * s_elt];
+            if (x0 != 0.0 && ilogb(x0) + 1 > E)
+                E = ilogb(x0) + 1;
+        }
+        exps[v] = E;
+        for (int p = 0; p < len; ++p) {
+            int8_t *dst = digits + v * s_vec + p * s_elt;
+            double R[8];
+            for (int r = 0; r < c; ++r)
+                R[r] = X[r * s_comp + v * s_vec + p * s_elt];
+            for (int d = 1; d <= D; ++d) {
+                int val = 0;
+                if (E != ZERO_EXP) {
+                    const int ue = E - 6 - 7 * (d - 1);
+                    const double q = nearbyint(ldexp(R[0], -ue));
+                    if (fabs(q) > 64.0)
+                        status = ORC_ENOTEXACT;
+                    val = (int)q;
+                    R[0] = R[0] - ldexp(q, ue); /* exact */
+                    renorm(R, c);
                 }
-                sa_clear(s);
-                for (int r = 0; r < c; ++r)
-                    sa_add(s, X[r * s_comp + v * s_vec + p * s_elt]);
-                sa_norm(s);
-                int sg = sa_sign(s);
-                sa_abs(s, mag);
-                if (sg != 0 && sa_lead(mag) >= E)
-                    status = ORC_ENOTEXACT;
-                for (int d = 1; d <= D; ++d) {
-                    int val = 0;
-                    for (int b = 6; b >= 0; --b)
-                        val = (val << 1) | sa_bit(mag, E - 7 * d + b);
-                    dst[(d - 1) * plane] = (int8_t)(sg < 0 ? -val : val);
-                }
+                dst[(d - 1) * plane] = (int8_t)val;
             }
         }
-        free(s);
-        free(mag);
     }
     return status;
 }
@@ -859,8 +850,11 @@ int oracle_int8_diag_sums(int m, int n, int k, int D, const int8_t *Ad, const in
 }
 
 /*
- * INT8-form result: C = sum_g S_g * 2^(E_i + F_j - 7 (g + 1)), summed exactly and
- * rounded once to a c-term binary64 expansion (planes of m x n).
+ * INT8-form result: digit s of A's row i has unit 2^(E_i - 6 - 7 (s - 1)) and
+ * digit t of B's column j 2^(F_j - 6 - 7 (t - 1)), so every product on the
+ * diagonal s + t = g + 1 has unit 2^(E_i + F_j + 2 - 7 (g + 1)):
+ * C = sum_g S_g 2^(E_i + F_j + 2 - 7 (g + 1)), summed exactly and rounded once
+ * to a c-term binary64 expansion (planes of m x n).
  */
 int oracle_int8_combine(int m, int n, int D, int c, const int64_t *Sg, const int *EA, const int *EB, double *C)
 {
@@ -881,7 +875,7 @@ int oracle_int8_combine(int m, int n, int D, int c, const int64_t *Sg, const int
                     for (int g = 1; g <= D; ++g) {
                         int64_t v = Sg[(g - 1) * pc + i + (long)j * m];
                         if (v != 0)
-                            sa_dep_u64(s, v < 0, (uint64_t)llabs(v), EA[i] + EB[j] - 7 * (g + 1));
+                            sa_dep_u64(s, v < 0, (uint64_t)llabs(v), EA[i] + EB[j] + 2 - 7 * (g + 1));
                     }
                 double out[8];
                 sa_to_expansion(s, out, c, 53, -1074);

@@ -206,7 +206,9 @@ def test_error_falls_with_D_and_saturates_on_eq1_data(orc):
 
 
 @pytest.mark.parametrize("fmt", ["dd", "qd"])
-def test_int8_digits_against_python_integers(orc, fmt):
+def test_int8_digits_against_python_rationals(orc, fmt):
+    """INT8 digits: equal to an independent rational implementation of the same
+    rule; |d| <= 64; a = sum_s d_s u_s + r exactly with |r| <= u_D/2 (1 + 2^-40)."""
     m, k, D = 4, 9, 17
     A = W.gen_matrix(fmt, m, k, E=16, seed=31, operand="A")
     dg, E = orc.split_int8(A, D, "rows")
@@ -215,13 +217,11 @@ def test_int8_digits_against_python_integers(orc, fmt):
         assert E[i] == Ew
         for p in range(k):
             assert list(dg[:, p, i]) == want[p]
-            assert np.all(np.abs(dg[:, p, i].astype(int)) <= 127)
-            # reconstruction: a = sum_s d_s 2^(E - 7 s) + r with 0 <= r sign(a) < 2^(E - 7 D)
+            assert np.all(np.abs(dg[:, p, i].astype(int)) <= 64)
             x = X.value(A[:, p, i])
-            approx = sum(Fraction(int(dg[s, p, i])) * Fraction(2) ** (int(E[i]) - 7 * (s + 1)) for s in range(D))
-            r = x - approx
-            sg = 1 if x >= 0 else -1
-            assert 0 <= r * sg < Fraction(2) ** (int(E[i]) - 7 * D)
+            approx = sum(Fraction(int(dg[s, p, i])) * Fraction(2) ** (int(E[i]) - 6 - 7 * s) for s in range(D))
+            uD = Fraction(2) ** (int(E[i]) - 6 - 7 * (D - 1))
+            assert abs(x - approx) <= uD / 2 * (1 + Fraction(2) ** -40)
 
 
 def test_int8_diag_sums_and_combination(orc):
@@ -241,7 +241,7 @@ def test_int8_diag_sums_and_combination(orc):
     C = orc.int8_combine(S, EA, EB, 2)
     for i in range(m):
         for j in range(n):
-            v = sum(Fraction(int(S[g - 1, j, i])) * Fraction(2) ** (int(EA[i]) + int(EB[j]) - 7 * (g + 1))
+            v = sum(Fraction(int(S[g - 1, j, i])) * Fraction(2) ** (int(EA[i]) + int(EB[j]) + 2 - 7 * (g + 1))
                     for g in range(1, D + 1))
             assert C[0, j, i] == float(v) and C[1, j, i] == float(v - Fraction(C[0, j, i]))
 
