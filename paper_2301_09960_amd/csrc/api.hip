@@ -71,10 +71,10 @@ int rho_of(int S, int64_t k) { return k < 1 ? 0 : (S + ceil_log2_int(k) + 1) / 2
 // g (guard bits) covers the gap between an element's |A||B| and the row and
 // column maxima that set the slice grids for exponent spreads up to 16 bits,
 // plus a margin; that gap shrinks as k grows.  INT8: 7 bits per digit slice,
-// D 7 >= t + 14.
+// D 7 >= t + g8 with g8 = 14 guard bits below k = 2048 and 10 from there on.
 int auto_slices(int fmt, int mode, int64_t k) {
   const int t = kBoundBits[fmt];
-  if (mode == MPGEMM_MODE_INT8) return (t + 14 + 6) / 7;
+  if (mode == MPGEMM_MODE_INT8) return (t + (k < 2048 ? 14 : 10) + 6) / 7;
   const int S = fmt == MPGEMM_TS ? 24 : 53;
   const int b = S - rho_of(S, k < 1 ? 1 : k);
   int g = 22 - (11 * ceil_log2_int(k < 1 ? 1 : k)) / 10;
@@ -97,7 +97,7 @@ struct Plan {
   int fmt, mode, C, D, rho;
   size_t elem;  // bytes per slice element
   int64_t mbp, nbp, kbp;
-  size_t off_resid_a, off_resid_b, off_pack_a, off_pack_b, off_mu_a, off_mu_b, off_exp_a, off_exp_b, total;
+  size_t off_resid_a, off_resid_b, off_pack_a, off_pack_b, off_mu_a, off_mu_b, off_exp_a, off_exp_b, off_sums, total;
 };
 
 Plan make_plan(int fmt, int mode, int64_t m, int64_t n, int64_t k, int D) {
@@ -132,14 +132,18 @@ Plan make_plan(int fmt, int mode, int64_t m, int64_t n, int64_t k, int D) {
   } else {
     p.elem = 1;
     p.rho = 0;
+    p.mbp = nblocks8_padded(m);
+    p.nbp = nblocks8_padded(n);
     p.kbp = kblocks8_padded(k);
     p.off_resid_a = p.off_resid_b = take(0);
     p.off_pack_a = take((size_t)D * p.mbp * p.kbp * 1024);
     p.off_pack_b = take((size_t)D * p.nbp * p.kbp * 1024);
-    p.off_mu_a = take(0);
-    p.off_mu_b = take(0);
+    p.off_mu_a = take((size_t)m * 8);
+    p.off_mu_b = take((size_t)n * 8);
     p.off_exp_a = take((size_t)m * 4);
     p.off_exp_b = take((size_t)n * 4);
+    const int64_t nchunks = ceil_div(p.kbp, int8_kblocks_per_chunk(D));
+    p.off_sums = take((size_t)D * nchunks * m * n * 4);
   }
   p.total = o;
   return p;
@@ -272,8 +276,9 @@ hipError_t gemm_launch(const Plan &p, char *base, int m, int n, int k, T *Cout, 
     if constexpr (sizeof(T) == 8)
       return launch_gemm_int8<C>(base + p.off_pack_a, base + p.off_pack_b,
                                  reinterpret_cast<const int *>(base + p.off_exp_a),
-                                 reinterpret_cast<const int *>(base + p.off_exp_b), p.mbp, p.nbp, p.kbp, k, m, n, p.D,
-                                 Cout, ldc, (int64_t)ldc * n, dbg_pair, static_cast<int64_t *>(dbg_out), lddbg, st);
+                                 reinterpret_cast<const int *>(base + p.off_exp_b),
+                                 reinterpret_cast<int32_t *>(base + p.off_sums), p.mbp, p.nbp, p.kbp, m, n, p.D, Cout,
+                                 ldc, (int64_t)ldc * n, dbg_pair, static_cast<int64_t *>(dbg_out), lddbg, st);
     return hipErrorInvalidValue;
   }
   return launch_gemm_plain<T, C>(base + p.off_pack_a, base + p.off_pack_b, p.mbp, p.nbp, p.kbp, m, n, p.D, Cout, ldc,

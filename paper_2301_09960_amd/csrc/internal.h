@@ -43,11 +43,15 @@ hipError_t launch_gemm_plain(const void *Apk, const void *Bpk, int64_t mbp, int6
                              int D, T *Cout, int ldc, int64_t c_stride, int single_pair, double *Cdbg, int lddbg,
                              hipStream_t st);
 
-// INT8 form GEMM: diagonal sums and their exact combination into C.
+// INT8 form GEMM: diagonal sums S_g into Sws (D x nchunks planes of m x n
+// int32), then their exact combination into C.  debug_g > 0 writes S_g for
+// that g as int64 into Sdbg instead of forming C.
 template <int C>
-hipError_t launch_gemm_int8(const void *Apk, const void *Bpk, const int *EA, const int *EB, int64_t mbp, int64_t nbp,
-                            int64_t kbp8, int k, int m, int n, int D, double *Cout, int ldc, int64_t c_stride,
+hipError_t launch_gemm_int8(const void *Apk, const void *Bpk, const int *EA, const int *EB, int32_t *Sws, int64_t mbp,
+                            int64_t nbp, int64_t kbp, int m, int n, int D, double *Cout, int ldc, int64_t c_stride,
                             int debug_g, int64_t *Sdbg, int lddbg, hipStream_t st);
+// k blocks (32 wide) per chunk of the INT8 GEMM for D digit slices.
+int int8_kblocks_per_chunk(int D);
 
 // Debug: unpack D packed slices into planes of rows x cols (column-major, ld rows).
 hipError_t launch_unpack(int elem_bytes, const void *packed, int64_t nbp, int64_t kbp, int D, int orient, int rows,

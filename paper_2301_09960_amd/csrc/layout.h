@@ -14,9 +14,10 @@
 // [nb][kb][256] with nb row/column blocks and kb k-blocks; slices follow one
 // another.  Padding (rows beyond m, k beyond k) holds zeros.
 //
-// INT8 digit slices use 16 x 64 blocks for the 16x16x64 integer instruction:
-// lane l holds index l % 16 and the 16 consecutive k values 16 (l / 16) + t,
-// t = 0..15, stored as 16 bytes at 16 l + t.
+// INT8 digit slices use 32 x 32 blocks for the 32x32x32 integer instruction:
+// lane l holds row/column index l % 32 and the 16 consecutive k values
+// 16 (l / 32) + t, t = 0..15, stored as 16 bytes at 16 l + t.  Rows/columns
+// are padded to the INT8 GEMM tile (128), k to its k step (64).
 #pragma once
 
 #include <stdint.h>
@@ -25,7 +26,10 @@ namespace mp {
 
 constexpr int kBlk = 16;      // rows/cols per block
 constexpr int kKBlk = 16;     // k per block (floating-point slices)
-constexpr int kKBlk8 = 64;    // k per block (INT8 slices)
+constexpr int kBlk8 = 32;     // rows/cols per block (INT8 slices)
+constexpr int kKBlk8 = 32;    // k per block (INT8 slices)
+constexpr int kTileBlocks8 = 4;   // INT8 GEMM tile = 4 x 4 blocks (128 x 128)
+constexpr int kKStepBlocks8 = 2;  // INT8 GEMM k step = 2 k-blocks (64)
 constexpr int kTileBlocks = 4;  // GEMM tile = 4 x 4 blocks (64 x 64)
 constexpr int kKStepBlocks = 2; // GEMM k step = 2 k-blocks (32)
 
@@ -38,7 +42,12 @@ __host__ __device__ inline int64_t nblocks_padded(int64_t rows) {
 __host__ __device__ inline int64_t kblocks_padded(int64_t k) {
   return ceil_div(k, kKBlk * kKStepBlocks) * kKStepBlocks;
 }
-__host__ __device__ inline int64_t kblocks8_padded(int64_t k) { return ceil_div(k, kKBlk8); }
+__host__ __device__ inline int64_t nblocks8_padded(int64_t rows) {
+  return ceil_div(rows, kBlk8 * kTileBlocks8) * kTileBlocks8;
+}
+__host__ __device__ inline int64_t kblocks8_padded(int64_t k) {
+  return ceil_div(k, kKBlk8 * kKStepBlocks8) * kKStepBlocks8;
+}
 
 // Offset (in elements) of element (v, p) of slice a: v = row of A / column of B,
 // p = k index.  nbp / kbp: padded block counts.
@@ -53,9 +62,9 @@ __host__ __device__ inline int64_t packed_index(int64_t a, int64_t v, int64_t p,
 }
 
 __host__ __device__ inline int64_t packed_index8(int64_t a, int64_t v, int64_t p, int64_t nbp, int64_t kbp) {
-  const int64_t vb = v / kBlk, vl = v % kBlk;
+  const int64_t vb = v / kBlk8, vl = v % kBlk8;
   const int64_t kb = p / kKBlk8, kl = p % kKBlk8;
-  const int64_t lane = (kl / 16) * 16 + vl;
+  const int64_t lane = (kl / 16) * 32 + vl;
   return ((a * nbp + vb) * kbp + kb) * 1024 + 16 * lane + (kl % 16);
 }
 

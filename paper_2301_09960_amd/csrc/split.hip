@@ -238,6 +238,88 @@ template hipError_t launch_split_plain<float, 3>(const SplitOperand<float> &, co
                                                  hipStream_t);
 
 // ---------------------------------------------------------------------------
+// INT8 digit split (the precision form).  Per vector: E = 1 + ilogb(max |x_0|)
+// (the frexp exponent of the maximum, so |x_0| < 2^E), then for s = 1..D the
+// extraction step of Algorithm 1 on the fixed grid u_s = 2^(E - 6 - 7 (s - 1)):
+// d_s = RN(lead / u_s), lead := lead - d_s u_s (exact), renormalize.  All D
+// digits of an element come from one read of its components.  |d_s| <= 64.
+// ---------------------------------------------------------------------------
+namespace {
+
+template <int C, int ORIENT>
+__device__ void int8_body(const SplitOperand<double> &op, int idx, int D) {
+  const int nvec_cover = (int)(op.nbp * kBlk8), len_cover = (int)(op.kbp * kKBlk8);
+  const TileCoord tc = tile_of<ORIENT>(idx, nvec_cover, len_cover);
+  const unsigned long long *mu = static_cast<const unsigned long long *>(op.mu);
+  int8_t *packed = static_cast<int8_t *>(op.packed);
+#pragma unroll 1
+  for (int t = 0; t < kPerThread; ++t) {
+    int v, p;
+    elem_of<ORIENT>(tc, t, v, p);
+    if (v >= nvec_cover || p >= len_cover) continue;
+    int E = kZeroExp;
+    if (v < op.nvec && mu[v] != 0) {
+      int ex;
+      (void)frexp(from_bits(mu[v], 0.0), &ex);
+      E = ex;
+    }
+    double R[C];
+    const bool live = v < op.nvec && p < op.len && E != kZeroExp;
+#pragma unroll
+    for (int r = 0; r < C; ++r)
+      R[r] = live ? op.X[r * op.comp_stride + (int64_t)v * op.sv + (int64_t)p * op.sp] : 0.0;
+#pragma unroll 1
+    for (int s = 1; s <= D; ++s) {
+      int8_t d = 0;
+      if (live) {
+        const int ue = E - 6 - 7 * (s - 1);
+        const double q = rint(ldexp(R[0], -ue));
+        d = (int8_t)(int)q;
+        R[0] = R[0] - ldexp(q, ue);  // exact
+        renorm<double, C>(R);
+      }
+      packed[packed_index8(s - 1, v, p, op.nbp, op.kbp)] = d;
+    }
+    if (p == 0 && v < op.nvec) op.exps[v] = E;
+  }
+}
+
+template <int C>
+__global__ __launch_bounds__(kThreads) void k_split_int8(SplitOperand<double> a, SplitOperand<double> b, int blocks_a,
+                                                         int D) {
+  if ((int)blockIdx.x < blocks_a)
+    int8_body<C, 0>(a, blockIdx.x, D);
+  else
+    int8_body<C, 1>(b, blockIdx.x - blocks_a, D);
+}
+
+}  // namespace
+
+template <int C>
+hipError_t launch_split_int8(const SplitOperand<double> &a, const SplitOperand<double> &b, int D, hipStream_t st) {
+  hipError_t err = launch_fill32(a.mu, (int64_t)a.nvec * 2, 0u, st);
+  if (err != hipSuccess) return err;
+  if ((err = launch_fill32(b.mu, (int64_t)b.nvec * 2, 0u, st)) != hipSuccess) return err;
+  const int ba0 = a.nvec > 0 && a.len > 0 ? tiles(a.nvec, a.len) : 0;
+  const int bb0 = b.nvec > 0 && b.len > 0 ? tiles(b.nvec, b.len) : 0;
+  if (ba0 + bb0 > 0) {
+    hipLaunchKernelGGL((k_split_max0<double, C>), dim3(ba0 + bb0), dim3(kThreads), 0, st, a, b, ba0);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
+  const int ba = a.nvec > 0 ? tiles(a.nbp * kBlk8, a.kbp * kKBlk8) : 0;
+  const int bb = b.nvec > 0 ? tiles(b.nbp * kBlk8, b.kbp * kKBlk8) : 0;
+  if (ba + bb > 0) {
+    hipLaunchKernelGGL((k_split_int8<C>), dim3(ba + bb), dim3(kThreads), 0, st, a, b, ba, D);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
+template hipError_t launch_split_int8<2>(const SplitOperand<double> &, const SplitOperand<double> &, int, hipStream_t);
+template hipError_t launch_split_int8<3>(const SplitOperand<double> &, const SplitOperand<double> &, int, hipStream_t);
+template hipError_t launch_split_int8<4>(const SplitOperand<double> &, const SplitOperand<double> &, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
 // Debug unpacking of packed slices.
 // ---------------------------------------------------------------------------
 namespace {

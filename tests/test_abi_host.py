@@ -54,7 +54,8 @@ def test_options_and_policy(L):
     import paper_2301_09960_amd as mp
     # the automatic slice counts at k = 4096 (binary64 slices carry 20 bits there)
     assert [mp.num_slices(f, "float", 4096) for f in ("dd", "td", "qd", "ts")] == [6, 8, 11, 13]
-    assert [mp.num_slices(f, "int8", 4096) for f in ("dd", "td", "qd")] == [17, 24, 31]
+    assert [mp.num_slices(f, "int8", 4096) for f in ("dd", "td", "qd")] == [16, 23, 30]
+    assert [mp.num_slices(f, "int8", 128) for f in ("dd", "td", "qd")] == [17, 24, 31]
     with pytest.raises(mp.MpgemmError):
         mp.set_mode("ts", "int8")
     mp.set_num_slices("dd", "float", 9)

@@ -1,0 +1,122 @@
+"""GPU parity of the INT8-slice form against the CPU oracle: digit slices and
+exponents bit-exact, diagonal sums S_g bit-exact (int64), C within
+2^-t (|A||B|) of the exact product (t = 100 / 150 / 200)."""
+import numpy as np
+import pytest
+
+import workload as W
+
+pytestmark = pytest.mark.gpu
+
+T_BITS = {"dd": 100, "td": 150, "qd": 200}
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2301_09960_amd as mp
+    mp.lib()
+    assert mp.check_device() == 0
+    return mp
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("fmt", ["dd", "td", "qd"])
+@pytest.mark.parametrize("E", [0, 16])
+def test_int8_split_bit_exact(mp, orc, fmt, E):
+    m, k, n = 140, 100, 70
+    A, B = W.gen_pair(fmt, m, n, k, E=E, seed=300 + E)
+    D = mp.num_slices(fmt, "int8", k)
+    say(f"int8 split {fmt} E={E} D={D}")
+    da, ea = orc.split_int8(A, D, "rows")
+    db, eb = orc.split_int8(B, D, "cols")
+    ga, gea = mp.debug_split(fmt, dev(A), 0, D, mode="int8")
+    gb, geb = mp.debug_split(fmt, dev(B), 1, D, mode="int8")
+    assert np.array_equal(host(ga), da)
+    assert np.array_equal(host(gea), ea)
+    assert np.array_equal(host(gb), db)
+    assert np.array_equal(host(geb), eb)
+
+
+@pytest.mark.parametrize("fmt", ["dd", "qd"])
+def test_int8_diagonal_sums_bit_exact(mp, orc, fmt):
+    m, n, k = 150, 130, 200
+    A, B = W.gen_pair(fmt, m, n, k, E=16, seed=9)
+    D = mp.num_slices(fmt, "int8", k)
+    da, _ = orc.split_int8(A, D, "rows")
+    db, _ = orc.split_int8(B, D, "cols")
+    S = orc.int8_diag_sums(da, db)
+    dA, dB = dev(A), dev(B)
+    for g in sorted({1, 2, D // 2, D}):
+        say(f"int8 diagonal {fmt} g={g} D={D}")
+        got = host(mp.debug_products(fmt, dA, dB, g, 0, D, mode="int8"))
+        assert np.array_equal(got, S[g - 1]), g
+
+
+@pytest.mark.parametrize("fmt,m,n,k,E", [
+    ("dd", 128, 128, 128, 8),
+    ("dd", 200, 150, 333, 16),
+    ("td", 200, 150, 333, 16),
+    ("qd", 200, 150, 333, 16),
+    ("qd", 1, 1, 1, 0),
+    ("td", 130, 3, 65, 8),
+    ("dd", 5, 129, 700, 16),
+])
+def test_int8_gemm_meets_bound(mp, orc, fmt, m, n, k, E):
+    A, B = W.gen_pair(fmt, m, n, k, E=E, seed=m * n + k)
+    say(f"int8 gemm {fmt} m={m} n={n} k={k} E={E}")
+    C = host(mp.gemm(fmt, dev(A), dev(B), mode="int8"))
+    D = mp.last_num_slices()
+    diff, absab, _ = orc.exact_check(A, B, C)
+    ok, worst = orc.bound_report(diff, absab, T_BITS[fmt])
+    say(f"  D={D} worst log2 ratio {worst:.1f} (bound -{T_BITS[fmt]})")
+    assert ok
+    # the oracle's INT8-form product with the same D: both round the same exact sum
+    Co = orc.int8_gemm(A, B, D)
+    assert np.array_equal(C[0], Co[0]) or np.max(np.abs(C[0] - Co[0]) / np.maximum(np.abs(Co[0]), 1e-300)) < 2.0 ** -100
+
+
+def test_int8_zero_rows_and_chunking(mp, orc):
+    """Zero rows/columns give zero output; a long k (several 32-bit chunks for
+    D = 40) still gives exact diagonal sums."""
+    import torch
+    m, n, k = 70, 66, 14000
+    A, B = W.gen_pair("dd", m, n, k, E=4, seed=5)
+    A[:, :, 3] = 0.0
+    D = 40
+    C = host(mp.gemm("dd", dev(A), dev(B), mode="int8", slices=D))
+    assert np.all(C[:, :, 3] == 0)
+    rows = [0, 3, 69]
+    diff, absab, _ = orc.exact_check(A, B, C, rows=rows)
+    ok, worst = orc.bound_report(diff, absab, 100)
+    say(f"  chunked k={k} D={D} worst {worst:.1f}")
+    assert ok
+
+
+@pytest.mark.parametrize("fmt,rows", [("dd", [0, 4095]), ("qd", [1234])])
+def test_int8_full_size_sampled(mp, orc, fmt, rows):
+    n = 4096
+    A, B = W.gen_pair(fmt, n, n, n, E=16, seed=4096)
+    say(f"int8 full {fmt} n={n}")
+    C = host(mp.gemm(fmt, dev(A), dev(B), mode="int8"))
+    say(f"  D={mp.last_num_slices()}")
+    diff, absab, _ = orc.exact_check(A, B, np.ascontiguousarray(C), rows=rows)
+    ok, worst = orc.bound_report(diff, absab, T_BITS[fmt])
+    say(f"  worst log2 ratio {worst:.1f}")
+    assert ok
