@@ -13,6 +13,9 @@ Extra objects on the JSON line:
                   launch time measured with HIP events on its stream.
   cpu_baseline -- the CPU oracle's Ozaki product timed on a bounded sample.
   stages       -- per format: split and fused-GEMM milliseconds per call.
+  int8         -- the same products with INT8 digit slices on the INT8 matrix
+                  cores (precision form), timed the same way; speedup over
+                  the binary64-slice form at the same error bound.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -33,6 +36,7 @@ sys.path.insert(0, ROOT)
 METRIC = "DD/QD GEMM 2n³/s at n=4096, %MFMA peak, INT8 vs FP64 slices; served p50/p99"
 FP64_MFMA_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
+INT8_MFMA_PEAK_TOPS = 5000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_plain_qd_n4096.json")
 GEMM_SOURCE = os.path.join(ROOT, "paper_2301_09960_amd", "csrc", "gemm_fp.hip")
 
@@ -50,6 +54,7 @@ def parse():
     ap.add_argument("--E", type=int, default=16)
     ap.add_argument("--formats", default="dd,qd")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-int8", action="store_true", help="skip the INT8-slice form")
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows of C in the CPU sample (0: auto)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 1 GiB (for scaling HBM counters)")
@@ -124,24 +129,26 @@ def main():
     slices = {f: mp.num_slices(f, "float", n) for f in fmts}
     torch.cuda.synchronize()
 
-    for w in range(args.warmup):
-        for f in fmts:
-            mp.gemm(f, *inputs[f], outs[f])
+    def timed(mode):
+        for w in range(args.warmup):
+            for f in fmts:
+                mp.gemm(f, *inputs[f], outs[f], mode=mode)
+            torch.cuda.synchronize()
+            log(f"{mode}: warmup step {w + 1}/{args.warmup} done")
+        mp.profile_enable(True)
         torch.cuda.synchronize()
-        log(f"warmup step {w + 1}/{args.warmup} done")
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            for f in fmts:
+                mp.gemm(f, *inputs[f], outs[f], mode=mode)
+        torch.cuda.synchronize()
+        t_end = time.perf_counter()
+        mp.profile_enable(False)
+        sp, gm = mp.profile_read()
+        log(f"{mode}: timed {args.steps} steps in {t_end - t_start:.3f} s")
+        return t_start, t_end, sp, gm
 
-    mp.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        for f in fmts:
-            mp.gemm(f, *inputs[f], outs[f])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    mp.profile_enable(False)
-    split_ms, gemm_ms = mp.profile_read()
-    log(f"timed {args.steps} steps in {t1 - t0:.3f} s")
-
+    t0, t1, split_ms, gemm_ms = timed("float")
     useful = 2.0 * n ** 3 * len(fmts) * args.steps
     value = useful / (t1 - t0) / 1e9
     stages = {}
@@ -174,6 +181,26 @@ def main():
         "traffic": traffic_for(kernel_key),
         "kernel": kernel_key,
     }
+
+    int8 = None
+    if not args.no_int8 and all(f != "ts" for f in fmts):
+        i0, i1, isp, igm = timed("int8")
+        int8 = {"wall_speedup": round((t1 - t0) / (i1 - i0), 3)}
+        for idx, f in enumerate(fmts):
+            D8 = mp.num_slices(f, "int8", n)
+            call_ms = float(np.mean(isp[idx::len(fmts)])) + float(np.mean(igm[idx::len(fmts)]))
+            gemm8 = float(np.mean(igm[idx::len(fmts)]))
+            ops = D8 * (D8 + 1) / 2 * 2.0 * n ** 3
+            int8[f] = {
+                "D": D8,
+                "split_ms": round(float(np.mean(isp[idx::len(fmts)])), 3),
+                "gemm_and_combine_ms": round(gemm8, 3),
+                "effective_gflops": round(2.0 * n ** 3 / (call_ms * 1e-3) / 1e9, 1),
+                "int8_tops": round(ops / (gemm8 * 1e-3) / 1e12, 1),
+                "int8_mfma_frac": round(ops / (gemm8 * 1e-3) / 1e12 / INT8_MFMA_PEAK_TOPS, 4),
+                "speedup_vs_float_slices": round(
+                    (stages[f]["split_ms"] + stages[f]["gemm_kernel_ms"]) / call_ms, 3),
+            }
 
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -211,6 +238,7 @@ def main():
             "mode": "float",
         },
         "stages": stages,
+        "int8": int8,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
