@@ -93,6 +93,37 @@ int mpgemm_ts(int m, int n, int k, const float *A, int lda, const float *B, int 
               hipStream_t stream);
 
 /*
+ * Batched products: C_i := A_i B_i for i < count, independent products of
+ * uneven sizes, each computed exactly as the single call computes it (the same
+ * per-tile kernel code, so the results are identical bit for bit).  All
+ * arguments after `count` are host arrays of count entries holding what the
+ * single call takes (device matrix pointers, sizes, leading dimensions).
+ * The split of all operands and one persistent slice-product kernel that takes
+ * (product, tile) work items longest first run as one launch sequence.  That
+ * sequence is captured once per batch shape (format, count, every m, n, k and
+ * slice count, device and stream) into a HIP graph and cached per host thread
+ * (up to 6 shapes; releasing the least recently used one synchronizes the
+ * device); later calls with the same shape replay it after one copy of this
+ * call's pointers.  The cached workspace of a shape stays allocated until it
+ * is released or mpgemm_batched_cache_clear is called.  Batched calls of one
+ * shape on one stream must not be issued from two host threads at once.
+ * FLOAT form only (INT8 mode returns MPGEMM_ERR_UNSUPPORTED).
+ * Return codes: -1 for count < 0; -i (i = 2..10) for a NULL array or an
+ * invalid entry of argument i (first failing product); positive codes as above.
+ */
+int mpgemm_dd_batched(int count, const int *m, const int *n, const int *k, const double *const *A, const int *lda,
+                      const double *const *B, const int *ldb, double *const *C, const int *ldc, hipStream_t stream);
+int mpgemm_td_batched(int count, const int *m, const int *n, const int *k, const double *const *A, const int *lda,
+                      const double *const *B, const int *ldb, double *const *C, const int *ldc, hipStream_t stream);
+int mpgemm_qd_batched(int count, const int *m, const int *n, const int *k, const double *const *A, const int *lda,
+                      const double *const *B, const int *ldb, double *const *C, const int *ldc, hipStream_t stream);
+int mpgemm_ts_batched(int count, const int *m, const int *n, const int *k, const float *const *A, const int *lda,
+                      const float *const *B, const int *ldb, float *const *C, const int *ldc, hipStream_t stream);
+
+/* Releases this host thread's cached batch plans (synchronizes the device). */
+int mpgemm_batched_cache_clear(void);
+
+/*
  * Options, per host thread and per format (fmt = MPGEMM_DD .. MPGEMM_TS).
  * mpgemm_set_mode selects the slice form (returns MPGEMM_ERR_UNSUPPORTED for
  * INT8 with TS).  mpgemm_set_num_slices sets D for (fmt, mode); 0 restores the

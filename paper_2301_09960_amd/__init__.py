@@ -54,6 +54,10 @@ def lib():
                     f = getattr(L, name)
                     f.restype = _I
                     f.argtypes = [_I, _I, _I, _P, _I, _P, _I, _P, _I, _P]
+                for name in ("mpgemm_dd_batched", "mpgemm_td_batched", "mpgemm_qd_batched", "mpgemm_ts_batched"):
+                    f = getattr(L, name)
+                    f.restype = _I
+                    f.argtypes = [_I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
                 L.mpgemm_set_mode.argtypes = [_I, _I]
                 L.mpgemm_get_mode.argtypes = [_I]
                 L.mpgemm_set_num_slices.argtypes = [_I, _I, _I]
@@ -218,6 +222,45 @@ def gemm(fmt, A, B, C=None, *, mode=None, slices=None, stream=None):
                 _stream(stream))
     _check(st, "mpgemm_" + name)
     return C
+
+
+def gemm_batched(fmt, As, Bs, Cs=None, *, slices=None, stream=None):
+    """C_i = A_i B_i for lists of tensors (conventions as in ``gemm``), as one
+    batched launch (graph-captured per batch shape).  Returns the list of C."""
+    import torch
+    f = _fmt(fmt)
+    name = [k for k, v in FORMATS.items() if v == f][0]
+    c = COMPONENTS[name]
+    dtype = torch.float32 if name == "ts" else torch.float64
+    count = len(As)
+    if len(Bs) != count or (Cs is not None and len(Cs) != count):
+        raise ValueError("As, Bs and Cs must have the same length")
+    ms, ns, ks = [], [], []
+    for i, (A, B) in enumerate(zip(As, Bs)):
+        _check_tensor(A, c, dtype, f"A[{i}]")
+        _check_tensor(B, c, dtype, f"B[{i}]")
+        if B.shape[2] != A.shape[1]:
+            raise ValueError(f"product {i}: inner dimensions differ")
+        ms.append(A.shape[2])
+        ks.append(A.shape[1])
+        ns.append(B.shape[1])
+    if Cs is None:
+        Cs = [torch.empty((c, n, m), dtype=dtype, device=A.device) for A, m, n in zip(As, ms, ns)]
+    for i, Cm in enumerate(Cs):
+        _check_tensor(Cm, c, dtype, f"C[{i}]")
+    IA = ctypes.c_int * max(count, 1)
+    PA = ctypes.c_void_p * max(count, 1)
+    fn = getattr(lib(), f"mpgemm_{name}_batched")
+    with _options(f, None, slices):
+        st = fn(count, IA(*ms), IA(*ns), IA(*ks), PA(*[A.data_ptr() for A in As]), IA(*[max(1, m) for m in ms]),
+                PA(*[B.data_ptr() for B in Bs]), IA(*[max(1, k) for k in ks]), PA(*[Cm.data_ptr() for Cm in Cs]),
+                IA(*[max(1, m) for m in ms]), _stream(stream))
+    _check(st, f"mpgemm_{name}_batched")
+    return Cs
+
+
+def batched_cache_clear():
+    _check(lib().mpgemm_batched_cache_clear(), "batched_cache_clear")
 
 
 def debug_split(fmt, X, operand: int, D: int = 0, mode="float", stream=None):

@@ -11,12 +11,14 @@
 #include <vector>
 
 #include "../../include/mpgemm.h"
+#include "host.h"
 #include "internal.h"
 #include "layout.h"
 
 using namespace mp;
 
-namespace {
+namespace mp {
+namespace host {
 
 constexpr int kNumFmt = 4;
 constexpr int kMaxDim = 1 << 20;
@@ -24,6 +26,7 @@ constexpr int kMaxDFloat = 16;
 constexpr int kMaxDInt8 = 40;
 constexpr int kBoundBits[kNumFmt] = {100, 150, 200, 66};  // 2^-t bound per format
 constexpr int kComps[kNumFmt] = {2, 3, 4, 3};
+const int kCompsH[kNumFmtH] = {2, 3, 4, 3};
 
 struct ThreadOptions {
   int mode[kNumFmt] = {MPGEMM_MODE_FLOAT, MPGEMM_MODE_FLOAT, MPGEMM_MODE_FLOAT, MPGEMM_MODE_FLOAT};
@@ -88,6 +91,20 @@ int auto_slices(int fmt, int mode, int64_t k) {
 int slices_for(int fmt, int mode, int64_t k) {
   const int s = g_opt.slices[fmt][mode];
   return s > 0 ? s : auto_slices(fmt, mode, k);
+}
+int thread_mode(int fmt) { return g_opt.mode[fmt]; }
+void set_last_slices(int D) { g_opt.last_slices = D; }
+bool profiling() { return g_prof.on; }
+void profile_mark3(hipEvent_t (&ev)[3]) {
+  for (auto &x : ev) x = g_prof.on ? g_prof.take() : nullptr;
+}
+void profile_commit(hipEvent_t (&ev)[3]) {
+  if (!g_prof.on) return;
+  if (ev[0] && ev[1] && ev[2])
+    g_prof.marks.push_back({ev[0], ev[1], ev[2]});
+  else
+    for (auto x : ev)
+      if (x) g_prof.pool.push_back(x);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -369,6 +386,13 @@ int debug_products_t(int fmt, int mode, int m, int n, int k, const T *A, int lda
   if (e == hipSuccess) e = gemm_launch<T, C>(p, ws.base, m, n, k, nullptr, m, sel, out, ldo, st);
   return hip_status(e);
 }
+
+}  // namespace host
+}  // namespace mp
+
+using namespace mp::host;
+
+namespace {
 
 bool fmt_ok(int fmt) { return fmt >= 0 && fmt < kNumFmt; }
 bool mode_ok(int fmt, int mode) {

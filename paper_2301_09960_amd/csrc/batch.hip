@@ -1,0 +1,406 @@
+// Batched products: many independent products of uneven sizes in one launch
+// sequence, captured once per batch shape in a HIP graph.
+//
+// A batch plan (per host thread, device, stream and shape: format, slice
+// form, and every product's m, n, k and D) owns one device workspace holding
+// every product's residuals, packed slices, maxima and exponents, plus
+//   - the split descriptors of all 2 x count operands and the GEMM
+//     descriptors (rewritten before every launch: they carry the caller's
+//     pointers),
+//   - prefix sums of the split tiles per operand and the (product, tile) work
+//     list of the persistent GEMM kernel, ordered by decreasing work
+//     (written once).
+// The graph holds: clear the maxima, one max-exponent launch and dmax pass
+// launches covering all operands, clear the work counter, and one persistent
+// GEMM launch.  Kernels take the caller's pointers from the descriptors, so a
+// cached graph is replayed with new pointers after one small host-to-device
+// copy of the descriptors.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "../../include/mpgemm.h"
+#include "host.h"
+#include "internal.h"
+#include "layout.h"
+
+namespace mp {
+namespace host {
+namespace {
+
+constexpr int kMaxPlans = 6;
+constexpr int kPersistentGrid = 512;  // 2 workgroups per CU on 256 CUs
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct ProductLayout {
+  int m, n, k, D, rho;
+  int64_t mbp, nbp, kbp;
+  size_t resid_a, resid_b, pack_a, pack_b, mu_a, mu_b, exp_a, exp_b;
+};
+
+struct BatchPlan {
+  int device = 0, fmt = 0, mode = 0;
+  hipStream_t stream = nullptr;
+  std::vector<int> m, n, k, D;
+  std::vector<ProductLayout> prod;
+  std::vector<int> live;  // products with m, n, k > 0
+  char *ws = nullptr;
+  size_t off_ops = 0, off_descs = 0, desc_bytes = 0, off_prefix0 = 0, off_prefixp = 0, off_items = 0,
+         off_counter = 0, off_mu = 0, mu_bytes = 0, total = 0;
+  int nops = 0, tiles0 = 0, tilesp = 0, dmax = 0, nitems = 0;
+  void *stage = nullptr;
+  hipEvent_t stage_done = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t last_use = 0;
+
+  void release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (stage_done) (void)hipEventDestroy(stage_done);
+    if (stage) (void)hipHostFree(stage);
+    if (ws) (void)hipFree(ws);
+    exec = nullptr;
+    graph = nullptr;
+    stage_done = nullptr;
+    stage = nullptr;
+    ws = nullptr;
+  }
+};
+
+struct BatchCache {
+  std::vector<BatchPlan *> plans;
+  hipStream_t capture[64] = {};
+  uint64_t clock = 0;
+};
+// Owned by the thread and intentionally not destroyed at thread exit (the HIP
+// runtime may already be gone then); mpgemm_batched_cache_clear frees it.
+thread_local BatchCache *g_batch = nullptr;
+
+BatchCache &cache() {
+  if (!g_batch) g_batch = new BatchCache();
+  return *g_batch;
+}
+
+int tiles64(int64_t a, int64_t b) { return (int)(ceil_div(a, 64) * ceil_div(b, 64)); }
+
+template <typename T, int C>
+int build_plan(BatchPlan &p, hipStream_t st) {
+  const size_t w = sizeof(T);
+  const int S = sizeof(T) == 8 ? 53 : 24;
+  const int count = (int)p.m.size();
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  p.prod.resize(count);
+  p.live.clear();
+  p.dmax = 0;
+  for (int g = 0; g < count; ++g) {
+    ProductLayout &L = p.prod[g];
+    L.m = p.m[g];
+    L.n = p.n[g];
+    L.k = p.k[g];
+    L.D = p.D[g];
+    if (L.m <= 0 || L.n <= 0 || L.k <= 0) continue;
+    p.live.push_back(g);
+    L.rho = rho_of(S, L.k);
+    L.mbp = nblocks_padded(L.m);
+    L.nbp = nblocks_padded(L.n);
+    L.kbp = kblocks_padded(L.k);
+    L.resid_a = take(L.D > 1 ? (size_t)C * L.m * L.k * w : 0);
+    L.resid_b = take(L.D > 1 ? (size_t)C * L.k * L.n * w : 0);
+    L.pack_a = take((size_t)L.D * L.mbp * L.kbp * 256 * w);
+    L.pack_b = take((size_t)L.D * L.nbp * L.kbp * 256 * w);
+    L.exp_a = take((size_t)L.D * L.m * 4);
+    L.exp_b = take((size_t)L.D * L.n * 4);
+    p.dmax = std::max(p.dmax, L.D);
+  }
+  // one region for all maxima (cleared by a single fill)
+  p.off_mu = o;
+  size_t mo = 0;
+  for (int g : p.live) {
+    ProductLayout &L = p.prod[g];
+    L.mu_a = p.off_mu + mo;
+    mo += (size_t)L.D * L.m * w;
+    L.mu_b = p.off_mu + mo;
+    mo += (size_t)L.D * L.n * w;
+  }
+  p.mu_bytes = (mo + 3) / 4 * 4;
+  o = p.off_mu + align256(mo);
+  p.nops = 2 * (int)p.live.size();
+  p.off_ops = take(0);
+  p.off_descs = p.off_ops + (size_t)p.nops * sizeof(SplitOperand<T>);
+  p.desc_bytes = (size_t)p.nops * sizeof(SplitOperand<T>) + p.live.size() * sizeof(PlainGemmDesc);
+  o = p.off_ops + align256(p.desc_bytes);
+  p.off_prefix0 = take((size_t)(p.nops + 1) * 4);
+  p.off_prefixp = take((size_t)(p.nops + 1) * 4);
+
+  // work list: (product slot, tile), longest first
+  struct Item {
+    int slot, tile;
+    int64_t cost;
+  };
+  std::vector<Item> items;
+  for (int slot = 0; slot < (int)p.live.size(); ++slot) {
+    const ProductLayout &L = p.prod[p.live[slot]];
+    const int ntiles = (int)((L.mbp / kTileBlocks) * (L.nbp / kTileBlocks));
+    const int64_t cost = (int64_t)L.D * (L.D + 1) / 2 * L.kbp;
+    for (int t = 0; t < ntiles; ++t) items.push_back({slot, t, cost});
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
+  p.nitems = (int)items.size();
+  p.off_items = take(items.size() * sizeof(int2));
+  p.off_counter = take(4);
+  p.total = o;
+
+  if (hipMalloc(&p.ws, p.total > 0 ? p.total : 256) != hipSuccess) {
+    (void)hipGetLastError();
+    p.ws = nullptr;
+    return MPGEMM_ERR_WORKSPACE;
+  }
+  if (hipHostMalloc(&p.stage, p.desc_bytes > 0 ? p.desc_bytes : 64, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    p.stage = nullptr;
+    return MPGEMM_ERR_WORKSPACE;
+  }
+  if (hipEventCreateWithFlags(&p.stage_done, hipEventDisableTiming) != hipSuccess) return MPGEMM_ERR_HIP;
+
+  // static device data: tile prefix sums and the work list
+  std::vector<int> pre0(p.nops + 1, 0), prep(p.nops + 1, 0);
+  for (int slot = 0; slot < (int)p.live.size(); ++slot) {
+    const ProductLayout &L = p.prod[p.live[slot]];
+    pre0[2 * slot + 1] = pre0[2 * slot] + tiles64(L.m, L.k);
+    pre0[2 * slot + 2] = pre0[2 * slot + 1] + tiles64(L.n, L.k);
+    prep[2 * slot + 1] = prep[2 * slot] + tiles64(L.mbp * kBlk, L.kbp * kKBlk);
+    prep[2 * slot + 2] = prep[2 * slot + 1] + tiles64(L.nbp * kBlk, L.kbp * kKBlk);
+  }
+  p.tiles0 = pre0[p.nops];
+  p.tilesp = prep[p.nops];
+  std::vector<int2> it2(items.size());
+  for (size_t i = 0; i < items.size(); ++i) it2[i] = make_int2(items[i].slot, items[i].tile);
+  if (hipMemcpy(p.ws + p.off_prefix0, pre0.data(), pre0.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p.ws + p.off_prefixp, prep.data(), prep.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      (it2.size() && hipMemcpy(p.ws + p.off_items, it2.data(), it2.size() * sizeof(int2), hipMemcpyHostToDevice) !=
+                         hipSuccess))
+    return MPGEMM_ERR_HIP;
+
+  // capture the launch sequence on a private stream
+  BatchCache &bc = cache();
+  hipStream_t &cs = bc.capture[p.device & 63];
+  if (!cs && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return MPGEMM_ERR_HIP;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return MPGEMM_ERR_HIP;
+  hipError_t e = launch_split_plain_batched<T, C>(
+      reinterpret_cast<const SplitOperand<T> *>(p.ws + p.off_ops), reinterpret_cast<const int *>(p.ws + p.off_prefix0),
+      reinterpret_cast<const int *>(p.ws + p.off_prefixp), p.nops, p.tiles0, p.tilesp, p.dmax, p.ws + p.off_mu,
+      (int64_t)(p.mu_bytes / 4), cs);
+  if (e == hipSuccess) e = launch_fill32(p.ws + p.off_counter, 1, 0u, cs);
+  if (e == hipSuccess)
+    e = launch_gemm_plain_batched<T, C>(reinterpret_cast<const PlainGemmDesc *>(p.ws + p.off_descs),
+                                        reinterpret_cast<const int2 *>(p.ws + p.off_items), p.nitems,
+                                        reinterpret_cast<int *>(p.ws + p.off_counter),
+                                        std::min(p.nitems, kPersistentGrid), cs);
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+  if (e != hipSuccess || e2 != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return MPGEMM_ERR_HIP;
+  }
+  p.graph = graph;
+  if (hipGraphInstantiate(&p.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return MPGEMM_ERR_HIP;
+  }
+  (void)st;
+  return 0;
+}
+
+// Descriptors carrying this call's pointers, written into the pinned stage.
+template <typename T, int C>
+void write_descriptors(BatchPlan &p, const T *const *A, const int *lda, const T *const *B, const int *ldb,
+                       T *const *Cm, const int *ldc) {
+  SplitOperand<T> *ops = static_cast<SplitOperand<T> *>(p.stage);
+  PlainGemmDesc *descs = reinterpret_cast<PlainGemmDesc *>(static_cast<char *>(p.stage) +
+                                                           (size_t)p.nops * sizeof(SplitOperand<T>));
+  for (int slot = 0; slot < (int)p.live.size(); ++slot) {
+    const int g = p.live[slot];
+    const ProductLayout &L = p.prod[g];
+    SplitOperand<T> a{}, b{};
+    a.X = A[g];
+    a.comp_stride = (int64_t)lda[g] * L.k;
+    a.sv = 1;
+    a.sp = lda[g];
+    a.nvec = L.m;
+    a.len = L.k;
+    a.orient = 0;
+    a.resid = reinterpret_cast<T *>(p.ws + L.resid_a);
+    a.packed = p.ws + L.pack_a;
+    a.nbp = L.mbp;
+    a.kbp = L.kbp;
+    a.mu = p.ws + L.mu_a;
+    a.exps = reinterpret_cast<int *>(p.ws + L.exp_a);
+    a.D = L.D;
+    a.rho = L.rho;
+    b.X = B[g];
+    b.comp_stride = (int64_t)ldb[g] * L.n;
+    b.sv = ldb[g];
+    b.sp = 1;
+    b.nvec = L.n;
+    b.len = L.k;
+    b.orient = 1;
+    b.resid = reinterpret_cast<T *>(p.ws + L.resid_b);
+    b.packed = p.ws + L.pack_b;
+    b.nbp = L.nbp;
+    b.kbp = L.kbp;
+    b.mu = p.ws + L.mu_b;
+    b.exps = reinterpret_cast<int *>(p.ws + L.exp_b);
+    b.D = L.D;
+    b.rho = L.rho;
+    ops[2 * slot] = a;
+    ops[2 * slot + 1] = b;
+    PlainGemmDesc d{};
+    d.Apk = p.ws + L.pack_a;
+    d.Bpk = p.ws + L.pack_b;
+    d.mbp = L.mbp;
+    d.nbp = L.nbp;
+    d.kbp = L.kbp;
+    d.m = L.m;
+    d.n = L.n;
+    d.D = L.D;
+    d.ldc = ldc[g];
+    d.C = Cm[g];
+    d.c_stride = (int64_t)ldc[g] * L.n;
+    descs[slot] = d;
+  }
+}
+
+template <typename T, int C>
+int run_batched(int fmt, int count, const int *m, const int *n, const int *k, const T *const *A, const int *lda,
+                const T *const *B, const int *ldb, T *const *Cm, const int *ldc, hipStream_t st) {
+  if (count < 0) return -1;
+  if (count > 0 && (!m || !n || !k || !A || !lda || !B || !ldb || !Cm || !ldc)) {
+    const void *args[] = {m, n, k, A, lda, B, ldb, Cm, ldc};
+    for (int i = 0; i < 9; ++i)
+      if (!args[i]) return -(i + 2);
+  }
+  for (int g = 0; g < count; ++g) {
+    const int s = validate(m[g], n[g], k[g], A[g], lda[g], B[g], ldb[g], Cm[g], ldc[g]);
+    if (s < 0) return s - 1;  // positions shifted by the leading count argument
+    if (s > 0) return s;
+  }
+  int s;
+  if ((s = check_device_cached())) return s;
+  const int mode = thread_mode(fmt);
+  if (mode != MPGEMM_MODE_FLOAT) return MPGEMM_ERR_UNSUPPORTED;
+  if (count == 0) return 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MPGEMM_ERR_HIP;
+
+  std::vector<int> Ds(count);
+  for (int g = 0; g < count; ++g) Ds[g] = slices_for(fmt, mode, k[g]);
+  set_last_slices(Ds.empty() ? 0 : *std::max_element(Ds.begin(), Ds.end()));
+
+  // products with k == 0 only need C cleared
+  for (int g = 0; g < count; ++g)
+    if (k[g] == 0 && m[g] > 0 && n[g] > 0) {
+      if (launch_zero_matrix(Cm[g], sizeof(T), C, m[g], n[g], ldc[g], (int64_t)ldc[g] * n[g], st) != hipSuccess)
+        return MPGEMM_ERR_HIP;
+    }
+
+  BatchCache &bc = cache();
+  BatchPlan *plan = nullptr;
+  for (BatchPlan *p : bc.plans)
+    if (p->device == dev && p->stream == st && p->fmt == fmt && p->mode == mode && (int)p->m.size() == count &&
+        std::equal(p->m.begin(), p->m.end(), m) && std::equal(p->n.begin(), p->n.end(), n) &&
+        std::equal(p->k.begin(), p->k.end(), k) && p->D == Ds) {
+      plan = p;
+      break;
+    }
+  if (!plan) {
+    if ((int)bc.plans.size() >= kMaxPlans) {
+      auto oldest = std::min_element(bc.plans.begin(), bc.plans.end(),
+                                     [](const BatchPlan *a, const BatchPlan *b) { return a->last_use < b->last_use; });
+      (void)hipDeviceSynchronize();  // its workspace may still be in use
+      (*oldest)->release();
+      delete *oldest;
+      bc.plans.erase(oldest);
+    }
+    plan = new BatchPlan();
+    plan->device = dev;
+    plan->stream = st;
+    plan->fmt = fmt;
+    plan->mode = mode;
+    plan->m.assign(m, m + count);
+    plan->n.assign(n, n + count);
+    plan->k.assign(k, k + count);
+    plan->D = Ds;
+    if ((s = build_plan<T, C>(*plan, st))) {
+      plan->release();
+      delete plan;
+      return s;
+    }
+    bc.plans.push_back(plan);
+  }
+  plan->last_use = ++bc.clock;
+  if (plan->live.empty()) return 0;
+
+  // the stage may still feed the previous launch's descriptor copy
+  if (hipEventSynchronize(plan->stage_done) != hipSuccess) return MPGEMM_ERR_HIP;
+  write_descriptors<T, C>(*plan, A, lda, B, ldb, Cm, ldc);
+  hipEvent_t ev[3];
+  profile_mark3(ev);
+  if (ev[0]) (void)hipEventRecord(ev[0], st);
+  if (hipMemcpyAsync(plan->ws + plan->off_ops, plan->stage, plan->desc_bytes, hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipEventRecord(plan->stage_done, st) != hipSuccess)
+    return MPGEMM_ERR_HIP;
+  if (ev[1]) (void)hipEventRecord(ev[1], st);
+  const hipError_t e = hipGraphLaunch(plan->exec, st);
+  if (ev[2]) (void)hipEventRecord(ev[2], st);
+  profile_commit(ev);
+  return hip_status(e);
+}
+
+}  // namespace
+}  // namespace host
+}  // namespace mp
+
+using namespace mp::host;
+
+extern "C" {
+
+int mpgemm_dd_batched(int count, const int *m, const int *n, const int *k, const double *const *A, const int *lda,
+                      const double *const *B, const int *ldb, double *const *C, const int *ldc, hipStream_t stream) {
+  return run_batched<double, 2>(MPGEMM_DD, count, m, n, k, A, lda, B, ldb, C, ldc, stream);
+}
+int mpgemm_td_batched(int count, const int *m, const int *n, const int *k, const double *const *A, const int *lda,
+                      const double *const *B, const int *ldb, double *const *C, const int *ldc, hipStream_t stream) {
+  return run_batched<double, 3>(MPGEMM_TD, count, m, n, k, A, lda, B, ldb, C, ldc, stream);
+}
+int mpgemm_qd_batched(int count, const int *m, const int *n, const int *k, const double *const *A, const int *lda,
+                      const double *const *B, const int *ldb, double *const *C, const int *ldc, hipStream_t stream) {
+  return run_batched<double, 4>(MPGEMM_QD, count, m, n, k, A, lda, B, ldb, C, ldc, stream);
+}
+int mpgemm_ts_batched(int count, const int *m, const int *n, const int *k, const float *const *A, const int *lda,
+                      const float *const *B, const int *ldb, float *const *C, const int *ldc, hipStream_t stream) {
+  return run_batched<float, 3>(MPGEMM_TS, count, m, n, k, A, lda, B, ldb, C, ldc, stream);
+}
+
+int mpgemm_batched_cache_clear(void) {
+  if (!g_batch) return 0;
+  const hipError_t e = hipDeviceSynchronize();
+  for (BatchPlan *p : g_batch->plans) {
+    p->release();
+    delete p;
+  }
+  g_batch->plans.clear();
+  return e == hipSuccess ? 0 : MPGEMM_ERR_HIP;
+}
+
+}  // extern "C"

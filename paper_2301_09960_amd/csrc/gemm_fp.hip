@@ -68,23 +68,25 @@ __device__ __forceinline__ void tile_coords(int bid, int nblocks, int tiles_m, i
   tn = in_group / gsize;
 }
 
+template <typename T>
+constexpr int panel_elems() {
+  return kTileBlocks * kKStepBlocks * 256;  // 64 rows x 32 k
+}
+
+// All slice products of one 64 x 64 tile (tm, tn) of one product, folded into
+// C.  `lds` is the workgroup's staging buffer [stage][A,B][panel].
 template <typename T, int C>
-__global__ __launch_bounds__(kThreads) void k_gemm_plain(const T *__restrict__ Apk, const T *__restrict__ Bpk,
-                                                         int64_t mbp, int64_t nbp, int64_t kbp, int m, int n, int D,
-                                                         T *__restrict__ Cout, int ldc, int64_t c_stride,
-                                                         int single_pair, double *__restrict__ Cdbg, int lddbg) {
+__device__ void gemm_plain_tile(const T *__restrict__ Apk, const T *__restrict__ Bpk, int64_t mbp, int64_t nbp,
+                                int64_t kbp, int m, int n, int D, T *__restrict__ Cout, int ldc, int64_t c_stride,
+                                int single_pair, double *__restrict__ Cdbg, int lddbg, int tm, int tn,
+                                T (*lds)[2][panel_elems<T>()]) {
   using M = Mma<T>;
   using acc_t = typename M::acc_t;
   constexpr int kSegElems = kKStepBlocks * 256;       // one row block x one k step
-  constexpr int kPanelElems = kTileBlocks * kSegElems;  // 64 rows x 32 k
+  constexpr int kPanelElems = panel_elems<T>();
   constexpr int kVec = sizeof(T) / 2;                   // 16-byte loads per thread per operand
   static_assert(kVec * 16 * kThreads == kPanelElems * (int)sizeof(T), "panel staging");
 
-  __shared__ __attribute__((aligned(16))) T lds[2][2][kPanelElems];  // [stage][A,B][panel]
-
-  const int tiles_m = (int)(mbp / kTileBlocks), tiles_n = (int)(nbp / kTileBlocks);
-  int tm, tn;
-  tile_coords(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int wm = wave % 2, wn = wave / 2;  // 32 x 32 sub-tile of this wavefront
 
@@ -231,7 +233,60 @@ __global__ __launch_bounds__(kThreads) void k_gemm_plain(const T *__restrict__ A
       }
 }
 
+template <typename T, int C>
+__global__ __launch_bounds__(kThreads) void k_gemm_plain(const T *__restrict__ Apk, const T *__restrict__ Bpk,
+                                                         int64_t mbp, int64_t nbp, int64_t kbp, int m, int n, int D,
+                                                         T *__restrict__ Cout, int ldc, int64_t c_stride,
+                                                         int single_pair, double *__restrict__ Cdbg, int lddbg) {
+  __shared__ __attribute__((aligned(16))) T lds[2][2][panel_elems<T>()];
+  int tm, tn;
+  tile_coords(blockIdx.x, gridDim.x, (int)(mbp / kTileBlocks), (int)(nbp / kTileBlocks), tm, tn);
+  gemm_plain_tile<T, C>(Apk, Bpk, mbp, nbp, kbp, m, n, D, Cout, ldc, c_stride, single_pair, Cdbg, lddbg, tm, tn, lds);
+}
+
+// Persistent batched kernel: each workgroup takes (product, tile) work items
+// from a shared counter until the list is exhausted (items are ordered by
+// decreasing work, so the long tiles start first).
+template <typename T, int C>
+__global__ __launch_bounds__(kThreads) void k_gemm_plain_batched(const PlainGemmDesc *__restrict__ descs,
+                                                                 const int2 *__restrict__ items, int nitems,
+                                                                 int *__restrict__ counter) {
+  __shared__ __attribute__((aligned(16))) T lds[2][2][panel_elems<T>()];
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = next;
+    __syncthreads();
+    if (it >= nitems) break;
+    const int2 w = items[it];
+    const PlainGemmDesc &d = descs[w.x];
+    const int tiles_m = (int)(d.mbp / kTileBlocks);
+    gemm_plain_tile<T, C>(static_cast<const T *>(d.Apk), static_cast<const T *>(d.Bpk), d.mbp, d.nbp, d.kbp, d.m,
+                          d.n, d.D, static_cast<T *>(d.C), d.ldc, d.c_stride, -1, nullptr, 0, w.y % tiles_m,
+                          w.y / tiles_m, lds);
+  }
+}
+
 }  // namespace
+
+template <typename T, int C>
+hipError_t launch_gemm_plain_batched(const PlainGemmDesc *descs, const int2 *items, int nitems, int *counter,
+                                     int grid, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_gemm_plain_batched<T, C>), dim3((unsigned)grid), dim3(kThreads), 0, st, descs, items, nitems,
+                     counter);
+  return hipGetLastError();
+}
+
+template hipError_t launch_gemm_plain_batched<double, 2>(const PlainGemmDesc *, const int2 *, int, int *, int,
+                                                         hipStream_t);
+template hipError_t launch_gemm_plain_batched<double, 3>(const PlainGemmDesc *, const int2 *, int, int *, int,
+                                                         hipStream_t);
+template hipError_t launch_gemm_plain_batched<double, 4>(const PlainGemmDesc *, const int2 *, int, int *, int,
+                                                         hipStream_t);
+template hipError_t launch_gemm_plain_batched<float, 3>(const PlainGemmDesc *, const int2 *, int, int *, int,
+                                                        hipStream_t);
 
 template <typename T, int C>
 hipError_t launch_gemm_plain(const void *Apk, const void *Bpk, int64_t mbp, int64_t nbp, int64_t kbp, int m, int n,

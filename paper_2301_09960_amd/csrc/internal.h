@@ -24,12 +24,38 @@ struct SplitOperand {
   int64_t nbp, kbp;      // padded block counts of the packed slices
   void *mu;              // per pass: nvec maxima as IEEE bit patterns (uint64 / uint32)
   int *exps;             // D x nvec exponents (FLOAT) or nvec (INT8)
+  int D, rho;            // slice count and shift (used by the batched kernels)
+};
+
+// One product of a batch, as read by the persistent GEMM kernel.
+struct PlainGemmDesc {
+  const void *Apk, *Bpk;
+  int64_t mbp, nbp, kbp;
+  int m, n, D, ldc;
+  void *C;
+  int64_t c_stride;
 };
 
 // Plain split (Algorithm 1): D passes, slices written packed.  `rho` is the
 // shift ceil((S + log2 k)/2).  Both operands in one sequence of launches.
 template <typename T, int C>
 hipError_t launch_split_plain(const SplitOperand<T> &a, const SplitOperand<T> &b, int D, int rho, hipStream_t st);
+
+// Plain split of many operands at once: ops[0..nops) in device memory;
+// prefix_max0 / prefix_pass (nops + 1 entries, device) are running sums of the
+// 64 x 64 tiles each operand needs in the max and pass kernels.  Operand i runs
+// ops[i].D passes; launches cover dmax passes.  mu_all / mu_words: one region
+// holding every operand's maxima, cleared first.
+template <typename T, int C>
+hipError_t launch_split_plain_batched(const SplitOperand<T> *ops, const int *prefix_max0, const int *prefix_pass,
+                                      int nops, int tiles_max0, int tiles_pass, int dmax, void *mu_all,
+                                      int64_t mu_words, hipStream_t st);
+
+// Persistent GEMM over a batch: items (product index, tile index) in device
+// memory, taken in order through *counter (cleared by the caller).
+template <typename T, int C>
+hipError_t launch_gemm_plain_batched(const PlainGemmDesc *descs, const int2 *items, int nitems, int *counter,
+                                     int grid, hipStream_t st);
 
 // INT8 digit split of both operands.
 template <int C>

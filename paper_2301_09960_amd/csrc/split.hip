@@ -189,6 +189,45 @@ __global__ __launch_bounds__(kThreads) void k_split_pass(SplitOperand<T> a, Spli
 
 int tiles(int64_t nvec, int64_t len) { return (int)(ceil_div(nvec, kTile) * ceil_div(len, kTile)); }
 
+// Operand owning global tile index b: the last i with prefix[i] <= b.
+__device__ __forceinline__ int find_operand(const int *prefix, int nops, int b) {
+  int lo = 0, hi = nops - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (prefix[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T, int C>
+__global__ __launch_bounds__(kThreads) void k_split_max0_batched(const SplitOperand<T> *ops, const int *prefix,
+                                                                 int nops) {
+  const int i = find_operand(prefix, nops, blockIdx.x);
+  const SplitOperand<T> &op = ops[i];
+  const int local = blockIdx.x - prefix[i];
+  if (op.orient == 0)
+    max0_body<T, C, 0>(op, local);
+  else
+    max0_body<T, C, 1>(op, local);
+}
+
+template <typename T, int C>
+__global__ __launch_bounds__(kThreads) void k_split_pass_batched(const SplitOperand<T> *ops, const int *prefix,
+                                                                 int nops, int pass) {
+  const int i = find_operand(prefix, nops, blockIdx.x);
+  const SplitOperand<T> &op = ops[i];
+  if (pass >= op.D) return;  // uniform over the block
+  const int local = blockIdx.x - prefix[i];
+  const bool first = pass == 0, last = pass == op.D - 1;
+  if (op.orient == 0)
+    pass_body<T, C, 0>(op, local, pass, op.rho, first, last);
+  else
+    pass_body<T, C, 1>(op, local, pass, op.rho, first, last);
+}
+
 __global__ void k_fill32(uint32_t *p, int64_t n, uint32_t value) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = value;
@@ -227,6 +266,33 @@ hipError_t launch_split_plain(const SplitOperand<T> &a, const SplitOperand<T> &b
   }
   return hipSuccess;
 }
+
+template <typename T, int C>
+hipError_t launch_split_plain_batched(const SplitOperand<T> *ops, const int *prefix_max0, const int *prefix_pass,
+                                      int nops, int tiles_max0, int tiles_pass, int dmax, void *mu_all,
+                                      int64_t mu_words, hipStream_t st) {
+  hipError_t err = launch_fill32(mu_all, mu_words, 0u, st);
+  if (err != hipSuccess || nops <= 0) return err;
+  if (tiles_max0 > 0) {
+    hipLaunchKernelGGL((k_split_max0_batched<T, C>), dim3(tiles_max0), dim3(kThreads), 0, st, ops, prefix_max0, nops);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
+  for (int pass = 0; pass < dmax && tiles_pass > 0; ++pass) {
+    hipLaunchKernelGGL((k_split_pass_batched<T, C>), dim3(tiles_pass), dim3(kThreads), 0, st, ops, prefix_pass, nops,
+                       pass);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
+#define MP_SPLIT_BATCHED(T, C)                                                                                   \
+  template hipError_t launch_split_plain_batched<T, C>(const SplitOperand<T> *, const int *, const int *, int, int, \
+                                                       int, int, void *, int64_t, hipStream_t);
+MP_SPLIT_BATCHED(double, 2)
+MP_SPLIT_BATCHED(double, 3)
+MP_SPLIT_BATCHED(double, 4)
+MP_SPLIT_BATCHED(float, 3)
+#undef MP_SPLIT_BATCHED
 
 template hipError_t launch_split_plain<double, 2>(const SplitOperand<double> &, const SplitOperand<double> &, int, int,
                                                   hipStream_t);

@@ -1,0 +1,235 @@
+"""Serving loop for multi-component GEMM requests (continuous batching).
+
+Requests (format uniform over DD/TD/QD, m, n, k log-uniform in [lo, hi],
+entries with exponent spread e ~ U{0..8}) arrive by a seeded Poisson process.
+The server admits a waiting request as soon as a stream slot is free and its
+device memory fits the HBM budget; the ledger charges its inputs, output and
+library workspace (``mpgemm_workspace_bytes``) and releases them at
+completion.  Admitted requests run concurrently, one per HIP stream, so work
+of requests that arrive while others are on the GPU overlaps on the device;
+their operands, slices and results stay resident in HBM.  Latency is measured
+from arrival to the completion event.
+
+Operands are views into a device pool of synthetic values generated once
+(so no host work sits on the request path); each request takes seeded
+offsets into the pool.
+
+Run a rate sweep: ``python -m paper_2301_09960_amd.serve --sweep``.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import COMPONENTS, gemm, workspace_bytes
+
+FMTS = ("dd", "td", "qd")
+GB = 1 << 30
+
+
+@dataclass
+class Request:
+    rid: int
+    fmt: str
+    m: int
+    n: int
+    k: int
+    arrival: float  # seconds from the start of the run
+    a_off: int = 0
+    b_off: int = 0
+    start: float = math.nan
+    done: float = math.nan
+    bytes: int = 0
+    C: object = None
+    event: object = None
+    stream_slot: int = -1
+
+    @property
+    def flops(self) -> float:
+        return 2.0 * self.m * self.n * self.k
+
+
+@dataclass
+class ServeStats:
+    rate: float
+    requests: int
+    p50_ms: float
+    p99_ms: float
+    mean_ms: float
+    throughput_gflops: float
+    max_inflight: int
+    peak_ledger_gb: float
+    wall_s: float
+    extra: dict = field(default_factory=dict)
+
+
+def make_requests(count: int, rate: float, seed: int = 0, lo: int = 64, hi: int = 2048, pool: int = 1 << 24):
+    """Seeded request stream: Poisson arrivals at ``rate`` per second."""
+    from workload import log_uniform_sizes, uniform01, uniform_int
+    m = log_uniform_sizes(seed, count, lo, hi, draw=0)
+    n = log_uniform_sizes(seed, count, lo, hi, draw=1)
+    k = log_uniform_sizes(seed, count, lo, hi, draw=2)
+    f = uniform_int(seed, 4, 0, count, 0, len(FMTS) - 1)
+    gaps = -np.log1p(-uniform01(seed, 4, 1, count)) / rate
+    t = np.cumsum(gaps)
+    ao = uniform_int(seed, 4, 2, count, 0, pool - 1)
+    bo = uniform_int(seed, 4, 3, count, 0, pool - 1)
+    out = []
+    for i in range(count):
+        r = Request(i, FMTS[f[i]], int(m[i]), int(n[i]), int(k[i]), float(t[i]))
+        r.a_off = int(ao[i]) % max(1, pool - r.m * r.k)
+        r.b_off = int(bo[i]) % max(1, pool - r.k * r.n)
+        out.append(r)
+    return out
+
+
+class DevicePool:
+    """Synthetic component planes on the device (one pool per format), from
+    which request operands are sliced."""
+
+    def __init__(self, elements: int = 1 << 24, seed: int = 99):
+        import torch
+
+        from workload import gen_matrix
+        self.elements = elements
+        self.planes = {}
+        for fmt in FMTS:
+            X = gen_matrix(fmt, elements, 1, E=8, seed=seed, operand="A")  # (c, 1, elements)
+            self.planes[fmt] = torch.from_numpy(np.ascontiguousarray(X[:, 0, :])).cuda()
+
+    def operand(self, fmt, rows, cols, offset):
+        P = self.planes[fmt]
+        return P[:, offset:offset + rows * cols].reshape(P.shape[0], cols, rows).contiguous()
+
+
+class Server:
+    """Admits requests under an HBM budget onto a fixed set of streams."""
+
+    def __init__(self, pool: DevicePool, budget_gb: float = 64.0, streams: int = 8):
+        import torch
+        self.pool = pool
+        self.budget = int(budget_gb * GB)
+        self.ledger = 0
+        self.peak = 0
+        self.streams = [torch.cuda.Stream() for _ in range(streams)]
+        self.free_slots = deque(range(streams))
+
+    def cost(self, r: Request) -> int:
+        c = COMPONENTS[r.fmt]
+        return 8 * c * (r.m * r.k + r.k * r.n + r.m * r.n) + workspace_bytes(r.fmt, "float", r.m, r.n, r.k)
+
+    def launch(self, r: Request, now: float):
+        import torch
+        slot = self.free_slots.popleft()
+        st = self.streams[slot]
+        r.stream_slot = slot
+        r.start = now
+        with torch.cuda.stream(st):
+            A = self.pool.operand(r.fmt, r.m, r.k, r.a_off)
+            B = self.pool.operand(r.fmt, r.k, r.n, r.b_off)
+            r.C = gemm(r.fmt, A, B, stream=st)
+            r.event = torch.cuda.Event()
+            r.event.record(st)
+        self.ledger += r.bytes
+        self.peak = max(self.peak, self.ledger)
+
+    def run(self, reqs, warmup: int = 0, keep_results: bool = False) -> ServeStats:
+        """Replays the arrival trace in real time; returns latency statistics of
+        the requests after the first ``warmup``."""
+        import torch
+        for r in reqs:
+            r.bytes = self.cost(r)
+            if r.bytes > self.budget:
+                raise ValueError(f"request {r.rid} needs {r.bytes / GB:.1f} GB, above the budget")
+        waiting = deque()
+        inflight = []
+        pending = deque(reqs)
+        max_inflight = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while pending or waiting or inflight:
+            now = time.perf_counter() - t0
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            # admit in arrival order while a slot and memory are free
+            while waiting and self.free_slots and self.ledger + waiting[0].bytes <= self.budget:
+                r = waiting.popleft()
+                self.launch(r, now)
+                inflight.append(r)
+            max_inflight = max(max_inflight, len(inflight))
+            still = []
+            for r in inflight:
+                if r.event.query():
+                    r.done = time.perf_counter() - t0
+                    self.ledger -= r.bytes
+                    self.free_slots.append(r.stream_slot)
+                    if not keep_results:
+                        r.C = None
+                else:
+                    still.append(r)
+            inflight = still
+            if not inflight and not waiting and pending:
+                time.sleep(max(0.0, min(pending[0].arrival - (time.perf_counter() - t0), 0.001)))
+        wall = time.perf_counter() - t0
+        meas = reqs[warmup:]
+        lat = np.array([(r.done - r.arrival) * 1e3 for r in meas])
+        span = max(r.done for r in meas) - min(r.arrival for r in meas)
+        return ServeStats(
+            rate=float(len(reqs) / max(reqs[-1].arrival, 1e-9)),
+            requests=len(meas),
+            p50_ms=float(np.percentile(lat, 50)),
+            p99_ms=float(np.percentile(lat, 99)),
+            mean_ms=float(lat.mean()),
+            throughput_gflops=float(sum(r.flops for r in meas) / span / 1e9),
+            max_inflight=max_inflight,
+            peak_ledger_gb=self.peak / GB,
+            wall_s=wall,
+        )
+
+
+def capacity(pool: DevicePool, count: int = 200, seed: int = 5, streams: int = 8) -> float:
+    """Requests per second the server completes with every request present at t = 0."""
+    reqs = make_requests(count, rate=1e9, seed=seed, pool=pool.elements)
+    for r in reqs:
+        r.arrival = 0.0
+    st = Server(pool, streams=streams).run(reqs)
+    return count / st.wall_s
+
+
+def sweep(fractions=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), requests: int = 2000, warmup: int = 200, seed: int = 1,
+          streams: int = 8):
+    pool = DevicePool()
+    cap = capacity(pool, streams=streams)
+    out = {"capacity_req_per_s": cap, "points": []}
+    for fr in fractions:
+        reqs = make_requests(requests + warmup, rate=fr * cap, seed=seed, pool=pool.elements)
+        st = Server(pool, streams=streams).run(reqs, warmup=warmup)
+        st.extra["fraction_of_capacity"] = fr
+        out["points"].append(st.__dict__)
+        print(json.dumps({k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.__dict__.items()}),
+              flush=True)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sweep", action="store_true")
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--streams", type=int, default=8)
+    ap.add_argument("--out", default="")
+    args = ap.parse_args()
+    res = sweep(requests=args.requests, warmup=args.warmup, streams=args.streams)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(res, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

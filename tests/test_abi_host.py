@@ -75,3 +75,13 @@ def test_workspace_bytes(L):
     assert big <= b <= big + 2 * 6 * 4096 * 8 * 2 + 4096
     # ragged sizes are padded to 64 rows/columns and 32 in k
     assert mp.workspace_bytes("ts", "float", 65, 1, 33, 1) >= 1 * 128 * 64 * 4 + 1 * 64 * 64 * 4
+
+
+def test_batched_argument_codes(L):
+    IA = ctypes.c_int * 1
+    PA = ctypes.c_void_p * 1
+    x = PA(16)
+    assert L.mpgemm_dd_batched(-1, None, None, None, None, None, None, None, None, None, None) == -1
+    assert L.mpgemm_dd_batched(1, None, IA(1), IA(1), x, IA(1), x, IA(1), x, IA(1), None) == -2
+    assert L.mpgemm_dd_batched(1, IA(4), IA(4), IA(4), x, IA(3), x, IA(4), x, IA(4), None) == -6
+    assert L.mpgemm_qd_batched(1, IA(4), IA(4), IA(4), x, IA(4), x, IA(4), x, IA(2), None) == -10

@@ -1,0 +1,108 @@
+"""GPU tests of the batched path (one graph-captured launch sequence for many
+uneven products): every product equals the single call bit for bit, meets the
+error bound, and graph replays with new inputs (with eager work in between)
+give the eager results."""
+import numpy as np
+import pytest
+
+import workload as W
+
+pytestmark = pytest.mark.gpu
+
+T_BITS = {"dd": 100, "td": 150, "qd": 200, "ts": 66}
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2301_09960_amd as mp
+    mp.lib()
+    assert mp.check_device() == 0
+    yield mp
+    mp.batched_cache_clear()
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def shapes(seed, count, lo, hi):
+    m = W.log_uniform_sizes(seed, count, lo, hi, draw=0)
+    n = W.log_uniform_sizes(seed, count, lo, hi, draw=1)
+    k = W.log_uniform_sizes(seed, count, lo, hi, draw=2)
+    return list(zip(m.tolist(), n.tolist(), k.tolist()))
+
+
+def make_batch(fmt, sh, seed, E=8):
+    return [W.gen_pair(fmt, m, n, k, E=E, seed=seed * 1000 + i) for i, (m, n, k) in enumerate(sh)]
+
+
+@pytest.mark.parametrize("fmt", ["dd", "qd", "ts"])
+def test_batched_equals_single_calls(mp, orc, fmt):
+    import torch
+    sh = shapes(1, 30, 1, 300) + [(0, 5, 7), (6, 0, 3), (5, 4, 0), (1, 1, 1), (64, 64, 64), (65, 1, 129)]
+    say(f"batched {fmt}: {len(sh)} products")
+    host = make_batch(fmt, sh, seed=7)
+    As = [dev(A) for A, _ in host]
+    Bs = [dev(B) for _, B in host]
+    Cs = mp.gemm_batched(fmt, As, Bs)
+    torch.cuda.synchronize()
+    for i, (A, B) in enumerate(zip(As, Bs)):
+        single = mp.gemm(fmt, A, B)
+        torch.cuda.synchronize()
+        assert torch.equal(single, Cs[i]), i
+    for i in range(0, len(sh), 5):
+        m, n, k = sh[i]
+        if m == 0 or n == 0:
+            continue
+        A, B = host[i]
+        diff, absab, _ = orc.exact_check(A, B, Cs[i].cpu().numpy())
+        ok, worst = orc.bound_report(diff, absab, T_BITS[fmt])
+        assert ok, (i, sh[i], worst)
+
+
+def test_graph_replays_with_new_inputs(mp):
+    import torch
+    sh = shapes(2, 24, 16, 200)
+    batches = [make_batch("td", sh, seed=s) for s in (11, 12, 13)]
+    outs = []
+    for r, host in enumerate(batches + batches[:1]):
+        As = [dev(A) for A, _ in host]
+        Bs = [dev(B) for _, B in host]
+        Cs = mp.gemm_batched("td", As, Bs)  # first call captures, the rest replay
+        torch.cuda.synchronize()
+        # eager work between replays
+        eager = [mp.gemm("td", A, B) for A, B in zip(As, Bs)]
+        torch.cuda.synchronize()
+        for i in range(len(sh)):
+            assert torch.equal(eager[i], Cs[i]), (r, i)
+        outs.append([c.cpu() for c in Cs])
+        say(f"replay {r} ok")
+    for a, b in zip(outs[0], outs[3]):  # same inputs, same results
+        assert torch.equal(a, b)
+
+
+def test_config3_like_batch(mp, orc):
+    """128 DD products, m, n, k log-uniform in [64, 512], e ~ U{0..8}: a sample
+    equals single calls bit for bit and meets the bound."""
+    import torch
+    sh = shapes(3, 128, 64, 512)
+    host = make_batch("dd", sh, seed=21)
+    As = [dev(A) for A, _ in host]
+    Bs = [dev(B) for _, B in host]
+    Cs = mp.gemm_batched("dd", As, Bs)
+    torch.cuda.synchronize()
+    for i in range(0, 128, 9):
+        assert torch.equal(mp.gemm("dd", As[i], Bs[i]), Cs[i]), i
+    for i in (0, 77):
+        A, B = host[i]
+        diff, absab, _ = orc.exact_check(A, B, Cs[i].cpu().numpy(), rows=[0, sh[i][0] - 1])
+        ok, worst = orc.bound_report(diff, absab, 100)
+        assert ok, worst
