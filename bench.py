@@ -16,6 +16,12 @@ Extra objects on the JSON line:
   int8         -- the same products with INT8 digit slices on the INT8 matrix
                   cores (precision form), timed the same way; speedup over
                   the binary64-slice form at the same error bound.
+  batched      -- 512 independent DD (and QD) products with m, n, k each
+                  log-uniform in [64, 1024], e ~ U{0..8}, as one graph launch:
+                  sum of 2mnk over the batch / launch time.
+  serving      -- Poisson arrivals of DD/TD/QD requests (m, n, k log-uniform in
+                  [64, 2048]) under a 64 GB HBM budget at 0.75 of the measured
+                  capacity: p50/p99 latency and throughput.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -55,6 +61,9 @@ def parse():
     ap.add_argument("--formats", default="dd,qd")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-int8", action="store_true", help="skip the INT8-slice form")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows of C in the CPU sample (0: auto)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 1 GiB (for scaling HBM counters)")
@@ -99,6 +108,42 @@ def cpu_baseline(n, E, rows_req):
         "kind": "oracle",
         "sample": f"DD n={n} E~U{{0..{E}}} D={D}: full split of B, split of {rows} rows of A, exact slice products "
                   f"and exact accumulation for {rows} x {n} entries of C ({dt:.1f} s)",
+    }
+
+
+def run_batched(mp, torch, pool, fmt, count=512, seed=31):
+    """One graph launch of `count` products with sizes log-uniform in [64, 1024]."""
+    import workload as W
+    m = W.log_uniform_sizes(seed, count, 64, 1024, draw=0)
+    n = W.log_uniform_sizes(seed, count, 64, 1024, draw=1)
+    k = W.log_uniform_sizes(seed, count, 64, 1024, draw=2)
+    offs = W.uniform_int(seed, 5, 0, 2 * count, 0, pool.elements - 1)
+    As, Bs = [], []
+    for i in range(count):
+        ao = int(offs[2 * i]) % (pool.elements - int(m[i] * k[i]))
+        bo = int(offs[2 * i + 1]) % (pool.elements - int(k[i] * n[i]))
+        As.append(pool.operand(fmt, int(m[i]), int(k[i]), ao))
+        Bs.append(pool.operand(fmt, int(k[i]), int(n[i]), bo))
+    Cs = mp.gemm_batched(fmt, As, Bs)  # captures the graph
+    torch.cuda.synchronize()
+    reps = 3
+    mp.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mp.gemm_batched(fmt, As, Bs, Cs)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    mp.profile_enable(False)
+    _, gms = mp.profile_read()
+    flops = float(np.sum(2.0 * m * n * k))
+    gpu_ms = float(np.mean(gms))
+    return {
+        "products": count,
+        "sum_2mnk": flops,
+        "launch_ms": round(gpu_ms, 3),
+        "effective_gflops": round(flops / (gpu_ms * 1e-3) / 1e9, 1),
+        "wall_ms_per_batch": round((t1 - t0) * 1e3 / reps, 3),
+        "max_slices": mp.last_num_slices(),
     }
 
 
@@ -202,6 +247,39 @@ def main():
                     (stages[f]["split_ms"] + stages[f]["gemm_kernel_ms"]) / call_ms, 3),
             }
 
+    batched = None
+    pool = None
+    if not args.no_batched or not args.no_serving:
+        from paper_2301_09960_amd import serve
+        pool = serve.DevicePool(elements=1 << 24, seed=99)
+    if not args.no_batched:
+        batched = {}
+        for f in ("dd", "qd"):
+            batched[f] = run_batched(mp, torch, pool, f)
+            log(f"batched {f}: {batched[f]}")
+        mp.batched_cache_clear()
+
+    serving = None
+    if not args.no_serving:
+        from paper_2301_09960_amd import serve
+        cap = serve.capacity(pool, count=200)
+        nreq = args.serve_requests
+        reqs = serve.make_requests(nreq + nreq // 10, rate=0.75 * cap, seed=1, pool=pool.elements)
+        st = serve.Server(pool, budget_gb=64, streams=8).run(reqs, warmup=nreq // 10)
+        serving = {
+            "capacity_req_per_s": round(cap, 1),
+            "offered_fraction": 0.75,
+            "requests": st.requests,
+            "p50_ms": round(st.p50_ms, 3),
+            "p99_ms": round(st.p99_ms, 3),
+            "throughput_gflops": round(st.throughput_gflops, 1),
+            "max_inflight": st.max_inflight,
+            "peak_ledger_gb": round(st.peak_ledger_gb, 3),
+            "budget_gb": 64,
+        }
+        log(f"serving: {serving}")
+    del pool
+
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -239,6 +317,8 @@ def main():
         },
         "stages": stages,
         "int8": int8,
+        "batched": batched,
+        "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

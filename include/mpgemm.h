@@ -135,6 +135,18 @@ int mpgemm_batched_cache_clear(void);
  */
 int mpgemm_set_mode(int fmt, int mode);
 int mpgemm_get_mode(int fmt);
+
+/*
+ * Wavefront layout of the FLOAT-form slice-product kernel (64 x 64 tile of C
+ * per workgroup): 1 = 4 wavefronts of 32 x 32, 2 = 8 of 32 x 16, 3 = 16 of
+ * 16 x 16; 0 restores the tuned default.  The defaults are compiled in and
+ * may be replaced by a file named in the environment variable
+ * MPGEMM_TUNE_FILE, read once per process, with lines "<fmt> <layout>" (fmt
+ * one of dd, td, qd, ts).  Per host thread; mpgemm_tile_layout returns the
+ * layout a call would use.
+ */
+int mpgemm_set_tile_layout(int fmt, int layout);
+int mpgemm_tile_layout(int fmt);
 int mpgemm_set_num_slices(int fmt, int mode, int D);
 int mpgemm_num_slices(int fmt, int mode, int k);
 int mpgemm_last_num_slices(void);

@@ -58,6 +58,8 @@ def lib():
                     f = getattr(L, name)
                     f.restype = _I
                     f.argtypes = [_I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+                L.mpgemm_set_tile_layout.argtypes = [_I, _I]
+                L.mpgemm_tile_layout.argtypes = [_I]
                 L.mpgemm_set_mode.argtypes = [_I, _I]
                 L.mpgemm_get_mode.argtypes = [_I]
                 L.mpgemm_set_num_slices.argtypes = [_I, _I, _I]
@@ -121,6 +123,15 @@ def set_mode(fmt, mode):
 def get_mode(fmt) -> str:
     m = lib().mpgemm_get_mode(_fmt(fmt))
     return {0: "float", 1: "int8"}[m]
+
+
+def set_tile_layout(fmt, layout: int):
+    """Wavefront layout of the slice-product kernel (0 = tuned default, 1..3)."""
+    _check(lib().mpgemm_set_tile_layout(_fmt(fmt), int(layout)), "set_tile_layout")
+
+
+def tile_layout(fmt) -> int:
+    return lib().mpgemm_tile_layout(_fmt(fmt))
 
 
 def set_num_slices(fmt, mode, D: int):

@@ -6,6 +6,8 @@
 #include <array>
 #include <climits>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -30,6 +32,7 @@ const int kCompsH[kNumFmtH] = {2, 3, 4, 3};
 
 struct ThreadOptions {
   int mode[kNumFmt] = {MPGEMM_MODE_FLOAT, MPGEMM_MODE_FLOAT, MPGEMM_MODE_FLOAT, MPGEMM_MODE_FLOAT};
+  int layout[kNumFmt] = {0, 0, 0, 0};  // 0: tuned default
   int slices[kNumFmt][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
   int last_slices = 0;
   void *ws = nullptr;
@@ -93,6 +96,33 @@ int slices_for(int fmt, int mode, int64_t k) {
   return s > 0 ? s : auto_slices(fmt, mode, k);
 }
 int thread_mode(int fmt) { return g_opt.mode[fmt]; }
+
+// Wave layout of the binary64/binary32 slice-product kernel per format:
+// compiled-in defaults (measured), replaced by the file named in the
+// environment variable MPGEMM_TUNE_FILE (lines "<fmt> <layout>", as written
+// by paper_2301_09960_amd.tune), replaced per thread by mpgemm_set_tile_layout.
+int g_layout_default[kNumFmt] = {2, 2, 2, 2};  // measured best at n = 4096 for every format
+std::once_flag g_tune_once;
+
+void load_tune_file() {
+  const char *path = std::getenv("MPGEMM_TUNE_FILE");
+  if (!path || !*path) return;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return;
+  char name[16];
+  int layout;
+  while (std::fscanf(f, "%15s %d", name, &layout) == 2) {
+    const char *names[kNumFmt] = {"dd", "td", "qd", "ts"};
+    for (int i = 0; i < kNumFmt; ++i)
+      if (std::strcmp(name, names[i]) == 0 && layout >= 1 && layout <= 3) g_layout_default[i] = layout;
+  }
+  std::fclose(f);
+}
+
+int layout_for(int fmt) {
+  std::call_once(g_tune_once, load_tune_file);
+  return g_opt.layout[fmt] > 0 ? g_opt.layout[fmt] : g_layout_default[fmt];
+}
 void set_last_slices(int D) { g_opt.last_slices = D; }
 bool profiling() { return g_prof.on; }
 void profile_mark3(hipEvent_t (&ev)[3]) {
@@ -299,7 +329,8 @@ hipError_t gemm_launch(const Plan &p, char *base, int m, int n, int k, T *Cout, 
     return hipErrorInvalidValue;
   }
   return launch_gemm_plain<T, C>(base + p.off_pack_a, base + p.off_pack_b, p.mbp, p.nbp, p.kbp, m, n, p.D, Cout, ldc,
-                                 (int64_t)ldc * n, dbg_pair, static_cast<double *>(dbg_out), lddbg, st);
+                                 (int64_t)ldc * n, dbg_pair, static_cast<double *>(dbg_out), lddbg,
+                                 layout_for(p.fmt), st);
 }
 
 template <typename T, int C>
@@ -454,6 +485,14 @@ int mpgemm_set_mode(int fmt, int mode) {
   return 0;
 }
 int mpgemm_get_mode(int fmt) { return fmt_ok(fmt) ? g_opt.mode[fmt] : -1; }
+
+int mpgemm_set_tile_layout(int fmt, int layout) {
+  if (!fmt_ok(fmt)) return -1;
+  if (layout < 0 || layout > 3) return -2;
+  g_opt.layout[fmt] = layout;
+  return 0;
+}
+int mpgemm_tile_layout(int fmt) { return fmt_ok(fmt) ? layout_for(fmt) : -1; }
 
 int mpgemm_set_num_slices(int fmt, int mode, int D) {
   if (!fmt_ok(fmt)) return -1;

@@ -42,7 +42,7 @@ struct ProductLayout {
 };
 
 struct BatchPlan {
-  int device = 0, fmt = 0, mode = 0;
+  int device = 0, fmt = 0, mode = 0, layout = 1;
   hipStream_t stream = nullptr;
   std::vector<int> m, n, k, D;
   std::vector<ProductLayout> prod;
@@ -204,7 +204,7 @@ int build_plan(BatchPlan &p, hipStream_t st) {
     e = launch_gemm_plain_batched<T, C>(reinterpret_cast<const PlainGemmDesc *>(p.ws + p.off_descs),
                                         reinterpret_cast<const int2 *>(p.ws + p.off_items), p.nitems,
                                         reinterpret_cast<int *>(p.ws + p.off_counter),
-                                        std::min(p.nitems, kPersistentGrid), cs);
+                                        std::min(p.nitems, kPersistentGrid), p.layout, cs);
   hipGraph_t graph = nullptr;
   const hipError_t e2 = hipStreamEndCapture(cs, &graph);
   if (e != hipSuccess || e2 != hipSuccess || !graph) {
@@ -298,6 +298,7 @@ int run_batched(int fmt, int count, const int *m, const int *n, const int *k, co
   if ((s = check_device_cached())) return s;
   const int mode = thread_mode(fmt);
   if (mode != MPGEMM_MODE_FLOAT) return MPGEMM_ERR_UNSUPPORTED;
+  const int layout = layout_for(fmt);
   if (count == 0) return 0;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return MPGEMM_ERR_HIP;
@@ -316,7 +317,8 @@ int run_batched(int fmt, int count, const int *m, const int *n, const int *k, co
   BatchCache &bc = cache();
   BatchPlan *plan = nullptr;
   for (BatchPlan *p : bc.plans)
-    if (p->device == dev && p->stream == st && p->fmt == fmt && p->mode == mode && (int)p->m.size() == count &&
+    if (p->device == dev && p->stream == st && p->fmt == fmt && p->mode == mode && p->layout == layout &&
+        (int)p->m.size() == count &&
         std::equal(p->m.begin(), p->m.end(), m) && std::equal(p->n.begin(), p->n.end(), n) &&
         std::equal(p->k.begin(), p->k.end(), k) && p->D == Ds) {
       plan = p;
@@ -336,6 +338,7 @@ int run_batched(int fmt, int count, const int *m, const int *n, const int *k, co
     plan->stream = st;
     plan->fmt = fmt;
     plan->mode = mode;
+    plan->layout = layout;
     plan->m.assign(m, m + count);
     plan->n.assign(n, n + count);
     plan->k.assign(k, k + count);

@@ -26,7 +26,6 @@
 namespace mp {
 namespace {
 
-constexpr int kThreads = 256;
 constexpr int kGroupM = 8;  // tile rows per group in the XCD-local ordering
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -73,159 +72,210 @@ constexpr int panel_elems() {
   return kTileBlocks * kKStepBlocks * 256;  // 64 rows x 32 k
 }
 
+// Wave layouts of the 64 x 64 tile: WM x WN wavefronts, each owning
+// (4 / WM) x (4 / WN) blocks of 16 x 16.
+//   layout 1: 2 x 2 waves, 32 x 32 each (256 threads)
+//   layout 2: 2 x 4 waves, 32 x 16 each (512 threads)
+//   layout 3: 4 x 4 waves, 16 x 16 each (1024 threads)
+// Fewer elements per lane means fewer accumulator registers and more
+// wavefronts per SIMD to hide latency, at the price of more LDS reads per
+// matrix-core instruction.
+template <int L> struct Layout;
+template <> struct Layout<1> { static constexpr int WM = 2, WN = 2; };
+template <> struct Layout<2> { static constexpr int WM = 2, WN = 4; };
+template <> struct Layout<3> { static constexpr int WM = 4, WN = 4; };
+
+// Wavefronts per SIMD the register allocation must allow.  Layout 1 with
+// three or four components is left free: forcing two wavefronts into 256
+// registers made those schedules far slower than one wavefront that keeps its
+// matrix-core accumulators in AGPRs.
+constexpr int waves_of(int layout, int C) { return layout == 3 ? 4 : layout == 2 ? 2 : (C <= 2 ? 2 : 1); }
+
+// 16 bytes per lane from global memory straight into LDS: lane l's bytes land
+// at lds_dst + 16 l (lds_dst is the same for the whole wavefront).
+__device__ __forceinline__ void load_lds16(const void *src, void *lds_dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds_dst, 16, 0, 0);
+}
+
+// Waits until at most N vector-memory operations of this wavefront are in
+// flight (the LDS-direct loads of later pipeline stages).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// Operand staging: every k step (32) of a pair needs a 64 x 32 panel of A_a and
+// one of B_b; the panels arrive by global-to-LDS loads (16 bytes per lane,
+// 1 KiB per wavefront instruction, no registers involved) into a ring of NS
+// stages, issued NS - 1 steps ahead of the matrix-core work.  A step waits
+// only for its own loads (s_waitcnt on the count of later loads still in
+// flight), then one barrier makes every wavefront's loads visible.
+template <typename T>
+constexpr int stage_elems() {
+  return 2 * panel_elems<T>();  // A panel, then B panel
+}
+constexpr int kStages = 4;
+
 // All slice products of one 64 x 64 tile (tm, tn) of one product, folded into
-// C.  `lds` is the workgroup's staging buffer [stage][A,B][panel].
-template <typename T, int C>
-__device__ void gemm_plain_tile(const T *__restrict__ Apk, const T *__restrict__ Bpk, int64_t mbp, int64_t nbp,
+// C.  `lds` is the workgroup's ring of kStages staging buffers of
+// stage_elems<T>() elements each.
+template <typename T, int C, int LAYOUT>
+__device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const T *__restrict__ Bpk, int64_t mbp, int64_t nbp,
                                 int64_t kbp, int m, int n, int D, T *__restrict__ Cout, int ldc, int64_t c_stride,
                                 int single_pair, double *__restrict__ Cdbg, int lddbg, int tm, int tn,
-                                T (*lds)[2][panel_elems<T>()]) {
+                                T *lds) {
   using M = Mma<T>;
   using acc_t = typename M::acc_t;
-  constexpr int kSegElems = kKStepBlocks * 256;       // one row block x one k step
+  constexpr int WM = Layout<LAYOUT>::WM, WN = Layout<LAYOUT>::WN;
+  constexpr int BI = kTileBlocks / WM, BJ = kTileBlocks / WN;  // 16 x 16 blocks per wavefront
+  constexpr int NW = WM * WN;
+  constexpr int kSegElems = kKStepBlocks * 256;              // one row block x one k step
   constexpr int kPanelElems = panel_elems<T>();
-  constexpr int kVec = sizeof(T) / 2;                   // 16-byte loads per thread per operand
-  static_assert(kVec * 16 * kThreads == kPanelElems * (int)sizeof(T), "panel staging");
+  constexpr int kInstElems = 64 * 16 / (int)sizeof(T);       // elements one wavefront instruction moves
+  constexpr int kInstPerSeg = kSegElems / kInstElems;
+  constexpr int kInstPerPanel = kTileBlocks * kInstPerSeg;
+  constexpr int kL = 2 * kInstPerPanel / NW;                 // instructions per wavefront per step
+  static_assert(2 * kInstPerPanel % NW == 0, "staging split");
 
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-  const int wm = wave % 2, wn = wave / 2;  // 32 x 32 sub-tile of this wavefront
+  const int wm = wave % WM, wn = wave / WM;
 
   const int nks = (int)(kbp / kKStepBlocks);
   const int npairs = single_pair >= 0 ? 1 : D * (D + 1) / 2;
   const int64_t total = (int64_t)npairs * nks;
 
-  // load cursor
   int la = single_pair >= 0 ? single_pair / D : 0, lb = single_pair >= 0 ? single_pair % D : 0, lks = 0;
-  const int seg = tid / 64;  // row block of the panel this thread moves
-  u4 ra[kVec], rb[kVec];
+  int64_t issued = 0;
 
-  auto load_step = [&](int a, int b, int ks) {
-    const u4 *pa = reinterpret_cast<const u4 *>(Apk + (((int64_t)a * mbp + tm * kTileBlocks + seg) * kbp +
-                                                       (int64_t)ks * kKStepBlocks) * 256);
-    const u4 *pb = reinterpret_cast<const u4 *>(Bpk + (((int64_t)b * nbp + tn * kTileBlocks + seg) * kbp +
-                                                       (int64_t)ks * kKStepBlocks) * 256);
+  // issue the loads of the step at the load cursor into its ring slot
+  auto issue = [&]() {
+    T *dst = lds + (issued % kStages) * stage_elems<T>();
+    const int64_t abase = ((int64_t)la * mbp + tm * kTileBlocks) * kbp + (int64_t)lks * kKStepBlocks;
+    const int64_t bbase = ((int64_t)lb * nbp + tn * kTileBlocks) * kbp + (int64_t)lks * kKStepBlocks;
 #pragma unroll
-    for (int j = 0; j < kVec; ++j) {
-      ra[j] = pa[j * 64 + lane];
-      rb[j] = pb[j * 64 + lane];
+    for (int j = 0; j < kL; ++j) {
+      const int q = wave * kL + j;  // instruction index within the step
+      const int op = q / kInstPerPanel, r = q % kInstPerPanel;
+      const int sg = r / kInstPerSeg, part = r % kInstPerSeg;
+      const T *src = (op == 0 ? Apk + (abase + (int64_t)sg * kbp) * 256 : Bpk + (bbase + (int64_t)sg * kbp) * 256) +
+                     part * kInstElems + lane * (16 / (int)sizeof(T));
+      load_lds16(src, dst + op * kPanelElems + sg * kSegElems + part * kInstElems);
     }
-  };
-  auto store_stage = [&](int stage) {
-    u4 *sa = reinterpret_cast<u4 *>(&lds[stage][0][seg * kSegElems]);
-    u4 *sb = reinterpret_cast<u4 *>(&lds[stage][1][seg * kSegElems]);
-#pragma unroll
-    for (int j = 0; j < kVec; ++j) {
-      sa[j * 64 + lane] = ra[j];
-      sb[j * 64 + lane] = rb[j];
-    }
-  };
-  auto advance = [&](int &a, int &b, int &ks) {
-    if (++ks == nks) {
-      ks = 0;
-      if (single_pair < 0) {
-        if (a + ++b > D - 1) {
-          ++a;
-          b = 0;
-        }
+    ++issued;
+    if (++lks == nks) {
+      lks = 0;
+      if (single_pair < 0 && la + ++lb > D - 1) {
+        ++la;
+        lb = 0;
       }
     }
   };
 
-  acc_t acc[2][2];
-  T sum[2][2][4][C + 1];
+  acc_t acc[BJ][BI];
+  T sum[BJ][BI][4][C + 1];
 #pragma unroll
-  for (int jb = 0; jb < 2; ++jb)
+  for (int y = 0; y < BJ; ++y)
 #pragma unroll
-    for (int ib = 0; ib < 2; ++ib) {
-      acc[jb][ib] = acc_t{0, 0, 0, 0};
+    for (int x = 0; x < BI; ++x) {
+      acc[y][x] = acc_t{0, 0, 0, 0};
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int q = 0; q <= C; ++q) sum[jb][ib][r][q] = T(0);
+        for (int q = 0; q <= C; ++q) sum[y][x][r][q] = T(0);
     }
 
-  load_step(la, lb, lks);
-  store_stage(0);
-  advance(la, lb, lks);
-  __syncthreads();
+  wait_vm<0>();  // nothing older than this tile's loads stays in flight
+#pragma unroll
+  for (int s = 0; s < kStages - 1; ++s)
+    if (issued < total) issue();
 
   int cks = 0;  // k step of the pair being computed
   for (int64_t step = 0; step < total; ++step) {
-    const int stage = (int)(step & 1);
-    const bool more = step + 1 < total;
-    if (more) load_step(la, lb, lks);
+    // later steps already in flight: min(kStages - 2, total - 1 - step)
+    const int64_t later = total - 1 - step;
+    if (later >= 2)
+      wait_vm<2 * kL>();
+    else if (later == 1)
+      wait_vm<kL>();
+    else
+      wait_vm<0>();
+    __builtin_amdgcn_s_barrier();
+    if (issued < total) issue();  // into the slot computed in the previous step
 
-    // matrix-core work on this stage: 2 k blocks x 4 instructions per 16 x 16 block
+    const T *stage = lds + (step % kStages) * stage_elems<T>();
 #pragma unroll
     for (int kb = 0; kb < kKStepBlocks; ++kb) {
-      T fa[2][4], fb[2][4];
+      T fa[BI][4], fb[BJ][4];
 #pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        const T *pa = &lds[stage][0][((wm * 2 + x) * kKStepBlocks + kb) * 256];
-        const T *pb = &lds[stage][1][((wn * 2 + x) * kKStepBlocks + kb) * 256];
+      for (int x = 0; x < BI; ++x) {
+        const T *pa = stage + ((wm * BI + x) * kKStepBlocks + kb) * 256;
         if constexpr (sizeof(T) == 8) {
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const d2 va = *reinterpret_cast<const d2 *>(pa + h * 128 + 2 * lane);
-            const d2 vb = *reinterpret_cast<const d2 *>(pb + h * 128 + 2 * lane);
             fa[x][2 * h] = va[0];
             fa[x][2 * h + 1] = va[1];
-            fb[x][2 * h] = vb[0];
-            fb[x][2 * h + 1] = vb[1];
           }
         } else {
           const f4 va = *reinterpret_cast<const f4 *>(pa + 4 * lane);
-          const f4 vb = *reinterpret_cast<const f4 *>(pb + 4 * lane);
 #pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            fa[x][s] = va[s];
-            fb[x][s] = vb[s];
-          }
+          for (int q = 0; q < 4; ++q) fa[x][q] = va[q];
         }
       }
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+      for (int y = 0; y < BJ; ++y) {
+        const T *pb = stage + kPanelElems + ((wn * BJ + y) * kKStepBlocks + kb) * 256;
+        if constexpr (sizeof(T) == 8) {
 #pragma unroll
-        for (int jb = 0; jb < 2; ++jb)
+          for (int h = 0; h < 2; ++h) {
+            const d2 vb = *reinterpret_cast<const d2 *>(pb + h * 128 + 2 * lane);
+            fb[y][2 * h] = vb[0];
+            fb[y][2 * h + 1] = vb[1];
+          }
+        } else {
+          const f4 vb = *reinterpret_cast<const f4 *>(pb + 4 * lane);
 #pragma unroll
-          for (int ib = 0; ib < 2; ++ib) acc[jb][ib] = M::run(fb[jb][s], fa[ib][s], acc[jb][ib]);
+          for (int q = 0; q < 4; ++q) fb[y][q] = vb[q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int y = 0; y < BJ; ++y)
+#pragma unroll
+          for (int x = 0; x < BI; ++x) acc[y][x] = M::run(fb[y][q], fa[x][q], acc[y][x]);
     }
 
     if (++cks == nks) {  // the pair's product is complete and exact: fold it in
       cks = 0;
 #pragma unroll
-      for (int jb = 0; jb < 2; ++jb)
+      for (int y = 0; y < BJ; ++y)
 #pragma unroll
-        for (int ib = 0; ib < 2; ++ib) {
+        for (int x = 0; x < BI; ++x) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) acc_add<T, C + 1>(sum[jb][ib][r], acc[jb][ib][r]);
-          acc[jb][ib] = acc_t{0, 0, 0, 0};
+          for (int r = 0; r < 4; ++r) acc_add<T, C + 1>(sum[y][x][r], acc[y][x][r]);
+          acc[y][x] = acc_t{0, 0, 0, 0};
         }
     }
-
-    if (more) {
-      store_stage(stage ^ 1);
-      advance(la, lb, lks);
-    }
-    __syncthreads();
   }
+  __builtin_amdgcn_s_barrier();  // every wavefront is done with the ring
 
   // store: element (i, j) with i along the lanes (contiguous in column-major C)
 #pragma unroll
-  for (int jb = 0; jb < 2; ++jb)
+  for (int y = 0; y < BJ; ++y)
 #pragma unroll
-    for (int ib = 0; ib < 2; ++ib)
+    for (int x = 0; x < BI; ++x)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = tm * 64 + wm * 32 + ib * 16 + lane % 16;
-        const int j = tn * 64 + wn * 32 + jb * 16 + M::out_row(lane, r);
+        const int i = tm * 64 + (wm * BI + x) * 16 + lane % 16;
+        const int j = tn * 64 + (wn * BJ + y) * 16 + M::out_row(lane, r);
         if (i >= m || j >= n) continue;
         if (single_pair >= 0) {
-          Cdbg[i + (int64_t)j * lddbg] = (double)sum[jb][ib][r][0];
+          Cdbg[i + (int64_t)j * lddbg] = (double)sum[y][x][r][0];
         } else {
           T v[C + 1];
 #pragma unroll
-          for (int q = 0; q <= C; ++q) v[q] = sum[jb][ib][r][q];
+          for (int q = 0; q <= C; ++q) v[q] = sum[y][x][r][q];
           renorm<T, C + 1>(v);
 #pragma unroll
           for (int q = 0; q < C; ++q) Cout[q * c_stride + i + (int64_t)j * ldc] = v[q];
@@ -233,25 +283,24 @@ __device__ void gemm_plain_tile(const T *__restrict__ Apk, const T *__restrict__
       }
 }
 
-template <typename T, int C>
-__global__ __launch_bounds__(kThreads) void k_gemm_plain(const T *__restrict__ Apk, const T *__restrict__ Bpk,
-                                                         int64_t mbp, int64_t nbp, int64_t kbp, int m, int n, int D,
-                                                         T *__restrict__ Cout, int ldc, int64_t c_stride,
-                                                         int single_pair, double *__restrict__ Cdbg, int lddbg) {
-  __shared__ __attribute__((aligned(16))) T lds[2][2][panel_elems<T>()];
+template <typename T, int C, int LAYOUT>
+__global__ __launch_bounds__(64 * Layout<LAYOUT>::WM * Layout<LAYOUT>::WN, waves_of(LAYOUT, C)) void k_gemm_plain(
+    const T *__restrict__ Apk, const T *__restrict__ Bpk, int64_t mbp, int64_t nbp, int64_t kbp, int m, int n, int D,
+    T *__restrict__ Cout, int ldc, int64_t c_stride, int single_pair, double *__restrict__ Cdbg, int lddbg) {
+  __shared__ __attribute__((aligned(16))) T lds[kStages][stage_elems<T>()];
   int tm, tn;
   tile_coords(blockIdx.x, gridDim.x, (int)(mbp / kTileBlocks), (int)(nbp / kTileBlocks), tm, tn);
-  gemm_plain_tile<T, C>(Apk, Bpk, mbp, nbp, kbp, m, n, D, Cout, ldc, c_stride, single_pair, Cdbg, lddbg, tm, tn, lds);
+  gemm_plain_tile<T, C, LAYOUT>(Apk, Bpk, mbp, nbp, kbp, m, n, D, Cout, ldc, c_stride, single_pair, Cdbg, lddbg, tm,
+                                tn, &lds[0][0]);
 }
 
 // Persistent batched kernel: each workgroup takes (product, tile) work items
 // from a shared counter until the list is exhausted (items are ordered by
 // decreasing work, so the long tiles start first).
-template <typename T, int C>
-__global__ __launch_bounds__(kThreads) void k_gemm_plain_batched(const PlainGemmDesc *__restrict__ descs,
-                                                                 const int2 *__restrict__ items, int nitems,
-                                                                 int *__restrict__ counter) {
-  __shared__ __attribute__((aligned(16))) T lds[2][2][panel_elems<T>()];
+template <typename T, int C, int LAYOUT>
+__global__ __launch_bounds__(64 * Layout<LAYOUT>::WM * Layout<LAYOUT>::WN, waves_of(LAYOUT, C)) void k_gemm_plain_batched(
+    const PlainGemmDesc *__restrict__ descs, const int2 *__restrict__ items, int nitems, int *__restrict__ counter) {
+  __shared__ __attribute__((aligned(16))) T lds[kStages][stage_elems<T>()];
   __shared__ int next;
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(counter, 1);
@@ -262,51 +311,69 @@ __global__ __launch_bounds__(kThreads) void k_gemm_plain_batched(const PlainGemm
     const int2 w = items[it];
     const PlainGemmDesc &d = descs[w.x];
     const int tiles_m = (int)(d.mbp / kTileBlocks);
-    gemm_plain_tile<T, C>(static_cast<const T *>(d.Apk), static_cast<const T *>(d.Bpk), d.mbp, d.nbp, d.kbp, d.m,
-                          d.n, d.D, static_cast<T *>(d.C), d.ldc, d.c_stride, -1, nullptr, 0, w.y % tiles_m,
-                          w.y / tiles_m, lds);
+    gemm_plain_tile<T, C, LAYOUT>(static_cast<const T *>(d.Apk), static_cast<const T *>(d.Bpk), d.mbp, d.nbp, d.kbp,
+                                  d.m, d.n, d.D, static_cast<T *>(d.C), d.ldc, d.c_stride, -1, (double *)nullptr,
+                                  0, w.y % tiles_m, w.y / tiles_m, &lds[0][0]);
   }
 }
+
+constexpr int threads_of(int layout) { return layout == 1 ? 256 : layout == 2 ? 512 : 1024; }
 
 }  // namespace
 
 template <typename T, int C>
-hipError_t launch_gemm_plain_batched(const PlainGemmDesc *descs, const int2 *items, int nitems, int *counter,
-                                     int grid, hipStream_t st) {
-  if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_gemm_plain_batched<T, C>), dim3((unsigned)grid), dim3(kThreads), 0, st, descs, items, nitems,
-                     counter);
-  return hipGetLastError();
-}
-
-template hipError_t launch_gemm_plain_batched<double, 2>(const PlainGemmDesc *, const int2 *, int, int *, int,
-                                                         hipStream_t);
-template hipError_t launch_gemm_plain_batched<double, 3>(const PlainGemmDesc *, const int2 *, int, int *, int,
-                                                         hipStream_t);
-template hipError_t launch_gemm_plain_batched<double, 4>(const PlainGemmDesc *, const int2 *, int, int *, int,
-                                                         hipStream_t);
-template hipError_t launch_gemm_plain_batched<float, 3>(const PlainGemmDesc *, const int2 *, int, int *, int,
-                                                        hipStream_t);
-
-template <typename T, int C>
 hipError_t launch_gemm_plain(const void *Apk, const void *Bpk, int64_t mbp, int64_t nbp, int64_t kbp, int m, int n,
                              int D, T *Cout, int ldc, int64_t c_stride, int single_pair, double *Cdbg, int lddbg,
-                             hipStream_t st) {
+                             int layout, hipStream_t st) {
   const int64_t tiles = (mbp / kTileBlocks) * (nbp / kTileBlocks);
   if (tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_gemm_plain<T, C>), dim3((unsigned)tiles), dim3(kThreads), 0, st,
-                     static_cast<const T *>(Apk), static_cast<const T *>(Bpk), mbp, nbp, kbp, m, n, D, Cout, ldc,
-                     c_stride, single_pair, Cdbg, lddbg);
+  const T *a = static_cast<const T *>(Apk);
+  const T *b = static_cast<const T *>(Bpk);
+  switch (layout) {
+    case 2:
+      hipLaunchKernelGGL((k_gemm_plain<T, C, 2>), dim3((unsigned)tiles), dim3(threads_of(2)), 0, st, a, b, mbp, nbp,
+                         kbp, m, n, D, Cout, ldc, c_stride, single_pair, Cdbg, lddbg);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_gemm_plain<T, C, 3>), dim3((unsigned)tiles), dim3(threads_of(3)), 0, st, a, b, mbp, nbp,
+                         kbp, m, n, D, Cout, ldc, c_stride, single_pair, Cdbg, lddbg);
+      break;
+    default:
+      hipLaunchKernelGGL((k_gemm_plain<T, C, 1>), dim3((unsigned)tiles), dim3(threads_of(1)), 0, st, a, b, mbp, nbp,
+                         kbp, m, n, D, Cout, ldc, c_stride, single_pair, Cdbg, lddbg);
+  }
   return hipGetLastError();
 }
 
-template hipError_t launch_gemm_plain<double, 2>(const void *, const void *, int64_t, int64_t, int64_t, int, int, int,
-                                                 double *, int, int64_t, int, double *, int, hipStream_t);
-template hipError_t launch_gemm_plain<double, 3>(const void *, const void *, int64_t, int64_t, int64_t, int, int, int,
-                                                 double *, int, int64_t, int, double *, int, hipStream_t);
-template hipError_t launch_gemm_plain<double, 4>(const void *, const void *, int64_t, int64_t, int64_t, int, int, int,
-                                                 double *, int, int64_t, int, double *, int, hipStream_t);
-template hipError_t launch_gemm_plain<float, 3>(const void *, const void *, int64_t, int64_t, int64_t, int, int, int,
-                                                float *, int, int64_t, int, double *, int, hipStream_t);
+template <typename T, int C>
+hipError_t launch_gemm_plain_batched(const PlainGemmDesc *descs, const int2 *items, int nitems, int *counter,
+                                     int grid, int layout, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  switch (layout) {
+    case 2:
+      hipLaunchKernelGGL((k_gemm_plain_batched<T, C, 2>), dim3((unsigned)grid), dim3(threads_of(2)), 0, st, descs,
+                         items, nitems, counter);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_gemm_plain_batched<T, C, 3>), dim3((unsigned)grid), dim3(threads_of(3)), 0, st, descs,
+                         items, nitems, counter);
+      break;
+    default:
+      hipLaunchKernelGGL((k_gemm_plain_batched<T, C, 1>), dim3((unsigned)grid), dim3(threads_of(1)), 0, st, descs,
+                         items, nitems, counter);
+  }
+  return hipGetLastError();
+}
+
+#define MP_GEMM_INST(T, C)                                                                                            \
+  template hipError_t launch_gemm_plain<T, C>(const void *, const void *, int64_t, int64_t, int64_t, int, int, int, \
+                                              T *, int, int64_t, int, double *, int, int, hipStream_t);              \
+  template hipError_t launch_gemm_plain_batched<T, C>(const PlainGemmDesc *, const int2 *, int, int *, int, int,    \
+                                                      hipStream_t);
+MP_GEMM_INST(double, 2)
+MP_GEMM_INST(double, 3)
+MP_GEMM_INST(double, 4)
+MP_GEMM_INST(float, 3)
+#undef MP_GEMM_INST
 
 }  // namespace mp

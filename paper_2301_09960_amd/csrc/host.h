@@ -12,6 +12,7 @@ extern const int kCompsH[kNumFmtH];
 
 // Options of the calling host thread.
 int thread_mode(int fmt);
+int layout_for(int fmt);
 int slices_for(int fmt, int mode, int64_t k);
 void set_last_slices(int D);
 

@@ -55,7 +55,7 @@ hipError_t launch_split_plain_batched(const SplitOperand<T> *ops, const int *pre
 // memory, taken in order through *counter (cleared by the caller).
 template <typename T, int C>
 hipError_t launch_gemm_plain_batched(const PlainGemmDesc *descs, const int2 *items, int nitems, int *counter,
-                                     int grid, hipStream_t st);
+                                     int grid, int layout, hipStream_t st);
 
 // INT8 digit split of both operands.
 template <int C>
@@ -64,10 +64,12 @@ hipError_t launch_split_int8(const SplitOperand<double> &a, const SplitOperand<d
 // Fused slice-product GEMM with error-free accumulation into C (C components).
 // single_pair >= 0 selects debug mode: only pair (a, b) = (single_pair / D,
 // single_pair % D) (0-based) is formed and written raw as binary64 into Cdbg.
+// `layout` selects the wavefront layout of the 64 x 64 tile (1: 4 waves of
+// 32 x 32, 2: 8 waves of 32 x 16, 3: 16 waves of 16 x 16).
 template <typename T, int C>
 hipError_t launch_gemm_plain(const void *Apk, const void *Bpk, int64_t mbp, int64_t nbp, int64_t kbp, int m, int n,
                              int D, T *Cout, int ldc, int64_t c_stride, int single_pair, double *Cdbg, int lddbg,
-                             hipStream_t st);
+                             int layout, hipStream_t st);
 
 // INT8 form GEMM: diagonal sums S_g into Sws (D x nchunks planes of m x n
 // int32), then their exact combination into C.  debug_g > 0 writes S_g for

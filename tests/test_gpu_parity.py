@@ -205,3 +205,26 @@ def test_full_size_sampled(mp, orc, fmt, rows):
     ok, worst = _check_bound(orc, fmt, A, B, np.ascontiguousarray(C), rows=rows)
     say(f"  worst log2 ratio {worst:.1f} (bound -{T_BITS[fmt]})")
     assert ok
+
+
+@pytest.mark.parametrize("layout", [1, 2, 3])
+@pytest.mark.parametrize("fmt", ["dd", "qd", "ts"])
+def test_every_tile_layout(mp, orc, fmt, layout):
+    """Every wavefront layout gives the same slice products (bit-exact) and a C
+    within the bound; layouts only reorder independent work."""
+    m, n, k = 150, 130, 333
+    A, B = W.gen_pair(fmt, m, n, k, E=16, seed=51)
+    say(f"layout {layout} {fmt}")
+    mp.set_tile_layout(fmt, layout)
+    try:
+        C = host(mp.gemm(fmt, dev(A), dev(B)))
+        D = mp.last_num_slices()
+        P = host(mp.debug_products(fmt, dev(A), dev(B), 1, D, D))
+    finally:
+        mp.set_tile_layout(fmt, 0)
+    ok, worst = _check_bound(orc, fmt, A, B, C)
+    assert ok, worst
+    S = 24 if fmt == "ts" else 53
+    sa, ea = orc.split_plain(A, D, "rows")
+    sb, eb = orc.split_plain(B, D, "cols")
+    assert np.array_equal(P, orc.slice_product(sa[0], ea[0], sb[D - 1], eb[D - 1], orc.rho(S, k), S))
