@@ -147,6 +147,14 @@ int mpgemm_get_mode(int fmt);
  */
 int mpgemm_set_tile_layout(int fmt, int layout);
 int mpgemm_tile_layout(int fmt);
+
+/*
+ * Tile configuration of the INT8-form kernel, per host thread: 0 automatic
+ * (256 x 256 tiles when they give at least one workgroup per CU, else
+ * 128 x 128), 1 = 128 x 128 with 4 wavefronts, 2 = 256 x 256 with 4,
+ * 3 = 256 x 256 with 8.  Returns -1 for other values.
+ */
+int mpgemm_set_int8_tile(int cfg);
 int mpgemm_set_num_slices(int fmt, int mode, int D);
 int mpgemm_num_slices(int fmt, int mode, int k);
 int mpgemm_last_num_slices(void);

@@ -60,6 +60,7 @@ def lib():
                     f.argtypes = [_I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
                 L.mpgemm_set_tile_layout.argtypes = [_I, _I]
                 L.mpgemm_tile_layout.argtypes = [_I]
+                L.mpgemm_set_int8_tile.argtypes = [_I]
                 L.mpgemm_set_mode.argtypes = [_I, _I]
                 L.mpgemm_get_mode.argtypes = [_I]
                 L.mpgemm_set_num_slices.argtypes = [_I, _I, _I]
@@ -128,6 +129,11 @@ def get_mode(fmt) -> str:
 def set_tile_layout(fmt, layout: int):
     """Wavefront layout of the slice-product kernel (0 = tuned default, 1..3)."""
     _check(lib().mpgemm_set_tile_layout(_fmt(fmt), int(layout)), "set_tile_layout")
+
+
+def set_int8_tile(cfg: int):
+    """INT8-form tile configuration (0 = automatic, 1..3)."""
+    _check(lib().mpgemm_set_int8_tile(int(cfg)), "set_int8_tile")
 
 
 def tile_layout(fmt) -> int:

@@ -33,6 +33,7 @@ const int kCompsH[kNumFmtH] = {2, 3, 4, 3};
 struct ThreadOptions {
   int mode[kNumFmt] = {MPGEMM_MODE_FLOAT, MPGEMM_MODE_FLOAT, MPGEMM_MODE_FLOAT, MPGEMM_MODE_FLOAT};
   int layout[kNumFmt] = {0, 0, 0, 0};  // 0: tuned default
+  int int8_tile = 0;                   // 0: automatic
   int slices[kNumFmt][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
   int last_slices = 0;
   void *ws = nullptr;
@@ -190,7 +191,7 @@ Plan make_plan(int fmt, int mode, int64_t m, int64_t n, int64_t k, int D) {
     p.off_exp_a = take((size_t)m * 4);
     p.off_exp_b = take((size_t)n * 4);
     const int64_t nchunks = ceil_div(p.kbp, int8_kblocks_per_chunk(D));
-    p.off_sums = take((size_t)D * nchunks * m * n * 4);
+    p.off_sums = take((size_t)D * nchunks * p.mbp * p.nbp * 1024 * 4);  // blocked, padded planes
   }
   p.total = o;
   return p;
@@ -325,7 +326,8 @@ hipError_t gemm_launch(const Plan &p, char *base, int m, int n, int k, T *Cout, 
                                  reinterpret_cast<const int *>(base + p.off_exp_a),
                                  reinterpret_cast<const int *>(base + p.off_exp_b),
                                  reinterpret_cast<int32_t *>(base + p.off_sums), p.mbp, p.nbp, p.kbp, m, n, p.D, Cout,
-                                 ldc, (int64_t)ldc * n, dbg_pair, static_cast<int64_t *>(dbg_out), lddbg, st);
+                                 ldc, (int64_t)ldc * n, dbg_pair, static_cast<int64_t *>(dbg_out), lddbg,
+                                 g_opt.int8_tile, st);
     return hipErrorInvalidValue;
   }
   return launch_gemm_plain<T, C>(base + p.off_pack_a, base + p.off_pack_b, p.mbp, p.nbp, p.kbp, m, n, p.D, Cout, ldc,
@@ -493,6 +495,12 @@ int mpgemm_set_tile_layout(int fmt, int layout) {
   return 0;
 }
 int mpgemm_tile_layout(int fmt) { return fmt_ok(fmt) ? layout_for(fmt) : -1; }
+
+int mpgemm_set_int8_tile(int cfg) {
+  if (cfg < 0 || cfg > 3) return -1;
+  g_opt.int8_tile = cfg;
+  return 0;
+}
 
 int mpgemm_set_num_slices(int fmt, int mode, int D) {
   if (!fmt_ok(fmt)) return -1;

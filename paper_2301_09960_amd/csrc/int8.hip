@@ -9,11 +9,12 @@
 // 32-bit sum of up to 2^31 / 4096 digit products is exact; k is cut into
 // chunks short enough for that bound, each chunk writing its own partial S_g.
 //
-// k_gemm_int8: one workgroup (4 wavefronts) per 128 x 128 tile of C and k
-// chunk; each wavefront owns 64 x 64 as 2 x 2 blocks of
-// v_mfma_i32_32x32x32_i8; 16 KiB panels (A_s and B_t, 128 x 64 digits each)
-// are staged through two LDS buffers as in the floating-point kernel.  After
-// the last pair of a diagonal the 32-bit tile is written to the S_g plane.
+// k_gemm_int8: one workgroup per tile of C (128 x 128 or 256 x 256) and k
+// chunk; each wavefront owns a grid of 32 x 32 blocks of
+// v_mfma_i32_32x32x32_i8.  Panels of A_s and B_t (64 k per step) move
+// global -> LDS by direct loads into a 4-stage ring, as in the
+// floating-point kernel.  After the last pair of a diagonal the 32-bit tile is
+// written to the S_g plane in a blocked layout (16-byte stores per lane).
 //
 // k_int8_combine: per element, C = sum_g S_g 2^(E_i + F_j + 2 - 7 (g + 1)),
 // every term exact in binary64, added with TwoSum into a (c+1)-term
@@ -26,7 +27,6 @@
 namespace mp {
 namespace {
 
-constexpr int kThreads = 256;
 constexpr int kGroupM = 8;
 
 typedef int i4v __attribute__((ext_vector_type(4)));
@@ -46,144 +46,212 @@ __device__ __forceinline__ void tile_coords(int bid, int nblocks, int tiles_m, i
   tn = in_group / gsize;
 }
 
-__global__ __launch_bounds__(kThreads) void k_gemm_int8(const int8_t *__restrict__ Apk, const int8_t *__restrict__ Bpk,
-                                                        int64_t mbp, int64_t nbp, int64_t kbp, int kb_chunk, int D,
-                                                        int m, int n, int32_t *__restrict__ S, int64_t plane) {
-  constexpr int kSegBytes = kKStepBlocks8 * 1024;       // one 32-row block x one k step
-  constexpr int kPanelBytes = kTileBlocks8 * kSegBytes;  // 128 rows x 64 k
-  __shared__ __attribute__((aligned(16))) int8_t lds[2][2][kPanelBytes];
+__device__ __forceinline__ void load_lds16(const void *src, void *lds_dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds_dst, 16, 0, 0);
+}
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
 
-  const int tiles_m = (int)(mbp / kTileBlocks8), tiles_n = (int)(nbp / kTileBlocks8);
-  int tm, tn;
-  tile_coords(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
-  const int chunk = blockIdx.y, nchunks = gridDim.y;
-  const int64_t kb0 = (int64_t)chunk * kb_chunk;
-  const int64_t kb1 = kb0 + kb_chunk < kbp ? kb0 + kb_chunk : kbp;
-  const int nks = (int)((kb1 - kb0) / kKStepBlocks8);
+// Tile configurations (in 32 x 32 blocks): TB x TB tile of C, WM x WN
+// wavefronts, KSB 32-wide k blocks per pipeline step, NS LDS stages.
+//   config 1: 128 x 128 tile, 4 wavefronts of 64 x 64 (small products)
+//   config 2: 256 x 256 tile, 4 wavefronts of 128 x 128 (accumulators in AGPRs;
+//             LDS traffic per instruction halved)
+//   config 3: 256 x 256 tile, 8 wavefronts of 128 x 64
+template <int CFG> struct Int8Cfg;
+template <> struct Int8Cfg<1> { static constexpr int TB = 4, WM = 2, WN = 2, KSB = 2, NS = 4; };
+template <> struct Int8Cfg<2> { static constexpr int TB = 8, WM = 2, WN = 2, KSB = 2, NS = 4; };
+template <> struct Int8Cfg<3> { static constexpr int TB = 8, WM = 2, WN = 4, KSB = 2, NS = 4; };
+
+template <int CFG>
+constexpr int int8_stage_bytes() {
+  return 2 * Int8Cfg<CFG>::TB * Int8Cfg<CFG>::KSB * 1024;  // A panel, then B panel
+}
+
+// Diagonal sums S_g of one tile (tm, tn) and k chunk, as in the file comment:
+// operand panels (TB blocks x KSB k blocks of A_s and of B_t) move
+// global -> LDS by direct loads into a ring of NS stages issued NS - 1 steps
+// ahead; each step waits for its own loads and passes one barrier.
+template <int CFG>
+__device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, const int8_t *__restrict__ Bpk,
+                                               int64_t mbp, int64_t nbp, int64_t kbp, int64_t kb0, int nks, int D,
+                                               int m, int n, int32_t *__restrict__ S, int64_t plane, int chunk,
+                                               int nchunks, int tm, int tn, int8_t *lds) {
+  using G = Int8Cfg<CFG>;
+  constexpr int TB = G::TB, WM = G::WM, WN = G::WN, KSB = G::KSB, NS = G::NS;
+  constexpr int BI = TB / WM, BJ = TB / WN;
+  constexpr int NW = WM * WN;
+  constexpr int kPanel = TB * KSB * 1024;
+  constexpr int kInst = 2 * TB * KSB;  // 1 KiB wavefront instructions per step
+  constexpr int kL = kInst / NW;
+  static_assert(kInst % NW == 0, "staging split");
+
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-  const int wm = wave % 2, wn = wave / 2;
-  const int seg = tid / 64;
+  const int wm = wave % WM, wn = wave / WM;
   const int64_t total = (int64_t)D * (D + 1) / 2 * nks;
 
-  // load cursor: diagonal g (1-based), pair index s (1..g), k step
-  int lg = 1, ls = 1, lks = 0;
-  u4 ra[2], rb[2];
-  auto load_step = [&](int g, int s, int ks) {
-    const int t = g + 1 - s;
-    const u4 *pa = reinterpret_cast<const u4 *>(
-        Apk + (((int64_t)(s - 1) * mbp + tm * kTileBlocks8 + seg) * kbp + kb0 + (int64_t)ks * kKStepBlocks8) * 1024);
-    const u4 *pb = reinterpret_cast<const u4 *>(
-        Bpk + (((int64_t)(t - 1) * nbp + tn * kTileBlocks8 + seg) * kbp + kb0 + (int64_t)ks * kKStepBlocks8) * 1024);
+  int lg = 1, ls = 1, lks = 0;  // load cursor: diagonal, pair within it, k step
+  int64_t issued = 0;
+  auto issue = [&]() {
+    int8_t *dst = lds + (issued % NS) * int8_stage_bytes<CFG>();
+    const int lt = lg + 1 - ls;
+    const int64_t abase = ((int64_t)(ls - 1) * mbp + (int64_t)tm * TB) * kbp + kb0 + (int64_t)lks * KSB;
+    const int64_t bbase = ((int64_t)(lt - 1) * nbp + (int64_t)tn * TB) * kbp + kb0 + (int64_t)lks * KSB;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      ra[j] = pa[j * 64 + lane];
-      rb[j] = pb[j * 64 + lane];
+    for (int j = 0; j < kL; ++j) {
+      const int q = wave * kL + j;
+      const int op = q / (TB * KSB), r = q % (TB * KSB);
+      const int blk = r / KSB, kb = r % KSB;
+      const int8_t *src = (op == 0 ? Apk + (abase + (int64_t)blk * kbp + kb) * 1024
+                                   : Bpk + (bbase + (int64_t)blk * kbp + kb) * 1024) +
+                          16 * lane;
+      load_lds16(src, dst + op * kPanel + (blk * KSB + kb) * 1024);
     }
-  };
-  auto store_stage = [&](int stage) {
-    u4 *sa = reinterpret_cast<u4 *>(&lds[stage][0][seg * kSegBytes]);
-    u4 *sb = reinterpret_cast<u4 *>(&lds[stage][1][seg * kSegBytes]);
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      sa[j * 64 + lane] = ra[j];
-      sb[j * 64 + lane] = rb[j];
-    }
-  };
-  auto advance = [&](int &g, int &s, int &ks) {
-    if (++ks == nks) {
-      ks = 0;
-      if (++s > g) {
-        ++g;
-        s = 1;
+    ++issued;
+    if (++lks == nks) {
+      lks = 0;
+      if (++ls > lg) {
+        ++lg;
+        ls = 1;
       }
     }
   };
 
-  i16v acc[2][2];
+  i16v acc[BJ][BI];
 #pragma unroll
-  for (int jb = 0; jb < 2; ++jb)
+  for (int y = 0; y < BJ; ++y)
 #pragma unroll
-    for (int ib = 0; ib < 2; ++ib)
+    for (int x = 0; x < BI; ++x)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[jb][ib][r] = 0;
+      for (int r = 0; r < 16; ++r) acc[y][x][r] = 0;
 
-  if (total > 0) {
-    load_step(lg, ls, lks);
-    store_stage(0);
-    advance(lg, ls, lks);
-  }
-  __syncthreads();
+  wait_vm<0>();
+#pragma unroll
+  for (int s = 0; s < NS - 1; ++s)
+    if (issued < total) issue();
 
   int cg = 1, cs = 1, cks = 0;  // compute cursor
   for (int64_t step = 0; step < total; ++step) {
-    const int stage = (int)(step & 1);
-    const bool more = step + 1 < total;
-    if (more) load_step(lg, ls, lks);
+    const int64_t later = total - 1 - step;
+    if (later >= 2)
+      wait_vm<2 * kL>();
+    else if (later == 1)
+      wait_vm<kL>();
+    else
+      wait_vm<0>();
+    __builtin_amdgcn_s_barrier();
+    if (issued < total) issue();
+
+    const int8_t *stage = lds + (step % NS) * int8_stage_bytes<CFG>();
 #pragma unroll
-    for (int kb = 0; kb < kKStepBlocks8; ++kb) {
-      i4v fa[2], fb[2];
+    for (int kb = 0; kb < KSB; ++kb) {
+      i4v fa[BI], fb[BJ];
 #pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        fa[x] = *reinterpret_cast<const i4v *>(&lds[stage][0][((wm * 2 + x) * kKStepBlocks8 + kb) * 1024 + 16 * lane]);
-        fb[x] = *reinterpret_cast<const i4v *>(&lds[stage][1][((wn * 2 + x) * kKStepBlocks8 + kb) * 1024 + 16 * lane]);
-      }
+      for (int x = 0; x < BI; ++x)
+        fa[x] = *reinterpret_cast<const i4v *>(stage + ((wm * BI + x) * KSB + kb) * 1024 + 16 * lane);
 #pragma unroll
-      for (int jb = 0; jb < 2; ++jb)
+      for (int y = 0; y < BJ; ++y)
+        fb[y] = *reinterpret_cast<const i4v *>(stage + kPanel + ((wn * BJ + y) * KSB + kb) * 1024 + 16 * lane);
 #pragma unroll
-        for (int ib = 0; ib < 2; ++ib)
-          acc[jb][ib] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fb[jb], fa[ib], acc[jb][ib], 0, 0, 0);
+      for (int y = 0; y < BJ; ++y)
+#pragma unroll
+        for (int x = 0; x < BI; ++x)
+          acc[y][x] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fb[y], fa[x], acc[y][x], 0, 0, 0);
     }
     if (++cks == nks) {
       cks = 0;
-      if (++cs > cg) {  // diagonal cg complete: write its exact partial sum
+      if (++cs > cg) {  // diagonal cg complete: write its exact partial sum (blocked layout)
         int32_t *out = S + ((int64_t)(cg - 1) * nchunks + chunk) * plane;
 #pragma unroll
-        for (int jb = 0; jb < 2; ++jb)
+        for (int y = 0; y < BJ; ++y)
 #pragma unroll
-          for (int ib = 0; ib < 2; ++ib) {
-            const int i = tm * 128 + wm * 64 + ib * 32 + lane % 32;
+          for (int x = 0; x < BI; ++x) {
+            const int64_t bi = (int64_t)tm * TB + wm * BI + x, bj = (int64_t)tn * TB + wn * BJ + y;
+            i4v *dst = reinterpret_cast<i4v *>(out + ((bj * mbp + bi) * 64 + lane) * 16);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              const int j = tn * 128 + wn * 64 + jb * 32 + 8 * (r / 4) + 4 * (lane / 32) + r % 4;
-              if (i < m && j < n) out[i + (int64_t)j * m] = acc[jb][ib][r];
-              acc[jb][ib][r] = 0;
-            }
+            for (int v = 0; v < 4; ++v) dst[v] = i4v{acc[y][x][4 * v], acc[y][x][4 * v + 1], acc[y][x][4 * v + 2],
+                                                     acc[y][x][4 * v + 3]};
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[y][x][r] = 0;
           }
         ++cg;
         cs = 1;
       }
     }
-    if (more) {
-      store_stage(stage ^ 1);
-      advance(lg, ls, lks);
-    }
-    __syncthreads();
   }
+  __builtin_amdgcn_s_barrier();
 }
 
+template <int CFG>
+__global__ __launch_bounds__(64 * Int8Cfg<CFG>::WM * Int8Cfg<CFG>::WN, 1) void k_gemm_int8(
+    const int8_t *__restrict__ Apk, const int8_t *__restrict__ Bpk, int64_t mbp, int64_t nbp, int64_t kbp,
+    int kb_chunk, int D, int m, int n, int32_t *__restrict__ S, int64_t plane) {
+  __shared__ __attribute__((aligned(16))) int8_t lds[Int8Cfg<CFG>::NS * int8_stage_bytes<CFG>()];
+  constexpr int TB = Int8Cfg<CFG>::TB;
+  int tm, tn;
+  tile_coords(blockIdx.x, gridDim.x, (int)(mbp / TB), (int)(nbp / TB), tm, tn);
+  const int chunk = blockIdx.y, nchunks = gridDim.y;
+  const int64_t kb0 = (int64_t)chunk * kb_chunk;
+  const int64_t kb1 = kb0 + kb_chunk < kbp ? kb0 + kb_chunk : kbp;
+  const int nks = (int)((kb1 - kb0) / Int8Cfg<CFG>::KSB);
+  gemm_int8_tile<CFG>(Apk, Bpk, mbp, nbp, kbp, kb0, nks, D, m, n, S, plane, chunk, nchunks, tm, tn, lds);
+}
+
+// Diagonal-sum planes are blocked: the 32 x 32 block (bi, bj) of C holds, for
+// lane l and accumulator r of the 32x32x32 instruction, element
+// (32 bi + l % 32, 32 bj + 8 (r / 4) + 4 (l / 32) + r % 4) at
+// ((bj * mbp + bi) * 64 + l) * 16 + r.  A combine thread takes four
+// consecutive r of one (block, lane): one 16-byte load per diagonal and chunk.
 template <int C>
 __global__ __launch_bounds__(256) void k_int8_combine(const int32_t *__restrict__ S, int64_t plane, int nchunks, int D,
-                                                      const int *__restrict__ EA, const int *__restrict__ EB, int m,
-                                                      int n, double *__restrict__ Cout, int ldc, int64_t c_stride,
+                                                      const int *__restrict__ EA, const int *__restrict__ EB,
+                                                      int64_t mbp, int64_t nbp, int m, int n,
+                                                      double *__restrict__ Cout, int ldc, int64_t c_stride,
                                                       int debug_g, int64_t *__restrict__ Sdbg, int lddbg) {
-  const int64_t total = (int64_t)m * n;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e % m), j = (int)(e / m);
-    const int Ei = EA[i], Fj = EB[j];
-    const bool live = Ei != kZeroExp && Fj != kZeroExp;
-    double acc[C + 1];
+  const int64_t total = mbp * nbp * 64 * 4;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int q = (int)(t % 4);
+    const int lane = (int)((t / 4) % 64);
+    const int64_t blk = t / 256;
+    const int64_t bi = blk % mbp, bj = blk / mbp;
+    const int i = (int)(bi * 32 + lane % 32);
+    const int j0 = (int)(bj * 32 + 8 * q + 4 * (lane / 32));
+    if (i >= m || j0 >= n) continue;
+    const int64_t off = (blk * 64 + lane) * 16 + 4 * q;
+    const int Ei = EA[i];
+    double acc[4][C + 1];
+    int Fj[4];
 #pragma unroll
-    for (int q = 0; q <= C; ++q) acc[q] = 0.0;
+    for (int e = 0; e < 4; ++e) {
+      Fj[e] = j0 + e < n ? EB[j0 + e] : kZeroExp;
+#pragma unroll
+      for (int c = 0; c <= C; ++c) acc[e][c] = 0.0;
+    }
     for (int g = 1; g <= D; ++g) {
-      int64_t s = 0;
-      for (int c = 0; c < nchunks; ++c) s += S[((int64_t)(g - 1) * nchunks + c) * plane + e];
-      if (debug_g == g) Sdbg[i + (int64_t)j * lddbg] = s;
-      if (live && s != 0) acc_add<double, C + 1>(acc, ldexp((double)s, Ei + Fj + 2 - 7 * (g + 1)));
+      int64_t s[4] = {0, 0, 0, 0};
+      for (int c = 0; c < nchunks; ++c) {
+        const i4v v = *reinterpret_cast<const i4v *>(S + ((int64_t)(g - 1) * nchunks + c) * plane + off);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s[e] += v[e];
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (j0 + e >= n) continue;
+        if (debug_g == g) Sdbg[i + (int64_t)(j0 + e) * lddbg] = s[e];
+        if (Ei != kZeroExp && Fj[e] != kZeroExp && s[e] != 0)
+          acc_add<double, C + 1>(acc[e], ldexp((double)s[e], Ei + Fj[e] + 2 - 7 * (g + 1)));
+      }
     }
     if (debug_g > 0) continue;
-    renorm<double, C + 1>(acc);
 #pragma unroll
-    for (int q = 0; q < C; ++q) Cout[q * c_stride + i + (int64_t)j * ldc] = acc[q];
+    for (int e = 0; e < 4; ++e) {
+      if (j0 + e >= n) continue;
+      renorm<double, C + 1>(acc[e]);
+#pragma unroll
+      for (int c = 0; c < C; ++c) Cout[c * c_stride + i + (int64_t)(j0 + e) * ldc] = acc[e][c];
+    }
   }
 }
 
@@ -197,34 +265,53 @@ int int8_kblocks_per_chunk(int D) {
   return (int)(blocks > kKStepBlocks8 ? blocks : kKStepBlocks8);
 }
 
+// Tile configuration for an m x n product (cfg > 0 forces one): the 256 x 256
+// tiles when they still give at least one workgroup per CU, else 128 x 128.
+int int8_tile_config(int64_t m, int64_t n, int cfg) {
+  if (cfg >= 1 && cfg <= 3) return cfg;
+  const int64_t big = ceil_div(m, 256) * ceil_div(n, 256);
+  return big >= 256 ? 3 : 1;
+}
+
 template <int C>
 hipError_t launch_gemm_int8(const void *Apk, const void *Bpk, const int *EA, const int *EB, int32_t *Sws, int64_t mbp,
                             int64_t nbp, int64_t kbp, int m, int n, int D, double *Cout, int ldc, int64_t c_stride,
-                            int debug_g, int64_t *Sdbg, int lddbg, hipStream_t st) {
-  const int64_t tiles = (mbp / kTileBlocks8) * (nbp / kTileBlocks8);
-  if (tiles <= 0 || m <= 0 || n <= 0) return hipSuccess;
+                            int debug_g, int64_t *Sdbg, int lddbg, int cfg, hipStream_t st) {
+  if (mbp <= 0 || nbp <= 0 || m <= 0 || n <= 0) return hipSuccess;
   const int kbc = int8_kblocks_per_chunk(D);
   const int nchunks = (int)ceil_div(kbp, kbc);
-  const int64_t plane = (int64_t)m * n;
-  hipLaunchKernelGGL(k_gemm_int8, dim3((unsigned)tiles, (unsigned)nchunks), dim3(kThreads), 0, st,
-                     static_cast<const int8_t *>(Apk), static_cast<const int8_t *>(Bpk), mbp, nbp, kbp, kbc, D, m, n,
-                     Sws, plane);
+  const int64_t plane = mbp * nbp * 1024;  // blocked, padded diagonal-sum plane
+  const auto *a = static_cast<const int8_t *>(Apk);
+  const auto *b = static_cast<const int8_t *>(Bpk);
+  const int use = int8_tile_config(m, n, cfg);
+  if (use == 2) {
+    const int64_t tiles = (mbp / 8) * (nbp / 8);
+    hipLaunchKernelGGL((k_gemm_int8<2>), dim3((unsigned)tiles, (unsigned)nchunks), dim3(256), 0, st, a, b, mbp, nbp,
+                       kbp, kbc, D, m, n, Sws, plane);
+  } else if (use == 3) {
+    const int64_t tiles = (mbp / 8) * (nbp / 8);
+    hipLaunchKernelGGL((k_gemm_int8<3>), dim3((unsigned)tiles, (unsigned)nchunks), dim3(512), 0, st, a, b, mbp, nbp,
+                       kbp, kbc, D, m, n, Sws, plane);
+  } else {
+    const int64_t tiles = (mbp / 4) * (nbp / 4);
+    hipLaunchKernelGGL((k_gemm_int8<1>), dim3((unsigned)tiles, (unsigned)nchunks), dim3(256), 0, st, a, b, mbp, nbp,
+                       kbp, kbc, D, m, n, Sws, plane);
+  }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  const int64_t blocks = ceil_div(plane, 256);
+  const int64_t blocks = ceil_div(mbp * nbp * 256, 256);
   hipLaunchKernelGGL((k_int8_combine<C>), dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, st, Sws,
-                     plane, nchunks, D, EA, EB, m, n, Cout, ldc, c_stride, debug_g, Sdbg, lddbg);
+                     plane, nchunks, D, EA, EB, mbp, nbp, m, n, Cout, ldc, c_stride, debug_g, Sdbg, lddbg);
   return hipGetLastError();
 }
 
-template hipError_t launch_gemm_int8<2>(const void *, const void *, const int *, const int *, int32_t *, int64_t,
-                                        int64_t, int64_t, int, int, int, double *, int, int64_t, int, int64_t *, int,
-                                        hipStream_t);
-template hipError_t launch_gemm_int8<3>(const void *, const void *, const int *, const int *, int32_t *, int64_t,
-                                        int64_t, int64_t, int, int, int, double *, int, int64_t, int, int64_t *, int,
-                                        hipStream_t);
-template hipError_t launch_gemm_int8<4>(const void *, const void *, const int *, const int *, int32_t *, int64_t,
-                                        int64_t, int64_t, int, int, int, double *, int, int64_t, int, int64_t *, int,
-                                        hipStream_t);
+#define MP_INT8_INST(C)                                                                                     \
+  template hipError_t launch_gemm_int8<C>(const void *, const void *, const int *, const int *, int32_t *, int64_t, \
+                                          int64_t, int64_t, int, int, int, double *, int, int64_t, int, int64_t *, \
+                                          int, int, hipStream_t);
+MP_INT8_INST(2)
+MP_INT8_INST(3)
+MP_INT8_INST(4)
+#undef MP_INT8_INST
 
 }  // namespace mp

@@ -74,10 +74,12 @@ hipError_t launch_gemm_plain(const void *Apk, const void *Bpk, int64_t mbp, int6
 // INT8 form GEMM: diagonal sums S_g into Sws (D x nchunks planes of m x n
 // int32), then their exact combination into C.  debug_g > 0 writes S_g for
 // that g as int64 into Sdbg instead of forming C.
+// cfg: INT8 tile configuration (0 automatic; 1: 128 x 128 with 4 wavefronts,
+// 2: 256 x 256 with 4, 3: 256 x 256 with 8).
 template <int C>
 hipError_t launch_gemm_int8(const void *Apk, const void *Bpk, const int *EA, const int *EB, int32_t *Sws, int64_t mbp,
                             int64_t nbp, int64_t kbp, int m, int n, int D, double *Cout, int ldc, int64_t c_stride,
-                            int debug_g, int64_t *Sdbg, int lddbg, hipStream_t st);
+                            int debug_g, int64_t *Sdbg, int lddbg, int cfg, hipStream_t st);
 // k blocks (32 wide) per chunk of the INT8 GEMM for D digit slices.
 int int8_kblocks_per_chunk(int D);
 

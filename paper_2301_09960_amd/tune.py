@@ -15,7 +15,7 @@ import json
 
 import numpy as np
 
-from . import COMPONENTS, gemm, profile_enable, profile_read, set_tile_layout
+from . import COMPONENTS, gemm, profile_enable, profile_read, set_int8_tile, set_tile_layout
 
 LAYOUTS = (1, 2, 3)
 
@@ -43,14 +43,45 @@ def time_layouts(fmt: str, n: int, reps: int = 3, E: int = 16):
     return out
 
 
+def time_int8_tiles(fmt: str, n: int, reps: int = 3, E: int = 16):
+    """INT8-form tile configurations 1..3 (GEMM + combine milliseconds)."""
+    import torch
+
+    from workload import gen_pair
+    A, B = gen_pair(fmt, n, n, n, E=E, seed=77)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    C = torch.empty((COMPONENTS[fmt], n, n), dtype=dA.dtype, device="cuda")
+    out = {}
+    for cfg in (1, 2, 3):
+        set_int8_tile(cfg)
+        gemm(fmt, dA, dB, C, mode="int8")
+        torch.cuda.synchronize()
+        profile_enable(True)
+        for _ in range(reps):
+            gemm(fmt, dA, dB, C, mode="int8")
+        torch.cuda.synchronize()
+        profile_enable(False)
+        _, g = profile_read()
+        out[cfg] = float(np.median(g))
+    set_int8_tile(0)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--formats", default="dd,td,qd,ts")
     ap.add_argument("--n", default="4096", help="comma-separated sizes; the largest decides")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", default="")
+    ap.add_argument("--int8", action="store_true", help="time the INT8-form tile configurations instead")
     args = ap.parse_args()
     sizes = [int(x) for x in args.n.split(",")]
+    if args.int8:
+        for fmt in args.formats.split(","):
+            for n in sizes:
+                print(json.dumps({"fmt": fmt, "n": n, "int8_gemm_and_combine_ms": time_int8_tiles(fmt, n, args.reps)}),
+                      flush=True)
+        return
     table = {}
     best = {}
     for fmt in args.formats.split(","):

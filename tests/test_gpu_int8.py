@@ -120,3 +120,26 @@ def test_int8_full_size_sampled(mp, orc, fmt, rows):
     ok, worst = orc.bound_report(diff, absab, T_BITS[fmt])
     say(f"  worst log2 ratio {worst:.1f}")
     assert ok
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_int8_every_tile_config(mp, orc, cfg):
+    """Each INT8 tile configuration gives the exact diagonal sums and a C within
+    the bound (sizes span several 256-wide tiles with ragged edges)."""
+    m, n, k = 300, 270, 200
+    A, B = W.gen_pair("td", m, n, k, E=16, seed=61)
+    D = mp.num_slices("td", "int8", k)
+    da, _ = orc.split_int8(A, D, "rows")
+    db, _ = orc.split_int8(B, D, "cols")
+    S = orc.int8_diag_sums(da, db)
+    say(f"int8 tile config {cfg}")
+    mp.set_int8_tile(cfg)
+    try:
+        C = host(mp.gemm("td", dev(A), dev(B), mode="int8"))
+        got = host(mp.debug_products("td", dev(A), dev(B), D // 2, 0, D, mode="int8"))
+    finally:
+        mp.set_int8_tile(0)
+    assert np.array_equal(got, S[D // 2 - 1])
+    diff, absab, _ = orc.exact_check(A, B, C)
+    ok, worst = orc.bound_report(diff, absab, 150)
+    assert ok, worst
