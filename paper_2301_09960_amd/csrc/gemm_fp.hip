@@ -88,8 +88,13 @@ template <> struct Layout<3> { static constexpr int WM = 4, WN = 4; };
 // Wavefronts per SIMD the register allocation must allow.  Layout 1 with
 // three or four components is left free: forcing two wavefronts into 256
 // registers made those schedules far slower than one wavefront that keeps its
-// matrix-core accumulators in AGPRs.
-constexpr int waves_of(int layout, int C) { return layout == 3 ? 4 : layout == 2 ? 2 : (C <= 2 ? 2 : 1); }
+// matrix-core accumulators in AGPRs.  Binary64 layout 2 is capped at 128
+// registers so that two workgroups of eight wavefronts share a CU (their
+// two-stage rings take 64 KiB of LDS each): while one waits on its loads the
+// other keeps the matrix cores busy.
+constexpr int waves_of(int layout, int C, int bytes) {
+  return layout == 3 ? 4 : layout == 2 ? (bytes == 8 ? 4 : 2) : (C <= 2 ? 2 : 1);
+}
 
 // 16 bytes per lane from global memory straight into LDS: lane l's bytes land
 // at lds_dst + 16 l (lds_dst is the same for the whole wavefront).
@@ -114,10 +119,38 @@ template <typename T>
 constexpr int stage_elems() {
   return 2 * panel_elems<T>();  // A panel, then B panel
 }
-constexpr int kStages = 4;
+// Ring depth: binary64 stages take 32 KiB, so two of them leave room for a
+// second workgroup per CU (which hides latency better than a deeper ring);
+// binary32 stages take 16 KiB and four of them still fit twice.
+template <typename T>
+constexpr int stages_of() {
+  return sizeof(T) == 8 ? 2 : 4;
+}
+
+// Waits until this wavefront's loads of the step about to be computed have
+// landed: with an NS-stage ring, min(NS - 2, later) later steps (kL loads
+// each) may stay in flight.
+template <int NS, int kL>
+__device__ __forceinline__ void wait_step(int64_t later) {
+  if constexpr (NS >= 4) {
+    if (later >= 2)
+      wait_vm<2 * kL>();
+    else if (later == 1)
+      wait_vm<kL>();
+    else
+      wait_vm<0>();
+  } else if constexpr (NS == 3) {
+    if (later >= 1)
+      wait_vm<kL>();
+    else
+      wait_vm<0>();
+  } else {
+    wait_vm<0>();
+  }
+}
 
 // All slice products of one 64 x 64 tile (tm, tn) of one product, folded into
-// C.  `lds` is the workgroup's ring of kStages staging buffers of
+// C.  `lds` is the workgroup's ring of stages_of<T>() staging buffers of
 // stage_elems<T>() elements each.
 template <typename T, int C, int LAYOUT>
 __device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const T *__restrict__ Bpk, int64_t mbp, int64_t nbp,
@@ -135,6 +168,8 @@ __device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const
   constexpr int kInstPerSeg = kSegElems / kInstElems;
   constexpr int kInstPerPanel = kTileBlocks * kInstPerSeg;
   constexpr int kL = 2 * kInstPerPanel / NW;                 // instructions per wavefront per step
+  constexpr int kStages = stages_of<T>();
+  static_assert(kStages >= 2 && kStages <= 4, "wait chain covers rings of 2 to 4 stages");
   static_assert(2 * kInstPerPanel % NW == 0, "staging split");
 
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
@@ -191,14 +226,7 @@ __device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const
 
   int cks = 0;  // k step of the pair being computed
   for (int64_t step = 0; step < total; ++step) {
-    // later steps already in flight: min(kStages - 2, total - 1 - step)
-    const int64_t later = total - 1 - step;
-    if (later >= 2)
-      wait_vm<2 * kL>();
-    else if (later == 1)
-      wait_vm<kL>();
-    else
-      wait_vm<0>();
+    wait_step<kStages, kL>(total - 1 - step);
     __builtin_amdgcn_s_barrier();
     if (issued < total) issue();  // into the slot computed in the previous step
 
@@ -284,10 +312,10 @@ __device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const
 }
 
 template <typename T, int C, int LAYOUT>
-__global__ __launch_bounds__(64 * Layout<LAYOUT>::WM * Layout<LAYOUT>::WN, waves_of(LAYOUT, C)) void k_gemm_plain(
+__global__ __launch_bounds__(64 * Layout<LAYOUT>::WM * Layout<LAYOUT>::WN, waves_of(LAYOUT, C, (int)sizeof(T))) void k_gemm_plain(
     const T *__restrict__ Apk, const T *__restrict__ Bpk, int64_t mbp, int64_t nbp, int64_t kbp, int m, int n, int D,
     T *__restrict__ Cout, int ldc, int64_t c_stride, int single_pair, double *__restrict__ Cdbg, int lddbg) {
-  __shared__ __attribute__((aligned(16))) T lds[kStages][stage_elems<T>()];
+  __shared__ __attribute__((aligned(16))) T lds[stages_of<T>()][stage_elems<T>()];
   int tm, tn;
   tile_coords(blockIdx.x, gridDim.x, (int)(mbp / kTileBlocks), (int)(nbp / kTileBlocks), tm, tn);
   gemm_plain_tile<T, C, LAYOUT>(Apk, Bpk, mbp, nbp, kbp, m, n, D, Cout, ldc, c_stride, single_pair, Cdbg, lddbg, tm,
@@ -298,9 +326,9 @@ __global__ __launch_bounds__(64 * Layout<LAYOUT>::WM * Layout<LAYOUT>::WN, waves
 // from a shared counter until the list is exhausted (items are ordered by
 // decreasing work, so the long tiles start first).
 template <typename T, int C, int LAYOUT>
-__global__ __launch_bounds__(64 * Layout<LAYOUT>::WM * Layout<LAYOUT>::WN, waves_of(LAYOUT, C)) void k_gemm_plain_batched(
+__global__ __launch_bounds__(64 * Layout<LAYOUT>::WM * Layout<LAYOUT>::WN, waves_of(LAYOUT, C, (int)sizeof(T))) void k_gemm_plain_batched(
     const PlainGemmDesc *__restrict__ descs, const int2 *__restrict__ items, int nitems, int *__restrict__ counter) {
-  __shared__ __attribute__((aligned(16))) T lds[kStages][stage_elems<T>()];
+  __shared__ __attribute__((aligned(16))) T lds[stages_of<T>()][stage_elems<T>()];
   __shared__ int next;
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(counter, 1);
