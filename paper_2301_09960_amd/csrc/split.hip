@@ -309,54 +309,70 @@ template hipError_t launch_split_plain<float, 3>(const SplitOperand<float> &, co
 // extraction step of Algorithm 1 on the fixed grid u_s = 2^(E - 6 - 7 (s - 1)):
 // d_s = RN(lead / u_s), lead := lead - d_s u_s (exact), renormalize.  All D
 // digits of an element come from one read of its components.  |d_s| <= 64.
+//
+// One workgroup per 32 x 32 block of one operand.  Thread T owns bytes
+// 4T .. 4T+3 of the block in every digit plane: with l = T / 4 and q = T % 4
+// these are row/column l % 32 of the block and k = 16 (l / 32) + 4 q + j,
+// j = 0..3 (the packed INT8 layout), so each digit plane of the block is
+// written by one coalesced 4-byte store per thread.
 // ---------------------------------------------------------------------------
 namespace {
 
 template <int C, int ORIENT>
-__device__ void int8_body(const SplitOperand<double> &op, int idx, int D) {
-  const int nvec_cover = (int)(op.nbp * kBlk8), len_cover = (int)(op.kbp * kKBlk8);
-  const TileCoord tc = tile_of<ORIENT>(idx, nvec_cover, len_cover);
+__device__ void int8_block(const SplitOperand<double> &op, int64_t blk, int D) {
+  // A (rows, contiguous along the row index): walk row blocks fastest;
+  // B (columns, contiguous along k): walk k blocks fastest.
+  const int64_t vb = ORIENT == 0 ? blk % op.nbp : blk / op.kbp;
+  const int64_t kb = ORIENT == 0 ? blk / op.nbp : blk % op.kbp;
+  const int T = threadIdx.x, l = T >> 2, q = T & 3;
+  const int v = (int)(vb * kBlk8) + (l & 31);
+  const int p0 = (int)(kb * kKBlk8) + 16 * (l >> 5) + 4 * q;
   const unsigned long long *mu = static_cast<const unsigned long long *>(op.mu);
-  int8_t *packed = static_cast<int8_t *>(op.packed);
-#pragma unroll 1
-  for (int t = 0; t < kPerThread; ++t) {
-    int v, p;
-    elem_of<ORIENT>(tc, t, v, p);
-    if (v >= nvec_cover || p >= len_cover) continue;
-    int E = kZeroExp;
-    if (v < op.nvec && mu[v] != 0) {
-      int ex;
-      (void)frexp(from_bits(mu[v], 0.0), &ex);
-      E = ex;
-    }
-    double R[C];
-    const bool live = v < op.nvec && p < op.len && E != kZeroExp;
+
+  int E = kZeroExp;
+  if (v < op.nvec && mu[v] != 0) {
+    int ex;
+    (void)frexp(from_bits(mu[v], 0.0), &ex);
+    E = ex;
+  }
+  double R[4][C];
+  bool live[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int p = p0 + j;
+    live[j] = v < op.nvec && p < op.len && E != kZeroExp;
 #pragma unroll
     for (int r = 0; r < C; ++r)
-      R[r] = live ? op.X[r * op.comp_stride + (int64_t)v * op.sv + (int64_t)p * op.sp] : 0.0;
-#pragma unroll 1
-    for (int s = 1; s <= D; ++s) {
-      int8_t d = 0;
-      if (live) {
-        const int ue = E - 6 - 7 * (s - 1);
-        const double q = rint(ldexp(R[0], -ue));
-        d = (int8_t)(int)q;
-        R[0] = R[0] - ldexp(q, ue);  // exact
-        renorm<double, C>(R);
-      }
-      packed[packed_index8(s - 1, v, p, op.nbp, op.kbp)] = d;
-    }
-    if (p == 0 && v < op.nvec) op.exps[v] = E;
+      R[j][r] = live[j] ? op.X[r * op.comp_stride + (int64_t)v * op.sv + (int64_t)p * op.sp] : 0.0;
   }
+  int8_t *dst = static_cast<int8_t *>(op.packed) + (vb * op.kbp + kb) * 1024 + 4 * T;
+  const int64_t plane = op.nbp * op.kbp * 1024;
+#pragma unroll 1
+  for (int s = 1; s <= D; ++s) {
+    const int ue = E - 6 - 7 * (s - 1);
+    unsigned int word = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (live[j]) {
+        const double qd = rint(ldexp(R[j][0], -ue));
+        word |= (unsigned int)(uint8_t)(int8_t)(int)qd << (8 * j);
+        R[j][0] = R[j][0] - ldexp(qd, ue);  // exact
+        renorm<double, C>(R[j]);
+      }
+    }
+    *reinterpret_cast<unsigned int *>(dst + (int64_t)(s - 1) * plane) = word;
+  }
+  if (p0 == 0 && v < op.nvec) op.exps[v] = E;
 }
 
 template <int C>
-__global__ __launch_bounds__(kThreads) void k_split_int8(SplitOperand<double> a, SplitOperand<double> b, int blocks_a,
-                                                         int D) {
-  if ((int)blockIdx.x < blocks_a)
-    int8_body<C, 0>(a, blockIdx.x, D);
+__global__ __launch_bounds__(kThreads) void k_split_int8(SplitOperand<double> a, SplitOperand<double> b,
+                                                         int64_t blocks_a, int D) {
+  const int64_t blk = (int64_t)blockIdx.x;
+  if (blk < blocks_a)
+    int8_block<C, 0>(a, blk, D);
   else
-    int8_body<C, 1>(b, blockIdx.x - blocks_a, D);
+    int8_block<C, 1>(b, blk - blocks_a, D);
 }
 
 }  // namespace
@@ -372,10 +388,13 @@ hipError_t launch_split_int8(const SplitOperand<double> &a, const SplitOperand<d
     hipLaunchKernelGGL((k_split_max0<double, C>), dim3(ba0 + bb0), dim3(kThreads), 0, st, a, b, ba0);
     if ((err = hipGetLastError()) != hipSuccess) return err;
   }
-  const int ba = a.nvec > 0 ? tiles(a.nbp * kBlk8, a.kbp * kKBlk8) : 0;
-  const int bb = b.nvec > 0 ? tiles(b.nbp * kBlk8, b.kbp * kKBlk8) : 0;
+  // one workgroup of kThreads (= 1024 / 4) threads per 32 x 32 block
+  static_assert(kThreads * 4 == kBlk8 * kKBlk8, "thread per 4 bytes of a block");
+  const int64_t ba = a.nvec > 0 ? a.nbp * a.kbp : 0;
+  const int64_t bb = b.nvec > 0 ? b.nbp * b.kbp : 0;
   if (ba + bb > 0) {
-    hipLaunchKernelGGL((k_split_int8<C>), dim3(ba + bb), dim3(kThreads), 0, st, a, b, ba, D);
+    if (ba + bb > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_split_int8<C>), dim3((unsigned)(ba + bb)), dim3(kThreads), 0, st, a, b, ba, D);
     if ((err = hipGetLastError()) != hipSuccess) return err;
   }
   return hipSuccess;
