@@ -204,9 +204,12 @@ def main():
         slice_flops = D * (D + 1) / 2 * 2.0 * n ** 3
         peak = FP32_MFMA_PEAK_TFLOPS if f == "ts" else FP64_MFMA_PEAK_TFLOPS
         g_avg = float(np.mean(gm))
+        c, w = W.FORMATS[f][0], (4 if f == "ts" else 8)
+        split_bytes = (c * w + D * w) * 2.0 * n * n  # read A and B once, write D slices of each
         stages[f] = {
             "D": D,
             "split_ms": round(float(np.mean(sp)), 3),
+            "split_gbs_algorithmic": round(split_bytes / (float(np.mean(sp)) * 1e-3) / 1e9, 1),
             "gemm_kernel_ms": round(g_avg, 3),
             "effective_gflops": round(2.0 * n ** 3 / ((float(np.mean(sp)) + g_avg) * 1e-3) / 1e9, 1),
             "slice_gemm_tflops": round(slice_flops / (g_avg * 1e-3) / 1e12, 2),
@@ -236,9 +239,11 @@ def main():
             call_ms = float(np.mean(isp[idx::len(fmts)])) + float(np.mean(igm[idx::len(fmts)]))
             gemm8 = float(np.mean(igm[idx::len(fmts)]))
             ops = D8 * (D8 + 1) / 2 * 2.0 * n ** 3
+            split8 = float(np.mean(isp[idx::len(fmts)]))
             int8[f] = {
                 "D": D8,
-                "split_ms": round(float(np.mean(isp[idx::len(fmts)])), 3),
+                "split_ms": round(split8, 3),
+                "split_gbs_algorithmic": round((W.FORMATS[f][0] * 8 + D8) * 2.0 * n * n / (split8 * 1e-3) / 1e9, 1),
                 "gemm_and_combine_ms": round(gemm8, 3),
                 "effective_gflops": round(2.0 * n ** 3 / (call_ms * 1e-3) / 1e9, 1),
                 "int8_tops": round(ops / (gemm8 * 1e-3) / 1e12, 1),

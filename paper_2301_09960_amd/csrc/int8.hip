@@ -11,8 +11,8 @@
 //
 // k_gemm_int8: one workgroup per tile of C (128 x 128 or 256 x 256) and k
 // chunk; each wavefront owns a grid of 32 x 32 blocks of
-// v_mfma_i32_32x32x32_i8.  Panels of A_s and B_t (64 k per step) move
-// global -> LDS by direct loads into a 4-stage ring, as in the
+// v_mfma_i32_32x32x32_i8.  Panels of A_s and B_t (64 or 128 k per step)
+// move global -> LDS by direct loads into a ring of 2 to 4 stages, as in the
 // floating-point kernel.  After the last pair of a diagonal the 32-bit tile is
 // written to the S_g plane in a blocked layout (16-byte stores per lane).
 //
@@ -54,16 +54,42 @@ __device__ __forceinline__ void wait_vm() {
   asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
+// Waits until this wavefront's loads of the step about to be computed have
+// landed: with an NS-stage ring, min(NS - 2, later) later steps (kL loads
+// each) may stay in flight.
+template <int NS, int kL>
+__device__ __forceinline__ void wait_step(int64_t later) {
+  static_assert(NS >= 2 && NS <= 4, "wait chain covers rings of 2 to 4 stages");
+  if constexpr (NS >= 4) {
+    if (later >= 2)
+      wait_vm<2 * kL>();
+    else if (later == 1)
+      wait_vm<kL>();
+    else
+      wait_vm<0>();
+  } else if constexpr (NS == 3) {
+    if (later >= 1)
+      wait_vm<kL>();
+    else
+      wait_vm<0>();
+  } else {
+    wait_vm<0>();
+  }
+}
+
 // Tile configurations (in 32 x 32 blocks): TB x TB tile of C, WM x WN
 // wavefronts, KSB 32-wide k blocks per pipeline step, NS LDS stages.
 //   config 1: 128 x 128 tile, 4 wavefronts of 64 x 64 (small products)
 //   config 2: 256 x 256 tile, 4 wavefronts of 128 x 128 (accumulators in AGPRs;
 //             LDS traffic per instruction halved)
-//   config 3: 256 x 256 tile, 8 wavefronts of 128 x 64
+//   config 3: 256 x 256 tile, 8 wavefronts of 128 x 64, k steps of 128 in a
+//             2-stage ring (half the barriers of 64-wide steps, and 64 KiB
+//             requested per step)
+// KSB divides kKStepBlocks8, the k padding unit of the INT8 slices.
 template <int CFG> struct Int8Cfg;
 template <> struct Int8Cfg<1> { static constexpr int TB = 4, WM = 2, WN = 2, KSB = 2, NS = 4; };
 template <> struct Int8Cfg<2> { static constexpr int TB = 8, WM = 2, WN = 2, KSB = 2, NS = 4; };
-template <> struct Int8Cfg<3> { static constexpr int TB = 8, WM = 2, WN = 4, KSB = 2, NS = 4; };
+template <> struct Int8Cfg<3> { static constexpr int TB = 8, WM = 2, WN = 4, KSB = 4, NS = 2; };
 
 template <int CFG>
 constexpr int int8_stage_bytes() {
@@ -87,6 +113,7 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
   constexpr int kInst = 2 * TB * KSB;  // 1 KiB wavefront instructions per step
   constexpr int kL = kInst / NW;
   static_assert(kInst % NW == 0, "staging split");
+  static_assert(kKStepBlocks8 % KSB == 0, "k steps tile the padded k");
 
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int wm = wave % WM, wn = wave / WM;
@@ -134,13 +161,7 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
 
   int cg = 1, cs = 1, cks = 0;  // compute cursor
   for (int64_t step = 0; step < total; ++step) {
-    const int64_t later = total - 1 - step;
-    if (later >= 2)
-      wait_vm<2 * kL>();
-    else if (later == 1)
-      wait_vm<kL>();
-    else
-      wait_vm<0>();
+    wait_step<NS, kL>(total - 1 - step);
     __builtin_amdgcn_s_barrier();
     if (issued < total) issue();
 

@@ -17,7 +17,8 @@
 // INT8 digit slices use 32 x 32 blocks for the 32x32x32 integer instruction:
 // lane l holds row/column index l % 32 and the 16 consecutive k values
 // 16 (l / 32) + t, t = 0..15, stored as 16 bytes at 16 l + t.  Rows/columns
-// are padded to 256 (the larger INT8 GEMM tile), k to its k step (64).
+// are padded to 256 (the larger INT8 GEMM tile), k to 128 (a multiple of every
+// INT8 k step).
 #pragma once
 
 #include <stdint.h>
@@ -29,7 +30,7 @@ constexpr int kKBlk = 16;     // k per block (floating-point slices)
 constexpr int kBlk8 = 32;     // rows/cols per block (INT8 slices)
 constexpr int kKBlk8 = 32;    // k per block (INT8 slices)
 constexpr int kTileBlocks8 = 8;   // INT8 padding unit: 8 blocks (the 256-row tile; 128 divides it)
-constexpr int kKStepBlocks8 = 2;  // INT8 GEMM k step = 2 k-blocks (64)
+constexpr int kKStepBlocks8 = 4;  // INT8 k padding unit: 4 k-blocks (128), a multiple of every k step
 constexpr int kTileBlocks = 4;  // GEMM tile = 4 x 4 blocks (64 x 64)
 constexpr int kKStepBlocks = 2; // GEMM k step = 2 k-blocks (32)
 

@@ -207,6 +207,25 @@ def test_full_size_sampled(mp, orc, fmt, rows):
     assert ok
 
 
+@pytest.mark.parametrize("fmt,n,E,rows", [
+    ("td", 4096, 16, [3, 3000]),
+    ("ts", 4096, 0, [100]),
+    ("dd", 2048, 0, [0, 2047]),
+    ("qd", 2048, 16, [777]),
+    ("td", 1024, 0, [512]),
+    ("qd", 1024, 0, [0, 1023]),
+])
+def test_square_grid_sampled(mp, orc, fmt, n, E, rows):
+    """The square products of the benchmark grid (n in {1024, 2048, 4096},
+    e ~ U{0..E} with E in {0, 16}): sampled rows of C against the exact product."""
+    A, B = W.gen_pair(fmt, n, n, n, E=E, seed=n + E)
+    say(f"grid {fmt} n={n} E={E} rows={rows}")
+    C = host(mp.gemm(fmt, dev(A), dev(B)))
+    ok, worst = _check_bound(orc, fmt, A, B, np.ascontiguousarray(C), rows=rows)
+    say(f"  D={mp.last_num_slices()} worst log2 ratio {worst:.1f} (bound -{T_BITS[fmt]})")
+    assert ok
+
+
 @pytest.mark.parametrize("layout", [1, 2, 3])
 @pytest.mark.parametrize("fmt", ["dd", "qd", "ts"])
 def test_every_tile_layout(mp, orc, fmt, layout):
