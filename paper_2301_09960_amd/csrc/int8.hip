@@ -98,8 +98,15 @@ constexpr int int8_stage_bytes() {
 
 // Diagonal sums S_g of one tile (tm, tn) and k chunk, as in the file comment:
 // operand panels (TB blocks x KSB k blocks of A_s and of B_t) move
-// global -> LDS by direct loads into a ring of NS stages issued NS - 1 steps
-// ahead; each step waits for its own loads and passes one barrier.
+// global -> LDS by direct loads into a ring of NS stages, NS - 1 steps ahead;
+// each step waits for its own loads and passes one barrier.
+//
+// Each wavefront moves kL 1 KiB pieces of one operand per step.  Their global
+// offsets from the step's panel base and their LDS offsets are fixed for the
+// whole tile, so a load costs one 64-bit add; and the loads of the next step
+// are spread evenly between this step's matrix-core instructions (one per
+// kEvery), which keeps the matrix cores fed where a burst of LDS-direct loads
+// would stall them.
 template <int CFG>
 __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, const int8_t *__restrict__ Bpk,
                                                int64_t mbp, int64_t nbp, int64_t kbp, int64_t kb0, int nks, int D,
@@ -112,30 +119,38 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
   constexpr int kPanel = TB * KSB * 1024;
   constexpr int kInst = 2 * TB * KSB;  // 1 KiB wavefront instructions per step
   constexpr int kL = kInst / NW;
+  constexpr int kMma = KSB * BI * BJ;  // matrix-core instructions per wavefront per step
+  constexpr int kEvery = kMma / kL;
   static_assert(kInst % NW == 0, "staging split");
+  static_assert((TB * KSB) % kL == 0, "a wavefront's loads of a step come from one operand");
+  static_assert(kMma % kL == 0, "one load per fixed number of matrix-core instructions");
   static_assert(kKStepBlocks8 % KSB == 0, "k steps tile the padded k");
 
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int wm = wave % WM, wn = wave / WM;
   const int64_t total = (int64_t)D * (D + 1) / 2 * nks;
 
+  // this wavefront's share of a step: operand op_w, pieces j = 0..kL-1
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  const int op_w = (wave_u * kL) / (TB * KSB);
+  uint32_t goff[kL];  // byte offset from the step's panel base (per lane; k <= 2^20 keeps it below 2^32)
+  int loff[kL];       // byte offset in the stage (uniform)
+#pragma unroll
+  for (int j = 0; j < kL; ++j) {
+    const int r = (wave_u * kL + j) % (TB * KSB);
+    const int blk = r / KSB, kb = r % KSB;
+    goff[j] = (uint32_t)(((int64_t)blk * kbp + kb) * 1024) + 16u * (uint32_t)lane;
+    loff[j] = op_w * kPanel + (blk * KSB + kb) * 1024;
+  }
+
   int lg = 1, ls = 1, lks = 0;  // load cursor: diagonal, pair within it, k step
   int64_t issued = 0;
-  auto issue = [&]() {
-    int8_t *dst = lds + (issued % NS) * int8_stage_bytes<CFG>();
-    const int lt = lg + 1 - ls;
-    const int64_t abase = ((int64_t)(ls - 1) * mbp + (int64_t)tm * TB) * kbp + kb0 + (int64_t)lks * KSB;
-    const int64_t bbase = ((int64_t)(lt - 1) * nbp + (int64_t)tn * TB) * kbp + kb0 + (int64_t)lks * KSB;
-#pragma unroll
-    for (int j = 0; j < kL; ++j) {
-      const int q = wave * kL + j;
-      const int op = q / (TB * KSB), r = q % (TB * KSB);
-      const int blk = r / KSB, kb = r % KSB;
-      const int8_t *src = (op == 0 ? Apk + (abase + (int64_t)blk * kbp + kb) * 1024
-                                   : Bpk + (bbase + (int64_t)blk * kbp + kb) * 1024) +
-                          16 * lane;
-      load_lds16(src, dst + op * kPanel + (blk * KSB + kb) * 1024);
-    }
+  // panel base of the step at the load cursor (A_ls or B_(lg+1-ls)), and its ring slot
+  auto panel_base = [&]() -> const int8_t * {
+    return op_w == 0 ? Apk + (((int64_t)(ls - 1) * mbp + (int64_t)tm * TB) * kbp + kb0 + (int64_t)lks * KSB) * 1024
+                     : Bpk + (((int64_t)(lg - ls) * nbp + (int64_t)tn * TB) * kbp + kb0 + (int64_t)lks * KSB) * 1024;
+  };
+  auto advance = [&]() {
     ++issued;
     if (++lks == nks) {
       lks = 0;
@@ -156,14 +171,23 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
 
   wait_vm<0>();
 #pragma unroll
-  for (int s = 0; s < NS - 1; ++s)
-    if (issued < total) issue();
+  for (int s0 = 0; s0 < NS - 1; ++s0)
+    if (issued < total) {
+      const int8_t *src = panel_base();
+      int8_t *dst = lds + (issued % NS) * int8_stage_bytes<CFG>();
+#pragma unroll
+      for (int j = 0; j < kL; ++j) load_lds16(src + goff[j], dst + loff[j]);
+      advance();
+    }
 
   int cg = 1, cs = 1, cks = 0;  // compute cursor
   for (int64_t step = 0; step < total; ++step) {
     wait_step<NS, kL>(total - 1 - step);
     __builtin_amdgcn_s_barrier();
-    if (issued < total) issue();
+    // the step NS - 1 ahead goes into the slot computed in the previous step
+    const bool more = issued < total;
+    const int8_t *nsrc = more ? panel_base() : Apk;
+    int8_t *ndst = lds + (issued % NS) * int8_stage_bytes<CFG>();
 
     const int8_t *stage = lds + (step % NS) * int8_stage_bytes<CFG>();
 #pragma unroll
@@ -178,9 +202,14 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
 #pragma unroll
       for (int y = 0; y < BJ; ++y)
 #pragma unroll
-        for (int x = 0; x < BI; ++x)
+        for (int x = 0; x < BI; ++x) {
+          const int mma = (kb * BJ + y) * BI + x;
+          if (mma % kEvery == 0 && more) load_lds16(nsrc + goff[mma / kEvery], ndst + loff[mma / kEvery]);
           acc[y][x] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fb[y], fa[x], acc[y][x], 0, 0, 0);
+          __builtin_amdgcn_sched_barrier(0);  // keep the loads where they were placed
+        }
     }
+    if (more) advance();
     if (++cks == nks) {
       cks = 0;
       if (++cs > cg) {  // diagonal cg complete: write its exact partial sum (blocked layout)
