@@ -179,23 +179,38 @@ __device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const
   const int npairs = single_pair >= 0 ? 1 : D * (D + 1) / 2;
   const int64_t total = (int64_t)npairs * nks;
 
+  // this wavefront's share of a step: operand op_w and kL consecutive 1 KiB
+  // pieces of its panel, starting at piece r0.  Piece j sits at a fixed
+  // offset from the step's panel base: g0 (per lane) plus a uniform term, so a
+  // load costs one 64-bit add.
+  static_assert(kInstPerPanel % kL == 0, "a wavefront's loads of a step come from one operand");
+  constexpr bool kOneSeg = kL <= kInstPerSeg;
+  static_assert(kOneSeg ? kInstPerSeg % kL == 0 : kL % kInstPerSeg == 0, "pieces tile the segments");
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  const int op_w = (wave_u * kL) / kInstPerPanel;
+  const int r0 = (wave_u * kL) % kInstPerPanel;
+  const int sg0 = r0 / kInstPerSeg, part0 = r0 % kInstPerSeg;
+  const int64_t seg_bytes = kbp * 256 * (int64_t)sizeof(T);  // one row block to the next (k <= 2^20: < 2^32 / 4)
+  const uint32_t g0 = (uint32_t)(sg0 * seg_bytes + part0 * 1024) + 16u * (uint32_t)lane;
+  const int l0 = op_w * kPanelElems + sg0 * kSegElems + part0 * kInstElems;
+  auto goff = [&](int j) -> int64_t {
+    return kOneSeg ? (int64_t)j * 1024 : (int64_t)(j / kInstPerSeg) * seg_bytes + (j % kInstPerSeg) * 1024;
+  };
+  auto loff = [&](int j) -> int {
+    return kOneSeg ? j * kInstElems : (j / kInstPerSeg) * kSegElems + (j % kInstPerSeg) * kInstElems;
+  };
+
   int la = single_pair >= 0 ? single_pair / D : 0, lb = single_pair >= 0 ? single_pair % D : 0, lks = 0;
   int64_t issued = 0;
-
-  // issue the loads of the step at the load cursor into its ring slot
-  auto issue = [&]() {
-    T *dst = lds + (issued % kStages) * stage_elems<T>();
-    const int64_t abase = ((int64_t)la * mbp + tm * kTileBlocks) * kbp + (int64_t)lks * kKStepBlocks;
-    const int64_t bbase = ((int64_t)lb * nbp + tn * kTileBlocks) * kbp + (int64_t)lks * kKStepBlocks;
-#pragma unroll
-    for (int j = 0; j < kL; ++j) {
-      const int q = wave * kL + j;  // instruction index within the step
-      const int op = q / kInstPerPanel, r = q % kInstPerPanel;
-      const int sg = r / kInstPerSeg, part = r % kInstPerSeg;
-      const T *src = (op == 0 ? Apk + (abase + (int64_t)sg * kbp) * 256 : Bpk + (bbase + (int64_t)sg * kbp) * 256) +
-                     part * kInstElems + lane * (16 / (int)sizeof(T));
-      load_lds16(src, dst + op * kPanelElems + sg * kSegElems + part * kInstElems);
-    }
+  // panel base (bytes, uniform) of the step at the load cursor: A_la or B_lb
+  auto panel_base = [&]() -> const char * {
+    return op_w == 0
+               ? reinterpret_cast<const char *>(Apk + (((int64_t)la * mbp + tm * kTileBlocks) * kbp +
+                                                       (int64_t)lks * kKStepBlocks) * 256)
+               : reinterpret_cast<const char *>(Bpk + (((int64_t)lb * nbp + tn * kTileBlocks) * kbp +
+                                                       (int64_t)lks * kKStepBlocks) * 256);
+  };
+  auto advance = [&]() {
     ++issued;
     if (++lks == nks) {
       lks = 0;
@@ -221,14 +236,30 @@ __device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const
 
   wait_vm<0>();  // nothing older than this tile's loads stays in flight
 #pragma unroll
-  for (int s = 0; s < kStages - 1; ++s)
-    if (issued < total) issue();
+  for (int s0 = 0; s0 < kStages - 1; ++s0)
+    if (issued < total) {
+      const char *src = panel_base();
+      T *dst = lds + (issued % kStages) * stage_elems<T>();
+#pragma unroll
+      for (int j = 0; j < kL; ++j) load_lds16(src + goff(j) + g0, dst + l0 + loff(j));
+      advance();
+    }
+
+  // matrix-core instructions per wavefront per step, and one load of the step
+  // kStages - 1 ahead after every kEvery of them (spread loads keep the
+  // matrix cores fed where a burst of LDS-direct loads would stall them)
+  constexpr int kMma = kKStepBlocks * 4 * BI * BJ;
+  static_assert(kMma % kL == 0, "one load per fixed number of matrix-core instructions");
+  constexpr int kEvery = kMma / kL;
 
   int cks = 0;  // k step of the pair being computed
   for (int64_t step = 0; step < total; ++step) {
     wait_step<kStages, kL>(total - 1 - step);
     __builtin_amdgcn_s_barrier();
-    if (issued < total) issue();  // into the slot computed in the previous step
+    // the step kStages - 1 ahead goes into the slot computed in the previous step
+    const bool more = issued < total;
+    const char *nsrc = more ? panel_base() : reinterpret_cast<const char *>(Apk);
+    T *ndst = lds + (issued % kStages) * stage_elems<T>();
 
     const T *stage = lds + (step % kStages) * stage_elems<T>();
 #pragma unroll
@@ -271,8 +302,15 @@ __device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const
 #pragma unroll
         for (int y = 0; y < BJ; ++y)
 #pragma unroll
-          for (int x = 0; x < BI; ++x) acc[y][x] = M::run(fb[y][q], fa[x][q], acc[y][x]);
+          for (int x = 0; x < BI; ++x) {
+            const int mma = ((kb * 4 + q) * BJ + y) * BI + x;
+            if (mma % kEvery == 0 && more)
+              load_lds16(nsrc + goff(mma / kEvery) + g0, ndst + l0 + loff(mma / kEvery));
+            acc[y][x] = M::run(fb[y][q], fa[x][q], acc[y][x]);
+            __builtin_amdgcn_sched_barrier(0);  // keep the loads where they were placed
+          }
     }
+    if (more) advance();
 
     if (++cks == nks) {  // the pair's product is complete and exact: fold it in
       cks = 0;
