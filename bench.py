@@ -137,11 +137,15 @@ def run_batched(mp, torch, pool, fmt, count=512, seed=31):
     _, gms = mp.profile_read()
     flops = float(np.sum(2.0 * m * n * k))
     gpu_ms = float(np.mean(gms))
+    Ds = np.array([mp.num_slices(fmt, "float", int(kk)) for kk in k], dtype=np.float64)
+    slice_flops = float(np.sum(Ds * (Ds + 1) / 2 * 2.0 * m * n * k))
     return {
         "products": count,
         "sum_2mnk": flops,
         "launch_ms": round(gpu_ms, 3),
         "effective_gflops": round(flops / (gpu_ms * 1e-3) / 1e9, 1),
+        "slice_gemm_tflops": round(slice_flops / (gpu_ms * 1e-3) / 1e12, 2),
+        "mfma_frac": round(slice_flops / (gpu_ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4),
         "wall_ms_per_batch": round((t1 - t0) * 1e3 / reps, 3),
         "max_slices": mp.last_num_slices(),
     }

@@ -102,7 +102,7 @@ int thread_mode(int fmt) { return g_opt.mode[fmt]; }
 // compiled-in defaults (measured), replaced by the file named in the
 // environment variable MPGEMM_TUNE_FILE (lines "<fmt> <layout>", as written
 // by paper_2301_09960_amd.tune), replaced per thread by mpgemm_set_tile_layout.
-int g_layout_default[kNumFmt] = {2, 2, 2, 2};  // measured best at n = 4096 for every format
+int g_layout_default[kNumFmt] = {1, 2, 2, 2};  // measured at n = 1024 and 4096 (DD, TD, QD, TS)
 std::once_flag g_tune_once;
 
 void load_tune_file() {

@@ -264,51 +264,51 @@ __device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const
     const T *stage = lds + (step % kStages) * stage_elems<T>();
 #pragma unroll
     for (int kb = 0; kb < kKStepBlocks; ++kb) {
-      T fa[BI][4], fb[BJ][4];
+      // binary64 fragments arrive in two halves (k substeps q = 0,1 and 2,3),
+      // each loaded just before its matrix-core instructions; binary32 in one
+      constexpr int kH = sizeof(T) == 8 ? 2 : 1, kQ = 4 / kH;
 #pragma unroll
-      for (int x = 0; x < BI; ++x) {
-        const T *pa = stage + ((wm * BI + x) * kKStepBlocks + kb) * 256;
-        if constexpr (sizeof(T) == 8) {
+      for (int h = 0; h < kH; ++h) {
+        T fa[BI][kQ], fb[BJ][kQ];
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
+        for (int x = 0; x < BI; ++x) {
+          const T *pa = stage + ((wm * BI + x) * kKStepBlocks + kb) * 256;
+          if constexpr (sizeof(T) == 8) {
             const d2 va = *reinterpret_cast<const d2 *>(pa + h * 128 + 2 * lane);
-            fa[x][2 * h] = va[0];
-            fa[x][2 * h + 1] = va[1];
+            fa[x][0] = va[0];
+            fa[x][1] = va[1];
+          } else {
+            const f4 va = *reinterpret_cast<const f4 *>(pa + 4 * lane);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) fa[x][q] = va[q];
           }
-        } else {
-          const f4 va = *reinterpret_cast<const f4 *>(pa + 4 * lane);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) fa[x][q] = va[q];
         }
-      }
 #pragma unroll
-      for (int y = 0; y < BJ; ++y) {
-        const T *pb = stage + kPanelElems + ((wn * BJ + y) * kKStepBlocks + kb) * 256;
-        if constexpr (sizeof(T) == 8) {
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
+        for (int y = 0; y < BJ; ++y) {
+          const T *pb = stage + kPanelElems + ((wn * BJ + y) * kKStepBlocks + kb) * 256;
+          if constexpr (sizeof(T) == 8) {
             const d2 vb = *reinterpret_cast<const d2 *>(pb + h * 128 + 2 * lane);
-            fb[y][2 * h] = vb[0];
-            fb[y][2 * h + 1] = vb[1];
-          }
-        } else {
-          const f4 vb = *reinterpret_cast<const f4 *>(pb + 4 * lane);
+            fb[y][0] = vb[0];
+            fb[y][1] = vb[1];
+          } else {
+            const f4 vb = *reinterpret_cast<const f4 *>(pb + 4 * lane);
 #pragma unroll
-          for (int q = 0; q < 4; ++q) fb[y][q] = vb[q];
+            for (int q = 0; q < 4; ++q) fb[y][q] = vb[q];
+          }
         }
+#pragma unroll
+        for (int qq = 0; qq < kQ; ++qq)
+#pragma unroll
+          for (int y = 0; y < BJ; ++y)
+#pragma unroll
+            for (int x = 0; x < BI; ++x) {
+              const int mma = ((kb * 4 + h * kQ + qq) * BJ + y) * BI + x;
+              if (mma % kEvery == 0 && more)
+                load_lds16(nsrc + goff(mma / kEvery) + g0, ndst + l0 + loff(mma / kEvery));
+              acc[y][x] = M::run(fb[y][qq], fa[x][qq], acc[y][x]);
+              __builtin_amdgcn_sched_barrier(0);  // keep the loads where they were placed
+            }
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int y = 0; y < BJ; ++y)
-#pragma unroll
-          for (int x = 0; x < BI; ++x) {
-            const int mma = ((kb * 4 + q) * BJ + y) * BI + x;
-            if (mma % kEvery == 0 && more)
-              load_lds16(nsrc + goff(mma / kEvery) + g0, ndst + l0 + loff(mma / kEvery));
-            acc[y][x] = M::run(fb[y][q], fa[x][q], acc[y][x]);
-            __builtin_amdgcn_sched_barrier(0);  // keep the loads where they were placed
-          }
     }
     if (more) advance();
 
