@@ -165,7 +165,11 @@ int mpgemm_last_num_slices(void);
  * device memory (at least 256-byte aligned) for this host thread's later calls;
  * NULL detaches it.  A call that finds the attached workspace too small returns
  * MPGEMM_ERR_WORKSPACE without enqueuing work.  Work on different streams must
- * not share one attached workspace concurrently.
+ * not share one attached workspace concurrently.  Without one, each call takes
+ * its workspace from the device's stream-ordered pool (hipMallocAsync, kept
+ * allocated after release); callers that keep several streams busy at once
+ * should attach one workspace per stream instead, since growing the pool under
+ * such load has stalled the calling thread for up to seconds.
  */
 size_t mpgemm_workspace_bytes(int fmt, int mode, int m, int n, int k, int D);
 int mpgemm_set_workspace(void *dev_ptr, size_t bytes);

@@ -10,9 +10,13 @@ of requests that arrive while others are on the GPU overlaps on the device;
 their operands, slices and results stay resident in HBM.  Latency is measured
 from arrival to the completion event.
 
-Operands are views into a device pool of synthetic values generated once
-(so no host work sits on the request path); each request takes seeded
-offsets into the pool.
+Operands come from a device pool of synthetic values generated once: each
+request takes seeded offsets into the pool, and its operands and output are
+staged in HBM before the clock starts (requests arrive with their data already
+on the device).  Each stream slot owns a library workspace sized for the
+largest request, attached before each call (``set_workspace``): the request
+path holds no host work and no allocation (a stream-ordered allocation inside
+the library could otherwise wait for the other streams under load).
 
 Run a rate sweep: ``python -m paper_2301_09960_amd.serve --sweep``.
 """
@@ -27,7 +31,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import COMPONENTS, gemm, workspace_bytes
+from . import COMPONENTS, gemm, set_workspace, workspace_bytes
 
 FMTS = ("dd", "td", "qd")
 GB = 1 << 30
@@ -46,6 +50,8 @@ class Request:
     start: float = math.nan
     done: float = math.nan
     bytes: int = 0
+    A: object = None
+    B: object = None
     C: object = None
     event: object = None
     stream_slot: int = -1
@@ -119,23 +125,31 @@ class Server:
         self.peak = 0
         self.streams = [torch.cuda.Stream() for _ in range(streams)]
         self.free_slots = deque(range(streams))
+        self.ws = [None] * streams  # per-slot library workspace
 
     def cost(self, r: Request) -> int:
         c = COMPONENTS[r.fmt]
         return 8 * c * (r.m * r.k + r.k * r.n + r.m * r.n) + workspace_bytes(r.fmt, "float", r.m, r.n, r.k)
 
-    def launch(self, r: Request, now: float):
+    def stage(self, r: Request):
+        """Operands (compact copies out of the pool) and output in HBM."""
         import torch
+        r.A = self.pool.operand(r.fmt, r.m, r.k, r.a_off)
+        r.B = self.pool.operand(r.fmt, r.k, r.n, r.b_off)
+        r.C = torch.empty((COMPONENTS[r.fmt], r.n, r.m), dtype=r.A.dtype, device=r.A.device)
+        r.event = torch.cuda.Event()
+
+    def launch(self, r: Request, now: float):
         slot = self.free_slots.popleft()
         st = self.streams[slot]
         r.stream_slot = slot
         r.start = now
-        with torch.cuda.stream(st):
-            A = self.pool.operand(r.fmt, r.m, r.k, r.a_off)
-            B = self.pool.operand(r.fmt, r.k, r.n, r.b_off)
-            r.C = gemm(r.fmt, A, B, stream=st)
-            r.event = torch.cuda.Event()
-            r.event.record(st)
+        set_workspace(self.ws[slot])
+        try:
+            gemm(r.fmt, r.A, r.B, r.C, stream=st)
+        finally:
+            set_workspace(None)
+        r.event.record(st)
         self.ledger += r.bytes
         self.peak = max(self.peak, self.ledger)
 
@@ -147,6 +161,12 @@ class Server:
             r.bytes = self.cost(r)
             if r.bytes > self.budget:
                 raise ValueError(f"request {r.rid} needs {r.bytes / GB:.1f} GB, above the budget")
+        for r in reqs:
+            self.stage(r)
+        need = max(workspace_bytes(r.fmt, "float", r.m, r.n, r.k) for r in reqs)
+        for i in range(len(self.ws)):
+            if self.ws[i] is None or self.ws[i].numel() < need:
+                self.ws[i] = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
         waiting = deque()
         inflight = []
         pending = deque(reqs)
@@ -169,6 +189,7 @@ class Server:
                     r.done = time.perf_counter() - t0
                     self.ledger -= r.bytes
                     self.free_slots.append(r.stream_slot)
+                    r.A = r.B = None
                     if not keep_results:
                         r.C = None
                 else:
