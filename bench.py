@@ -271,21 +271,27 @@ def main():
     serving = None
     if not args.no_serving:
         from paper_2301_09960_amd import serve
-        cap = serve.capacity(pool, count=200)
-        nreq = args.serve_requests
-        reqs = serve.make_requests(nreq + nreq // 10, rate=0.75 * cap, seed=1, pool=pool.elements)
-        st = serve.Server(pool, budget_gb=64, streams=8).run(reqs, warmup=nreq // 10)
-        serving = {
-            "capacity_req_per_s": round(cap, 1),
-            "offered_fraction": 0.75,
-            "requests": st.requests,
-            "p50_ms": round(st.p50_ms, 3),
-            "p99_ms": round(st.p99_ms, 3),
-            "throughput_gflops": round(st.throughput_gflops, 1),
-            "max_inflight": st.max_inflight,
-            "peak_ledger_gb": round(st.peak_ledger_gb, 3),
-            "budget_gb": 64,
-        }
+
+        def serve_at(mode):
+            cap = serve.capacity(pool, count=200, mode=mode)
+            nreq = args.serve_requests
+            reqs = serve.make_requests(nreq + nreq // 10, rate=0.75 * cap, seed=1, pool=pool.elements)
+            st = serve.Server(pool, budget_gb=64, streams=8, mode=mode).run(reqs, warmup=nreq // 10)
+            return {
+                "capacity_req_per_s": round(cap, 1),
+                "offered_fraction": 0.75,
+                "requests": st.requests,
+                "p50_ms": round(st.p50_ms, 3),
+                "p99_ms": round(st.p99_ms, 3),
+                "throughput_gflops": round(st.throughput_gflops, 1),
+                "max_inflight": st.max_inflight,
+                "peak_ledger_gb": round(st.peak_ledger_gb, 3),
+                "budget_gb": 64,
+            }
+
+        serving = serve_at("float")
+        if not args.no_int8:
+            serving["int8"] = serve_at("int8")
         log(f"serving: {serving}")
     del pool
 

@@ -143,6 +143,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Workspace carve-up for one call.
 struct Plan {
   int fmt, mode, C, D, rho;
+  int int8_cfg;  // INT8 GEMM tile configuration the slices are padded for
   size_t elem;  // bytes per slice element
   int64_t mbp, nbp, kbp;
   size_t off_resid_a, off_resid_b, off_pack_a, off_pack_b, off_mu_a, off_mu_b, off_exp_a, off_exp_b, off_sums, total;
@@ -180,8 +181,9 @@ Plan make_plan(int fmt, int mode, int64_t m, int64_t n, int64_t k, int D) {
   } else {
     p.elem = 1;
     p.rho = 0;
-    p.mbp = nblocks8_padded(m);
-    p.nbp = nblocks8_padded(n);
+    p.int8_cfg = int8_tile_config(m, n, g_opt.int8_tile);
+    p.mbp = nblocks8_padded(m, int8_tile_blocks(p.int8_cfg));
+    p.nbp = nblocks8_padded(n, int8_tile_blocks(p.int8_cfg));
     p.kbp = kblocks8_padded(k);
     p.off_resid_a = p.off_resid_b = take(0);
     p.off_pack_a = take((size_t)D * p.mbp * p.kbp * 1024);
@@ -327,7 +329,7 @@ hipError_t gemm_launch(const Plan &p, char *base, int m, int n, int k, T *Cout, 
                                  reinterpret_cast<const int *>(base + p.off_exp_b),
                                  reinterpret_cast<int32_t *>(base + p.off_sums), p.mbp, p.nbp, p.kbp, m, n, p.D, Cout,
                                  ldc, (int64_t)ldc * n, dbg_pair, static_cast<int64_t *>(dbg_out), lddbg,
-                                 g_opt.int8_tile, st);
+                                 p.int8_cfg, st);
     return hipErrorInvalidValue;
   }
   return launch_gemm_plain<T, C>(base + p.off_pack_a, base + p.off_pack_b, p.mbp, p.nbp, p.kbp, m, n, p.D, Cout, ldc,

@@ -20,6 +20,8 @@
 // every term exact in binary64, added with TwoSum into a (c+1)-term
 // accumulator and renormalized into the c components of C (HBM-bound: it
 // reads D 32-bit sums per element per chunk and writes C once).
+#include <algorithm>
+
 #include "internal.h"
 #include "layout.h"
 #include "mp_device.h"
@@ -111,7 +113,7 @@ template <int CFG>
 __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, const int8_t *__restrict__ Bpk,
                                                int64_t mbp, int64_t nbp, int64_t kbp, int64_t kb0, int nks, int D,
                                                int m, int n, int32_t *__restrict__ S, int64_t plane, int chunk,
-                                               int nchunks, int tm, int tn, int8_t *lds) {
+                                               int nchunks, int tm, int tn, int g0, int g1, int8_t *lds) {
   using G = Int8Cfg<CFG>;
   constexpr int TB = G::TB, WM = G::WM, WN = G::WN, KSB = G::KSB, NS = G::NS;
   constexpr int BI = TB / WM, BJ = TB / WN;
@@ -128,7 +130,8 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
 
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int wm = wave % WM, wn = wave / WM;
-  const int64_t total = (int64_t)D * (D + 1) / 2 * nks;
+  // diagonals g0 .. g1 - 1 (g pairs each)
+  const int64_t total = ((int64_t)(g1 - 1) * g1 / 2 - (int64_t)(g0 - 1) * g0 / 2) * nks;
 
   // this wavefront's share of a step: operand op_w, pieces j = 0..kL-1
   const int wave_u = __builtin_amdgcn_readfirstlane(wave);
@@ -143,7 +146,7 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
     loff[j] = op_w * kPanel + (blk * KSB + kb) * 1024;
   }
 
-  int lg = 1, ls = 1, lks = 0;  // load cursor: diagonal, pair within it, k step
+  int lg = g0, ls = 1, lks = 0;  // load cursor: diagonal, pair within it, k step
   int64_t issued = 0;
   // panel base of the step at the load cursor (A_ls or B_(lg+1-ls)), and its ring slot
   auto panel_base = [&]() -> const int8_t * {
@@ -180,7 +183,7 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
       advance();
     }
 
-  int cg = 1, cs = 1, cks = 0;  // compute cursor
+  int cg = g0, cs = 1, cks = 0;  // compute cursor
   for (int64_t step = 0; step < total; ++step) {
     wait_step<NS, kL>(total - 1 - step);
     __builtin_amdgcn_s_barrier();
@@ -246,7 +249,20 @@ __global__ __launch_bounds__(64 * Int8Cfg<CFG>::WM * Int8Cfg<CFG>::WN, 1) void k
   const int64_t kb0 = (int64_t)chunk * kb_chunk;
   const int64_t kb1 = kb0 + kb_chunk < kbp ? kb0 + kb_chunk : kbp;
   const int nks = (int)((kb1 - kb0) / Int8Cfg<CFG>::KSB);
-  gemm_int8_tile<CFG>(Apk, Bpk, mbp, nbp, kbp, kb0, nks, D, m, n, S, plane, chunk, nchunks, tm, tn, lds);
+  // diagonal group blockIdx.z of gridDim.z: the D (D + 1) / 2 pairs are cut into
+  // nearly equal parts at diagonal boundaries (a group may be empty)
+  int g0 = 1, g1 = D + 1;
+  if (gridDim.z > 1) {
+    const int64_t pairs = (int64_t)D * (D + 1) / 2;
+    auto first_reaching = [&](int64_t target) {  // smallest g with g (g + 1) / 2 >= target
+      int g = 0;
+      while ((int64_t)g * (g + 1) / 2 < target) ++g;
+      return g;
+    };
+    g0 = first_reaching(pairs * blockIdx.z / gridDim.z) + 1;
+    g1 = first_reaching(pairs * (blockIdx.z + 1) / gridDim.z) + 1;
+  }
+  gemm_int8_tile<CFG>(Apk, Bpk, mbp, nbp, kbp, kb0, nks, D, m, n, S, plane, chunk, nchunks, tm, tn, g0, g1, lds);
 }
 
 // Diagonal-sum planes are blocked: the 32 x 32 block (bi, bj) of C holds, for
@@ -334,17 +350,25 @@ hipError_t launch_gemm_int8(const void *Apk, const void *Bpk, const int *EA, con
   const auto *a = static_cast<const int8_t *>(Apk);
   const auto *b = static_cast<const int8_t *>(Bpk);
   const int use = int8_tile_config(m, n, cfg);
+  const int tb = int8_tile_blocks(use);
+  if (mbp % tb != 0 || nbp % tb != 0) return hipErrorInvalidValue;  // slices padded for another tile
+  // small products: diagonals (independent sums, each with its own plane) spread
+  // over gridDim.z so the grid still fills the chip (256 workgroups of the
+  // 256 x 256 configuration, 512 of the smaller ones)
+  const int64_t wgs = (mbp / tb) * (nbp / tb) * nchunks;
+  const int64_t want = use == 3 ? 256 : 512;
+  const int groups = wgs >= want ? 1 : (int)std::min<int64_t>(D, ceil_div(want, wgs));
   if (use == 2) {
     const int64_t tiles = (mbp / 8) * (nbp / 8);
-    hipLaunchKernelGGL((k_gemm_int8<2>), dim3((unsigned)tiles, (unsigned)nchunks), dim3(256), 0, st, a, b, mbp, nbp,
+    hipLaunchKernelGGL((k_gemm_int8<2>), dim3((unsigned)tiles, (unsigned)nchunks, (unsigned)groups), dim3(256), 0, st, a, b, mbp, nbp,
                        kbp, kbc, D, m, n, Sws, plane);
   } else if (use == 3) {
     const int64_t tiles = (mbp / 8) * (nbp / 8);
-    hipLaunchKernelGGL((k_gemm_int8<3>), dim3((unsigned)tiles, (unsigned)nchunks), dim3(512), 0, st, a, b, mbp, nbp,
+    hipLaunchKernelGGL((k_gemm_int8<3>), dim3((unsigned)tiles, (unsigned)nchunks, (unsigned)groups), dim3(512), 0, st, a, b, mbp, nbp,
                        kbp, kbc, D, m, n, Sws, plane);
   } else {
     const int64_t tiles = (mbp / 4) * (nbp / 4);
-    hipLaunchKernelGGL((k_gemm_int8<1>), dim3((unsigned)tiles, (unsigned)nchunks), dim3(256), 0, st, a, b, mbp, nbp,
+    hipLaunchKernelGGL((k_gemm_int8<1>), dim3((unsigned)tiles, (unsigned)nchunks, (unsigned)groups), dim3(256), 0, st, a, b, mbp, nbp,
                        kbp, kbc, D, m, n, Sws, plane);
   }
   hipError_t err = hipGetLastError();

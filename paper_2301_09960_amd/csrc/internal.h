@@ -82,6 +82,10 @@ hipError_t launch_gemm_int8(const void *Apk, const void *Bpk, const int *EA, con
                             int debug_g, int64_t *Sdbg, int lddbg, int cfg, hipStream_t st);
 // k blocks (32 wide) per chunk of the INT8 GEMM for D digit slices.
 int int8_kblocks_per_chunk(int D);
+// INT8 GEMM tile configuration for an m x n product (cfg in 1..3 forces one,
+// 0 chooses by size), and its tile edge in 32-row blocks.
+int int8_tile_config(int64_t m, int64_t n, int cfg);
+inline int int8_tile_blocks(int cfg) { return cfg == 1 ? 4 : 8; }
 
 // Debug: unpack D packed slices into planes of rows x cols (column-major, ld rows).
 hipError_t launch_unpack(int elem_bytes, const void *packed, int64_t nbp, int64_t kbp, int D, int orient, int rows,

@@ -17,8 +17,8 @@
 // INT8 digit slices use 32 x 32 blocks for the 32x32x32 integer instruction:
 // lane l holds row/column index l % 32 and the 16 consecutive k values
 // 16 (l / 32) + t, t = 0..15, stored as 16 bytes at 16 l + t.  Rows/columns
-// are padded to 256 (the larger INT8 GEMM tile), k to 128 (a multiple of every
-// INT8 k step).
+// are padded to the INT8 GEMM tile in use (128 or 256), k to 128 (a multiple of
+// every INT8 k step).
 #pragma once
 
 #include <stdint.h>
@@ -29,7 +29,7 @@ constexpr int kBlk = 16;      // rows/cols per block
 constexpr int kKBlk = 16;     // k per block (floating-point slices)
 constexpr int kBlk8 = 32;     // rows/cols per block (INT8 slices)
 constexpr int kKBlk8 = 32;    // k per block (INT8 slices)
-constexpr int kTileBlocks8 = 8;   // INT8 padding unit: 8 blocks (the 256-row tile; 128 divides it)
+constexpr int kTileBlocks8 = 8;   // largest INT8 tile: 8 blocks (256 rows); the 128-row tile uses 4
 constexpr int kKStepBlocks8 = 4;  // INT8 k padding unit: 4 k-blocks (128), a multiple of every k step
 constexpr int kTileBlocks = 4;  // GEMM tile = 4 x 4 blocks (64 x 64)
 constexpr int kKStepBlocks = 2; // GEMM k step = 2 k-blocks (32)
@@ -43,8 +43,10 @@ __host__ __device__ inline int64_t nblocks_padded(int64_t rows) {
 __host__ __device__ inline int64_t kblocks_padded(int64_t k) {
   return ceil_div(k, kKBlk * kKStepBlocks) * kKStepBlocks;
 }
-__host__ __device__ inline int64_t nblocks8_padded(int64_t rows) {
-  return ceil_div(rows, kBlk8 * kTileBlocks8) * kTileBlocks8;
+// INT8 rows/columns are padded to the tile of the GEMM configuration that will
+// consume them (tile_blocks = 4 or 8 blocks of 32).
+__host__ __device__ inline int64_t nblocks8_padded(int64_t rows, int tile_blocks) {
+  return ceil_div(rows, (int64_t)kBlk8 * tile_blocks) * tile_blocks;
 }
 __host__ __device__ inline int64_t kblocks8_padded(int64_t k) {
   return ceil_div(k, kKBlk8 * kKStepBlocks8) * kKStepBlocks8;

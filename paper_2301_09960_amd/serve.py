@@ -117,9 +117,10 @@ class DevicePool:
 class Server:
     """Admits requests under an HBM budget onto a fixed set of streams."""
 
-    def __init__(self, pool: DevicePool, budget_gb: float = 64.0, streams: int = 8):
+    def __init__(self, pool: DevicePool, budget_gb: float = 64.0, streams: int = 8, mode: str = "float"):
         import torch
         self.pool = pool
+        self.mode = mode  # slice form of every request: "float" (binary64 slices) or "int8"
         self.budget = int(budget_gb * GB)
         self.ledger = 0
         self.peak = 0
@@ -129,7 +130,7 @@ class Server:
 
     def cost(self, r: Request) -> int:
         c = COMPONENTS[r.fmt]
-        return 8 * c * (r.m * r.k + r.k * r.n + r.m * r.n) + workspace_bytes(r.fmt, "float", r.m, r.n, r.k)
+        return 8 * c * (r.m * r.k + r.k * r.n + r.m * r.n) + workspace_bytes(r.fmt, self.mode, r.m, r.n, r.k)
 
     def stage(self, r: Request):
         """Operands (compact copies out of the pool) and output in HBM."""
@@ -146,7 +147,7 @@ class Server:
         r.start = now
         set_workspace(self.ws[slot])
         try:
-            gemm(r.fmt, r.A, r.B, r.C, stream=st)
+            gemm(r.fmt, r.A, r.B, r.C, mode=self.mode, stream=st)
         finally:
             set_workspace(None)
         r.event.record(st)
@@ -163,7 +164,7 @@ class Server:
                 raise ValueError(f"request {r.rid} needs {r.bytes / GB:.1f} GB, above the budget")
         for r in reqs:
             self.stage(r)
-        need = max(workspace_bytes(r.fmt, "float", r.m, r.n, r.k) for r in reqs)
+        need = max(workspace_bytes(r.fmt, self.mode, r.m, r.n, r.k) for r in reqs)
         for i in range(len(self.ws)):
             if self.ws[i] is None or self.ws[i].numel() < need:
                 self.ws[i] = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
@@ -214,23 +215,24 @@ class Server:
         )
 
 
-def capacity(pool: DevicePool, count: int = 200, seed: int = 5, streams: int = 8) -> float:
+def capacity(pool: DevicePool, count: int = 200, seed: int = 5, streams: int = 8, mode: str = "float") -> float:
     """Requests per second the server completes with every request present at t = 0."""
     reqs = make_requests(count, rate=1e9, seed=seed, pool=pool.elements)
     for r in reqs:
         r.arrival = 0.0
-    st = Server(pool, streams=streams).run(reqs)
+    st = Server(pool, streams=streams, mode=mode).run(reqs)
     return count / st.wall_s
 
 
 def sweep(fractions=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2), requests: int = 2000, warmup: int = 200, seed: int = 1,
-          streams: int = 8):
+          streams: int = 8, mode: str = "float"):
     pool = DevicePool()
-    cap = capacity(pool, streams=streams)
-    out = {"capacity_req_per_s": cap, "points": []}
+    cap = capacity(pool, streams=streams, mode=mode)
+    out = {"capacity_req_per_s": cap, "mode": mode, "points": []}
     for fr in fractions:
         reqs = make_requests(requests + warmup, rate=fr * cap, seed=seed, pool=pool.elements)
-        st = Server(pool, streams=streams).run(reqs, warmup=warmup)
+        st = Server(pool, streams=streams, mode=mode).run(reqs, warmup=warmup)
+        st.extra["mode"] = mode
         st.extra["fraction_of_capacity"] = fr
         out["points"].append(st.__dict__)
         print(json.dumps({k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.__dict__.items()}),
@@ -244,9 +246,10 @@ def main():
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--streams", type=int, default=8)
+    ap.add_argument("--mode", default="float", choices=("float", "int8"))
     ap.add_argument("--out", default="")
     args = ap.parse_args()
-    res = sweep(requests=args.requests, warmup=args.warmup, streams=args.streams)
+    res = sweep(requests=args.requests, warmup=args.warmup, streams=args.streams, mode=args.mode)
     if args.out:
         with open(args.out, "w") as f:
             json.dump(res, f, indent=1)
