@@ -111,7 +111,7 @@ def cpu_baseline(n, E, rows_req):
     }
 
 
-def run_batched(mp, torch, pool, fmt, count=512, seed=31):
+def run_batched(mp, torch, pool, fmt, count=512, seed=31, mode="float"):
     """One graph launch of `count` products with sizes log-uniform in [64, 1024]."""
     import workload as W
     m = W.log_uniform_sizes(seed, count, 64, 1024, draw=0)
@@ -124,28 +124,30 @@ def run_batched(mp, torch, pool, fmt, count=512, seed=31):
         bo = int(offs[2 * i + 1]) % (pool.elements - int(k[i] * n[i]))
         As.append(pool.operand(fmt, int(m[i]), int(k[i]), ao))
         Bs.append(pool.operand(fmt, int(k[i]), int(n[i]), bo))
-    Cs = mp.gemm_batched(fmt, As, Bs)  # captures the graph
+    Cs = mp.gemm_batched(fmt, As, Bs, mode=mode)  # captures the graph
     torch.cuda.synchronize()
     reps = 3
     mp.profile_enable(True)
     t0 = time.perf_counter()
     for _ in range(reps):
-        mp.gemm_batched(fmt, As, Bs, Cs)
+        mp.gemm_batched(fmt, As, Bs, Cs, mode=mode)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     mp.profile_enable(False)
     _, gms = mp.profile_read()
     flops = float(np.sum(2.0 * m * n * k))
     gpu_ms = float(np.mean(gms))
-    Ds = np.array([mp.num_slices(fmt, "float", int(kk)) for kk in k], dtype=np.float64)
+    Ds = np.array([mp.num_slices(fmt, mode, int(kk)) for kk in k], dtype=np.float64)
     slice_flops = float(np.sum(Ds * (Ds + 1) / 2 * 2.0 * m * n * k))
+    peak = INT8_MFMA_PEAK_TOPS if mode == "int8" else FP64_MFMA_PEAK_TFLOPS
     return {
         "products": count,
+        "mode": mode,
         "sum_2mnk": flops,
         "launch_ms": round(gpu_ms, 3),
         "effective_gflops": round(flops / (gpu_ms * 1e-3) / 1e9, 1),
         "slice_gemm_tflops": round(slice_flops / (gpu_ms * 1e-3) / 1e12, 2),
-        "mfma_frac": round(slice_flops / (gpu_ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4),
+        "mfma_frac": round(slice_flops / (gpu_ms * 1e-3) / 1e12 / peak, 4),
         "wall_ms_per_batch": round((t1 - t0) * 1e3 / reps, 3),
         "max_slices": mp.last_num_slices(),
     }
@@ -266,6 +268,11 @@ def main():
         for f in ("dd", "qd"):
             batched[f] = run_batched(mp, torch, pool, f)
             log(f"batched {f}: {batched[f]}")
+        if not args.no_int8:
+            batched["int8"] = {}
+            for f in ("dd", "qd"):
+                batched["int8"][f] = run_batched(mp, torch, pool, f, mode="int8")
+                log(f"batched int8 {f}: {batched['int8'][f]}")
         mp.batched_cache_clear()
 
     serving = None

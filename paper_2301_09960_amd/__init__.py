@@ -241,9 +241,10 @@ def gemm(fmt, A, B, C=None, *, mode=None, slices=None, stream=None):
     return C
 
 
-def gemm_batched(fmt, As, Bs, Cs=None, *, slices=None, stream=None):
+def gemm_batched(fmt, As, Bs, Cs=None, *, mode=None, slices=None, stream=None):
     """C_i = A_i B_i for lists of tensors (conventions as in ``gemm``), as one
-    batched launch (graph-captured per batch shape).  Returns the list of C."""
+    batched launch (graph-captured per batch shape).  ``mode``: 'float' or
+    'int8' (DD/TD/QD).  Returns the list of C."""
     import torch
     f = _fmt(fmt)
     name = [k for k, v in FORMATS.items() if v == f][0]
@@ -268,7 +269,7 @@ def gemm_batched(fmt, As, Bs, Cs=None, *, slices=None, stream=None):
     IA = ctypes.c_int * max(count, 1)
     PA = ctypes.c_void_p * max(count, 1)
     fn = getattr(lib(), f"mpgemm_{name}_batched")
-    with _options(f, None, slices):
+    with _options(f, None if mode is None else _mode(mode), slices):
         st = fn(count, IA(*ms), IA(*ns), IA(*ks), PA(*[A.data_ptr() for A in As]), IA(*[max(1, m) for m in ms]),
                 PA(*[B.data_ptr() for B in Bs]), IA(*[max(1, k) for k in ks]), PA(*[Cm.data_ptr() for Cm in Cs]),
                 IA(*[max(1, m) for m in ms]), _stream(stream))

@@ -12,7 +12,10 @@
 //     (written once).
 // The graph holds: clear the maxima, one max-exponent launch and dmax pass
 // launches covering all operands, clear the work counter, and one persistent
-// GEMM launch.  Kernels take the caller's pointers from the descriptors, so a
+// GEMM launch.  In the INT8 form: clear the maxima, the max-exponent launch,
+// one digit-split launch over all operands' blocks, clear the work counter,
+// the persistent INT8 GEMM over (product, tile, k chunk, diagonal group)
+// items and one combine launch over all products.  Kernels take the caller's pointers from the descriptors, so a
 // cached graph is replayed with new pointers after one small host-to-device
 // copy of the descriptors.
 #include <hip/hip_runtime.h>
@@ -39,6 +42,9 @@ struct ProductLayout {
   int m, n, k, D, rho;
   int64_t mbp, nbp, kbp;
   size_t resid_a, resid_b, pack_a, pack_b, mu_a, mu_b, exp_a, exp_b;
+  // INT8 form: k blocks per chunk, chunks, diagonal groups, diagonal sums
+  int kbc = 0, nchunks = 0, groups = 1;
+  size_t sums = 0;
 };
 
 struct BatchPlan {
@@ -49,8 +55,9 @@ struct BatchPlan {
   std::vector<int> live;  // products with m, n, k > 0
   char *ws = nullptr;
   size_t off_ops = 0, off_descs = 0, desc_bytes = 0, off_prefix0 = 0, off_prefixp = 0, off_items = 0,
-         off_counter = 0, off_mu = 0, mu_bytes = 0, total = 0;
+         off_counter = 0, off_mu = 0, mu_bytes = 0, off_prefixc = 0, total = 0;
   int nops = 0, tiles0 = 0, tilesp = 0, dmax = 0, nitems = 0;
+  int64_t blocks8 = 0, blocksc = 0;  // INT8 form: split blocks, combine blocks
   void *stage = nullptr;
   hipEvent_t stage_done = nullptr;
   hipGraph_t graph = nullptr;
@@ -280,6 +287,227 @@ void write_descriptors(BatchPlan &p, const T *const *A, const int *lda, const T 
   }
 }
 
+// INT8-form batch: the digit split of every operand, one persistent INT8
+// GEMM over (product, 128 x 128 tile, k chunk, diagonal group) items, longest
+// first, and one combine over every product's blocks.
+template <int C>
+int build_plan_int8(BatchPlan &p) {
+  constexpr int kTB = 4;  // the 128 x 128 configuration: slices padded to 128 rows
+  const int count = (int)p.m.size();
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  p.prod.resize(count);
+  p.live.clear();
+  p.dmax = 0;
+  for (int g = 0; g < count; ++g) {
+    ProductLayout &L = p.prod[g];
+    L.m = p.m[g];
+    L.n = p.n[g];
+    L.k = p.k[g];
+    L.D = p.D[g];
+    if (L.m <= 0 || L.n <= 0 || L.k <= 0) continue;
+    p.live.push_back(g);
+    L.rho = 0;
+    L.mbp = nblocks8_padded(L.m, kTB);
+    L.nbp = nblocks8_padded(L.n, kTB);
+    L.kbp = kblocks8_padded(L.k);
+    L.kbc = int8_kblocks_per_chunk(L.D);
+    L.nchunks = (int)ceil_div(L.kbp, L.kbc);
+    L.resid_a = L.resid_b = 0;
+    L.pack_a = take((size_t)L.D * L.mbp * L.kbp * 1024);
+    L.pack_b = take((size_t)L.D * L.nbp * L.kbp * 1024);
+    L.exp_a = take((size_t)L.m * 4);
+    L.exp_b = take((size_t)L.n * 4);
+    L.sums = take((size_t)L.D * L.nchunks * L.mbp * L.nbp * 1024 * 4);
+    p.dmax = std::max(p.dmax, L.D);
+  }
+  p.off_mu = o;
+  size_t mo = 0;
+  for (int g : p.live) {
+    ProductLayout &L = p.prod[g];
+    L.mu_a = p.off_mu + mo;
+    mo += (size_t)L.m * 8;
+    L.mu_b = p.off_mu + mo;
+    mo += (size_t)L.n * 8;
+  }
+  p.mu_bytes = (mo + 3) / 4 * 4;
+  o = p.off_mu + align256(mo);
+  p.nops = 2 * (int)p.live.size();
+  p.off_ops = take(0);
+  p.off_descs = p.off_ops + (size_t)p.nops * sizeof(SplitOperand<double>);
+  p.desc_bytes = (size_t)p.nops * sizeof(SplitOperand<double>) + p.live.size() * sizeof(Int8GemmDesc);
+  o = p.off_ops + align256(p.desc_bytes);
+  p.off_prefix0 = take((size_t)(p.nops + 1) * 4);
+  p.off_prefixp = take((size_t)(p.nops + 1) * 4);
+  p.off_prefixc = take((size_t)(p.live.size() + 1) * 4);
+
+  // diagonal groups: items of about 1/4 of a persistent workgroup's fair share
+  auto cum = [](int64_t g) { return g * (g + 1) / 2; };
+  int64_t work = 0;
+  for (int g : p.live) {
+    const ProductLayout &L = p.prod[g];
+    work += (L.mbp / kTB) * (L.nbp / kTB) * cum(L.D) * L.kbp;
+  }
+  const int64_t target = std::max<int64_t>(1, work / (4 * (int64_t)kPersistentGrid));
+  struct Item {
+    int slot, tile, chunk, group;
+    int64_t cost;
+  };
+  std::vector<Item> items;
+  for (int slot = 0; slot < (int)p.live.size(); ++slot) {
+    ProductLayout &L = p.prod[p.live[slot]];
+    L.groups = (int)std::min<int64_t>(L.D, std::max<int64_t>(1, ceil_div(cum(L.D) * L.kbc, target)));
+    const int ntiles = (int)((L.mbp / kTB) * (L.nbp / kTB));
+    for (int z = 0; z < L.groups; ++z) {
+      // the same cut as the device: smallest g with cum(g) >= target pairs
+      auto first_reaching = [&](int64_t t) {
+        int64_t gg = 0;
+        while (cum(gg) < t) ++gg;
+        return gg;
+      };
+      const int64_t pairs = cum(L.D);
+      const int64_t b0 = first_reaching(pairs * z / L.groups), b1 = first_reaching(pairs * (z + 1) / L.groups);
+      if (b1 == b0) continue;  // empty group
+      for (int c = 0; c < L.nchunks; ++c) {
+        const int64_t kblocks = std::min<int64_t>(L.kbc, L.kbp - (int64_t)c * L.kbc);
+        for (int t = 0; t < ntiles; ++t) items.push_back({slot, t, c, z, (cum(b1) - cum(b0)) * kblocks});
+      }
+    }
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
+  p.nitems = (int)items.size();
+  p.off_items = take(items.size() * sizeof(int4));
+  p.off_counter = take(4);
+  p.total = o;
+
+  if (hipMalloc(&p.ws, p.total > 0 ? p.total : 256) != hipSuccess) {
+    (void)hipGetLastError();
+    p.ws = nullptr;
+    return MPGEMM_ERR_WORKSPACE;
+  }
+  if (hipHostMalloc(&p.stage, p.desc_bytes > 0 ? p.desc_bytes : 64, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    p.stage = nullptr;
+    return MPGEMM_ERR_WORKSPACE;
+  }
+  if (hipEventCreateWithFlags(&p.stage_done, hipEventDisableTiming) != hipSuccess) return MPGEMM_ERR_HIP;
+
+  std::vector<int> pre0(p.nops + 1, 0), preb(p.nops + 1, 0), prec(p.live.size() + 1, 0);
+  for (int slot = 0; slot < (int)p.live.size(); ++slot) {
+    const ProductLayout &L = p.prod[p.live[slot]];
+    pre0[2 * slot + 1] = pre0[2 * slot] + tiles64(L.m, L.k);
+    pre0[2 * slot + 2] = pre0[2 * slot + 1] + tiles64(L.n, L.k);
+    preb[2 * slot + 1] = preb[2 * slot] + (int)(L.mbp * L.kbp);
+    preb[2 * slot + 2] = preb[2 * slot + 1] + (int)(L.nbp * L.kbp);
+    prec[slot + 1] = prec[slot] + (int)(L.mbp * L.nbp);
+  }
+  p.tiles0 = pre0[p.nops];
+  p.blocks8 = preb[p.nops];
+  p.blocksc = prec[p.live.size()];
+  std::vector<int4> it4(items.size());
+  for (size_t i = 0; i < items.size(); ++i)
+    it4[i] = make_int4(items[i].slot, items[i].tile, items[i].chunk, items[i].group);
+  if (hipMemcpy(p.ws + p.off_prefix0, pre0.data(), pre0.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p.ws + p.off_prefixp, preb.data(), preb.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p.ws + p.off_prefixc, prec.data(), prec.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      (it4.size() && hipMemcpy(p.ws + p.off_items, it4.data(), it4.size() * sizeof(int4), hipMemcpyHostToDevice) !=
+                         hipSuccess))
+    return MPGEMM_ERR_HIP;
+
+  BatchCache &bc = cache();
+  hipStream_t &cs = bc.capture[p.device & 63];
+  if (!cs && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return MPGEMM_ERR_HIP;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return MPGEMM_ERR_HIP;
+  hipError_t e = launch_split_int8_batched<C>(
+      reinterpret_cast<const SplitOperand<double> *>(p.ws + p.off_ops),
+      reinterpret_cast<const int *>(p.ws + p.off_prefix0), reinterpret_cast<const int *>(p.ws + p.off_prefixp),
+      p.nops, p.tiles0, p.blocks8, p.ws + p.off_mu, (int64_t)(p.mu_bytes / 4), cs);
+  if (e == hipSuccess) e = launch_fill32(p.ws + p.off_counter, 1, 0u, cs);
+  if (e == hipSuccess)
+    e = launch_int8_batched<C>(reinterpret_cast<const Int8GemmDesc *>(p.ws + p.off_descs),
+                               reinterpret_cast<const int4 *>(p.ws + p.off_items), p.nitems,
+                               reinterpret_cast<int *>(p.ws + p.off_counter), std::min(p.nitems, kPersistentGrid),
+                               reinterpret_cast<const int *>(p.ws + p.off_prefixc), (int)p.live.size(), p.blocksc,
+                               cs);
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+  if (e != hipSuccess || e2 != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return MPGEMM_ERR_HIP;
+  }
+  p.graph = graph;
+  if (hipGraphInstantiate(&p.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return MPGEMM_ERR_HIP;
+  }
+  return 0;
+}
+
+void write_descriptors_int8(BatchPlan &p, const double *const *A, const int *lda, const double *const *B,
+                            const int *ldb, double *const *Cm, const int *ldc) {
+  SplitOperand<double> *ops = static_cast<SplitOperand<double> *>(p.stage);
+  Int8GemmDesc *descs = reinterpret_cast<Int8GemmDesc *>(static_cast<char *>(p.stage) +
+                                                         (size_t)p.nops * sizeof(SplitOperand<double>));
+  for (int slot = 0; slot < (int)p.live.size(); ++slot) {
+    const int g = p.live[slot];
+    const ProductLayout &L = p.prod[g];
+    SplitOperand<double> a{}, b{};
+    a.X = A[g];
+    a.comp_stride = (int64_t)lda[g] * L.k;
+    a.sv = 1;
+    a.sp = lda[g];
+    a.nvec = L.m;
+    a.len = L.k;
+    a.orient = 0;
+    a.packed = p.ws + L.pack_a;
+    a.nbp = L.mbp;
+    a.kbp = L.kbp;
+    a.mu = p.ws + L.mu_a;
+    a.exps = reinterpret_cast<int *>(p.ws + L.exp_a);
+    a.D = L.D;
+    b.X = B[g];
+    b.comp_stride = (int64_t)ldb[g] * L.n;
+    b.sv = ldb[g];
+    b.sp = 1;
+    b.nvec = L.n;
+    b.len = L.k;
+    b.orient = 1;
+    b.packed = p.ws + L.pack_b;
+    b.nbp = L.nbp;
+    b.kbp = L.kbp;
+    b.mu = p.ws + L.mu_b;
+    b.exps = reinterpret_cast<int *>(p.ws + L.exp_b);
+    b.D = L.D;
+    ops[2 * slot] = a;
+    ops[2 * slot + 1] = b;
+    Int8GemmDesc d{};
+    d.Apk = reinterpret_cast<const int8_t *>(p.ws + L.pack_a);
+    d.Bpk = reinterpret_cast<const int8_t *>(p.ws + L.pack_b);
+    d.EA = reinterpret_cast<const int *>(p.ws + L.exp_a);
+    d.EB = reinterpret_cast<const int *>(p.ws + L.exp_b);
+    d.S = reinterpret_cast<int32_t *>(p.ws + L.sums);
+    d.mbp = L.mbp;
+    d.nbp = L.nbp;
+    d.kbp = L.kbp;
+    d.plane = L.mbp * L.nbp * 1024;
+    d.kbc = L.kbc;
+    d.nchunks = L.nchunks;
+    d.groups = L.groups;
+    d.D = L.D;
+    d.m = L.m;
+    d.n = L.n;
+    d.ldc = ldc[g];
+    d.C = Cm[g];
+    d.c_stride = (int64_t)ldc[g] * L.n;
+    descs[slot] = d;
+  }
+}
+
 template <typename T, int C>
 int run_batched(int fmt, int count, const int *m, const int *n, const int *k, const T *const *A, const int *lda,
                 const T *const *B, const int *ldb, T *const *Cm, const int *ldc, hipStream_t st) {
@@ -297,7 +525,7 @@ int run_batched(int fmt, int count, const int *m, const int *n, const int *k, co
   int s;
   if ((s = check_device_cached())) return s;
   const int mode = thread_mode(fmt);
-  if (mode != MPGEMM_MODE_FLOAT) return MPGEMM_ERR_UNSUPPORTED;
+  if (mode != MPGEMM_MODE_FLOAT && (mode != MPGEMM_MODE_INT8 || sizeof(T) != 8)) return MPGEMM_ERR_UNSUPPORTED;
   const int layout = layout_for(fmt);
   if (count == 0) return 0;
   int dev = 0;
@@ -343,7 +571,12 @@ int run_batched(int fmt, int count, const int *m, const int *n, const int *k, co
     plan->n.assign(n, n + count);
     plan->k.assign(k, k + count);
     plan->D = Ds;
-    if ((s = build_plan<T, C>(*plan, st))) {
+    if (mode == MPGEMM_MODE_INT8) {
+      if constexpr (sizeof(T) == 8) s = build_plan_int8<C>(*plan);
+    } else {
+      s = build_plan<T, C>(*plan, st);
+    }
+    if (s) {
       plan->release();
       delete plan;
       return s;
@@ -355,7 +588,14 @@ int run_batched(int fmt, int count, const int *m, const int *n, const int *k, co
 
   // the stage may still feed the previous launch's descriptor copy
   if (hipEventSynchronize(plan->stage_done) != hipSuccess) return MPGEMM_ERR_HIP;
-  write_descriptors<T, C>(*plan, A, lda, B, ldb, Cm, ldc);
+  if constexpr (sizeof(T) == 8) {
+    if (mode == MPGEMM_MODE_INT8)
+      write_descriptors_int8(*plan, A, lda, B, ldb, Cm, ldc);
+    else
+      write_descriptors<T, C>(*plan, A, lda, B, ldb, Cm, ldc);
+  } else {
+    write_descriptors<T, C>(*plan, A, lda, B, ldb, Cm, ldc);
+  }
   hipEvent_t ev[3];
   profile_mark3(ev);
   if (ev[0]) (void)hipEventRecord(ev[0], st);

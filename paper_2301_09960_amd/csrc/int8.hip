@@ -237,6 +237,22 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
   __builtin_amdgcn_s_barrier();
 }
 
+// Diagonals [g0, g1) of group z of `groups`: the D (D + 1) / 2 pairs cut into
+// nearly equal parts at diagonal boundaries (a group may be empty).
+__device__ __forceinline__ void diagonal_group(int D, int z, int groups, int &g0, int &g1) {
+  g0 = 1;
+  g1 = D + 1;
+  if (groups <= 1) return;
+  const int64_t pairs = (int64_t)D * (D + 1) / 2;
+  auto first_reaching = [&](int64_t target) {  // smallest g with g (g + 1) / 2 >= target
+    int g = 0;
+    while ((int64_t)g * (g + 1) / 2 < target) ++g;
+    return g;
+  };
+  g0 = first_reaching(pairs * z / groups) + 1;
+  g1 = first_reaching(pairs * (z + 1) / groups) + 1;
+}
+
 template <int CFG>
 __global__ __launch_bounds__(64 * Int8Cfg<CFG>::WM * Int8Cfg<CFG>::WN, 1) void k_gemm_int8(
     const int8_t *__restrict__ Apk, const int8_t *__restrict__ Bpk, int64_t mbp, int64_t nbp, int64_t kbp,
@@ -249,19 +265,9 @@ __global__ __launch_bounds__(64 * Int8Cfg<CFG>::WM * Int8Cfg<CFG>::WN, 1) void k
   const int64_t kb0 = (int64_t)chunk * kb_chunk;
   const int64_t kb1 = kb0 + kb_chunk < kbp ? kb0 + kb_chunk : kbp;
   const int nks = (int)((kb1 - kb0) / Int8Cfg<CFG>::KSB);
-  // diagonal group blockIdx.z of gridDim.z: the D (D + 1) / 2 pairs are cut into
-  // nearly equal parts at diagonal boundaries (a group may be empty)
-  int g0 = 1, g1 = D + 1;
-  if (gridDim.z > 1) {
-    const int64_t pairs = (int64_t)D * (D + 1) / 2;
-    auto first_reaching = [&](int64_t target) {  // smallest g with g (g + 1) / 2 >= target
-      int g = 0;
-      while ((int64_t)g * (g + 1) / 2 < target) ++g;
-      return g;
-    };
-    g0 = first_reaching(pairs * blockIdx.z / gridDim.z) + 1;
-    g1 = first_reaching(pairs * (blockIdx.z + 1) / gridDim.z) + 1;
-  }
+  // diagonal group blockIdx.z of gridDim.z
+  int g0, g1;
+  diagonal_group(D, blockIdx.z, gridDim.z, g0, g1);
   gemm_int8_tile<CFG>(Apk, Bpk, mbp, nbp, kbp, kb0, nks, D, m, n, S, plane, chunk, nchunks, tm, tn, g0, g1, lds);
 }
 
@@ -270,6 +276,55 @@ __global__ __launch_bounds__(64 * Int8Cfg<CFG>::WM * Int8Cfg<CFG>::WN, 1) void k
 // (32 bi + l % 32, 32 bj + 8 (r / 4) + 4 (l / 32) + r % 4) at
 // ((bj * mbp + bi) * 64 + l) * 16 + r.  A combine thread takes four
 // consecutive r of one (block, lane): one 16-byte load per diagonal and chunk.
+// Combine thread t (0 <= t < mbp * nbp * 256) of one product: four
+// consecutive accumulator entries r of one (block, lane).
+template <int C>
+__device__ __forceinline__ void combine_one(int64_t t, const int32_t *__restrict__ S, int64_t plane, int nchunks,
+                                            int D, const int *__restrict__ EA, const int *__restrict__ EB,
+                                            int64_t mbp, int m, int n, double *__restrict__ Cout, int ldc,
+                                            int64_t c_stride, int debug_g, int64_t *__restrict__ Sdbg, int lddbg) {
+  const int q = (int)(t % 4);
+  const int lane = (int)((t / 4) % 64);
+  const int64_t blk = t / 256;
+  const int64_t bi = blk % mbp, bj = blk / mbp;
+  const int i = (int)(bi * 32 + lane % 32);
+  const int j0 = (int)(bj * 32 + 8 * q + 4 * (lane / 32));
+  if (i >= m || j0 >= n) return;
+  const int64_t off = (blk * 64 + lane) * 16 + 4 * q;
+  const int Ei = EA[i];
+  double acc[4][C + 1];
+  int Fj[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    Fj[e] = j0 + e < n ? EB[j0 + e] : kZeroExp;
+#pragma unroll
+    for (int c = 0; c <= C; ++c) acc[e][c] = 0.0;
+  }
+  for (int g = 1; g <= D; ++g) {
+    int64_t s[4] = {0, 0, 0, 0};
+    for (int c = 0; c < nchunks; ++c) {
+      const i4v v = *reinterpret_cast<const i4v *>(S + ((int64_t)(g - 1) * nchunks + c) * plane + off);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) s[e] += v[e];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (j0 + e >= n) continue;
+      if (debug_g == g) Sdbg[i + (int64_t)(j0 + e) * lddbg] = s[e];
+      if (Ei != kZeroExp && Fj[e] != kZeroExp && s[e] != 0)
+        acc_add<double, C + 1>(acc[e], ldexp((double)s[e], Ei + Fj[e] + 2 - 7 * (g + 1)));
+    }
+  }
+  if (debug_g > 0) return;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if (j0 + e >= n) continue;
+    renorm<double, C + 1>(acc[e]);
+#pragma unroll
+    for (int c = 0; c < C; ++c) Cout[c * c_stride + i + (int64_t)(j0 + e) * ldc] = acc[e][c];
+  }
+}
+
 template <int C>
 __global__ __launch_bounds__(256) void k_int8_combine(const int32_t *__restrict__ S, int64_t plane, int nchunks, int D,
                                                       const int *__restrict__ EA, const int *__restrict__ EB,
@@ -277,48 +332,55 @@ __global__ __launch_bounds__(256) void k_int8_combine(const int32_t *__restrict_
                                                       double *__restrict__ Cout, int ldc, int64_t c_stride,
                                                       int debug_g, int64_t *__restrict__ Sdbg, int lddbg) {
   const int64_t total = mbp * nbp * 64 * 4;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-    const int q = (int)(t % 4);
-    const int lane = (int)((t / 4) % 64);
-    const int64_t blk = t / 256;
-    const int64_t bi = blk % mbp, bj = blk / mbp;
-    const int i = (int)(bi * 32 + lane % 32);
-    const int j0 = (int)(bj * 32 + 8 * q + 4 * (lane / 32));
-    if (i >= m || j0 >= n) continue;
-    const int64_t off = (blk * 64 + lane) * 16 + 4 * q;
-    const int Ei = EA[i];
-    double acc[4][C + 1];
-    int Fj[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      Fj[e] = j0 + e < n ? EB[j0 + e] : kZeroExp;
-#pragma unroll
-      for (int c = 0; c <= C; ++c) acc[e][c] = 0.0;
-    }
-    for (int g = 1; g <= D; ++g) {
-      int64_t s[4] = {0, 0, 0, 0};
-      for (int c = 0; c < nchunks; ++c) {
-        const i4v v = *reinterpret_cast<const i4v *>(S + ((int64_t)(g - 1) * nchunks + c) * plane + off);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) s[e] += v[e];
-      }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (j0 + e >= n) continue;
-        if (debug_g == g) Sdbg[i + (int64_t)(j0 + e) * lddbg] = s[e];
-        if (Ei != kZeroExp && Fj[e] != kZeroExp && s[e] != 0)
-          acc_add<double, C + 1>(acc[e], ldexp((double)s[e], Ei + Fj[e] + 2 - 7 * (g + 1)));
-      }
-    }
-    if (debug_g > 0) continue;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      if (j0 + e >= n) continue;
-      renorm<double, C + 1>(acc[e]);
-#pragma unroll
-      for (int c = 0; c < C; ++c) Cout[c * c_stride + i + (int64_t)(j0 + e) * ldc] = acc[e][c];
-    }
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x)
+    combine_one<C>(t, S, plane, nchunks, D, EA, EB, mbp, m, n, Cout, ldc, c_stride, debug_g, Sdbg, lddbg);
+}
+
+// Persistent INT8 GEMM of a batch (128 x 128 tiles): each workgroup takes
+// (product, tile, k chunk, diagonal group) items from a shared counter; items
+// are ordered by decreasing work.
+__global__ __launch_bounds__(64 * Int8Cfg<1>::WM * Int8Cfg<1>::WN, 1) void k_gemm_int8_batched(
+    const Int8GemmDesc *__restrict__ descs, const int4 *__restrict__ items, int nitems, int *__restrict__ counter) {
+  __shared__ __attribute__((aligned(16))) int8_t lds[Int8Cfg<1>::NS * int8_stage_bytes<1>()];
+  __shared__ int next;
+  constexpr int TB = Int8Cfg<1>::TB;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = next;
+    __syncthreads();
+    if (it >= nitems) break;
+    const int4 w = items[it];
+    const Int8GemmDesc &d = descs[w.x];
+    const int tiles_m = (int)(d.mbp / TB);
+    const int tm = w.y % tiles_m, tn = w.y / tiles_m;
+    const int chunk = w.z;
+    const int64_t kb0 = (int64_t)chunk * d.kbc;
+    const int64_t kb1 = kb0 + d.kbc < d.kbp ? kb0 + d.kbc : d.kbp;
+    const int nks = (int)((kb1 - kb0) / Int8Cfg<1>::KSB);
+    int g0, g1;
+    diagonal_group(d.D, w.w, d.groups, g0, g1);
+    gemm_int8_tile<1>(d.Apk, d.Bpk, d.mbp, d.nbp, d.kbp, kb0, nks, d.D, d.m, d.n, d.S, d.plane, chunk, d.nchunks,
+                      tm, tn, g0, g1, lds);
   }
+}
+
+// Combine of a batch: workgroup b takes 32 x 32 block b - prefix[p] of product p.
+template <int C>
+__global__ __launch_bounds__(256) void k_int8_combine_batched(const Int8GemmDesc *__restrict__ descs,
+                                                              const int *__restrict__ prefix, int nprod) {
+  int lo = 0, hi = nprod - 1;  // last p with prefix[p] <= blockIdx.x
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (prefix[mid] <= (int)blockIdx.x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const Int8GemmDesc &d = descs[lo];
+  const int64_t t = ((int64_t)blockIdx.x - prefix[lo]) * 256 + threadIdx.x;
+  combine_one<C>(t, d.S, d.plane, d.nchunks, d.D, d.EA, d.EB, d.mbp, d.m, d.n, d.C, d.ldc, d.c_stride, 0, nullptr,
+                 0);
 }
 
 }  // namespace
@@ -379,6 +441,24 @@ hipError_t launch_gemm_int8(const void *Apk, const void *Bpk, const int *EA, con
   return hipGetLastError();
 }
 
+template <int C>
+hipError_t launch_int8_batched(const Int8GemmDesc *descs, const int4 *items, int nitems, int *counter, int grid,
+                               const int *prefix_blocks, int nprod, int64_t blocks, hipStream_t st) {
+  if (nitems > 0 && grid > 0) {
+    hipLaunchKernelGGL(k_gemm_int8_batched, dim3(grid), dim3(64 * Int8Cfg<1>::WM * Int8Cfg<1>::WN), 0, st, descs,
+                       items, nitems, counter);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  if (blocks > 0) {
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_int8_combine_batched<C>), dim3((unsigned)blocks), dim3(256), 0, st, descs, prefix_blocks,
+                       nprod);
+    return hipGetLastError();
+  }
+  return hipSuccess;
+}
+
 #define MP_INT8_INST(C)                                                                                     \
   template hipError_t launch_gemm_int8<C>(const void *, const void *, const int *, const int *, int32_t *, int64_t, \
                                           int64_t, int64_t, int, int, int, double *, int, int64_t, int, int64_t *, \
@@ -386,6 +466,12 @@ hipError_t launch_gemm_int8(const void *Apk, const void *Bpk, const int *EA, con
 MP_INT8_INST(2)
 MP_INT8_INST(3)
 MP_INT8_INST(4)
+template hipError_t launch_int8_batched<2>(const Int8GemmDesc *, const int4 *, int, int *, int, const int *, int,
+                                           int64_t, hipStream_t);
+template hipError_t launch_int8_batched<3>(const Int8GemmDesc *, const int4 *, int, int *, int, const int *, int,
+                                           int64_t, hipStream_t);
+template hipError_t launch_int8_batched<4>(const Int8GemmDesc *, const int4 *, int, int *, int, const int *, int,
+                                           int64_t, hipStream_t);
 #undef MP_INT8_INST
 
 }  // namespace mp

@@ -27,6 +27,19 @@ struct SplitOperand {
   int D, rho;            // slice count and shift (used by the batched kernels)
 };
 
+// One product of an INT8-form batch, as read by the persistent INT8 GEMM and
+// the batched combine.  The diagonals of a (tile, k chunk) are cut into
+// `groups` work items of nearly equal pair counts.
+struct Int8GemmDesc {
+  const int8_t *Apk, *Bpk;
+  const int *EA, *EB;
+  int32_t *S;
+  int64_t mbp, nbp, kbp, plane;
+  int kbc, nchunks, groups, D, m, n, ldc;
+  double *C;
+  int64_t c_stride;
+};
+
 // One product of a batch, as read by the persistent GEMM kernel.
 struct PlainGemmDesc {
   const void *Apk, *Bpk;
@@ -60,6 +73,23 @@ hipError_t launch_gemm_plain_batched(const PlainGemmDesc *descs, const int2 *ite
 // INT8 digit split of both operands.
 template <int C>
 hipError_t launch_split_int8(const SplitOperand<double> &a, const SplitOperand<double> &b, int D, hipStream_t st);
+
+// INT8 digit split of many operands at once (operand i: ops[i].D digits).
+// prefix_max0: running sums of each operand's 64 x 64 max-kernel tiles;
+// prefix_blk: running sums of its 32 x 32 packed blocks (nbp * kbp).
+template <int C>
+hipError_t launch_split_int8_batched(const SplitOperand<double> *ops, const int *prefix_max0, const int *prefix_blk,
+                                     int nops, int tiles_max0, int64_t blocks, void *mu_all, int64_t mu_words,
+                                     hipStream_t st);
+
+// INT8-form batch: persistent GEMM over items (product, tile, k chunk,
+// diagonal group) taken through *counter (cleared by the caller), with the
+// 128 x 128 tile configuration (slices padded to 128 rows); then the combine
+// of every product, prefix_blocks giving the running sums of the 32 x 32
+// blocks of each product's C.
+template <int C>
+hipError_t launch_int8_batched(const Int8GemmDesc *descs, const int4 *items, int nitems, int *counter, int grid,
+                               const int *prefix_blocks, int nprod, int64_t blocks, hipStream_t st);
 
 // Fused slice-product GEMM with error-free accumulation into C (C components).
 // single_pair >= 0 selects debug mode: only pair (a, b) = (single_pair / D,

@@ -375,6 +375,19 @@ __global__ __launch_bounds__(kThreads) void k_split_int8(SplitOperand<double> a,
     int8_block<C, 1>(b, blk - blocks_a, D);
 }
 
+// Batched: workgroup b takes block b - prefix[i] of operand i.
+template <int C>
+__global__ __launch_bounds__(kThreads) void k_split_int8_batched(const SplitOperand<double> *ops, const int *prefix,
+                                                                 int nops) {
+  const int i = find_operand(prefix, nops, blockIdx.x);
+  const SplitOperand<double> &op = ops[i];
+  const int64_t local = (int64_t)blockIdx.x - prefix[i];
+  if (op.orient == 0)
+    int8_block<C, 0>(op, local, op.D);
+  else
+    int8_block<C, 1>(op, local, op.D);
+}
+
 }  // namespace
 
 template <int C>
@@ -399,6 +412,33 @@ hipError_t launch_split_int8(const SplitOperand<double> &a, const SplitOperand<d
   }
   return hipSuccess;
 }
+
+template <int C>
+hipError_t launch_split_int8_batched(const SplitOperand<double> *ops, const int *prefix_max0, const int *prefix_blk,
+                                     int nops, int tiles_max0, int64_t blocks, void *mu_all, int64_t mu_words,
+                                     hipStream_t st) {
+  hipError_t err = launch_fill32(mu_all, mu_words, 0u, st);
+  if (err != hipSuccess) return err;
+  if (tiles_max0 > 0) {
+    hipLaunchKernelGGL((k_split_max0_batched<double, C>), dim3(tiles_max0), dim3(kThreads), 0, st, ops, prefix_max0,
+                       nops);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
+  if (blocks > 0) {
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_split_int8_batched<C>), dim3((unsigned)blocks), dim3(kThreads), 0, st, ops, prefix_blk,
+                       nops);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
+template hipError_t launch_split_int8_batched<2>(const SplitOperand<double> *, const int *, const int *, int, int,
+                                                 int64_t, void *, int64_t, hipStream_t);
+template hipError_t launch_split_int8_batched<3>(const SplitOperand<double> *, const int *, const int *, int, int,
+                                                 int64_t, void *, int64_t, hipStream_t);
+template hipError_t launch_split_int8_batched<4>(const SplitOperand<double> *, const int *, const int *, int, int,
+                                                 int64_t, void *, int64_t, hipStream_t);
 
 template hipError_t launch_split_int8<2>(const SplitOperand<double> &, const SplitOperand<double> &, int, hipStream_t);
 template hipError_t launch_split_int8<3>(const SplitOperand<double> &, const SplitOperand<double> &, int, hipStream_t);

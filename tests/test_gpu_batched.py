@@ -68,6 +68,32 @@ def test_batched_equals_single_calls(mp, orc, fmt):
         assert ok, (i, sh[i], worst)
 
 
+@pytest.mark.parametrize("fmt", ["dd", "td", "qd"])
+def test_batched_int8_equals_single_calls(mp, orc, fmt):
+    """The INT8 form batched: every product equals its single INT8 call bit for
+    bit (exact digit sums, same combination order), and meets the bound."""
+    import torch
+    sh = shapes(4, 26, 1, 400) + [(0, 5, 7), (5, 4, 0), (1, 1, 1), (300, 257, 129)]
+    say(f"batched int8 {fmt}: {len(sh)} products")
+    host = make_batch(fmt, sh, seed=17, E=16)
+    As = [dev(A) for A, _ in host]
+    Bs = [dev(B) for _, B in host]
+    Cs = mp.gemm_batched(fmt, As, Bs, mode="int8")
+    torch.cuda.synchronize()
+    for i, (A, B) in enumerate(zip(As, Bs)):
+        single = mp.gemm(fmt, A, B, mode="int8")
+        torch.cuda.synchronize()
+        assert torch.equal(single, Cs[i]), (i, sh[i])
+    for i in range(0, len(sh), 6):
+        m, n, k = sh[i]
+        if m == 0 or n == 0:
+            continue
+        A, B = host[i]
+        diff, absab, _ = orc.exact_check(A, B, Cs[i].cpu().numpy())
+        ok, worst = orc.bound_report(diff, absab, T_BITS[fmt])
+        assert ok, (i, sh[i], worst)
+
+
 def test_graph_replays_with_new_inputs(mp):
     import torch
     sh = shapes(2, 24, 16, 200)
