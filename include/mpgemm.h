@@ -213,6 +213,33 @@ int mpgemm_debug_products(int fmt, int mode, int m, int n, int k, const void *A,
 int mpgemm_profile_enable(int on);
 int mpgemm_profile_read(double *split_ms, double *gemm_ms, int max_calls);
 
+/*
+ * Longer binary64 expansions (the paper's arbitrary-precision section
+ * multiplies 212- to 742-bit numbers in 53-bit steps): A, B and C hold
+ * c = 2 .. 14 binary64 components per element, planes as for DD/TD/QD
+ * (normalized expansions, each component below half an ulp of the one above).
+ * The product uses the INT8-slice form with D digit slices (D = 0: automatic,
+ * mpgemm_nd_num_slices) and meets |C - AB| <= 2^-(50 c) (|A||B|) elementwise
+ * for the automatic D on inputs whose exponents spread up to 16 bits within a
+ * row or column (c = 2, 3, 4 give the DD, TD and QD bounds).  At most 112
+ * digits.  Return codes: -1 bad c, -2 bad D, then -(i + 2) for argument i of
+ * the DD signature; positive codes as above.  Workspace as for the other
+ * calls (mpgemm_nd_workspace_bytes; 0 for an invalid or empty shape).
+ * mpgemm_nd_debug_split writes the D digit planes (int8, rows x cols,
+ * column-major) and the per-row (operand 0) or per-column (operand 1)
+ * exponents E of one operand; mpgemm_nd_debug_products writes the diagonal sum
+ * S_g (1 <= g <= D) as int64 (m x n, leading dimension ldo).  Both return 0 or
+ * a code as above (-1 bad c; then the positions of their own arguments).
+ */
+int mpgemm_nd(int c, int D, int m, int n, int k, const double *A, int lda, const double *B, int ldb, double *C,
+              int ldc, hipStream_t stream);
+int mpgemm_nd_num_slices(int c, int k);
+size_t mpgemm_nd_workspace_bytes(int c, int D, int m, int n, int k);
+int mpgemm_nd_debug_split(int c, int operand, int rows, int cols, const double *X, int ldx, int D, int8_t *digits,
+                          int *exps, hipStream_t stream);
+int mpgemm_nd_debug_products(int c, int m, int n, int k, const double *A, int lda, const double *B, int ldb, int D,
+                             int g, int64_t *out, int ldo, hipStream_t stream);
+
 /* Text for a return code. */
 const char *mpgemm_status_string(int status);
 

@@ -62,6 +62,7 @@
 #define ORC_ENOTEXACT 3 /* a slice was off its grid or a product sum too large */
 
 #define ZERO_EXP INT_MIN
+#define ORC_MAXC 16 /* longest expansion handled (components of binary64) */
 
 /* ------------------------------------------------------------------------- */
 /* Error-free transformations.                                                */
@@ -540,7 +541,7 @@ static void sa_to_expansion(sacc *s, double *x, int c, int p, int emin)
 int oracle_gemm_exact_check(int c, int is_f32, int m, int n, int k, const void *Av, const void *Bv, const void *Cv,
                             int ldc, const int *rows, int nrows, double *diff, double *absab, double *cex)
 {
-    if (c < 1 || c > 8 || m < 0 || n < 0 || k < 0)
+    if (c < 1 || c > ORC_MAXC || m < 0 || n < 0 || k < 0)
         return ORC_EINVAL;
     const long pa = (long)m * k, pb = (long)k * n, pc = (long)ldc * n;
     int status = ORC_OK;
@@ -787,7 +788,7 @@ done:
 int oracle_split_int8(int nvec, int len, int c, const double *X, long s_vec, long s_elt, long s_comp, int D,
                       int8_t *digits, int *exps)
 {
-    if (nvec < 0 || len < 0 || c < 1 || c > 8 || D < 1)
+    if (nvec < 0 || len < 0 || c < 1 || c > ORC_MAXC || D < 1)
         return ORC_EINVAL;
     const long plane = (long)nvec * len;
     int status = ORC_OK;
@@ -802,7 +803,7 @@ int oracle_split_int8(int nvec, int len, int c, const double *X, long s_vec, lon
         exps[v] = E;
         for (int p = 0; p < len; ++p) {
             int8_t *dst = digits + v * s_vec + p * s_elt;
-            double R[8];
+            double R[ORC_MAXC];
             for (int r = 0; r < c; ++r)
                 R[r] = X[r * s_comp + v * s_vec + p * s_elt];
             for (int d = 1; d <= D; ++d) {
@@ -858,6 +859,8 @@ int oracle_int8_diag_sums(int m, int n, int k, int D, const int8_t *Ad, const in
  */
 int oracle_int8_combine(int m, int n, int D, int c, const int64_t *Sg, const int *EA, const int *EB, double *C)
 {
+    if (c < 1 || c > ORC_MAXC || m < 0 || n < 0 || D < 1)
+        return ORC_EINVAL;
     const long pc = (long)m * n;
     int status = ORC_OK;
 #pragma omp parallel
@@ -877,7 +880,7 @@ int oracle_int8_combine(int m, int n, int D, int c, const int64_t *Sg, const int
                         if (v != 0)
                             sa_dep_u64(s, v < 0, (uint64_t)llabs(v), EA[i] + EB[j] + 2 - 7 * (g + 1));
                     }
-                double out[8];
+                double out[ORC_MAXC];
                 sa_to_expansion(s, out, c, 53, -1074);
                 for (int r = 0; r < c; ++r)
                     C[r * pc + i + (long)j * m] = out[r];

@@ -72,6 +72,13 @@ def lib():
                 L.mpgemm_debug_products.argtypes = [_I, _I, _I, _I, _I, _P, _I, _P, _I, _I, _I, _I, _P, _I, _P]
                 L.mpgemm_profile_enable.argtypes = [_I]
                 L.mpgemm_profile_read.argtypes = [_P, _P, _I]
+                L.mpgemm_nd.restype = _I
+                L.mpgemm_nd.argtypes = [_I, _I, _I, _I, _I, _P, _I, _P, _I, _P, _I, _P]
+                L.mpgemm_nd_num_slices.argtypes = [_I, _I]
+                L.mpgemm_nd_workspace_bytes.restype = ctypes.c_size_t
+                L.mpgemm_nd_workspace_bytes.argtypes = [_I, _I, _I, _I, _I]
+                L.mpgemm_nd_debug_split.argtypes = [_I, _I, _I, _I, _P, _I, _I, _P, _P, _P]
+                L.mpgemm_nd_debug_products.argtypes = [_I, _I, _I, _I, _P, _I, _P, _I, _I, _I, _P, _I, _P]
                 L.mpgemm_status_string.restype = ctypes.c_char_p
                 L.mpgemm_status_string.argtypes = [_I]
                 _lib = L
@@ -307,6 +314,75 @@ def debug_split(fmt, X, operand: int, D: int = 0, mode="float", stream=None):
     _check(lib().mpgemm_debug_split(f, md, operand, rows, cols, _P(X.data_ptr()), max(1, rows), D,
                                     _P(slices.data_ptr()), _P(exps.data_ptr()), _stream(stream)), "debug_split")
     return slices, exps
+
+
+def _check_nd(X, name):
+    import torch
+    if X.dim() != 3 or X.dtype != torch.float64 or not X.is_cuda or not X.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape (c, cols, rows)")
+    if not 2 <= X.shape[0] <= 14:
+        raise ValueError(f"{name}: 2 to 14 components, got {X.shape[0]}")
+
+
+def gemm_nd(A, B, C=None, *, slices: int = 0, stream=None):
+    """C = A B for binary64 expansions of c = 2..14 components (A ``(c, k, m)``,
+    B ``(c, n, k)``, C ``(c, n, m)``), INT8-slice form with ``slices`` digit
+    slices (0 = automatic: 2^-(50 c) (|A||B|))."""
+    import torch
+    _check_nd(A, "A")
+    _check_nd(B, "B")
+    c = A.shape[0]
+    if B.shape[0] != c:
+        raise ValueError("A and B must have the same number of components")
+    k, m = A.shape[1], A.shape[2]
+    n, kb = B.shape[1], B.shape[2]
+    if kb != k:
+        raise ValueError(f"inner dimensions differ: A has k={k}, B has k={kb}")
+    if C is None:
+        C = torch.empty((c, n, m), dtype=torch.float64, device=A.device)
+    elif tuple(C.shape) != (c, n, m) or C.dtype != torch.float64 or not C.is_contiguous():
+        raise ValueError(f"C must be a contiguous float64 tensor of shape {(c, n, m)}")
+    _check(lib().mpgemm_nd(c, int(slices), m, n, k, _P(A.data_ptr()), max(1, m), _P(B.data_ptr()), max(1, k),
+                           _P(C.data_ptr()), max(1, m), _stream(stream)), "mpgemm_nd")
+    return C
+
+
+def nd_num_slices(c: int, k: int) -> int:
+    return lib().mpgemm_nd_num_slices(int(c), int(k))
+
+
+def nd_workspace_bytes(c: int, m: int, n: int, k: int, D: int = 0) -> int:
+    return lib().mpgemm_nd_workspace_bytes(int(c), int(D), int(m), int(n), int(k))
+
+
+def nd_debug_split(X, operand: int, D: int = 0, stream=None):
+    """INT8 digits ``(D, cols, rows)`` and exponents ``(nvec,)`` of one operand of gemm_nd."""
+    import torch
+    _check_nd(X, "X")
+    c, cols, rows = X.shape
+    k = cols if operand == 0 else rows
+    if D == 0:
+        D = nd_num_slices(c, k)
+    nvec = rows if operand == 0 else cols
+    digits = torch.zeros((D, cols, rows), dtype=torch.int8, device=X.device)
+    exps = torch.zeros((nvec,), dtype=torch.int32, device=X.device)
+    _check(lib().mpgemm_nd_debug_split(c, operand, rows, cols, _P(X.data_ptr()), max(1, rows), D,
+                                       _P(digits.data_ptr()), _P(exps.data_ptr()), _stream(stream)), "nd_debug_split")
+    return digits, exps
+
+
+def nd_debug_products(A, B, g: int, D: int = 0, stream=None):
+    """The INT8 diagonal sum S_g of gemm_nd, ``(n, m)`` int64."""
+    import torch
+    _check_nd(A, "A")
+    _check_nd(B, "B")
+    c, k, m = A.shape
+    n = B.shape[1]
+    out = torch.zeros((n, m), dtype=torch.int64, device=A.device)
+    _check(lib().mpgemm_nd_debug_products(c, m, n, k, _P(A.data_ptr()), max(1, m), _P(B.data_ptr()), max(1, k),
+                                          int(D), int(g), _P(out.data_ptr()), max(1, m), _stream(stream)),
+           "nd_debug_products")
+    return out
 
 
 def debug_products(fmt, A, B, a: int, b: int = 0, D: int = 0, mode="float", stream=None):

@@ -26,6 +26,8 @@ constexpr int kNumFmt = 4;
 constexpr int kMaxDim = 1 << 20;
 constexpr int kMaxDFloat = 16;
 constexpr int kMaxDInt8 = 40;
+constexpr int kMaxNd = 14;    // longest expansion of mpgemm_nd (binary64 components)
+constexpr int kMaxDNd = 112;  // most INT8 digit slices of mpgemm_nd
 constexpr int kBoundBits[kNumFmt] = {100, 150, 200, 66};  // 2^-t bound per format
 constexpr int kComps[kNumFmt] = {2, 3, 4, 3};
 const int kCompsH[kNumFmtH] = {2, 3, 4, 3};
@@ -316,7 +318,8 @@ hipError_t split_both(const SplitOperand<T> &a, const SplitOperand<T> &b, const 
     if constexpr (sizeof(T) == 8) return launch_split_int8<C>(a, b, p.D, st);
     return hipErrorInvalidValue;
   }
-  return launch_split_plain<T, C>(a, b, p.D, p.rho, st);
+  if constexpr (C <= 4) return launch_split_plain<T, C>(a, b, p.D, p.rho, st);
+  return hipErrorInvalidValue;  // longer expansions: INT8 form only
 }
 
 template <typename T, int C>
@@ -332,18 +335,18 @@ hipError_t gemm_launch(const Plan &p, char *base, int m, int n, int k, T *Cout, 
                                  p.int8_cfg, st);
     return hipErrorInvalidValue;
   }
-  return launch_gemm_plain<T, C>(base + p.off_pack_a, base + p.off_pack_b, p.mbp, p.nbp, p.kbp, m, n, p.D, Cout, ldc,
-                                 (int64_t)ldc * n, dbg_pair, static_cast<double *>(dbg_out), lddbg,
-                                 layout_for(p.fmt), st);
+  if constexpr (C <= 4)
+    return launch_gemm_plain<T, C>(base + p.off_pack_a, base + p.off_pack_b, p.mbp, p.nbp, p.kbp, m, n, p.D, Cout,
+                                   ldc, (int64_t)ldc * n, dbg_pair, static_cast<double *>(dbg_out), lddbg,
+                                   layout_for(p.fmt), st);
+  return hipErrorInvalidValue;
 }
 
+// One product in the given form with D slices (arguments already validated).
 template <typename T, int C>
-int run(int fmt, int m, int n, int k, const T *A, int lda, const T *B, int ldb, T *Cm, int ldc, hipStream_t st) {
-  int s = validate(m, n, k, A, lda, B, ldb, Cm, ldc);
-  if (s) return s;
-  if ((s = check_device_cached())) return s;
-  const int mode = g_opt.mode[fmt];
-  const int D = slices_for(fmt, mode, k);
+int run_with(int fmt, int mode, int D, int m, int n, int k, const T *A, int lda, const T *B, int ldb, T *Cm, int ldc,
+             hipStream_t st) {
+  int s;
   g_opt.last_slices = D;
   if (m == 0 || n == 0) return 0;
   if (k == 0) return hip_status(launch_zero_matrix(Cm, sizeof(T), C, m, n, ldc, (int64_t)ldc * n, st));
@@ -368,6 +371,30 @@ int run(int fmt, int m, int n, int k, const T *A, int lda, const T *B, int ldb, 
         if (x) g_prof.pool.push_back(x);
   }
   return hip_status(e);
+}
+
+template <typename T, int C>
+int run(int fmt, int m, int n, int k, const T *A, int lda, const T *B, int ldb, T *Cm, int ldc, hipStream_t st) {
+  int s = validate(m, n, k, A, lda, B, ldb, Cm, ldc);
+  if (s) return s;
+  if ((s = check_device_cached())) return s;
+  const int mode = g_opt.mode[fmt];
+  return run_with<T, C>(fmt, mode, slices_for(fmt, mode, k), m, n, k, A, lda, B, ldb, Cm, ldc, st);
+}
+
+// Longer binary64 expansions (c = 2 .. kMaxNd components), INT8 form: the
+// policy of the INT8 form with the bound 2^-(50 c) (|A||B|) (DD / TD / QD:
+// 100 / 150 / 200 bits).
+int nd_auto_slices(int c, int64_t k) { return (50 * c + (k < 2048 ? 14 : 10) + 6) / 7; }
+
+template <int C>
+int run_nd(int D, int m, int n, int k, const double *A, int lda, const double *B, int ldb, double *Cm, int ldc,
+           hipStream_t st) {
+  int s = validate(m, n, k, A, lda, B, ldb, Cm, ldc);
+  if (s) return s < 0 ? s - 2 : s;  // shifted past (c, D)
+  if ((s = check_device_cached())) return s;
+  return run_with<double, C>(MPGEMM_QD, MPGEMM_MODE_INT8, D > 0 ? D : nd_auto_slices(C, k), m, n, k, A, lda, B, ldb,
+                             Cm, ldc, st);
 }
 
 template <typename T, int C>
@@ -479,6 +506,73 @@ int mpgemm_qd(int m, int n, int k, const double *A, int lda, const double *B, in
 int mpgemm_ts(int m, int n, int k, const float *A, int lda, const float *B, int ldb, float *C, int ldc,
               hipStream_t stream) {
   return run<float, 3>(MPGEMM_TS, m, n, k, A, lda, B, ldb, C, ldc, stream);
+}
+
+#define MP_ND_CASES(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
+
+int mpgemm_nd(int c, int D, int m, int n, int k, const double *A, int lda, const double *B, int ldb, double *C,
+              int ldc, hipStream_t stream) {
+  if (c < 2 || c > kMaxNd) return -1;
+  if (D < 0 || D > kMaxDNd) return -2;
+  switch (c) {
+#define MP_CASE(CC) \
+  case CC:          \
+    return run_nd<CC>(D, m, n, k, A, lda, B, ldb, C, ldc, stream);
+    MP_ND_CASES(MP_CASE)
+#undef MP_CASE
+  }
+  return -1;
+}
+
+int mpgemm_nd_num_slices(int c, int k) {
+  if (c < 2 || c > kMaxNd) return -1;
+  if (k < 0) return -2;
+  return nd_auto_slices(c, k);
+}
+
+size_t mpgemm_nd_workspace_bytes(int c, int D, int m, int n, int k) {
+  if (c < 2 || c > kMaxNd || D < 0 || D > kMaxDNd || m < 0 || n < 0 || k < 0) return 0;
+  if (m == 0 || n == 0 || k == 0) return 0;
+  return make_plan(MPGEMM_QD, MPGEMM_MODE_INT8, m, n, k, D > 0 ? D : nd_auto_slices(c, k)).total;
+}
+
+int mpgemm_nd_debug_split(int c, int operand, int rows, int cols, const double *X, int ldx, int D, int8_t *digits,
+                          int *exps, hipStream_t stream) {
+  if (c < 2 || c > kMaxNd) return -1;
+  if (operand != 0 && operand != 1) return -2;
+  if (D < 0 || D > kMaxDNd) return -7;
+  const int k = operand == 0 ? cols : rows;
+  if (D == 0) D = nd_auto_slices(c, k);
+  switch (c) {
+#define MP_CASE(CC)                                                                                            \
+  case CC: {                                                                                                   \
+    const int s = debug_split_t<double, CC>(MPGEMM_QD, MPGEMM_MODE_INT8, operand, rows, cols, X, ldx, D, digits, \
+                                            exps, stream);                                                     \
+    return s < 0 ? s + 1 : s; /* (c, operand) in place of (fmt, mode, operand) */                              \
+  }
+    MP_ND_CASES(MP_CASE)
+#undef MP_CASE
+  }
+  return -1;
+}
+
+int mpgemm_nd_debug_products(int c, int m, int n, int k, const double *A, int lda, const double *B, int ldb, int D,
+                             int g, int64_t *out, int ldo, hipStream_t stream) {
+  if (c < 2 || c > kMaxNd) return -1;
+  if (D < 0 || D > kMaxDNd) return -9;
+  if (D == 0) D = nd_auto_slices(c, k < 0 ? 0 : k);
+  if (g < 1 || g > D) return -10;
+  switch (c) {
+#define MP_CASE(CC)                                                                                                  \
+  case CC: {                                                                                                         \
+    const int s = debug_products_t<double, CC>(MPGEMM_QD, MPGEMM_MODE_INT8, m, n, k, A, lda, B, ldb, D, g, 0, out, ldo, \
+                                               stream);                                                              \
+    return s < 0 ? s + 1 : s; /* c in place of (fmt, mode) */                                                        \
+  }
+    MP_ND_CASES(MP_CASE)
+#undef MP_CASE
+  }
+  return -1;
 }
 
 int mpgemm_set_mode(int fmt, int mode) {

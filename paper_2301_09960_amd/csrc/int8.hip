@@ -466,6 +466,16 @@ hipError_t launch_int8_batched(const Int8GemmDesc *descs, const int4 *items, int
 MP_INT8_INST(2)
 MP_INT8_INST(3)
 MP_INT8_INST(4)
+MP_INT8_INST(5)
+MP_INT8_INST(6)
+MP_INT8_INST(7)
+MP_INT8_INST(8)
+MP_INT8_INST(9)
+MP_INT8_INST(10)
+MP_INT8_INST(11)
+MP_INT8_INST(12)
+MP_INT8_INST(13)
+MP_INT8_INST(14)
 template hipError_t launch_int8_batched<2>(const Int8GemmDesc *, const int4 *, int, int *, int, const int *, int,
                                            int64_t, hipStream_t);
 template hipError_t launch_int8_batched<3>(const Int8GemmDesc *, const int4 *, int, int *, int, const int *, int,

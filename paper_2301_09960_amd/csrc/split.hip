@@ -440,6 +440,19 @@ template hipError_t launch_split_int8_batched<3>(const SplitOperand<double> *, c
 template hipError_t launch_split_int8_batched<4>(const SplitOperand<double> *, const int *, const int *, int, int,
                                                  int64_t, void *, int64_t, hipStream_t);
 
+#define MP_SPLIT_INT8_LONG(C) \
+  template hipError_t launch_split_int8<C>(const SplitOperand<double> &, const SplitOperand<double> &, int, hipStream_t);
+MP_SPLIT_INT8_LONG(5)
+MP_SPLIT_INT8_LONG(6)
+MP_SPLIT_INT8_LONG(7)
+MP_SPLIT_INT8_LONG(8)
+MP_SPLIT_INT8_LONG(9)
+MP_SPLIT_INT8_LONG(10)
+MP_SPLIT_INT8_LONG(11)
+MP_SPLIT_INT8_LONG(12)
+MP_SPLIT_INT8_LONG(13)
+MP_SPLIT_INT8_LONG(14)
+#undef MP_SPLIT_INT8_LONG
 template hipError_t launch_split_int8<2>(const SplitOperand<double> &, const SplitOperand<double> &, int, hipStream_t);
 template hipError_t launch_split_int8<3>(const SplitOperand<double> &, const SplitOperand<double> &, int, hipStream_t);
 template hipError_t launch_split_int8<4>(const SplitOperand<double> &, const SplitOperand<double> &, int, hipStream_t);

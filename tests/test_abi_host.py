@@ -77,6 +77,26 @@ def test_workspace_bytes(L):
     assert mp.workspace_bytes("ts", "float", 65, 1, 33, 1) >= 1 * 128 * 64 * 4 + 1 * 64 * 64 * 4
 
 
+def test_long_expansion_entry_points(L):
+    P = ctypes.c_void_p
+    x = P(16)
+    f = L.mpgemm_nd
+    assert f(1, 0, 4, 4, 4, x, 4, x, 4, x, 4, None) == -1
+    assert f(15, 0, 4, 4, 4, x, 4, x, 4, x, 4, None) == -1
+    assert f(8, -1, 4, 4, 4, x, 4, x, 4, x, 4, None) == -2
+    assert f(8, 113, 4, 4, 4, x, 4, x, 4, x, 4, None) == -2
+    assert f(8, 0, -1, 4, 4, x, 4, x, 4, x, 4, None) == -3
+    assert f(8, 0, 4, 4, 4, x, 3, x, 4, x, 4, None) == -7
+    assert f(8, 0, 4, 4, 4, x, 4, x, 4, x, 3, None) == -11
+    # automatic digit slices: the INT8 policy with t = 50 c (c = 2, 3, 4 as DD, TD, QD)
+    assert [L.mpgemm_nd_num_slices(c, 128) for c in (2, 3, 4)] == [17, 24, 31]
+    assert [L.mpgemm_nd_num_slices(c, 4096) for c in (2, 3, 4)] == [16, 23, 30]
+    assert L.mpgemm_nd_num_slices(14, 128) == 102 and L.mpgemm_nd_num_slices(8, 4096) == 59
+    assert L.mpgemm_nd_num_slices(1, 128) == -1
+    assert L.mpgemm_nd_workspace_bytes(8, 0, 0, 5, 5) == 0
+    assert L.mpgemm_nd_workspace_bytes(8, 0, 100, 100, 100) > 59 * 2 * 128 * 128
+
+
 def test_batched_argument_codes(L):
     IA = ctypes.c_int * 1
     PA = ctypes.c_void_p * 1

@@ -205,11 +205,12 @@ def test_error_falls_with_D_and_saturates_on_eq1_data(orc):
     assert abs(errs[-1] - errs[-3]) < 6 and errs[-1] < -95  # D = 6..8 saturate near 2^-106
 
 
-@pytest.mark.parametrize("fmt", ["dd", "qd"])
-def test_int8_digits_against_python_rationals(orc, fmt):
+@pytest.mark.parametrize("fmt,D", [("dd", 17), ("qd", 17), ("8d", 61), ("14d", 104)])
+def test_int8_digits_against_python_rationals(orc, fmt, D):
     """INT8 digits: equal to an independent rational implementation of the same
-    rule; |d| <= 64; a = sum_s d_s u_s + r exactly with |r| <= u_D/2 (1 + 2^-40)."""
-    m, k, D = 4, 9, 17
+    rule; |d| <= 64; a = sum_s d_s u_s + r exactly with |r| <= u_D/2 (1 + 2^-40).
+    Long expansions (8 and 14 binary64 components) included."""
+    m, k = 4, 9
     A = W.gen_matrix(fmt, m, k, E=16, seed=31, operand="A")
     dg, E = orc.split_int8(A, D, "rows")
     for i in range(m):
@@ -246,14 +247,43 @@ def test_int8_diag_sums_and_combination(orc):
             assert C[0, j, i] == float(v) and C[1, j, i] == float(v - Fraction(C[0, j, i]))
 
 
-@pytest.mark.parametrize("fmt,D", [("dd", 17), ("td", 24), ("qd", 31)])
+@pytest.mark.parametrize("fmt,D", [("dd", 17), ("td", 24), ("qd", 31), ("6d", 46), ("10d", 74), ("14d", 103)])
 def test_int8_form_meets_bound(orc, fmt, D):
-    m, n, k = 19, 13, 200
+    """INT8 form within 2^-t (|A||B|), t = 50 c (100 / 150 / 200 for DD / TD / QD)."""
+    m, n, k = 19, 13, 200 if fmt in T_BITS else 60
     A, B = W.gen_pair(fmt, m, n, k, E=16, seed=23)
     C = orc.int8_gemm(A, B, D)
     diff, absab, _ = orc.exact_check(A, B, C)
-    ok, worst = orc.bound_report(diff, absab, T_BITS[fmt])
+    t = T_BITS.get(fmt, 50 * A.shape[0])
+    ok, worst = orc.bound_report(diff, absab, t)
     assert ok, worst
+    if fmt not in T_BITS:  # the last digits matter: four fewer miss the bound
+        C4 = orc.int8_gemm(A, B, D - 4)
+        diff4, _, _ = orc.exact_check(A, B, C4)
+        assert not orc.bound_report(diff4, absab, t)[0]
+
+
+@pytest.mark.parametrize("fmt", ["8d", "14d"])
+def test_exact_check_long_expansions(orc, fmt):
+    """The exact checker with 8 and 14 components: AB rounded once equals the
+    rational product rounded, and C = that rounding's greedy expansion has
+    |C - AB| below 2^-(53 c - 1) |AB|."""
+    m, n, k = 3, 2, 4
+    A, B = W.gen_pair(fmt, m, n, k, E=8, seed=41)
+    c = A.shape[0]
+    P = X.matmul_fraction(A, B)  # (m, n) exact
+    C = np.zeros((c, n, m))
+    for i in range(m):
+        for j in range(n):
+            r = P[i][j]
+            for q in range(c):  # greedy expansion of the exact value
+                C[q, j, i] = float(r)
+                r -= Fraction(C[q, j, i])
+    diff, absab, cex = orc.exact_check(A, B, C)
+    for i in range(m):
+        for j in range(n):
+            assert cex[j, i] == float(P[i][j])
+            assert diff[j, i] <= abs(float(P[i][j])) * 2.0 ** -(53 * c - 1)
 
 
 @pytest.mark.parametrize("fmt", ["dd", "td", "qd", "ts"])

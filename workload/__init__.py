@@ -10,7 +10,8 @@ Recipe (synthetic stand-in for the paper's random test matrices of Section 1,
 eq. (1), which draw ``(ru - 0.5) * exp(rn)``; here the exponent spread is a
 uniform integer instead of a log-normal factor, so the spread is a parameter):
 
-* binary64 formats (DD, TD, QD with c = 2, 3, 4 components):
+* binary64 formats (DD, TD, QD with c = 2, 3, 4 components; "5d" .. "14d"
+  with c = 5 .. 14):
   ``x0 = u * 2**e`` with ``u`` uniform on ``[-1, 1)`` on a ``2**-52`` grid and
   ``e`` a uniform integer in ``{0..E}``; then
   ``x_r = RN(x_{r-1} * 2**-53 * v_r)`` with ``v_r`` uniform on ``[-0.5, 0.5)``,
@@ -30,6 +31,8 @@ from __future__ import annotations
 import numpy as np
 
 FORMATS = {"dd": (2, np.float64), "td": (3, np.float64), "qd": (4, np.float64), "ts": (3, np.float32)}
+# longer binary64 expansions ("5d" .. "14d": 265 to 742 bits in 53-bit steps)
+FORMATS.update({f"{c}d": (c, np.float64) for c in range(5, 15)})
 
 _GOLDEN = np.uint64(0x9E3779B97F4A7C15)
 _M1 = np.uint64(0xBF58476D1CE4E5B9)
