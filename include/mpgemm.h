@@ -107,8 +107,10 @@ int mpgemm_ts(int m, int n, int k, const float *A, int lda, const float *B, int 
  * call's pointers.  The cached workspace of a shape stays allocated until it
  * is released or mpgemm_batched_cache_clear is called.  Batched calls of one
  * shape on one stream must not be issued from two host threads at once.
- * Both slice forms (the thread's mode for the format).  The INT8 form uses
- * 128 x 128 tiles and spreads each product's diagonals over several work items.
+ * Both slice forms (the thread's mode for the format).  In the INT8 form each
+ * product takes the tile configuration a single call would (two persistent
+ * launches, 128 x 128 and 256 x 256 tiles), its diagonals spread over several
+ * work items.
  * Return codes: -1 for count < 0; -i (i = 2..10) for a NULL array or an
  * invalid entry of argument i (first failing product); positive codes as above.
  */

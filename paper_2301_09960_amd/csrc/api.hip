@@ -99,6 +99,7 @@ int slices_for(int fmt, int mode, int64_t k) {
   return s > 0 ? s : auto_slices(fmt, mode, k);
 }
 int thread_mode(int fmt) { return g_opt.mode[fmt]; }
+int int8_tile_override() { return g_opt.int8_tile; }
 
 // Wave layout of the binary64/binary32 slice-product kernel per format:
 // compiled-in defaults (measured), replaced by the file named in the

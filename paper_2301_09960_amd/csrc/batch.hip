@@ -43,12 +43,12 @@ struct ProductLayout {
   int64_t mbp, nbp, kbp;
   size_t resid_a, resid_b, pack_a, pack_b, mu_a, mu_b, exp_a, exp_b;
   // INT8 form: k blocks per chunk, chunks, diagonal groups, diagonal sums
-  int kbc = 0, nchunks = 0, groups = 1;
+  int kbc = 0, nchunks = 0, groups = 1, cfg = 1;
   size_t sums = 0;
 };
 
 struct BatchPlan {
-  int device = 0, fmt = 0, mode = 0, layout = 1;
+  int device = 0, fmt = 0, mode = 0, layout = 1, int8_tile = 0;
   hipStream_t stream = nullptr;
   std::vector<int> m, n, k, D;
   std::vector<ProductLayout> prod;
@@ -56,7 +56,7 @@ struct BatchPlan {
   char *ws = nullptr;
   size_t off_ops = 0, off_descs = 0, desc_bytes = 0, off_prefix0 = 0, off_prefixp = 0, off_items = 0,
          off_counter = 0, off_mu = 0, mu_bytes = 0, off_prefixc = 0, total = 0;
-  int nops = 0, tiles0 = 0, tilesp = 0, dmax = 0, nitems = 0;
+  int nops = 0, tiles0 = 0, tilesp = 0, dmax = 0, nitems = 0, nitems3 = 0;
   int64_t blocks8 = 0, blocksc = 0;  // INT8 form: split blocks, combine blocks
   void *stage = nullptr;
   hipEvent_t stage_done = nullptr;
@@ -291,8 +291,7 @@ void write_descriptors(BatchPlan &p, const T *const *A, const int *lda, const T 
 // GEMM over (product, 128 x 128 tile, k chunk, diagonal group) items, longest
 // first, and one combine over every product's blocks.
 template <int C>
-int build_plan_int8(BatchPlan &p) {
-  constexpr int kTB = 4;  // the 128 x 128 configuration: slices padded to 128 rows
+int build_plan_int8(BatchPlan &p, int cfg_override) {
   const int count = (int)p.m.size();
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -312,8 +311,10 @@ int build_plan_int8(BatchPlan &p) {
     if (L.m <= 0 || L.n <= 0 || L.k <= 0) continue;
     p.live.push_back(g);
     L.rho = 0;
-    L.mbp = nblocks8_padded(L.m, kTB);
-    L.nbp = nblocks8_padded(L.n, kTB);
+    // tile configuration as for a single call (configuration 2 runs as 3)
+    L.cfg = int8_tile_config(L.m, L.n, cfg_override) == 1 ? 1 : 3;
+    L.mbp = nblocks8_padded(L.m, int8_tile_blocks(L.cfg));
+    L.nbp = nblocks8_padded(L.n, int8_tile_blocks(L.cfg));
     L.kbp = kblocks8_padded(L.k);
     L.kbc = int8_kblocks_per_chunk(L.D);
     L.nchunks = (int)ceil_div(L.kbp, L.kbc);
@@ -350,18 +351,22 @@ int build_plan_int8(BatchPlan &p) {
   int64_t work = 0;
   for (int g : p.live) {
     const ProductLayout &L = p.prod[g];
-    work += (L.mbp / kTB) * (L.nbp / kTB) * cum(L.D) * L.kbp;
+    const int tb = int8_tile_blocks(L.cfg);
+    work += (L.mbp / tb) * (L.nbp / tb) * (tb / 4) * (tb / 4) * cum(L.D) * L.kbp;  // in 128 x 128 tile units
   }
   const int64_t target = std::max<int64_t>(1, work / (4 * (int64_t)kPersistentGrid));
   struct Item {
     int slot, tile, chunk, group;
     int64_t cost;
   };
-  std::vector<Item> items;
+  std::vector<Item> items, items3;
   for (int slot = 0; slot < (int)p.live.size(); ++slot) {
     ProductLayout &L = p.prod[p.live[slot]];
-    L.groups = (int)std::min<int64_t>(L.D, std::max<int64_t>(1, ceil_div(cum(L.D) * L.kbc, target)));
-    const int ntiles = (int)((L.mbp / kTB) * (L.nbp / kTB));
+    const int tb = int8_tile_blocks(L.cfg);
+    const int64_t unit = (tb / 4) * (tb / 4);  // 128 x 128 tiles in one tile
+    L.groups = (int)std::min<int64_t>(L.D, std::max<int64_t>(1, ceil_div(cum(L.D) * L.kbc * unit, target)));
+    const int ntiles = (int)((L.mbp / tb) * (L.nbp / tb));
+    std::vector<Item> &dst = L.cfg == 1 ? items : items3;
     for (int z = 0; z < L.groups; ++z) {
       // the same cut as the device: smallest g with cum(g) >= target pairs
       auto first_reaching = [&](int64_t t) {
@@ -374,14 +379,18 @@ int build_plan_int8(BatchPlan &p) {
       if (b1 == b0) continue;  // empty group
       for (int c = 0; c < L.nchunks; ++c) {
         const int64_t kblocks = std::min<int64_t>(L.kbc, L.kbp - (int64_t)c * L.kbc);
-        for (int t = 0; t < ntiles; ++t) items.push_back({slot, t, c, z, (cum(b1) - cum(b0)) * kblocks});
+        for (int t = 0; t < ntiles; ++t) dst.push_back({slot, t, c, z, (cum(b1) - cum(b0)) * kblocks});
       }
     }
   }
-  std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
+  auto longest_first = [](const Item &a, const Item &b) { return a.cost > b.cost; };
+  std::stable_sort(items.begin(), items.end(), longest_first);
+  std::stable_sort(items3.begin(), items3.end(), longest_first);
   p.nitems = (int)items.size();
+  p.nitems3 = (int)items3.size();
+  items.insert(items.end(), items3.begin(), items3.end());
   p.off_items = take(items.size() * sizeof(int4));
-  p.off_counter = take(4);
+  p.off_counter = take(8);
   p.total = o;
 
   if (hipMalloc(&p.ws, p.total > 0 ? p.total : 256) != hipSuccess) {
@@ -426,11 +435,11 @@ int build_plan_int8(BatchPlan &p) {
       reinterpret_cast<const SplitOperand<double> *>(p.ws + p.off_ops),
       reinterpret_cast<const int *>(p.ws + p.off_prefix0), reinterpret_cast<const int *>(p.ws + p.off_prefixp),
       p.nops, p.tiles0, p.blocks8, p.ws + p.off_mu, (int64_t)(p.mu_bytes / 4), cs);
-  if (e == hipSuccess) e = launch_fill32(p.ws + p.off_counter, 1, 0u, cs);
+  if (e == hipSuccess) e = launch_fill32(p.ws + p.off_counter, 2, 0u, cs);
   if (e == hipSuccess)
     e = launch_int8_batched<C>(reinterpret_cast<const Int8GemmDesc *>(p.ws + p.off_descs),
-                               reinterpret_cast<const int4 *>(p.ws + p.off_items), p.nitems,
-                               reinterpret_cast<int *>(p.ws + p.off_counter), std::min(p.nitems, kPersistentGrid),
+                               reinterpret_cast<const int4 *>(p.ws + p.off_items), p.nitems, p.nitems3,
+                               reinterpret_cast<int *>(p.ws + p.off_counter),
                                reinterpret_cast<const int *>(p.ws + p.off_prefixc), (int)p.live.size(), p.blocksc,
                                cs);
   hipGraph_t graph = nullptr;
@@ -546,6 +555,7 @@ int run_batched(int fmt, int count, const int *m, const int *n, const int *k, co
   BatchPlan *plan = nullptr;
   for (BatchPlan *p : bc.plans)
     if (p->device == dev && p->stream == st && p->fmt == fmt && p->mode == mode && p->layout == layout &&
+        p->int8_tile == int8_tile_override() &&
         (int)p->m.size() == count &&
         std::equal(p->m.begin(), p->m.end(), m) && std::equal(p->n.begin(), p->n.end(), n) &&
         std::equal(p->k.begin(), p->k.end(), k) && p->D == Ds) {
@@ -567,12 +577,13 @@ int run_batched(int fmt, int count, const int *m, const int *n, const int *k, co
     plan->fmt = fmt;
     plan->mode = mode;
     plan->layout = layout;
+    plan->int8_tile = int8_tile_override();
     plan->m.assign(m, m + count);
     plan->n.assign(n, n + count);
     plan->k.assign(k, k + count);
     plan->D = Ds;
     if (mode == MPGEMM_MODE_INT8) {
-      if constexpr (sizeof(T) == 8) s = build_plan_int8<C>(*plan);
+      if constexpr (sizeof(T) == 8) s = build_plan_int8<C>(*plan, int8_tile_override());
     } else {
       s = build_plan<T, C>(*plan, st);
     }

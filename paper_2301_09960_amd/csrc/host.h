@@ -13,6 +13,8 @@ extern const int kCompsH[kNumFmtH];
 // Options of the calling host thread.
 int thread_mode(int fmt);
 int layout_for(int fmt);
+// The INT8 tile configuration this thread forces (0: chosen by size).
+int int8_tile_override();
 int slices_for(int fmt, int mode, int64_t k);
 void set_last_slices(int D);
 

@@ -336,14 +336,15 @@ __global__ __launch_bounds__(256) void k_int8_combine(const int32_t *__restrict_
     combine_one<C>(t, S, plane, nchunks, D, EA, EB, mbp, m, n, Cout, ldc, c_stride, debug_g, Sdbg, lddbg);
 }
 
-// Persistent INT8 GEMM of a batch (128 x 128 tiles): each workgroup takes
-// (product, tile, k chunk, diagonal group) items from a shared counter; items
-// are ordered by decreasing work.
-__global__ __launch_bounds__(64 * Int8Cfg<1>::WM * Int8Cfg<1>::WN, 1) void k_gemm_int8_batched(
+// Persistent INT8 GEMM of a batch in tile configuration CFG: each workgroup
+// takes (product, tile, k chunk, diagonal group) items from a shared counter;
+// items are ordered by decreasing work.
+template <int CFG>
+__global__ __launch_bounds__(64 * Int8Cfg<CFG>::WM * Int8Cfg<CFG>::WN, 1) void k_gemm_int8_batched(
     const Int8GemmDesc *__restrict__ descs, const int4 *__restrict__ items, int nitems, int *__restrict__ counter) {
-  __shared__ __attribute__((aligned(16))) int8_t lds[Int8Cfg<1>::NS * int8_stage_bytes<1>()];
+  __shared__ __attribute__((aligned(16))) int8_t lds[Int8Cfg<CFG>::NS * int8_stage_bytes<CFG>()];
   __shared__ int next;
-  constexpr int TB = Int8Cfg<1>::TB;
+  constexpr int TB = Int8Cfg<CFG>::TB;
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(counter, 1);
     __syncthreads();
@@ -357,10 +358,10 @@ __global__ __launch_bounds__(64 * Int8Cfg<1>::WM * Int8Cfg<1>::WN, 1) void k_gem
     const int chunk = w.z;
     const int64_t kb0 = (int64_t)chunk * d.kbc;
     const int64_t kb1 = kb0 + d.kbc < d.kbp ? kb0 + d.kbc : d.kbp;
-    const int nks = (int)((kb1 - kb0) / Int8Cfg<1>::KSB);
+    const int nks = (int)((kb1 - kb0) / Int8Cfg<CFG>::KSB);
     int g0, g1;
     diagonal_group(d.D, w.w, d.groups, g0, g1);
-    gemm_int8_tile<1>(d.Apk, d.Bpk, d.mbp, d.nbp, d.kbp, kb0, nks, d.D, d.m, d.n, d.S, d.plane, chunk, d.nchunks,
+    gemm_int8_tile<CFG>(d.Apk, d.Bpk, d.mbp, d.nbp, d.kbp, kb0, nks, d.D, d.m, d.n, d.S, d.plane, chunk, d.nchunks,
                       tm, tn, g0, g1, lds);
   }
 }
@@ -445,11 +446,19 @@ hipError_t launch_gemm_int8(const void *Apk, const void *Bpk, const int *EA, con
 }
 
 template <int C>
-hipError_t launch_int8_batched(const Int8GemmDesc *descs, const int4 *items, int nitems, int *counter, int grid,
+hipError_t launch_int8_batched(const Int8GemmDesc *descs, const int4 *items, int nitems1, int nitems3, int *counters,
                                const int *prefix_blocks, int nprod, int64_t blocks, hipStream_t st) {
-  if (nitems > 0 && grid > 0) {
-    hipLaunchKernelGGL(k_gemm_int8_batched, dim3(grid), dim3(64 * Int8Cfg<1>::WM * Int8Cfg<1>::WN), 0, st, descs,
-                       items, nitems, counter);
+  // items [0, nitems1): 128 x 128 tiles, two workgroups per CU; then the 256 x 256 ones, one per CU
+  if (nitems1 > 0) {
+    hipLaunchKernelGGL(k_gemm_int8_batched<1>, dim3(std::min(nitems1, 512)),
+                       dim3(64 * Int8Cfg<1>::WM * Int8Cfg<1>::WN), 0, st, descs, items, nitems1, counters);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  if (nitems3 > 0) {
+    hipLaunchKernelGGL(k_gemm_int8_batched<3>, dim3(std::min(nitems3, 256)),
+                       dim3(64 * Int8Cfg<3>::WM * Int8Cfg<3>::WN), 0, st, descs, items + nitems1, nitems3,
+                       counters + 1);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
@@ -479,11 +488,11 @@ MP_INT8_INST(11)
 MP_INT8_INST(12)
 MP_INT8_INST(13)
 MP_INT8_INST(14)
-template hipError_t launch_int8_batched<2>(const Int8GemmDesc *, const int4 *, int, int *, int, const int *, int,
+template hipError_t launch_int8_batched<2>(const Int8GemmDesc *, const int4 *, int, int, int *, const int *, int,
                                            int64_t, hipStream_t);
-template hipError_t launch_int8_batched<3>(const Int8GemmDesc *, const int4 *, int, int *, int, const int *, int,
+template hipError_t launch_int8_batched<3>(const Int8GemmDesc *, const int4 *, int, int, int *, const int *, int,
                                            int64_t, hipStream_t);
-template hipError_t launch_int8_batched<4>(const Int8GemmDesc *, const int4 *, int, int *, int, const int *, int,
+template hipError_t launch_int8_batched<4>(const Int8GemmDesc *, const int4 *, int, int, int *, const int *, int,
                                            int64_t, hipStream_t);
 #undef MP_INT8_INST
 

@@ -82,13 +82,14 @@ hipError_t launch_split_int8_batched(const SplitOperand<double> *ops, const int 
                                      int nops, int tiles_max0, int64_t blocks, void *mu_all, int64_t mu_words,
                                      hipStream_t st);
 
-// INT8-form batch: persistent GEMM over items (product, tile, k chunk,
-// diagonal group) taken through *counter (cleared by the caller), with the
-// 128 x 128 tile configuration (slices padded to 128 rows); then the combine
-// of every product, prefix_blocks giving the running sums of the 32 x 32
-// blocks of each product's C.
+// INT8-form batch: persistent GEMMs over items (product, tile, k chunk,
+// diagonal group): items[0, nitems1) in the 128 x 128 configuration (their
+// products' slices padded to 128 rows), then nitems3 in the 256 x 256 one,
+// taken through counters[0] and counters[1] (cleared by the caller); then the
+// combine of every product, prefix_blocks giving the running sums of the
+// 32 x 32 blocks of each product's C.
 template <int C>
-hipError_t launch_int8_batched(const Int8GemmDesc *descs, const int4 *items, int nitems, int *counter, int grid,
+hipError_t launch_int8_batched(const Int8GemmDesc *descs, const int4 *items, int nitems1, int nitems3, int *counters,
                                const int *prefix_blocks, int nprod, int64_t blocks, hipStream_t st);
 
 // Fused slice-product GEMM with error-free accumulation into C (C components).
