@@ -49,8 +49,9 @@ __device__ __forceinline__ void renorm(T (&x)[N]) {
     T err;
     T nt = two_sum(t, e[i], err);
     const bool emit = err != T(0);
+    // before step i at most i - 1 terms were emitted, so w < i
 #pragma unroll
-    for (int q = 0; q < N; ++q)
+    for (int q = 0; q < i; ++q)
       if (emit && q == w) out[q] = nt;
     t = emit ? err : nt;
     w += emit ? 1 : 0;
