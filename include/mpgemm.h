@@ -153,9 +153,10 @@ int mpgemm_tile_layout(int fmt);
 
 /*
  * Tile configuration of the INT8-form kernel, per host thread: 0 automatic
- * (256 x 256 tiles when they give at least one workgroup per CU, else
- * 128 x 128), 1 = 128 x 128 with 4 wavefronts, 2 = 256 x 256 with 4,
- * 3 = 256 x 256 with 8.  Returns -1 for other values.
+ * (256 x 256 tiles with 8 wavefronts unless padding to them more than doubles
+ * the area padded to 128 x 128, else 128 x 128), 1 = 128 x 128 with 4
+ * wavefronts, 2 = 256 x 256 with 4, 3 = 256 x 256 with 8, 4 = 256 x 256 with
+ * 16.  Slices are padded to the chosen tile.  Returns -1 for other values.
  */
 int mpgemm_set_int8_tile(int cfg);
 int mpgemm_set_num_slices(int fmt, int mode, int D);

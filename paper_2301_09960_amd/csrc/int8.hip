@@ -9,12 +9,15 @@
 // 32-bit sum of up to 2^31 / 4096 digit products is exact; k is cut into
 // chunks short enough for that bound, each chunk writing its own partial S_g.
 //
-// k_gemm_int8: one workgroup per tile of C (128 x 128 or 256 x 256) and k
-// chunk; each wavefront owns a grid of 32 x 32 blocks of
-// v_mfma_i32_32x32x32_i8.  Panels of A_s and B_t (64 or 128 k per step)
-// move global -> LDS by direct loads into a ring of 2 to 4 stages, as in the
-// floating-point kernel.  After the last pair of a diagonal the 32-bit tile is
-// written to the S_g plane in a blocked layout (16-byte stores per lane).
+// k_gemm_int8: one workgroup per tile of C (128 x 128 or 256 x 256), k chunk
+// and group of diagonals (the diagonal sums are independent, so a small
+// product spreads its diagonals over the grid); each wavefront owns a grid of
+// 32 x 32 blocks of v_mfma_i32_32x32x32_i8.  Panels of A_s and B_t (64 or 128
+// k per step) move global -> LDS by direct loads into a ring of 2 to 4
+// stages, as in the floating-point kernel.  After the last pair of a diagonal
+// the 32-bit tile is written to the S_g plane in a blocked layout (16-byte
+// stores per lane).  k_gemm_int8_batched runs the same tiles as items of a
+// persistent launch over many products.
 //
 // k_int8_combine: per element, C = sum_g S_g 2^(E_i + F_j + 2 - 7 (g + 1)),
 // every term exact in binary64, added with TwoSum into a (c+1)-term
@@ -84,6 +87,8 @@ __device__ __forceinline__ void wait_step(int64_t later) {
 //   config 1: 128 x 128 tile, 4 wavefronts of 64 x 64 (small products)
 //   config 2: 256 x 256 tile, 4 wavefronts of 128 x 128 (accumulators in AGPRs;
 //             LDS traffic per instruction halved)
+//   config 4: 256 x 256 tile, 16 wavefronts of 64 x 64 (more wavefronts to
+//             hide latency, more LDS reads per instruction), k steps of 128
 //   config 3: 256 x 256 tile, 8 wavefronts of 128 x 64, k steps of 128 in a
 //             2-stage ring (half the barriers of 64-wide steps, and 64 KiB
 //             requested per step)
@@ -92,6 +97,7 @@ template <int CFG> struct Int8Cfg;
 template <> struct Int8Cfg<1> { static constexpr int TB = 4, WM = 2, WN = 2, KSB = 2, NS = 4; };
 template <> struct Int8Cfg<2> { static constexpr int TB = 8, WM = 2, WN = 2, KSB = 2, NS = 4; };
 template <> struct Int8Cfg<3> { static constexpr int TB = 8, WM = 2, WN = 4, KSB = 4, NS = 2; };
+template <> struct Int8Cfg<4> { static constexpr int TB = 8, WM = 4, WN = 4, KSB = 4, NS = 2; };
 
 template <int CFG>
 constexpr int int8_stage_bytes() {
@@ -400,7 +406,7 @@ int int8_kblocks_per_chunk(int D) {
 // the larger tile ran 1.6 to 2 times faster from n = 1024 up
 // (DD and QD at n = 1024, 2048, 3072).
 int int8_tile_config(int64_t m, int64_t n, int cfg) {
-  if (cfg >= 1 && cfg <= 3) return cfg;
+  if (cfg >= 1 && cfg <= 4) return cfg;
   const int64_t area3 = ceil_div(m, 256) * ceil_div(n, 256) * 4, area1 = ceil_div(m, 128) * ceil_div(n, 128);
   return area3 <= 2 * area1 ? 3 : 1;
 }
@@ -422,12 +428,16 @@ hipError_t launch_gemm_int8(const void *Apk, const void *Bpk, const int *EA, con
   // over gridDim.z so the grid still fills the chip (256 workgroups of the
   // 256 x 256 configuration, 512 of the smaller ones)
   const int64_t wgs = (mbp / tb) * (nbp / tb) * nchunks;
-  const int64_t want = use == 3 ? 256 : 512;
+  const int64_t want = use >= 3 ? 256 : 512;
   const int groups = wgs >= want ? 1 : (int)std::min<int64_t>(D, ceil_div(want, wgs));
   if (use == 2) {
     const int64_t tiles = (mbp / 8) * (nbp / 8);
     hipLaunchKernelGGL((k_gemm_int8<2>), dim3((unsigned)tiles, (unsigned)nchunks, (unsigned)groups), dim3(256), 0, st, a, b, mbp, nbp,
                        kbp, kbc, D, m, n, Sws, plane);
+  } else if (use == 4) {
+    const int64_t tiles = (mbp / 8) * (nbp / 8);
+    hipLaunchKernelGGL((k_gemm_int8<4>), dim3((unsigned)tiles, (unsigned)nchunks, (unsigned)groups), dim3(1024), 0, st,
+                       a, b, mbp, nbp, kbp, kbc, D, m, n, Sws, plane);
   } else if (use == 3) {
     const int64_t tiles = (mbp / 8) * (nbp / 8);
     hipLaunchKernelGGL((k_gemm_int8<3>), dim3((unsigned)tiles, (unsigned)nchunks, (unsigned)groups), dim3(512), 0, st, a, b, mbp, nbp,

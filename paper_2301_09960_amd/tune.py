@@ -44,7 +44,7 @@ def time_layouts(fmt: str, n: int, reps: int = 3, E: int = 16):
 
 
 def time_int8_tiles(fmt: str, n: int, reps: int = 3, E: int = 16):
-    """INT8-form tile configurations 1..3 (GEMM + combine milliseconds)."""
+    """INT8-form tile configurations 1..4 (GEMM + combine milliseconds)."""
     import torch
 
     from workload import gen_pair
@@ -52,7 +52,7 @@ def time_int8_tiles(fmt: str, n: int, reps: int = 3, E: int = 16):
     dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
     C = torch.empty((COMPONENTS[fmt], n, n), dtype=dA.dtype, device="cuda")
     out = {}
-    for cfg in (1, 2, 3):
+    for cfg in (1, 2, 3, 4):
         set_int8_tile(cfg)
         gemm(fmt, dA, dB, C, mode="int8")
         torch.cuda.synchronize()

@@ -125,7 +125,7 @@ def test_int8_full_size_sampled(mp, orc, fmt, E, rows):
     assert ok
 
 
-@pytest.mark.parametrize("cfg", [1, 2, 3])
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
 def test_int8_every_tile_config(mp, orc, cfg):
     """Each INT8 tile configuration gives the exact diagonal sums and a C within
     the bound (sizes span several 256-wide tiles with ragged edges)."""
