@@ -247,3 +247,22 @@ def test_every_tile_layout(mp, orc, fmt, layout):
     sa, ea = orc.split_plain(A, D, "rows")
     sb, eb = orc.split_plain(B, D, "cols")
     assert np.array_equal(P, orc.slice_product(sa[0], ea[0], sb[D - 1], eb[D - 1], orc.rho(S, k), S))
+
+
+@pytest.mark.parametrize("fmt,mode,fewer", [("dd", "float", 2), ("qd", "float", 2), ("dd", "int8", 3),
+                                            ("qd", "int8", 3)])
+def test_automatic_slice_count_is_tight(mp, orc, fmt, mode, fewer):
+    """The automatic D meets the bound, and its guard is at most one slice
+    (binary64 slices, about 21 bits at k = 1024) or two digits (INT8, 7 bits
+    each): two slices or three digits fewer miss the bound on the same inputs
+    (e ~ U{0..16}, k = 1024)."""
+    m, n, k = 64, 48, 1024
+    A, B = W.gen_pair(fmt, m, n, k, E=16, seed=99)
+    dA, dB = dev(A), dev(B)
+    D = mp.num_slices(fmt, mode, k)
+    C = host(mp.gemm(fmt, dA, dB, mode=mode))
+    ok, worst = _check_bound(orc, fmt, A, B, C)
+    Cf = host(mp.gemm(fmt, dA, dB, mode=mode, slices=D - fewer))
+    ok_f, worst_f = _check_bound(orc, fmt, A, B, Cf)
+    say(f"{fmt} {mode}: D={D} worst {worst:.1f}; D={D - fewer} worst {worst_f:.1f} (bound -{T_BITS[fmt]})")
+    assert ok and not ok_f
