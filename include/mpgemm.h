@@ -142,14 +142,26 @@ int mpgemm_get_mode(int fmt);
 /*
  * Wavefront layout of the FLOAT-form slice-product kernel (64 x 64 tile of C
  * per workgroup): 1 = 4 wavefronts of 32 x 32, 2 = 8 of 32 x 16, 3 = 16 of
- * 16 x 16; 0 restores the tuned default.  The defaults are compiled in and
- * may be replaced by a file named in the environment variable
- * MPGEMM_TUNE_FILE, read once per process, with lines "<fmt> <layout>" (fmt
- * one of dd, td, qd, ts).  Per host thread; mpgemm_tile_layout returns the
- * layout a call would use.
+ * 16 x 16; 0 restores the tuned default.  Per host thread;
+ * mpgemm_tile_layout returns the layout a call would use.
+ *
+ * Tuned tables (process-wide).  The default layouts and the automatic slice
+ * counts are compiled in; a tuning file replaces them, read at first use from
+ * the path in the environment variable MPGEMM_TUNE_FILE, or loaded with
+ * mpgemm_load_tune_file (NULL restores the compiled-in tables).  Lines:
+ *   "<fmt> <layout>"                  fmt one of dd, td, qd, ts
+ *   "slices <fmt> <mode> <kmax> <D>"  mode float or int8: D slices for
+ *                                     k <= kmax (the smallest kmax covering
+ *                                     k applies; beyond them, the formula)
+ * as written by the autotuner (python -m paper_2301_09960_amd.tune).
+ * Returns 0, -1 if the file cannot be read, -2 for a line it does not accept
+ * (tables unchanged).  Per-thread settings (mpgemm_set_tile_layout,
+ * mpgemm_set_num_slices) take precedence.  Do not load while other threads
+ * are inside a call.
  */
 int mpgemm_set_tile_layout(int fmt, int layout);
 int mpgemm_tile_layout(int fmt);
+int mpgemm_load_tune_file(const char *path);
 
 /*
  * Tile configuration of the INT8-form kernel, per host thread: 0 automatic

@@ -72,6 +72,7 @@ def lib():
                 L.mpgemm_debug_products.argtypes = [_I, _I, _I, _I, _I, _P, _I, _P, _I, _I, _I, _I, _P, _I, _P]
                 L.mpgemm_profile_enable.argtypes = [_I]
                 L.mpgemm_profile_read.argtypes = [_P, _P, _I]
+                L.mpgemm_load_tune_file.argtypes = [ctypes.c_char_p]
                 L.mpgemm_nd.restype = _I
                 L.mpgemm_nd.argtypes = [_I, _I, _I, _I, _I, _P, _I, _P, _I, _P, _I, _P]
                 L.mpgemm_nd_num_slices.argtypes = [_I, _I]
@@ -149,6 +150,15 @@ def tile_layout(fmt) -> int:
 
 def set_num_slices(fmt, mode, D: int):
     _check(lib().mpgemm_set_num_slices(_fmt(fmt), _mode(mode), int(D)), "set_num_slices")
+
+
+def load_tune_file(path=None) -> None:
+    """Replace the process-wide tuned tables (wave layouts, slice counts) by a
+    tuning file's; None restores the compiled-in tables."""
+    st = lib().mpgemm_load_tune_file(None if path is None else str(path).encode())
+    if st == -1:
+        raise OSError(f"cannot read tuning file {path}")
+    _check(st, "load_tune_file")
 
 
 def num_slices(fmt, mode, k: int) -> int:

@@ -3,6 +3,7 @@
 //   split(A rows, B columns) -> fused slice-product GEMM + accumulation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <climits>
 #include <cstdint>
@@ -94,38 +95,98 @@ int auto_slices(int fmt, int mode, int64_t k) {
   return D;
 }
 
+// Tuned tables, process-wide: wave layouts per format and slice counts per
+// (format, form, k range), read from the file named in MPGEMM_TUNE_FILE at
+// first use, or from mpgemm_load_tune_file.  Lines:
+//   "<fmt> <layout>"                   wave layout of the FLOAT-form kernel
+//   "slices <fmt> <mode> <kmax> <D>"   D for k <= kmax (the smallest kmax that
+//                                      covers k wins; beyond all, the formula)
+// as written by paper_2301_09960_amd.tune.
+struct SliceEntry {
+  int fmt, mode;
+  int64_t kmax;
+  int D;
+};
+int g_layout_default[kNumFmt] = {1, 2, 2, 2};  // measured at n = 1024 and 4096 (DD, TD, QD, TS)
+std::vector<SliceEntry> g_slice_table;
+std::mutex g_tune_mu;
+std::once_flag g_tune_once;
+
+int fmt_index(const char *name) {
+  const char *names[kNumFmt] = {"dd", "td", "qd", "ts"};
+  for (int i = 0; i < kNumFmt; ++i)
+    if (std::strcmp(name, names[i]) == 0) return i;
+  return -1;
+}
+
+// Replaces the tables by the file's (nullptr: back to the compiled defaults).
+// Returns 0, -1 if the file cannot be read, -2 for a line it does not accept
+// (the tables are then left unchanged).
+int load_tune_tables(const char *path) {
+  int layout[kNumFmt] = {1, 2, 2, 2};
+  std::vector<SliceEntry> table;
+  if (path) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) return -1;
+    char line[256];
+    int bad = 0;
+    while (std::fgets(line, sizeof line, f)) {
+      char a[16], b[16];
+      int x = 0, D = 0;
+      long long kmax = 0;
+      if (line[0] == '#' || line[0] == '\n') continue;
+      if (std::sscanf(line, "slices %15s %15s %lld %d", a, b, &kmax, &D) == 4) {
+        const int fi = fmt_index(a);
+        const int mode = std::strcmp(b, "float") == 0 ? MPGEMM_MODE_FLOAT : std::strcmp(b, "int8") == 0 ? MPGEMM_MODE_INT8 : -1;
+        const int dmax = mode == MPGEMM_MODE_FLOAT ? kMaxDFloat : kMaxDInt8;
+        if (fi < 0 || mode < 0 || kmax < 1 || D < 1 || D > dmax || (mode == MPGEMM_MODE_INT8 && fi == MPGEMM_TS)) {
+          bad = 1;
+          break;
+        }
+        table.push_back({fi, mode, (int64_t)kmax, D});
+      } else if (std::sscanf(line, "%15s %d", a, &x) == 2 && fmt_index(a) >= 0 && x >= 1 && x <= 3) {
+        layout[fmt_index(a)] = x;
+      } else {
+        bad = 1;
+        break;
+      }
+    }
+    std::fclose(f);
+    if (bad) return -2;
+  }
+  std::sort(table.begin(), table.end(), [](const SliceEntry &p, const SliceEntry &q) { return p.kmax < q.kmax; });
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  std::copy(layout, layout + kNumFmt, g_layout_default);
+  g_slice_table = std::move(table);
+  return 0;
+}
+
+void load_tune_file() {
+  const char *path = std::getenv("MPGEMM_TUNE_FILE");
+  if (path && *path) (void)load_tune_tables(path);
+}
+
 int slices_for(int fmt, int mode, int64_t k) {
   const int s = g_opt.slices[fmt][mode];
-  return s > 0 ? s : auto_slices(fmt, mode, k);
+  if (s > 0) return s;
+  std::call_once(g_tune_once, load_tune_file);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (const SliceEntry &e : g_slice_table)
+      if (e.fmt == fmt && e.mode == mode && k <= e.kmax) return e.D;
+  }
+  return auto_slices(fmt, mode, k);
 }
 int thread_mode(int fmt) { return g_opt.mode[fmt]; }
 int int8_tile_override() { return g_opt.int8_tile; }
 
-// Wave layout of the binary64/binary32 slice-product kernel per format:
-// compiled-in defaults (measured), replaced by the file named in the
-// environment variable MPGEMM_TUNE_FILE (lines "<fmt> <layout>", as written
-// by paper_2301_09960_amd.tune), replaced per thread by mpgemm_set_tile_layout.
-int g_layout_default[kNumFmt] = {1, 2, 2, 2};  // measured at n = 1024 and 4096 (DD, TD, QD, TS)
-std::once_flag g_tune_once;
-
-void load_tune_file() {
-  const char *path = std::getenv("MPGEMM_TUNE_FILE");
-  if (!path || !*path) return;
-  FILE *f = std::fopen(path, "r");
-  if (!f) return;
-  char name[16];
-  int layout;
-  while (std::fscanf(f, "%15s %d", name, &layout) == 2) {
-    const char *names[kNumFmt] = {"dd", "td", "qd", "ts"};
-    for (int i = 0; i < kNumFmt; ++i)
-      if (std::strcmp(name, names[i]) == 0 && layout >= 1 && layout <= 3) g_layout_default[i] = layout;
-  }
-  std::fclose(f);
-}
-
+// Wave layout of the binary64/binary32 slice-product kernel per format: the
+// tuned table (above), replaced per thread by mpgemm_set_tile_layout.
 int layout_for(int fmt) {
+  if (g_opt.layout[fmt] > 0) return g_opt.layout[fmt];
   std::call_once(g_tune_once, load_tune_file);
-  return g_opt.layout[fmt] > 0 ? g_opt.layout[fmt] : g_layout_default[fmt];
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  return g_layout_default[fmt];
 }
 void set_last_slices(int D) { g_opt.last_slices = D; }
 bool profiling() { return g_prof.on; }
@@ -574,6 +635,11 @@ int mpgemm_nd_debug_products(int c, int m, int n, int k, const double *A, int ld
 #undef MP_CASE
   }
   return -1;
+}
+
+int mpgemm_load_tune_file(const char *path) {
+  std::call_once(g_tune_once, [] {});  // an explicit load replaces the environment's file
+  return load_tune_tables(path);
 }
 
 int mpgemm_set_mode(int fmt, int mode) {

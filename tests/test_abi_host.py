@@ -77,6 +77,33 @@ def test_workspace_bytes(L):
     assert mp.workspace_bytes("ts", "float", 65, 1, 33, 1) >= 1 * 128 * 64 * 4 + 1 * 64 * 64 * 4
 
 
+def test_tuning_file_tables(L, tmp_path):
+    import paper_2301_09960_amd as mp
+    f = tmp_path / "tune.txt"
+    f.write_text("# tuned\nqd 3\nslices dd float 1024 5\nslices dd float 4096 7\nslices qd int8 256 29\n")
+    try:
+        mp.load_tune_file(f)
+        assert mp.num_slices("dd", "float", 512) == 5
+        assert mp.num_slices("dd", "float", 2048) == 7
+        assert mp.num_slices("dd", "float", 8192) == 6  # beyond the table: the formula
+        assert mp.num_slices("qd", "int8", 200) == 29 and mp.num_slices("qd", "int8", 300) == 31
+        assert mp.num_slices("td", "float", 512) == 8
+        assert mp.tile_layout("qd") == 3
+        mp.set_num_slices("dd", "float", 9)  # per-thread settings take precedence
+        assert mp.num_slices("dd", "float", 512) == 9
+        mp.set_num_slices("dd", "float", 0)
+        bad = tmp_path / "bad.txt"
+        bad.write_text("slices dd float 100 99\n")  # D beyond the limit: rejected, tables kept
+        with pytest.raises(mp.MpgemmError):
+            mp.load_tune_file(bad)
+        assert mp.num_slices("dd", "float", 512) == 5
+        with pytest.raises(OSError):
+            mp.load_tune_file(tmp_path / "missing.txt")
+    finally:
+        mp.load_tune_file(None)
+    assert mp.num_slices("dd", "float", 512) == 6 and mp.tile_layout("qd") == 2
+
+
 def test_long_expansion_entry_points(L):
     P = ctypes.c_void_p
     x = P(16)

@@ -266,3 +266,25 @@ def test_automatic_slice_count_is_tight(mp, orc, fmt, mode, fewer):
     ok_f, worst_f = _check_bound(orc, fmt, A, B, Cf)
     say(f"{fmt} {mode}: D={D} worst {worst:.1f}; D={D - fewer} worst {worst_f:.1f} (bound -{T_BITS[fmt]})")
     assert ok and not ok_f
+
+
+def test_slice_autotuner_table(mp, orc, tmp_path):
+    """The autotuner's slice counts, loaded as a table, give products within the
+    bound (checked exactly) on inputs it did not tune on."""
+    from paper_2301_09960_amd import tune
+    lines = tune.slice_table([("dd", "float"), ("qd", "int8")], ks=(128, 512), size=64, seeds=(1,))
+    f = tmp_path / "slices.txt"
+    f.write_text("\n".join(lines) + "\n")
+    try:
+        mp.load_tune_file(f)
+        for fmt, mode, k in (("dd", "float", 100), ("dd", "float", 512), ("qd", "int8", 300)):
+            A, B = W.gen_pair(fmt, 48, 40, k, E=16, seed=777)
+            C = host(mp.gemm(fmt, dev(A), dev(B), mode=mode))
+            D = mp.last_num_slices()
+            want = [int(l.split()[4]) for l in lines if l.split()[1:3] == [fmt, mode] and int(l.split()[3]) >= k][0]
+            assert D == want
+            ok, worst = _check_bound(orc, fmt, A, B, C)
+            say(f"tuned {fmt} {mode} k={k}: D={D} worst {worst:.1f} (bound -{T_BITS[fmt]})")
+            assert ok
+    finally:
+        mp.load_tune_file(None)
