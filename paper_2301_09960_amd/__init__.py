@@ -49,6 +49,10 @@ def lib():
             if _lib is None:
                 if not os.path.exists(LIB_PATH):
                     raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2301_09960_amd.build`")
+                # torch first: it brings its own HIP runtime, and the library must
+                # bind to that same runtime (loaded first, the library would pull in
+                # the system one and torch's device memory would be foreign to it)
+                import torch  # noqa: F401
                 L = ctypes.CDLL(LIB_PATH)
                 for name in ("mpgemm_dd", "mpgemm_td", "mpgemm_qd", "mpgemm_ts"):
                     f = getattr(L, name)

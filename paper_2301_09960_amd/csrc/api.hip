@@ -309,7 +309,12 @@ int acquire(Workspace &ws, size_t bytes, hipStream_t st) {
   return 0;
 }
 
+// Called on entry by every call that launches work.  It also clears the
+// thread's last-error slot: the launches below report their own failures
+// through hipGetLastError, so an error left there by an earlier, unrelated
+// runtime call (another library on this thread) must not be taken for theirs.
 int check_device_cached() {
+  (void)hipGetLastError();
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return MPGEMM_ERR_HIP;
   if (dev >= 0 && dev < 64 && g_arch_ok[dev] != 0) return g_arch_ok[dev] > 0 ? 0 : MPGEMM_ERR_DEVICE;
