@@ -245,12 +245,16 @@ __device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const
       advance();
     }
 
-  // matrix-core instructions per wavefront per step, and one load of the step
-  // kStages - 1 ahead after every kEvery of them (spread loads keep the
-  // matrix cores fed where a burst of LDS-direct loads would stall them)
+  // matrix-core instructions per wavefront per step.  The loads of the step
+  // kStages - 1 ahead are issued either spread, one after every kEvery of them
+  // (binary64 with 4 wavefronts of 32 x 32, where each wavefront issues many
+  // loads and a burst would stall its matrix cores), or all at once at the
+  // step's first instruction (the other layouts and binary32, where a wavefront
+  // issues few loads and grouping them measured faster with less L2 traffic)
   constexpr int kMma = kKStepBlocks * 4 * BI * BJ;
   static_assert(kMma % kL == 0, "one load per fixed number of matrix-core instructions");
   constexpr int kEvery = kMma / kL;
+  constexpr bool kSpread = sizeof(T) == 8 && LAYOUT == 1;
 
   int cks = 0;  // k step of the pair being computed
   for (int64_t step = 0; step < total; ++step) {
@@ -303,8 +307,13 @@ __device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const
 #pragma unroll
             for (int x = 0; x < BI; ++x) {
               const int mma = ((kb * 4 + h * kQ + qq) * BJ + y) * BI + x;
-              if (mma % kEvery == 0 && more)
-                load_lds16(nsrc + goff(mma / kEvery) + g0, ndst + l0 + loff(mma / kEvery));
+              if constexpr (kSpread) {
+                if (mma % kEvery == 0 && more)
+                  load_lds16(nsrc + goff(mma / kEvery) + g0, ndst + l0 + loff(mma / kEvery));
+              } else if (mma == 0 && more) {
+#pragma unroll
+                for (int j = 0; j < kL; ++j) load_lds16(nsrc + goff(j) + g0, ndst + l0 + loff(j));
+              }
               acc[y][x] = M::run(fb[y][qq], fa[x][qq], acc[y][x]);
               __builtin_amdgcn_sched_barrier(0);  // keep the loads where they were placed
             }
