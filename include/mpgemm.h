@@ -171,6 +171,18 @@ int mpgemm_load_tune_file(const char *path);
  * 16.  Slices are padded to the chosen tile.  Returns -1 for other values.
  */
 int mpgemm_set_int8_tile(int cfg);
+
+/*
+ * Kernel of the binary64/binary32 split (Algorithm 1), per host thread.
+ * 0 (default): while the padded k of a product is short enough that a
+ * workgroup holds two or more whole rows of A (columns of B) in registers
+ * (k <= 8192 for DD, 5120 for TD, 4096 for QD, 8192 for TS), one fused launch
+ * runs all D passes and reads each operand once; longer products use one
+ * launch per pass.  1: one launch per pass always.  Both give the same slices
+ * bit for bit.  Returns -1 for other values.
+ */
+int mpgemm_set_split_kernel(int kind);
+int mpgemm_split_kernel(void);
 int mpgemm_set_num_slices(int fmt, int mode, int D);
 int mpgemm_num_slices(int fmt, int mode, int k);
 int mpgemm_last_num_slices(void);

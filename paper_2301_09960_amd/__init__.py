@@ -65,6 +65,8 @@ def lib():
                 L.mpgemm_set_tile_layout.argtypes = [_I, _I]
                 L.mpgemm_tile_layout.argtypes = [_I]
                 L.mpgemm_set_int8_tile.argtypes = [_I]
+                L.mpgemm_set_split_kernel.argtypes = [_I]
+                L.mpgemm_split_kernel.argtypes = []
                 L.mpgemm_set_mode.argtypes = [_I, _I]
                 L.mpgemm_get_mode.argtypes = [_I]
                 L.mpgemm_set_num_slices.argtypes = [_I, _I, _I]
@@ -141,6 +143,17 @@ def get_mode(fmt) -> str:
 def set_tile_layout(fmt, layout: int):
     """Wavefront layout of the slice-product kernel (0 = tuned default, 1..3)."""
     _check(lib().mpgemm_set_tile_layout(_fmt(fmt), int(layout)), "set_tile_layout")
+
+
+def set_split_kernel(kind: int):
+    """Kernel of the binary64/binary32 split, this thread: 0 = fused where the
+    rows of A / columns of B fit one workgroup (else one launch per pass),
+    1 = one launch per pass always.  Both give the same slices."""
+    _check(lib().mpgemm_set_split_kernel(int(kind)), "set_split_kernel")
+
+
+def split_kernel() -> int:
+    return int(lib().mpgemm_split_kernel())
 
 
 def set_int8_tile(cfg: int):

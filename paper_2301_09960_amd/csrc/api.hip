@@ -37,6 +37,7 @@ struct ThreadOptions {
   int mode[kNumFmt] = {MPGEMM_MODE_FLOAT, MPGEMM_MODE_FLOAT, MPGEMM_MODE_FLOAT, MPGEMM_MODE_FLOAT};
   int layout[kNumFmt] = {0, 0, 0, 0};  // 0: tuned default
   int int8_tile = 0;                   // 0: automatic
+  int split_kernel = 0;                // 0: fused where vectors fit, 1: pass kernels only
   int slices[kNumFmt][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
   int last_slices = 0;
   void *ws = nullptr;
@@ -179,6 +180,7 @@ int slices_for(int fmt, int mode, int64_t k) {
 }
 int thread_mode(int fmt) { return g_opt.mode[fmt]; }
 int int8_tile_override() { return g_opt.int8_tile; }
+int split_kernel_override() { return g_opt.split_kernel; }
 
 // Wave layout of the binary64/binary32 slice-product kernel per format: the
 // tuned table (above), replaced per thread by mpgemm_set_tile_layout.
@@ -385,7 +387,7 @@ hipError_t split_both(const SplitOperand<T> &a, const SplitOperand<T> &b, const 
     if constexpr (sizeof(T) == 8) return launch_split_int8<C>(a, b, p.D, st);
     return hipErrorInvalidValue;
   }
-  if constexpr (C <= 4) return launch_split_plain<T, C>(a, b, p.D, p.rho, st);
+  if constexpr (C <= 4) return launch_split_plain<T, C>(a, b, p.D, p.rho, g_opt.split_kernel == 0, st);
   return hipErrorInvalidValue;  // longer expansions: INT8 form only
 }
 
@@ -669,6 +671,13 @@ int mpgemm_set_int8_tile(int cfg) {
   g_opt.int8_tile = cfg;
   return 0;
 }
+
+int mpgemm_set_split_kernel(int kind) {
+  if (kind < 0 || kind > 1) return -1;
+  g_opt.split_kernel = kind;
+  return 0;
+}
+int mpgemm_split_kernel(void) { return g_opt.split_kernel; }
 
 int mpgemm_set_num_slices(int fmt, int mode, int D) {
   if (!fmt_ok(fmt)) return -1;

@@ -45,18 +45,25 @@ struct ProductLayout {
   // INT8 form: k blocks per chunk, chunks, diagonal groups, diagonal sums
   int kbc = 0, nchunks = 0, groups = 1, cfg = 1;
   size_t sums = 0;
+  // binary64/binary32 slices: operand split by the fused kernel (no residual)
+  bool fused_a = false, fused_b = false;
+};
+
+// The part of an operand that decides its split kernel.
+struct OperandShape {
+  int64_t kbp, nbp, nvec;
 };
 
 struct BatchPlan {
-  int device = 0, fmt = 0, mode = 0, layout = 1, int8_tile = 0;
+  int device = 0, fmt = 0, mode = 0, layout = 1, int8_tile = 0, split_kernel = 0;
   hipStream_t stream = nullptr;
   std::vector<int> m, n, k, D;
   std::vector<ProductLayout> prod;
   std::vector<int> live;  // products with m, n, k > 0
   char *ws = nullptr;
-  size_t off_ops = 0, off_descs = 0, desc_bytes = 0, off_prefix0 = 0, off_prefixp = 0, off_items = 0,
-         off_counter = 0, off_mu = 0, mu_bytes = 0, off_prefixc = 0, total = 0;
-  int nops = 0, tiles0 = 0, tilesp = 0, dmax = 0, nitems = 0, nitems3 = 0;
+  size_t off_ops = 0, off_descs = 0, desc_bytes = 0, off_prefix0 = 0, off_prefixp = 0, off_prefixf = 0,
+         off_items = 0, off_counter = 0, off_mu = 0, mu_bytes = 0, off_prefixc = 0, total = 0;
+  int nops = 0, tiles0 = 0, tilesp = 0, stripsf = 0, dmax = 0, nitems = 0, nitems3 = 0;
   int64_t blocks8 = 0, blocksc = 0;  // INT8 form: split blocks, combine blocks
   void *stage = nullptr;
   hipEvent_t stage_done = nullptr;
@@ -120,8 +127,10 @@ int build_plan(BatchPlan &p, hipStream_t st) {
     L.mbp = nblocks_padded(L.m);
     L.nbp = nblocks_padded(L.n);
     L.kbp = kblocks_padded(L.k);
-    L.resid_a = take(L.D > 1 ? (size_t)C * L.m * L.k * w : 0);
-    L.resid_b = take(L.D > 1 ? (size_t)C * L.k * L.n * w : 0);
+    L.fused_a = p.split_kernel == 0 && fused_strips<T, C>(OperandShape{L.kbp, L.mbp, L.m}) >= 0;
+    L.fused_b = p.split_kernel == 0 && fused_strips<T, C>(OperandShape{L.kbp, L.nbp, L.n}) >= 0;
+    L.resid_a = take(L.D > 1 && !L.fused_a ? (size_t)C * L.m * L.k * w : 0);
+    L.resid_b = take(L.D > 1 && !L.fused_b ? (size_t)C * L.k * L.n * w : 0);
     L.pack_a = take((size_t)L.D * L.mbp * L.kbp * 256 * w);
     L.pack_b = take((size_t)L.D * L.nbp * L.kbp * 256 * w);
     L.exp_a = take((size_t)L.D * L.m * 4);
@@ -147,6 +156,7 @@ int build_plan(BatchPlan &p, hipStream_t st) {
   o = p.off_ops + align256(p.desc_bytes);
   p.off_prefix0 = take((size_t)(p.nops + 1) * 4);
   p.off_prefixp = take((size_t)(p.nops + 1) * 4);
+  p.off_prefixf = take((size_t)(p.nops + 1) * 4);
 
   // work list: (product slot, tile), longest first
   struct Item {
@@ -178,21 +188,31 @@ int build_plan(BatchPlan &p, hipStream_t st) {
   }
   if (hipEventCreateWithFlags(&p.stage_done, hipEventDisableTiming) != hipSuccess) return MPGEMM_ERR_HIP;
 
-  // static device data: tile prefix sums and the work list
-  std::vector<int> pre0(p.nops + 1, 0), prep(p.nops + 1, 0);
+  // static device data: prefix sums of the split work and the work list.  An
+  // operand whose vectors fit a fused workgroup is split by the fused kernel
+  // alone; the others by the max and pass kernels.
+  std::vector<int> pre0(p.nops + 1, 0), prep(p.nops + 1, 0), pref(p.nops + 1, 0);
+  int dpass = 0;
   for (int slot = 0; slot < (int)p.live.size(); ++slot) {
     const ProductLayout &L = p.prod[p.live[slot]];
-    pre0[2 * slot + 1] = pre0[2 * slot] + tiles64(L.m, L.k);
-    pre0[2 * slot + 2] = pre0[2 * slot + 1] + tiles64(L.n, L.k);
-    prep[2 * slot + 1] = prep[2 * slot] + tiles64(L.mbp * kBlk, L.kbp * kKBlk);
-    prep[2 * slot + 2] = prep[2 * slot + 1] + tiles64(L.nbp * kBlk, L.kbp * kKBlk);
+    for (int side = 0; side < 2; ++side) {
+      const int i = 2 * slot + side;
+      const int64_t nvec = side == 0 ? L.m : L.n, nbp = side == 0 ? L.mbp : L.nbp;
+      const bool fused = side == 0 ? L.fused_a : L.fused_b;
+      pref[i + 1] = pref[i] + (fused ? fused_strips<T, C>(OperandShape{L.kbp, nbp, nvec}) : 0);
+      pre0[i + 1] = pre0[i] + (fused ? 0 : tiles64(nvec, L.k));
+      prep[i + 1] = prep[i] + (fused ? 0 : tiles64(nbp * kBlk, L.kbp * kKBlk));
+      if (!fused) dpass = std::max(dpass, L.D);
+    }
   }
   p.tiles0 = pre0[p.nops];
   p.tilesp = prep[p.nops];
+  p.stripsf = pref[p.nops];
   std::vector<int2> it2(items.size());
   for (size_t i = 0; i < items.size(); ++i) it2[i] = make_int2(items[i].slot, items[i].tile);
   if (hipMemcpy(p.ws + p.off_prefix0, pre0.data(), pre0.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p.ws + p.off_prefixp, prep.data(), prep.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p.ws + p.off_prefixf, pref.data(), pref.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
       (it2.size() && hipMemcpy(p.ws + p.off_items, it2.data(), it2.size() * sizeof(int2), hipMemcpyHostToDevice) !=
                          hipSuccess))
     return MPGEMM_ERR_HIP;
@@ -204,8 +224,8 @@ int build_plan(BatchPlan &p, hipStream_t st) {
   if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return MPGEMM_ERR_HIP;
   hipError_t e = launch_split_plain_batched<T, C>(
       reinterpret_cast<const SplitOperand<T> *>(p.ws + p.off_ops), reinterpret_cast<const int *>(p.ws + p.off_prefix0),
-      reinterpret_cast<const int *>(p.ws + p.off_prefixp), p.nops, p.tiles0, p.tilesp, p.dmax, p.ws + p.off_mu,
-      (int64_t)(p.mu_bytes / 4), cs);
+      reinterpret_cast<const int *>(p.ws + p.off_prefixp), reinterpret_cast<const int *>(p.ws + p.off_prefixf),
+      p.nops, p.tiles0, p.tilesp, p.stripsf, dpass, p.ws + p.off_mu, (int64_t)(p.mu_bytes / 4), cs);
   if (e == hipSuccess) e = launch_fill32(p.ws + p.off_counter, 1, 0u, cs);
   if (e == hipSuccess)
     e = launch_gemm_plain_batched<T, C>(reinterpret_cast<const PlainGemmDesc *>(p.ws + p.off_descs),
@@ -555,7 +575,7 @@ int run_batched(int fmt, int count, const int *m, const int *n, const int *k, co
   BatchPlan *plan = nullptr;
   for (BatchPlan *p : bc.plans)
     if (p->device == dev && p->stream == st && p->fmt == fmt && p->mode == mode && p->layout == layout &&
-        p->int8_tile == int8_tile_override() &&
+        p->int8_tile == int8_tile_override() && p->split_kernel == split_kernel_override() &&
         (int)p->m.size() == count &&
         std::equal(p->m.begin(), p->m.end(), m) && std::equal(p->n.begin(), p->n.end(), n) &&
         std::equal(p->k.begin(), p->k.end(), k) && p->D == Ds) {
@@ -578,6 +598,7 @@ int run_batched(int fmt, int count, const int *m, const int *n, const int *k, co
     plan->mode = mode;
     plan->layout = layout;
     plan->int8_tile = int8_tile_override();
+    plan->split_kernel = split_kernel_override();
     plan->m.assign(m, m + count);
     plan->n.assign(n, n + count);
     plan->k.assign(k, k + count);

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "layout.h"
+
 namespace mp {
 
 constexpr int kZeroExp = INT32_MIN;
@@ -49,20 +51,46 @@ struct PlainGemmDesc {
   int64_t c_stride;
 };
 
-// Plain split (Algorithm 1): D passes, slices written packed.  `rho` is the
-// shift ceil((S + log2 k)/2).  Both operands in one sequence of launches.
+// Fused plain split: a workgroup of kFusedThreads threads holds the residual of
+// nv whole vectors in registers, fused_per_thread<T, C>() elements per thread.
+constexpr int kFusedThreads = 1024;
 template <typename T, int C>
-hipError_t launch_split_plain(const SplitOperand<T> &a, const SplitOperand<T> &b, int D, int rho, hipStream_t st);
+__host__ __device__ constexpr int fused_per_thread() {
+  return sizeof(T) == 8 ? (C == 2 ? 16 : C == 3 ? 10 : 8) : 16;
+}
+// Vectors per workgroup (16, 8, 4 or 2; a divisor of the 16 of a packed
+// block) for vectors of padded length len_cover; 0 when not even two fit.
+__host__ __device__ inline int fused_vectors(int64_t len_cover, int per_thread) {
+  for (int nv = kBlk; nv >= 2; nv /= 2)
+    if (nv * len_cover <= (int64_t)kFusedThreads * per_thread) return nv;
+  return 0;
+}
+// Workgroups of the fused split for one operand; -1 if its vectors are too long.
+template <typename T, int C, typename Op>
+inline int fused_strips(const Op &op) {
+  const int nv = fused_vectors(op.kbp * kKBlk, fused_per_thread<T, C>());
+  if (nv == 0) return -1;
+  return op.nvec > 0 ? (int)(op.nbp * kBlk / nv) : 0;
+}
 
-// Plain split of many operands at once: ops[0..nops) in device memory;
-// prefix_max0 / prefix_pass (nops + 1 entries, device) are running sums of the
-// 64 x 64 tiles each operand needs in the max and pass kernels.  Operand i runs
-// ops[i].D passes; launches cover dmax passes.  mu_all / mu_words: one region
-// holding every operand's maxima, cleared first.
+// Plain split (Algorithm 1): D passes, slices written packed.  `rho` is the
+// shift ceil((S + log2 k)/2).  Both operands in one sequence of launches: one
+// fused launch when `fused` is set and their vectors fit, else D + 1 sweeps.
+template <typename T, int C>
+hipError_t launch_split_plain(const SplitOperand<T> &a, const SplitOperand<T> &b, int D, int rho, bool fused,
+                              hipStream_t st);
+
+// Plain split of many operands at once: ops[0..nops) in device memory.
+// prefix_fused (nops + 1 entries, device) holds running sums of the fused
+// workgroups of each operand (0 for operands left to the pass kernels);
+// prefix_max0 / prefix_pass the running sums of the 64 x 64 tiles each
+// remaining operand needs in the max and pass kernels (0 for fused operands).
+// Operand i runs ops[i].D passes; pass launches cover dmax passes.  mu_all /
+// mu_words: one region holding every operand's maxima, cleared first.
 template <typename T, int C>
 hipError_t launch_split_plain_batched(const SplitOperand<T> *ops, const int *prefix_max0, const int *prefix_pass,
-                                      int nops, int tiles_max0, int tiles_pass, int dmax, void *mu_all,
-                                      int64_t mu_words, hipStream_t st);
+                                      const int *prefix_fused, int nops, int tiles_max0, int tiles_pass,
+                                      int strips_fused, int dmax, void *mu_all, int64_t mu_words, hipStream_t st);
 
 // Persistent GEMM over a batch: items (product index, tile index) in device
 // memory, taken in order through *counter (cleared by the caller).

@@ -228,6 +228,146 @@ __global__ __launch_bounds__(kThreads) void k_split_pass_batched(const SplitOper
     pass_body<T, C, 1>(op, local, pass, op.rho, first, last);
 }
 
+// ---------------------------------------------------------------------------
+// Fused plain split.  While whole vectors fit in one workgroup's registers, a
+// workgroup of kFusedThreads threads takes nv vectors (nv of the 16 of one
+// packed row/column block) over their full padded length and runs all D
+// passes itself.  The maximum of each pass is reduced inside the workgroup, so
+// the operand is read once and only the slices are written, instead of D + 1
+// sweeps that read and write the residual.  Every element goes through the
+// arithmetic of pass_body, step for step, so the slices and exponents are the
+// same as those of the pass kernels.
+//
+// Thread t holds the strip elements t + kFusedThreads j, numbered in packed
+// order.  Each slice store is then a run of 2 nv (binary64) or 4 nv (binary32)
+// consecutive elements per group of lanes, and every element of a thread lies
+// in the same vector (that run length divides 64).
+// ---------------------------------------------------------------------------
+template <typename U>
+__device__ __forceinline__ U umax(U a, U b) {
+  return a > b ? a : b;
+}
+
+// Workgroups are dealt to the 8 XCDs in turn (b % 8); renumber them so that
+// each XCD takes one contiguous range of strips.  Neighbouring strips of A
+// share cache lines (a line holds 16 rows at one k), and this keeps those
+// lines in one L2.  A bijection of [0, total).
+__device__ __forceinline__ int xcd_contiguous(int b, int total) {
+  const int per = total / 8, rem = total % 8, x = b % 8;
+  return x * per + (x < rem ? x : rem) + b / 8;
+}
+
+template <typename T, int C>
+__device__ void fused_strip(const SplitOperand<T> &op, int strip, int D, int rho) {
+  using U = typename bits_of<T>::type;
+  constexpr int kPer = fused_per_thread<T, C>();
+  constexpr int kRunPer = sizeof(T) == 8 ? 2 : 4;  // consecutive packed elements of one vector
+  constexpr int kWaves = kFusedThreads / 64;
+  const int64_t len_cover = op.kbp * kKBlk;
+  const int nv = fused_vectors(len_cover, kPer);
+  const int run = kRunPer * nv, per_block = kBlk * nv;
+  const int v0 = strip * nv, vb = v0 / kBlk, vl0 = v0 % kBlk;
+  const int nl = (int)(nv * len_cover);
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int vo = (lane % run) / kRunPer;
+  const int v = v0 + vo;
+  const bool vec_ok = v < op.nvec;
+
+  T R[kPer][C];
+  int off[kPer];  // offset inside the strip's part of a slice plane; -1: beyond the strip
+  bool valid[kPer];
+  bool has_p0 = false;
+  U m = 0;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int idx = tid + kFusedThreads * j;
+    off[j] = -1;
+    valid[j] = false;
+#pragma unroll
+    for (int r = 0; r < C; ++r) R[j][r] = T(0);
+    if (idx < nl) {
+      const int kb = idx / per_block, rr = idx % per_block, g = rr / run, q = rr % run;
+      int kl, within;
+      if constexpr (sizeof(T) == 8) {
+        const int st = 2 * (g / 4) + (q & 1);
+        kl = 4 * st + g % 4;
+        within = (g / 4) * 128 + 2 * ((g % 4) * 16 + vl0 + vo) + (q & 1);
+      } else {
+        const int st = q % 4;
+        kl = 4 * st + g;
+        within = 4 * (g * 16 + vl0 + vo) + st;
+      }
+      const int p = kb * kKBlk + kl;
+      off[j] = kb * 256 + within;
+      has_p0 = has_p0 || p == 0;
+      valid[j] = vec_ok && p < op.len;
+      if (valid[j]) {
+#pragma unroll
+        for (int r = 0; r < C; ++r) R[j][r] = op.X[r * op.comp_stride + (int64_t)v * op.sv + (int64_t)p * op.sp];
+        m = umax(m, abs_bits(R[j][0]));
+      }
+    }
+  }
+
+  __shared__ U red[2][kWaves][kBlk];
+  T *packed = static_cast<T *>(op.packed);
+#pragma unroll 1
+  for (int a = 0; a < D; ++a) {
+    // maximum of the leading components of this vector's residual: lanes of
+    // one vector first (xor over the bits below the run and from the run up),
+    // then the waves through LDS (two buffers, so one barrier per pass)
+    U mw = m;
+#pragma unroll
+    for (int o = 1; o < kRunPer; o <<= 1) mw = umax(mw, (U)__shfl_xor(mw, o, 64));
+    for (int o = run; o < 64; o <<= 1) mw = umax(mw, (U)__shfl_xor(mw, o, 64));
+    if (lane < run && lane % kRunPer == 0) red[a & 1][wave][vo] = mw;
+    __syncthreads();
+    U mu = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) mu = umax(mu, red[a & 1][w][vo]);
+    int e = kZeroExp;
+    if (vec_ok && mu != 0) e = ceil_log2(from_bits(mu, T(0)));
+    const T tau = e != kZeroExp ? pow2(e + rho, T(0)) : T(0);
+    T *dst = packed + ((int64_t)a * op.nbp + vb) * op.kbp * 256;
+    m = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      if (off[j] < 0) continue;
+      T sl = T(0);
+      if (valid[j] && e != kZeroExp) {
+        const T lead = R[j][0];
+        sl = (lead + tau) - tau;
+        R[j][0] = lead - sl;  // exact
+        renorm<T, C>(R[j]);
+      }
+      dst[off[j]] = sl;
+      if (valid[j]) m = umax(m, abs_bits(R[j][0]));
+    }
+    if (has_p0 && vec_ok) op.exps[(int64_t)a * op.nvec + v] = e;
+  }
+}
+
+template <typename T, int C>
+__global__ __launch_bounds__(kFusedThreads) void k_split_fused(SplitOperand<T> a, SplitOperand<T> b, int strips_a,
+                                                               int D, int rho) {
+  const int w = xcd_contiguous(blockIdx.x, gridDim.x);
+  if (w < strips_a)
+    fused_strip<T, C>(a, w, D, rho);
+  else
+    fused_strip<T, C>(b, w - strips_a, D, rho);
+}
+
+// Batched: workgroup b takes strip b - prefix[i] of operand i (operands split
+// by the pass kernels own no strips).
+template <typename T, int C>
+__global__ __launch_bounds__(kFusedThreads) void k_split_fused_batched(const SplitOperand<T> *ops, const int *prefix,
+                                                                       int nops) {
+  const int w = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int i = __builtin_amdgcn_readfirstlane(find_operand(prefix, nops, w));
+  const SplitOperand<T> op = ops[i];  // uniform: kept in scalar registers
+  fused_strip<T, C>(op, w - prefix[i], op.D, op.rho);
+}
+
 __global__ void k_fill32(uint32_t *p, int64_t n, uint32_t value) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = value;
@@ -244,8 +384,17 @@ hipError_t launch_fill32(void *p, int64_t nwords, uint32_t value, hipStream_t st
 }
 
 template <typename T, int C>
-hipError_t launch_split_plain(const SplitOperand<T> &a, const SplitOperand<T> &b, int D, int rho, hipStream_t st) {
+hipError_t launch_split_plain(const SplitOperand<T> &a, const SplitOperand<T> &b, int D, int rho, bool fused,
+                              hipStream_t st) {
   using U = typename bits_of<T>::type;
+  if (fused && fused_strips<T, C>(a) >= 0 && fused_strips<T, C>(b) >= 0) {
+    const int sa = fused_strips<T, C>(a), sb = fused_strips<T, C>(b);
+    if (sa + sb > 0 && D > 0) {
+      hipLaunchKernelGGL((k_split_fused<T, C>), dim3(sa + sb), dim3(kFusedThreads), 0, st, a, b, sa, D, rho);
+      return hipGetLastError();
+    }
+    return hipSuccess;
+  }
   // zero the per-pass maxima (a and b own separate arrays)
   hipError_t err = launch_fill32(a.mu, (int64_t)D * a.nvec * sizeof(U) / 4, 0u, st);
   if (err != hipSuccess) return err;
@@ -269,10 +418,17 @@ hipError_t launch_split_plain(const SplitOperand<T> &a, const SplitOperand<T> &b
 
 template <typename T, int C>
 hipError_t launch_split_plain_batched(const SplitOperand<T> *ops, const int *prefix_max0, const int *prefix_pass,
-                                      int nops, int tiles_max0, int tiles_pass, int dmax, void *mu_all,
-                                      int64_t mu_words, hipStream_t st) {
-  hipError_t err = launch_fill32(mu_all, mu_words, 0u, st);
-  if (err != hipSuccess || nops <= 0) return err;
+                                      const int *prefix_fused, int nops, int tiles_max0, int tiles_pass,
+                                      int strips_fused, int dmax, void *mu_all, int64_t mu_words, hipStream_t st) {
+  hipError_t err = hipSuccess;
+  if (nops <= 0) return err;
+  if (strips_fused > 0) {
+    hipLaunchKernelGGL((k_split_fused_batched<T, C>), dim3(strips_fused), dim3(kFusedThreads), 0, st, ops,
+                       prefix_fused, nops);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
+  if (tiles_max0 <= 0 && tiles_pass <= 0) return hipSuccess;
+  if ((err = launch_fill32(mu_all, mu_words, 0u, st)) != hipSuccess) return err;
   if (tiles_max0 > 0) {
     hipLaunchKernelGGL((k_split_max0_batched<T, C>), dim3(tiles_max0), dim3(kThreads), 0, st, ops, prefix_max0, nops);
     if ((err = hipGetLastError()) != hipSuccess) return err;
@@ -285,9 +441,10 @@ hipError_t launch_split_plain_batched(const SplitOperand<T> *ops, const int *pre
   return hipSuccess;
 }
 
-#define MP_SPLIT_BATCHED(T, C)                                                                                   \
-  template hipError_t launch_split_plain_batched<T, C>(const SplitOperand<T> *, const int *, const int *, int, int, \
-                                                       int, int, void *, int64_t, hipStream_t);
+#define MP_SPLIT_BATCHED(T, C)                                                                                 \
+  template hipError_t launch_split_plain_batched<T, C>(const SplitOperand<T> *, const int *, const int *,         \
+                                                       const int *, int, int, int, int, int, void *, int64_t, \
+                                                       hipStream_t);
 MP_SPLIT_BATCHED(double, 2)
 MP_SPLIT_BATCHED(double, 3)
 MP_SPLIT_BATCHED(double, 4)
@@ -295,13 +452,13 @@ MP_SPLIT_BATCHED(float, 3)
 #undef MP_SPLIT_BATCHED
 
 template hipError_t launch_split_plain<double, 2>(const SplitOperand<double> &, const SplitOperand<double> &, int, int,
-                                                  hipStream_t);
+                                                  bool, hipStream_t);
 template hipError_t launch_split_plain<double, 3>(const SplitOperand<double> &, const SplitOperand<double> &, int, int,
-                                                  hipStream_t);
+                                                  bool, hipStream_t);
 template hipError_t launch_split_plain<double, 4>(const SplitOperand<double> &, const SplitOperand<double> &, int, int,
-                                                  hipStream_t);
+                                                  bool, hipStream_t);
 template hipError_t launch_split_plain<float, 3>(const SplitOperand<float> &, const SplitOperand<float> &, int, int,
-                                                 hipStream_t);
+                                                 bool, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // INT8 digit split (the precision form).  Per vector: E = 1 + ilogb(max |x_0|)

@@ -65,6 +65,14 @@ def test_options_and_policy(L):
     with pytest.raises(mp.MpgemmError):
         mp.set_num_slices("dd", "float", 17)
     assert L.mpgemm_status_string(2) == b"workspace too small or allocation failed"
+    # split kernel switch: 0 fused where the vectors fit, 1 one launch per pass
+    assert mp.split_kernel() == 0
+    mp.set_split_kernel(1)
+    assert mp.split_kernel() == 1
+    mp.set_split_kernel(0)
+    with pytest.raises(mp.MpgemmError):
+        mp.set_split_kernel(2)
+    assert mp.split_kernel() == 0
 
 
 def test_workspace_bytes(L):

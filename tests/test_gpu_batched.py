@@ -68,6 +68,32 @@ def test_batched_equals_single_calls(mp, orc, fmt):
         assert ok, (i, sh[i], worst)
 
 
+@pytest.mark.parametrize("fmt", ["dd", "qd", "ts"])
+def test_batched_split_kernels_agree(mp, fmt):
+    """A batch whose operands are split partly by the fused kernel and partly
+    by the per-pass kernels (k beyond the fused limit) gives the same C as the
+    per-pass split alone and as single calls."""
+    import torch
+    sh = shapes(3, 12, 1, 700) + [(9, 7, 4097), (3, 5, 8200), (40, 33, 4096), (17, 2, 1)]
+    say(f"batched split kernels {fmt}: {len(sh)} products")
+    host = make_batch(fmt, sh, seed=11)
+    As = [dev(A) for A, _ in host]
+    Bs = [dev(B) for _, B in host]
+    try:
+        out = []
+        for kind in (0, 1):
+            mp.set_split_kernel(kind)
+            out.append(mp.gemm_batched(fmt, As, Bs))
+            torch.cuda.synchronize()
+        for i, (A, B) in enumerate(zip(As, Bs)):
+            assert torch.equal(out[0][i], out[1][i]), (i, sh[i])
+            single = mp.gemm(fmt, A, B)
+            torch.cuda.synchronize()
+            assert torch.equal(single, out[1][i]), (i, sh[i])
+    finally:
+        mp.set_split_kernel(0)
+
+
 @pytest.mark.parametrize("fmt", ["dd", "td", "qd"])
 def test_batched_int8_equals_single_calls(mp, orc, fmt):
     """The INT8 form batched: every product equals its single INT8 call bit for

@@ -43,13 +43,24 @@ def say(*a):
     print(*a, flush=True)
 
 
+@pytest.fixture
+def split_kernel(mp):
+    """Select the split kernel for one test and restore the default after."""
+    def use(kind):
+        mp.set_split_kernel(kind)
+    yield use
+    mp.set_split_kernel(0)
+
+
 @pytest.mark.parametrize("fmt", FMTS)
 @pytest.mark.parametrize("E", [0, 16])
-def test_split_bit_exact(mp, orc, fmt, E):
+@pytest.mark.parametrize("kind", [0, 1], ids=["fused", "passes"])
+def test_split_bit_exact(mp, orc, split_kernel, fmt, E, kind):
     m, k, n = 130, 75, 70
     A, B = W.gen_pair(fmt, m, n, k, E=E, seed=100 + E)
     D = mp.num_slices(fmt, "float", k)
-    say(f"split {fmt} E={E} m={m} n={n} k={k} D={D}")
+    split_kernel(kind)
+    say(f"split {fmt} E={E} m={m} n={n} k={k} D={D} kernel={kind}")
     sa, ea = orc.split_plain(A, D, "rows")
     sb, eb = orc.split_plain(B, D, "cols")
     ga, gea = mp.debug_split(fmt, dev(A), 0, D)
@@ -58,6 +69,33 @@ def test_split_bit_exact(mp, orc, fmt, E):
     assert np.array_equal(host(gea), ea)
     assert np.array_equal(host(gb), sb)
     assert np.array_equal(host(geb), eb)
+
+
+# Shapes around the fused split's limits: 16, 8, 4 and 2 vectors per
+# workgroup, the longest fused k of QD (4096) and TD (5120), and k just past
+# them (one launch per pass even in automatic mode), with ragged m and n.
+FUSED_EDGE = [(300, 200, 1000), (70, 45, 2050), (33, 17, 4096), (21, 9, 4097), (7, 12, 5120), (5, 3, 8200)]
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("m,n,k", FUSED_EDGE)
+def test_split_kernels_agree(mp, split_kernel, fmt, m, n, k):
+    """The fused split and the per-pass split give the same slices, exponents
+    and C, bit for bit (the per-pass split is checked against the oracle at
+    small sizes above)."""
+    A, B = W.gen_pair(fmt, m, n, k, E=16, seed=m + n + k)
+    dA, dB = dev(A), dev(B)
+    D = mp.num_slices(fmt, "float", k)
+    say(f"split kernels {fmt} m={m} n={n} k={k} D={D}")
+    out = []
+    for kind in (0, 1):
+        split_kernel(kind)
+        ga, gea = mp.debug_split(fmt, dA, 0, D)
+        gb, geb = mp.debug_split(fmt, dB, 1, D)
+        C = mp.gemm(fmt, dA, dB)
+        out.append([host(x) for x in (ga, gea, gb, geb, C)])
+    for x, y in zip(*out):
+        assert np.array_equal(x, y)
 
 
 @pytest.mark.parametrize("fmt", FMTS)
