@@ -47,8 +47,8 @@ def lib():
         L.oracle_renorm_f.argtypes = [_P, _I]
         L.oracle_rho.restype = _I
         L.oracle_rho.argtypes = [_I, _L]
-        L.oracle_split_plain.argtypes = [_I, _I, _I, _P, _L, _L, _L, _I, _I, _P, _P, _P]
-        L.oracle_split_plain_f.argtypes = [_I, _I, _I, _P, _L, _L, _L, _I, _I, _P, _P, _P]
+        L.oracle_split_plain.argtypes = [_I, _I, _I, _P, _L, _L, _L, _I, _I, _I, _P, _P, _P]
+        L.oracle_split_plain_f.argtypes = [_I, _I, _I, _P, _L, _L, _L, _I, _I, _I, _P, _P, _P]
         L.oracle_slice_product.argtypes = [_I, _I, _I, _P, _P, _P, _P, _I, _I, _P]
         L.oracle_gemm_exact_check.argtypes = [_I, _I, _I, _I, _I, _P, _P, _P, _I, _P, _I, _P, _P, _P]
         L.oracle_exact_sum.argtypes = [_P, _L, _I, _I, _P]
@@ -116,14 +116,20 @@ def _split_axes(X, along):
     raise ValueError(along)
 
 
-def split_plain(X: np.ndarray, D: int, along: str, *, want_resid: bool = False):
+def split_plain(X: np.ndarray, D: int, along: str, *, want_resid: bool = False, last: str = "extract"):
     """Algorithm 1's split of every row (``along='rows'``, operand A) or column
     (``along='cols'``, operand B) of X (shape ``(c, cols, rows)``).
 
     Returns ``(slices, exps[, resid])``: slices ``(D, cols, rows)`` in X's
     dtype, exps ``(D, nvec)`` int32 holding ceil(log2 mu) per pass (ZERO_EXP
     when mu = 0), resid ``(c, cols, rows)`` the remainder after D passes.
+
+    ``last='extract'``: D slices on the grid of tau, remainder dropped (every
+    slice product exact).  ``last='remainder'``: Algorithm 1 as printed, the
+    D-th slice is the leading component of the residual after D - 1 passes.
     """
+    if last not in ("extract", "remainder"):
+        raise ValueError(last)
     X = np.ascontiguousarray(X)
     c = X.shape[0]
     nvec, ln, s_vec, s_elt, s_comp = _split_axes(X, along)
@@ -134,7 +140,8 @@ def split_plain(X: np.ndarray, D: int, along: str, *, want_resid: bool = False):
     exps = np.zeros((D, nvec), dtype=np.int32)
     resid = np.zeros_like(X) if want_resid else None
     fn = lib().oracle_split_plain_f if f32 else lib().oracle_split_plain
-    _check(fn(nvec, ln, c, _ptr(X), s_vec, s_elt, s_comp, D, r, _ptr(slices), _ptr(exps), _ptr(resid)), "split")
+    _check(fn(nvec, ln, c, _ptr(X), s_vec, s_elt, s_comp, D, r, 1 if last == "remainder" else 0, _ptr(slices),
+              _ptr(exps), _ptr(resid)), "split")
     return (slices, exps, resid) if want_resid else (slices, exps)
 
 

@@ -110,12 +110,14 @@ def renorm_py(x, f32: bool = False):
     return out
 
 
-def split_vector_py(vec, D: int, f32: bool = False):
+def split_vector_py(vec, D: int, f32: bool = False, last_remainder: bool = False):
     """Algorithm 1's split of one row/column (a list of component tuples).
 
     Returns ``(slices[D][len], exps[D], residual[len][c])`` with the same
     readings as the C oracle (D passes, remainder dropped, mu = 0 gives a zero
-    slice and exponent None).
+    slice and exponent None).  ``last_remainder``: the D-th slice is instead the
+    leading component of the residual after D - 1 passes (Algorithm 1 as
+    printed).
     """
     t = np.float32 if f32 else float
     S = 24 if f32 else 53
@@ -123,7 +125,7 @@ def split_vector_py(vec, D: int, f32: bool = False):
     r = rho_exact(S, ln)
     R = [[t(v) for v in comps] for comps in vec]
     slices, exps = [], []
-    for _ in range(D):
+    for a in range(D):
         mu = max((abs(x[0]) for x in R), default=t(0))
         if mu == 0:
             slices.append([t(0)] * ln)
@@ -140,7 +142,7 @@ def split_vector_py(vec, D: int, f32: bool = False):
         row = []
         for x in R:
             lead = x[0]
-            sl = (lead + tau) - tau
+            sl = lead if (last_remainder and a == D - 1) else (lead + tau) - tau
             row.append(sl)
             x[0] = lead - sl
             x[:] = renorm_py(x, f32)

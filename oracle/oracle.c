@@ -193,9 +193,15 @@ static int ceil_log2_pos(double mu)
  * exponent ceil(log2 mu_a) of vector v at exps[a*nvec + v] (ZERO_EXP if
  * mu_a = 0), and optionally the final residual (c components) at
  * resid[r*nvec*len + ...] when resid != NULL.
+ *
+ * last_remainder = 0: all D slices are extracted on the grid of tau and the
+ * remainder is dropped, so every slice product is exact (the reading this
+ * library uses).  last_remainder = 1: Algorithm 1 as printed, where the last
+ * slice is the leading component of the residual left by the first D - 1
+ * passes (A_D := A^(S)); its exponent entry is still ceil(log2 mu_D).
  */
 int oracle_split_plain(int nvec, int len, int c, const double *X, long s_vec, long s_elt, long s_comp,
-                       int D, int rho, double *slices, int *exps, double *resid)
+                       int D, int rho, int last_remainder, double *slices, int *exps, double *resid)
 {
     if (nvec < 0 || len < 0 || c < 1 || c > 8 || D < 1)
         return ORC_EINVAL;
@@ -225,9 +231,10 @@ int oracle_split_plain(int nvec, int len, int c, const double *X, long s_vec, lo
             int e = ceil_log2_pos(mu);
             exps[a * nvec + v] = e;
             double tau = ldexp(1.0, e + rho);
+            const int literal = last_remainder && a == D - 1;
             for (int p = 0; p < len; ++p) {
                 double lead = R[(long)p * c];
-                double sl = (lead + tau) - tau;
+                double sl = literal ? lead : (lead + tau) - tau;
                 out[p * s_elt] = sl;
                 R[(long)p * c] = lead - sl; /* exact */
                 renorm(&R[(long)p * c], c);
@@ -243,7 +250,7 @@ int oracle_split_plain(int nvec, int len, int c, const double *X, long s_vec, lo
 }
 
 int oracle_split_plain_f(int nvec, int len, int c, const float *X, long s_vec, long s_elt, long s_comp,
-                         int D, int rho, float *slices, int *exps, float *resid)
+                         int D, int rho, int last_remainder, float *slices, int *exps, float *resid)
 {
     if (nvec < 0 || len < 0 || c < 1 || c > 8 || D < 1)
         return ORC_EINVAL;
@@ -273,9 +280,10 @@ int oracle_split_plain_f(int nvec, int len, int c, const float *X, long s_vec, l
             int e = ceil_log2_pos((double)mu);
             exps[a * nvec + v] = e;
             float tau = ldexpf(1.0f, e + rho);
+            const int literal = last_remainder && a == D - 1;
             for (int p = 0; p < len; ++p) {
                 float lead = R[(long)p * c];
-                float sl = (lead + tau) - tau;
+                float sl = literal ? lead : (lead + tau) - tau;
                 out[p * s_elt] = sl;
                 R[(long)p * c] = lead - sl;
                 renorm_f(&R[(long)p * c], c);
@@ -689,18 +697,18 @@ int oracle_ozaki_gemm(int c, int is_f32, int m, int n, int k, const void *Av, co
             Af[t] = (float)Ar[t];
         for (long t = 0; t < (long)c * k * n; ++t)
             Bf[t] = (float)Bd[t];
-        status = oracle_split_plain_f(nrows, k, c, Af, 1, nrows, (long)nrows * k, D, rho, Asf, ea, NULL);
+        status = oracle_split_plain_f(nrows, k, c, Af, 1, nrows, (long)nrows * k, D, rho, 0, Asf, ea, NULL);
         if (status == ORC_OK)
-            status = oracle_split_plain_f(n, k, c, Bf, k, 1, (long)k * n, D, rho, Bsf, eb, NULL);
+            status = oracle_split_plain_f(n, k, c, Bf, k, 1, (long)k * n, D, rho, 0, Bsf, eb, NULL);
         for (long t = 0; t < (long)D * k * nrows; ++t)
             As[t] = Asf[t];
         for (long t = 0; t < (long)D * k * n; ++t)
             Bs[t] = Bsf[t];
         free(Af), free(Bf), free(Asf), free(Bsf);
     } else {
-        status = oracle_split_plain(nrows, k, c, Ar, 1, nrows, (long)nrows * k, D, rho, As, ea, NULL);
+        status = oracle_split_plain(nrows, k, c, Ar, 1, nrows, (long)nrows * k, D, rho, 0, As, ea, NULL);
         if (status == ORC_OK)
-            status = oracle_split_plain(n, k, c, Bd, k, 1, (long)k * n, D, rho, Bs, eb, NULL);
+            status = oracle_split_plain(n, k, c, Bd, k, 1, (long)k * n, D, rho, 0, Bs, eb, NULL);
     }
     if (status != ORC_OK)
         goto done;

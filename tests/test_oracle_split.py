@@ -110,6 +110,36 @@ def test_first_slice_is_round_to_grid(orc, fmt):
             assert Fraction(float(sl[0, p, i])) == nearest * step
 
 
+@pytest.mark.parametrize("fmt", ["dd", "qd", "ts"])
+def test_literal_last_slice(orc, fmt):
+    """Algorithm 1 as printed (last slice = leading component of the residual
+    after D - 1 passes): the first D - 1 slices are those of the extracting
+    split; slice D is the leading component of the (D - 1)-pass residual;
+    slices plus the remaining residual still equal the input exactly; D = 1
+    returns the input's leading components; and the independent Python split
+    agrees bit for bit."""
+    m, k, D = 6, 29, 5
+    A = W.gen_matrix(fmt, m, k, E=16, seed=31, operand="A")
+    f32 = fmt == "ts"
+    lit, lex, lres = orc.split_plain(A, D, "rows", want_resid=True, last="remainder")
+    ext, eex = orc.split_plain(A, D, "rows")
+    _, _, res1 = orc.split_plain(A, D - 1, "rows", want_resid=True)
+    assert np.array_equal(lit[: D - 1], ext[: D - 1]) and np.array_equal(lex, eex)
+    assert np.array_equal(lit[D - 1], res1[0])
+    for i in range(m):
+        for p in range(k):
+            tot = sum((Fraction(float(lit[a, p, i])) for a in range(D)), Fraction(0)) + X.value(lres[:, p, i])
+            assert tot == X.value(A[:, p, i])
+        vec = [tuple(A[:, p, i]) for p in range(k)]
+        s2, _, _ = X.split_vector_py(vec, D, f32, last_remainder=True)
+        for a in range(D):
+            assert [float(v) for v in lit[a, :, i]] == [float(v) for v in s2[a]]
+    one, _ = orc.split_plain(A, 1, "rows", last="remainder")
+    assert np.array_equal(one[0], A[0])
+    with pytest.raises(ValueError):
+        orc.split_plain(A, D, "rows", last="rounded")
+
+
 def test_zero_row_gives_zero_slices(orc):
     A = W.gen_matrix("dd", 4, 9, seed=1, operand="A")
     A[:, :, 2] = 0.0
