@@ -183,6 +183,18 @@ int mpgemm_set_int8_tile(int cfg);
  */
 int mpgemm_set_split_kernel(int kind);
 int mpgemm_split_kernel(void);
+
+/*
+ * Last slice of the binary64/binary32 split (Algorithm 1, Section 3), per host
+ * thread.  0 (default): all D slices are extracted on the grid of tau and the
+ * remainder is dropped, so every slice product is exact in the slice format.
+ * 1: the last slice is the leading component of the residual left by the first
+ * D - 1 passes, as Algorithm 1 is printed; the products of that full-width
+ * slice are then rounded by the matrix cores.  For comparison of the two
+ * readings; the INT8 form ignores it.  Returns -1 for other values.
+ */
+int mpgemm_set_last_slice(int kind);
+int mpgemm_last_slice(void);
 int mpgemm_set_num_slices(int fmt, int mode, int D);
 int mpgemm_num_slices(int fmt, int mode, int k);
 int mpgemm_last_num_slices(void);

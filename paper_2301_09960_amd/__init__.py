@@ -67,6 +67,8 @@ def lib():
                 L.mpgemm_set_int8_tile.argtypes = [_I]
                 L.mpgemm_set_split_kernel.argtypes = [_I]
                 L.mpgemm_split_kernel.argtypes = []
+                L.mpgemm_set_last_slice.argtypes = [_I]
+                L.mpgemm_last_slice.argtypes = []
                 L.mpgemm_set_mode.argtypes = [_I, _I]
                 L.mpgemm_get_mode.argtypes = [_I]
                 L.mpgemm_set_num_slices.argtypes = [_I, _I, _I]
@@ -154,6 +156,19 @@ def set_split_kernel(kind: int):
 
 def split_kernel() -> int:
     return int(lib().mpgemm_split_kernel())
+
+
+def set_last_slice(last: str):
+    """Last slice of the binary64/binary32 split, this thread: ``"extract"``
+    (default; every slice product exact) or ``"remainder"`` (Algorithm 1 as
+    printed: the residual's leading component after D - 1 passes)."""
+    if last not in ("extract", "remainder"):
+        raise ValueError(last)
+    _check(lib().mpgemm_set_last_slice(1 if last == "remainder" else 0), "set_last_slice")
+
+
+def last_slice() -> str:
+    return "remainder" if lib().mpgemm_last_slice() == 1 else "extract"
 
 
 def set_int8_tile(cfg: int):

@@ -38,6 +38,7 @@ struct ThreadOptions {
   int layout[kNumFmt] = {0, 0, 0, 0};  // 0: tuned default
   int int8_tile = 0;                   // 0: automatic
   int split_kernel = 0;                // 0: fused where vectors fit, 1: pass kernels only
+  int last_slice = 0;                  // 0: D extractions, 1: last slice = residual's leading component
   int slices[kNumFmt][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
   int last_slices = 0;
   void *ws = nullptr;
@@ -181,6 +182,7 @@ int slices_for(int fmt, int mode, int64_t k) {
 int thread_mode(int fmt) { return g_opt.mode[fmt]; }
 int int8_tile_override() { return g_opt.int8_tile; }
 int split_kernel_override() { return g_opt.split_kernel; }
+int last_slice_option() { return g_opt.last_slice; }
 
 // Wave layout of the binary64/binary32 slice-product kernel per format: the
 // tuned table (above), replaced per thread by mpgemm_set_tile_layout.
@@ -358,6 +360,7 @@ SplitOperand<T> operand_a(const T *A, int m, int k, int lda, const Plan &p, char
   o.nbp = p.mbp;
   o.kbp = p.kbp;
   o.mu = base + p.off_mu_a;
+  o.last_literal = g_opt.last_slice;
   o.exps = reinterpret_cast<int *>(base + p.off_exp_a);
   return o;
 }
@@ -377,6 +380,7 @@ SplitOperand<T> operand_b(const T *B, int k, int n, int ldb, const Plan &p, char
   o.nbp = p.nbp;
   o.kbp = p.kbp;
   o.mu = base + p.off_mu_b;
+  o.last_literal = g_opt.last_slice;
   o.exps = reinterpret_cast<int *>(base + p.off_exp_b);
   return o;
 }
@@ -678,6 +682,13 @@ int mpgemm_set_split_kernel(int kind) {
   return 0;
 }
 int mpgemm_split_kernel(void) { return g_opt.split_kernel; }
+
+int mpgemm_set_last_slice(int kind) {
+  if (kind < 0 || kind > 1) return -1;
+  g_opt.last_slice = kind;
+  return 0;
+}
+int mpgemm_last_slice(void) { return g_opt.last_slice; }
 
 int mpgemm_set_num_slices(int fmt, int mode, int D) {
   if (!fmt_ok(fmt)) return -1;

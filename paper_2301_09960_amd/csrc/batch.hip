@@ -55,7 +55,7 @@ struct OperandShape {
 };
 
 struct BatchPlan {
-  int device = 0, fmt = 0, mode = 0, layout = 1, int8_tile = 0, split_kernel = 0;
+  int device = 0, fmt = 0, mode = 0, layout = 1, int8_tile = 0, split_kernel = 0, last_slice = 0;
   hipStream_t stream = nullptr;
   std::vector<int> m, n, k, D;
   std::vector<ProductLayout> prod;
@@ -274,6 +274,7 @@ void write_descriptors(BatchPlan &p, const T *const *A, const int *lda, const T 
     a.exps = reinterpret_cast<int *>(p.ws + L.exp_a);
     a.D = L.D;
     a.rho = L.rho;
+    a.last_literal = p.last_slice;
     b.X = B[g];
     b.comp_stride = (int64_t)ldb[g] * L.n;
     b.sv = ldb[g];
@@ -289,6 +290,7 @@ void write_descriptors(BatchPlan &p, const T *const *A, const int *lda, const T 
     b.exps = reinterpret_cast<int *>(p.ws + L.exp_b);
     b.D = L.D;
     b.rho = L.rho;
+    b.last_literal = p.last_slice;
     ops[2 * slot] = a;
     ops[2 * slot + 1] = b;
     PlainGemmDesc d{};
@@ -576,6 +578,7 @@ int run_batched(int fmt, int count, const int *m, const int *n, const int *k, co
   for (BatchPlan *p : bc.plans)
     if (p->device == dev && p->stream == st && p->fmt == fmt && p->mode == mode && p->layout == layout &&
         p->int8_tile == int8_tile_override() && p->split_kernel == split_kernel_override() &&
+        p->last_slice == last_slice_option() &&
         (int)p->m.size() == count &&
         std::equal(p->m.begin(), p->m.end(), m) && std::equal(p->n.begin(), p->n.end(), n) &&
         std::equal(p->k.begin(), p->k.end(), k) && p->D == Ds) {
@@ -599,6 +602,7 @@ int run_batched(int fmt, int count, const int *m, const int *n, const int *k, co
     plan->layout = layout;
     plan->int8_tile = int8_tile_override();
     plan->split_kernel = split_kernel_override();
+    plan->last_slice = last_slice_option();
     plan->m.assign(m, m + count);
     plan->n.assign(n, n + count);
     plan->k.assign(k, k + count);

@@ -16,6 +16,7 @@ int layout_for(int fmt);
 // The INT8 tile configuration this thread forces (0: chosen by size).
 int int8_tile_override();
 int split_kernel_override();
+int last_slice_option();
 int slices_for(int fmt, int mode, int64_t k);
 void set_last_slices(int D);
 

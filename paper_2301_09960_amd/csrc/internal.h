@@ -27,6 +27,7 @@ struct SplitOperand {
   void *mu;              // per pass: nvec maxima as IEEE bit patterns (uint64 / uint32)
   int *exps;             // D x nvec exponents (FLOAT) or nvec (INT8)
   int D, rho;            // slice count and shift (used by the batched kernels)
+  int last_literal;      // 1: the last slice is the residual's leading component (FLOAT only)
 };
 
 // One product of an INT8-form batch, as read by the persistent INT8 GEMM and

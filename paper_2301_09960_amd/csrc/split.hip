@@ -161,7 +161,9 @@ __device__ void pass_body(const SplitOperand<T> &op, int idx, int pass, int rho,
       if (e != kZeroExp) {
         const T tau = pow2(e + rho, T(0));
         const T lead = R[0];
-        sl = (lead + tau) - tau;
+        // Algorithm 1 as printed takes the residual's leading component as the
+        // last slice (op.last_literal); by default it is extracted like the rest
+        sl = last && op.last_literal ? lead : (lead + tau) - tau;
         R[0] = lead - sl;  // exact
         renorm<T, C>(R);
       }
@@ -328,6 +330,7 @@ __device__ void fused_strip(const SplitOperand<T> &op, int strip, int D, int rho
     int e = kZeroExp;
     if (vec_ok && mu != 0) e = ceil_log2(from_bits(mu, T(0)));
     const T tau = e != kZeroExp ? pow2(e + rho, T(0)) : T(0);
+    const bool literal = op.last_literal && a == D - 1;
     T *dst = packed + ((int64_t)a * op.nbp + vb) * op.kbp * 256;
     m = 0;
 #pragma unroll
@@ -336,7 +339,7 @@ __device__ void fused_strip(const SplitOperand<T> &op, int strip, int D, int rho
       T sl = T(0);
       if (valid[j] && e != kZeroExp) {
         const T lead = R[j][0];
-        sl = (lead + tau) - tau;
+        sl = literal ? lead : (lead + tau) - tau;
         R[j][0] = lead - sl;  // exact
         renorm<T, C>(R[j]);
       }

@@ -73,6 +73,13 @@ def test_options_and_policy(L):
     with pytest.raises(mp.MpgemmError):
         mp.set_split_kernel(2)
     assert mp.split_kernel() == 0
+    # last slice of the split: extracted (default) or Algorithm 1's remainder
+    assert mp.last_slice() == "extract"
+    mp.set_last_slice("remainder")
+    assert mp.last_slice() == "remainder"
+    mp.set_last_slice("extract")
+    assert L.mpgemm_set_last_slice(2) == -1
+    assert mp.last_slice() == "extract"
 
 
 def test_workspace_bytes(L):

@@ -94,6 +94,30 @@ def test_batched_split_kernels_agree(mp, fmt):
         mp.set_split_kernel(0)
 
 
+def test_batched_literal_last_slice(mp):
+    """Algorithm 1's printed last slice in a batch: the same C as single calls
+    with that option, and a different one from the default extraction."""
+    import torch
+    fmt = "qd"
+    sh = shapes(5, 10, 1, 300) + [(9, 7, 4097)]
+    host = make_batch(fmt, sh, seed=13)
+    As = [dev(A) for A, _ in host]
+    Bs = [dev(B) for _, B in host]
+    try:
+        mp.set_last_slice("remainder")
+        Cs = mp.gemm_batched(fmt, As, Bs)
+        singles = [mp.gemm(fmt, A, B) for A, B in zip(As, Bs)]
+    finally:
+        mp.set_last_slice("extract")
+    Cd = mp.gemm_batched(fmt, As, Bs)
+    torch.cuda.synchronize()
+    differs = 0
+    for i in range(len(sh)):
+        assert torch.equal(singles[i], Cs[i]), (i, sh[i])
+        differs += int(not torch.equal(Cd[i], Cs[i]))
+    assert differs > 0
+
+
 @pytest.mark.parametrize("fmt", ["dd", "td", "qd"])
 def test_batched_int8_equals_single_calls(mp, orc, fmt):
     """The INT8 form batched: every product equals its single INT8 call bit for

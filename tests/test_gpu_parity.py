@@ -117,6 +117,38 @@ def test_slice_products_bit_exact(mp, orc, fmt):
         assert np.array_equal(got, want), (a, b, np.max(np.abs(got - want)))
 
 
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("kind", [0, 1], ids=["fused", "passes"])
+def test_literal_last_slice(mp, orc, split_kernel, fmt, kind):
+    """Algorithm 1 as printed (last slice = leading component of the residual
+    after D - 1 passes): slices and exponents bit-exact against the oracle in
+    both split kernels, and C, whose products with the full-width last slice
+    are rounded, still within 2^-t |A||B| (the log2 of the worst ratio is
+    printed beside the extracting reading's)."""
+    m, k, n = 130, 75, 70
+    A, B = W.gen_pair(fmt, m, n, k, E=16, seed=140)
+    D = mp.num_slices(fmt, "float", k)
+    dA, dB = dev(A), dev(B)
+    split_kernel(kind)
+    try:
+        mp.set_last_slice("remainder")
+        say(f"literal last slice {fmt} m={m} n={n} k={k} D={D} kernel={kind}")
+        sa, ea = orc.split_plain(A, D, "rows", last="remainder")
+        sb, eb = orc.split_plain(B, D, "cols", last="remainder")
+        ga, gea = mp.debug_split(fmt, dA, 0, D)
+        gb, geb = mp.debug_split(fmt, dB, 1, D)
+        assert np.array_equal(host(ga), sa) and np.array_equal(host(gea), ea)
+        assert np.array_equal(host(gb), sb) and np.array_equal(host(geb), eb)
+        lit = host(mp.gemm(fmt, dA, dB))
+    finally:
+        mp.set_last_slice("extract")
+    ext = host(mp.gemm(fmt, dA, dB))
+    ok, worst = _check_bound(orc, fmt, A, B, lit)
+    _, worst_ext = _check_bound(orc, fmt, A, B, ext)
+    say(f"  log2 worst ratio: remainder {worst:.1f}, extract {worst_ext:.1f}")
+    assert ok, worst
+
+
 def _check_bound(orc, fmt, A, B, C, rows=None):
     diff, absab, _ = orc.exact_check(A, B, C, rows=rows)
     ok, worst = orc.bound_report(diff, absab, T_BITS[fmt])
