@@ -215,6 +215,33 @@ size_t mpgemm_workspace_bytes(int fmt, int mode, int m, int n, int k, int D);
 int mpgemm_set_workspace(void *dev_ptr, size_t bytes);
 
 /*
+ * C = AB with an a-posteriori certificate (binary64/binary32 slices).  Computes
+ * C exactly as mpgemm_<fmt> does in the FLOAT form, with the thread's slice
+ * count, then bounds its error from the same split (Algorithm 1, Section 3):
+ * with A = A_s + RA (slices plus the remainder after D passes) and likewise B,
+ * AB - C = (the pairs a + b > D + 1 that are not formed) + A_s RB + RA B + (the
+ * rounding of the sum to c components).  Each part is bounded per entry from
+ * the slice exponents, the remainder bound of the last pass, the row sums of
+ * |A| and column sums of |B|, and one extra binary64 product |A_0||B_0| of the
+ * leading components, which also gives a lower bound of (|A||B|)_ij.
+ *
+ * cert (device, 2 m n doubles): plane 0 (m x n, column-major, leading
+ * dimension m) receives beta_ij >= |C_ij - (AB)_ij|, plane 1 lambda_ij <=
+ * (|A||B|)_ij.  *worst (device, one double) receives the largest beta / lambda
+ * (0 when every beta is 0; +inf where lambda is 0 and beta is not, e.g. a row
+ * and a column with disjoint supports).  The result meets 2^-t (|A||B|) in every
+ * entry if worst <= 2^-t (t = 100 / 150 / 200 / 66 for DD / TD / QD / TS).
+ * Assumes |A||B| and the bounds stay in the normal binary64 range.
+ *
+ * Returns MPGEMM_ERR_UNSUPPORTED in the INT8 form, with the printed last slice
+ * (mpgemm_set_last_slice(1)), and for TS with D = 1.  Argument codes as for
+ * mpgemm_<fmt>, shifted by one (fmt is argument 1); -11 / -12 for a NULL cert
+ * (with m, n > 0) / worst.  Enqueued on `stream` like the other calls.
+ */
+int mpgemm_certify(int fmt, int m, int n, int k, const void *A, int lda, const void *B, int ldb, void *C, int ldc,
+                   double *cert, double *worst, hipStream_t stream);
+
+/*
  * Parity hooks (used by the tests to compare intermediate results bit for bit).
  *
  * mpgemm_debug_split: split one operand as the GEMM does.  operand 0: the rows

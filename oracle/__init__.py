@@ -286,3 +286,64 @@ def bound_report(diff, absab, t: int):
     worst = float(np.max(ratio))
     ok = bool(np.all(diff[nz] <= np.ldexp(absab[nz], -t) * (1 + 2.0 ** -30)))
     return ok, (float(np.log2(worst)) if worst > 0 else float("-inf"))
+
+
+def certificate_terms(A, B, D: int):
+    """The truncation part of the a-posteriori error bound of the D-slice
+    product (Algorithm 1 and the pairs a + b <= D + 1 of Section 3), in exact
+    rational arithmetic (small inputs only).
+
+    With A = A_s + RA and B = B_s + RB (slices plus the remainder of the D
+    passes), AB - C_tri = (pairs a + b > D + 1) + A_s RB + RA B.  Per entry:
+      T1 = k sum over the left-out pairs of 2^(eA_a,i + eB_b,j)   (|A_a| <= 2^eA_a)
+      T2 = rB_j (sum_p |a_ip| + k rA_i),  T3 = rA_i sum_p |b_pj|,
+    rA_i = 2^(eA_D,i + rho - S) (1 + 2^(1 - rho)) bounding the remainder.
+    Returns ``(trunc, T1, T23, absab)`` as lists ``[i][j]`` of Fractions: the
+    exact |C_tri - AB| from this oracle's slices, T1, T2 + T3, and (|A||B|)_ij.
+    """
+    from fractions import Fraction
+
+    from . import exact as X
+    f32 = A.dtype == np.float32
+    S = 24 if f32 else 53
+    c, k, m = A.shape
+    n = B.shape[1]
+    r = rho(S, k)
+    sa, ea = split_plain(A, D, "rows")
+    sb, eb = split_plain(B, D, "cols")
+    Av = X.matrix_values(A)  # Av[i][p]
+    Bv = X.matrix_values(B)  # Bv[p][j]
+    SA = [[[Fraction(float(sa[a, p, i])) for p in range(k)] for i in range(m)] for a in range(D)]
+    SB = [[[Fraction(float(sb[b, j, p])) for p in range(k)] for j in range(n)] for b in range(D)]
+
+    def p2(e):
+        return Fraction(2) ** int(e)
+
+    rem = 1 + Fraction(2) ** (1 - r)
+    rA = [0 if ea[D - 1, i] == ZERO_EXP else p2(ea[D - 1, i] + r - S) * rem for i in range(m)]
+    rB = [0 if eb[D - 1, j] == ZERO_EXP else p2(eb[D - 1, j] + r - S) * rem for j in range(n)]
+    rs = [sum((abs(Av[i][p]) for p in range(k)), Fraction(0)) for i in range(m)]
+    cs = [sum((abs(Bv[p][j]) for p in range(k)), Fraction(0)) for j in range(n)]
+    trunc, T1, T23, absab = [], [], [], []
+    for i in range(m):
+        tr, t1s, t23s, ab = [], [], [], []
+        for j in range(n):
+            exact = sum((Av[i][p] * Bv[p][j] for p in range(k)), Fraction(0))
+            ctri = Fraction(0)
+            for a in range(D):
+                for b in range(D - a):  # 0-based a + b <= D - 1, i.e. 1-based a + b <= D + 1
+                    ctri += sum((SA[a][i][p] * SB[b][j][p] for p in range(k)), Fraction(0))
+            t1 = Fraction(0)
+            for a in range(1, D):
+                for b in range(D - a, D):
+                    if ea[a, i] != ZERO_EXP and eb[b, j] != ZERO_EXP:
+                        t1 += p2(ea[a, i] + eb[b, j])
+            t1s.append(t1 * k)
+            t23s.append(rB[j] * (rs[i] + k * rA[i]) + rA[i] * cs[j])
+            tr.append(abs(ctri - exact))
+            ab.append(sum((abs(Av[i][p] * Bv[p][j]) for p in range(k)), Fraction(0)))
+        trunc.append(tr)
+        T1.append(t1s)
+        T23.append(t23s)
+        absab.append(ab)
+    return trunc, T1, T23, absab

@@ -78,6 +78,7 @@ def lib():
                 L.mpgemm_set_workspace.argtypes = [_P, ctypes.c_size_t]
                 L.mpgemm_debug_split.argtypes = [_I, _I, _I, _I, _I, _P, _I, _I, _P, _P, _P]
                 L.mpgemm_debug_products.argtypes = [_I, _I, _I, _I, _I, _P, _I, _P, _I, _I, _I, _I, _P, _I, _P]
+                L.mpgemm_certify.argtypes = [_I, _I, _I, _I, _P, _I, _P, _I, _P, _I, _P, _P, _P]
                 L.mpgemm_profile_enable.argtypes = [_I]
                 L.mpgemm_profile_read.argtypes = [_P, _P, _I]
                 L.mpgemm_load_tune_file.argtypes = [ctypes.c_char_p]
@@ -288,6 +289,38 @@ def gemm(fmt, A, B, C=None, *, mode=None, slices=None, stream=None):
                 _stream(stream))
     _check(st, "mpgemm_" + name)
     return C
+
+
+def certify(fmt, A, B, C=None, *, slices=None, stream=None):
+    """C = A B (binary64/binary32 slices) with its a-posteriori certificate.
+
+    Returns ``(C, cert, worst)``: cert ``(2, n, m)`` float64 holding, per entry,
+    an upper bound of |C - AB| (plane 0) and a lower bound of (|A||B|)_ij (plane
+    1); worst a one-element float64 tensor with the largest ratio of the two
+    (the result meets 2^-t |A||B| everywhere when worst <= 2^-t).  Enqueued on
+    ``stream`` without synchronizing.
+    """
+    import torch
+    f = _fmt(fmt)
+    name = [k for k, v in FORMATS.items() if v == f][0]
+    c = COMPONENTS[name]
+    dtype = torch.float32 if name == "ts" else torch.float64
+    _check_tensor(A, c, dtype, "A")
+    _check_tensor(B, c, dtype, "B")
+    k, m = A.shape[1], A.shape[2]
+    n, kb = B.shape[1], B.shape[2]
+    if kb != k:
+        raise ValueError(f"inner dimensions differ: A has k={k}, B has k={kb}")
+    if C is None:
+        C = torch.empty((c, n, m), dtype=dtype, device=A.device)
+    cert = torch.empty((2, n, m), dtype=torch.float64, device=A.device)
+    worst = torch.empty((1,), dtype=torch.float64, device=A.device)
+    with _options(f, _mode("float"), slices):
+        st = lib().mpgemm_certify(f, m, n, k, _P(A.data_ptr()), max(1, m), _P(B.data_ptr()), max(1, k),
+                                  _P(C.data_ptr()), max(1, m), _P(cert.data_ptr()), _P(worst.data_ptr()),
+                                  _stream(stream))
+    _check(st, "mpgemm_certify")
+    return C, cert, worst
 
 
 def gemm_batched(fmt, As, Bs, Cs=None, *, mode=None, slices=None, stream=None):

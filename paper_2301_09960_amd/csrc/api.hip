@@ -522,6 +522,41 @@ int debug_products_t(int fmt, int mode, int m, int n, int k, const T *A, int lda
   return hip_status(e);
 }
 
+// C = AB as run() computes it in the binary64/binary32 form, then the
+// a-posteriori certificate (certify.hip) from the same split.
+template <typename T, int C>
+int certify_t(int fmt, int m, int n, int k, const T *A, int lda, const T *B, int ldb, T *Cm, int ldc, double *cert,
+              double *worst, hipStream_t st) {
+  int s = validate(m, n, k, A, lda, B, ldb, Cm, ldc);
+  if (s) return s < 0 ? s - 1 : s;  // shifted past fmt
+  if (!cert && m > 0 && n > 0) return -11;
+  if (!worst) return -12;
+  if ((s = check_device_cached())) return s;
+  if (g_opt.mode[fmt] != MPGEMM_MODE_FLOAT || g_opt.last_slice != 0) return MPGEMM_ERR_UNSUPPORTED;
+  const int D = slices_for(fmt, MPGEMM_MODE_FLOAT, k);
+  g_opt.last_slices = D;
+  if (sizeof(T) == 4 && D < 2) return MPGEMM_ERR_UNSUPPORTED;  // plane 0 of the binary32 slices holds |A_0|
+  if (m == 0 || n == 0 || k == 0) {
+    hipError_t e = launch_fill32(worst, 2, 0u, st);
+    if (e == hipSuccess && m > 0 && n > 0) e = launch_fill32(cert, (int64_t)4 * m * n, 0u, st);
+    if (e == hipSuccess && m > 0 && n > 0)
+      e = launch_zero_matrix(Cm, sizeof(T), C, m, n, ldc, (int64_t)ldc * n, st);
+    return hip_status(e);
+  }
+  const Plan p = make_plan(fmt, MPGEMM_MODE_FLOAT, m, n, k, D);
+  Workspace ws;
+  if ((s = acquire(ws, p.total, st))) return s;
+  const SplitOperand<T> a = operand_a(A, m, k, lda, p, ws.base), b = operand_b(B, k, n, ldb, p, ws.base);
+  hipError_t e = split_both<T, C>(a, b, p, st);
+  if (e == hipSuccess) e = gemm_launch<T, C>(p, ws.base, m, n, k, Cm, ldc, -1, nullptr, 0, st);
+  if (e == hipSuccess)
+    e = launch_certify<T>(a, b, m, n, k, D, p.rho, C, cert, worst, reinterpret_cast<double *>(ws.base + p.off_pack_a),
+                          reinterpret_cast<double *>(ws.base + p.off_pack_b),
+                          reinterpret_cast<double *>(ws.base + p.off_mu_a),
+                          reinterpret_cast<double *>(ws.base + p.off_mu_b), 1, st);
+  return hip_status(e);
+}
+
 }  // namespace host
 }  // namespace mp
 
@@ -756,6 +791,25 @@ int mpgemm_debug_products(int fmt, int mode, int m, int n, int k, const void *A,
     default:
       return debug_products_t<float, 3>(fmt, mode, m, n, k, (const float *)A, lda, (const float *)B, ldb, D, a, b,
                                         out, ldo, stream);
+  }
+}
+
+int mpgemm_certify(int fmt, int m, int n, int k, const void *A, int lda, const void *B, int ldb, void *C, int ldc,
+                   double *cert, double *worst, hipStream_t stream) {
+  if (!fmt_ok(fmt)) return -1;
+  switch (fmt) {
+    case MPGEMM_DD:
+      return certify_t<double, 2>(fmt, m, n, k, (const double *)A, lda, (const double *)B, ldb, (double *)C, ldc, cert,
+                                  worst, stream);
+    case MPGEMM_TD:
+      return certify_t<double, 3>(fmt, m, n, k, (const double *)A, lda, (const double *)B, ldb, (double *)C, ldc, cert,
+                                  worst, stream);
+    case MPGEMM_QD:
+      return certify_t<double, 4>(fmt, m, n, k, (const double *)A, lda, (const double *)B, ldb, (double *)C, ldc, cert,
+                                  worst, stream);
+    default:
+      return certify_t<float, 3>(fmt, m, n, k, (const float *)A, lda, (const float *)B, ldb, (float *)C, ldc, cert,
+                                 worst, stream);
   }
 }
 

@@ -1,0 +1,146 @@
+// A-posteriori error certificate of the binary64/binary32-slice product.
+//
+// With D slices per row of A and column of B (Algorithm 1, Section 3), write
+// A = A_s + RA and B = B_s + RB, where A_s is the sum of the slices and RA the
+// remainder left by the D passes.  The product computed from the triangle
+// a + b <= D + 1 (the pairs the statement after Fig. 1 keeps) differs from AB by
+//   AB - C_tri = sum_{a,b <= D, a + b > D + 1} A_a B_b + A_s RB + RA B,
+// and the computed C differs from C_tri by the rounding of the accumulation to
+// c components.  Per entry (i, j) this file bounds each part from quantities
+// the split already produced, and bounds (|A||B|)_ij from below:
+//   T1 = k sum_{dropped (a, b)} 2^(eA_a,i + eB_b,j)      |A_a,ip| <= 2^eA_a,i
+//   T2 = rB_j (rsA_i + k rA_i)                             |A_s| <= |A| + |RA|
+//   T3 = rA_i csB_j
+//   T4 = 2^(4 - S c) UB_ij                                 final rounding of C
+// with rA_i = 2^(eA_D,i + rho - S) (1 + 2^(1 - rho)) the bound on the remainder
+// after the last pass, rsA_i / csB_j upper bounds of the row sums of |A| and
+// column sums of |B|, and UB_ij / LB_ij upper / lower bounds of (|A||B|)_ij
+// from one binary64 product of the absolute leading components |A_0| |B_0|
+// (run on the slice-product kernel as a single pair).  Entry (i, j) is
+// certified when T1 + T2 + T3 + T4 <= 2^-t LB_ij.
+#include "internal.h"
+#include "layout.h"
+#include "mp_device.h"
+
+namespace mp {
+namespace {
+
+constexpr int kCertThreads = 256;
+
+// |X_0| of one operand in the packed binary64 layout (slice plane 0), zero in
+// the padding: thread per packed element, so stores are contiguous.
+template <typename T>
+__global__ __launch_bounds__(kCertThreads) void k_pack_abs_lead(SplitOperand<T> op, double *out) {
+  const int64_t total = op.nbp * op.kbp * 256;
+  for (int64_t idx = blockIdx.x * (int64_t)kCertThreads + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * kCertThreads) {
+    const int64_t blk = idx / 256, kb = blk % op.kbp, vb = blk / op.kbp;
+    const int within = (int)(idx % 256);
+    // invert the binary64 packed order: within = (s / 2) 128 + 2 lane + (s % 2)
+    const int half = within / 128, r = within % 128, lane = r / 2, s = 2 * half + r % 2;
+    const int64_t v = vb * kBlk + lane % 16, p = kb * kKBlk + 4 * s + lane / 16;
+    double x = 0.0;
+    if (v < op.nvec && p < op.len) x = fabs((double)op.X[v * op.sv + p * op.sp]);
+    out[idx] = x;
+  }
+}
+
+// Sum over p of |X_0(v, p)| for every vector v (one thread per vector).
+template <typename T>
+__global__ __launch_bounds__(kCertThreads) void k_abs_sums(SplitOperand<T> op, double *sums) {
+  const int v = blockIdx.x * kCertThreads + threadIdx.x;
+  if (v >= op.nvec) return;
+  double s = 0.0;
+  for (int p = 0; p < op.len; ++p) s += fabs((double)op.X[(int64_t)v * op.sv + (int64_t)p * op.sp]);
+  sums[v] = s;
+}
+
+__device__ __forceinline__ double pow2d(int e) { return ldexp(1.0, e); }
+
+// Per entry: reads the single-pair product of |A_0| |B_0| from plane 0 of
+// `cert`, writes the error bound there and the lower bound of (|A||B|)_ij to
+// plane 1, and raises *worst to the largest ratio (bit patterns of
+// non-negative doubles order like the values).
+__global__ __launch_bounds__(kCertThreads) void k_certify(int m, int n, int k, int D, int rho, int S, int comps,
+                                                          const int *__restrict__ eA, const int *__restrict__ eB,
+                                                          const double *__restrict__ rsA,
+                                                          const double *__restrict__ csB, double *cert,
+                                                          unsigned long long *worst) {
+  const int64_t mn = (int64_t)m * n;
+  const double u = ldexp(1.0, -52);
+  const double sum_up = 1.0 + (k + 2) * u;  // |computed sum - exact| <= (k - 1) u' (sum), u' = 2^-53
+  const double lead_lo = 1.0 - ldexp(1.0, 2 - S), lead_hi = 1.0 + ldexp(1.0, 2 - S);  // |x_0| vs |x|
+  const double rem = 1.0 + ldexp(1.0, 1 - rho);
+  unsigned long long local = 0;
+  for (int64_t idx = blockIdx.x * (int64_t)kCertThreads + threadIdx.x; idx < mn;
+       idx += (int64_t)gridDim.x * kCertThreads) {
+    const int i = (int)(idx % m), j = (int)(idx / m);
+    const double raw = cert[idx];
+    const double lb = raw * (1.0 - (k + 2) * u) * lead_lo * lead_lo;
+    const double ub = raw * sum_up * lead_hi * lead_hi;
+    // T1: the pairs outside the triangle (both indices >= 2)
+    double t1 = 0.0;
+    for (int a = 2; a <= D; ++a) {
+      const int ea = eA[(int64_t)(a - 1) * m + i];
+      if (ea == kZeroExp) break;  // later passes are zero too
+      for (int b = D + 2 - a; b <= D; ++b) {
+        const int eb = eB[(int64_t)(b - 1) * n + j];
+        if (eb == kZeroExp) break;
+        t1 += pow2d(ea + eb);
+      }
+    }
+    t1 *= (double)k;
+    const int eAD = eA[(int64_t)(D - 1) * m + i], eBD = eB[(int64_t)(D - 1) * n + j];
+    const double rA = eAD == kZeroExp ? 0.0 : pow2d(eAD + rho - S) * rem;
+    const double rB = eBD == kZeroExp ? 0.0 : pow2d(eBD + rho - S) * rem;
+    const double rs = rsA[i] * sum_up * lead_hi, cs = csB[j] * sum_up * lead_hi;
+    const double t2 = rB * (rs + (double)k * rA);
+    const double t3 = rA * cs;
+    const double t4 = ldexp(ub, 4 - S * comps);
+    const double beta = (t1 + t2 + t3 + t4) * (1.0 + ldexp(1.0, -40));
+    cert[idx] = beta;
+    cert[mn + idx] = lb;
+    const double ratio = lb > 0.0 ? beta / lb : (beta > 0.0 ? __builtin_inf() : 0.0);
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(ratio);
+    local = bits > local ? bits : local;
+  }
+  // one atomic per wavefront
+  for (int off = 32; off >= 1; off >>= 1) {
+    const unsigned long long o = __shfl_xor(local, off, 64);
+    local = o > local ? o : local;
+  }
+  if (threadIdx.x % 64 == 0 && local != 0) atomicMax(worst, local);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_certify(const SplitOperand<T> &a, const SplitOperand<T> &b, int m, int n, int k, int D, int rho,
+                          int comps, double *cert, double *worst, double *pack_a, double *pack_b, double *rs_a,
+                          double *cs_b, int layout, hipStream_t st) {
+  const int S = sizeof(T) == 8 ? 53 : 24;
+  hipError_t e = launch_fill32(worst, 2, 0u, st);
+  if (e != hipSuccess) return e;
+  const auto grid_of = [](int64_t work) { return (unsigned)std::min<int64_t>(ceil_div(work, kCertThreads), 8192); };
+  hipLaunchKernelGGL((k_pack_abs_lead<T>), dim3(grid_of(a.nbp * a.kbp * 256)), dim3(kCertThreads), 0, st, a, pack_a);
+  hipLaunchKernelGGL((k_pack_abs_lead<T>), dim3(grid_of(b.nbp * b.kbp * 256)), dim3(kCertThreads), 0, st, b, pack_b);
+  hipLaunchKernelGGL((k_abs_sums<T>), dim3((unsigned)ceil_div(m, kCertThreads)), dim3(kCertThreads), 0, st, a, rs_a);
+  hipLaunchKernelGGL((k_abs_sums<T>), dim3((unsigned)ceil_div(n, kCertThreads)), dim3(kCertThreads), 0, st, b, cs_b);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // |A_0| |B_0| as one pair on the binary64 slice-product kernel, into planes 0 and 1
+  e = launch_gemm_plain<double, 2>(pack_a, pack_b, a.nbp, b.nbp, a.kbp, m, n, 1, cert, m, (int64_t)m * n, -1, nullptr,
+                                   0, layout, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_certify, dim3(grid_of((int64_t)m * n)), dim3(kCertThreads), 0, st, m, n, k, D, rho, S, comps,
+                     a.exps, b.exps, rs_a, cs_b, cert, reinterpret_cast<unsigned long long *>(worst));
+  return hipGetLastError();
+}
+
+template hipError_t launch_certify<double>(const SplitOperand<double> &, const SplitOperand<double> &, int, int, int,
+                                           int, int, int, double *, double *, double *, double *, double *, double *,
+                                           int, hipStream_t);
+template hipError_t launch_certify<float>(const SplitOperand<float> &, const SplitOperand<float> &, int, int, int, int,
+                                          int, int, double *, double *, double *, double *, double *, double *, int,
+                                          hipStream_t);
+
+}  // namespace mp

@@ -147,6 +147,17 @@ int int8_kblocks_per_chunk(int D);
 int int8_tile_config(int64_t m, int64_t n, int cfg);
 inline int int8_tile_blocks(int cfg) { return cfg == 1 ? 4 : 8; }
 
+// A-posteriori certificate of a binary64/binary32-slice product whose split
+// (a, b: exponents filled) and GEMM have been enqueued: per entry, an upper
+// bound of |C - AB| into plane 0 of `cert` and a lower bound of (|A||B|)_ij
+// into plane 1 (m x n each, column-major, leading dimension m), and the largest
+// ratio of the two into *worst.  pack_a / pack_b (the packed slice planes,
+// reused) and rs_a / cs_b (m and n doubles) are scratch.
+template <typename T>
+hipError_t launch_certify(const SplitOperand<T> &a, const SplitOperand<T> &b, int m, int n, int k, int D, int rho,
+                          int comps, double *cert, double *worst, double *pack_a, double *pack_b, double *rs_a,
+                          double *cs_b, int layout, hipStream_t st);
+
 // Debug: unpack D packed slices into planes of rows x cols (column-major, ld rows).
 hipError_t launch_unpack(int elem_bytes, const void *packed, int64_t nbp, int64_t kbp, int D, int orient, int rows,
                          int cols, void *out, hipStream_t st);

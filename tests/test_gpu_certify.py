@@ -1,0 +1,159 @@
+"""GPU: the a-posteriori certificate (mpgemm_certify) against the oracle.
+
+* C is the product mpgemm_<fmt> computes, bit for bit;
+* the error bound beta dominates the oracle's exact truncation bound T1 + T2 +
+  T3 and stays within 2^-30 of it plus the final-rounding term, and it bounds
+  the actual |C - AB| (exact arithmetic) in every entry;
+* lambda is a lower bound of (|A||B|)_ij within a few ulps of it;
+* the automatic slice counts are certified (worst <= 2^-t); too few are not.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import workload as W
+
+pytestmark = pytest.mark.gpu
+
+T_BITS = {"dd": 100, "td": 150, "qd": 200, "ts": 66}
+SC = {"dd": 106, "td": 159, "qd": 212, "ts": 72}  # S * c
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2301_09960_amd as mp
+    mp.lib()
+    assert mp.check_device() == 0, "device is not gfx950"
+    return mp
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("fmt", ["dd", "td", "qd", "ts"])
+def test_certificate_against_oracle(mp, orc, fmt):
+    import torch
+    m, n, k = 9, 7, 37
+    A, B = W.gen_pair(fmt, m, n, k, E=16, seed=41)
+    dA, dB = dev(A), dev(B)
+    C, cert, worst = mp.certify(fmt, dA, dB)
+    D = mp.last_num_slices()
+    say(f"certify {fmt} m={m} n={n} k={k} D={D}")
+    ref = mp.gemm(fmt, dA, dB)
+    torch.cuda.synchronize()
+    assert torch.equal(C, ref)
+    beta, lam = cert[0].cpu().numpy(), cert[1].cpu().numpy()  # (n, m)
+    tr, t1, t23, absab = orc.certificate_terms(A, B, D)
+    diff, _, _ = orc.exact_check(A, B, C.cpu().numpy())  # (n, m): |C - AB| rounded once
+    ratios = []
+    for i in range(m):
+        for j in range(n):
+            b, l = Fraction(float(beta[j, i])), Fraction(float(lam[j, i]))
+            T = t1[i][j] + t23[i][j]
+            assert T <= b <= T * (1 + Fraction(2) ** -30) + Fraction(2) ** (6 - SC[fmt]) * absab[i][j], (i, j)
+            # lambda gives up (k + 2) 2^-52 for the rounding of |A_0||B_0| and
+            # 2^(2 - S) per factor for |x_0| against |x|
+            slack = (k + 2) * Fraction(2) ** -52 + Fraction(2) ** (3 - (24 if fmt == "ts" else 53))
+            assert absab[i][j] * (1 - 2 * slack) <= l <= absab[i][j], (i, j)
+            assert diff[j, i] <= float(beta[j, i]) * (1 + 2.0 ** -50), (i, j)
+            ratios.append(float(beta[j, i]) / float(lam[j, i]))
+    w = float(worst.cpu()[0])
+    assert abs(w - max(ratios)) <= 2.0 ** -40 * max(ratios)
+    say(f"  log2 worst beta/lambda {np.log2(w):.1f} (t = {T_BITS[fmt]})")
+
+
+@pytest.mark.parametrize("fmt,m,n,k,extra", [("dd", 300, 200, 1000, 0), ("td", 130, 70, 600, 0),
+                                             ("qd", 200, 150, 333, 0), ("ts", 256, 129, 700, 1),
+                                             ("dd", 4096, 4096, 4096, 0)])
+def test_certified_at_automatic_slices(mp, orc, fmt, m, n, k, extra):
+    """The automatic slice counts certify DD / TD / QD on the workload; TS (7 to
+    9 bits per binary32 slice) needs one slice more, since the bound takes every
+    left-out pair at its largest.  The bound also holds against the exact error
+    on sampled rows."""
+    A, B = W.gen_pair(fmt, m, n, k, E=16, seed=m + k)
+    D = mp.num_slices(fmt, "float", k) + extra
+    C, cert, worst = mp.certify(fmt, dev(A), dev(B), slices=D)
+    w = float(worst.cpu()[0])
+    say(f"certify {fmt} {m}x{n}x{k} D={mp.last_num_slices()}: log2 worst {np.log2(w):.1f} (t = {T_BITS[fmt]})")
+    assert w <= 2.0 ** -T_BITS[fmt]
+    rows = [0, m // 2, m - 1]
+    diff, _, _ = orc.exact_check(A, B, C.cpu().numpy(), rows=rows)
+    beta = cert[0].cpu().numpy()
+    for c, i in enumerate(rows):
+        assert np.all(diff[:, c] <= beta[:, i] * (1 + 2.0 ** -50))
+
+
+def test_too_few_slices_not_certified(mp, orc):
+    """D = 3 for DD cannot reach 2^-100: the certificate says so, and its bound
+    still holds against the exact error."""
+    m, n, k = 40, 30, 200
+    A, B = W.gen_pair("dd", m, n, k, E=16, seed=5)
+    C, cert, worst = mp.certify("dd", dev(A), dev(B), slices=3)
+    w = float(worst.cpu()[0])
+    say(f"certify dd D=3: log2 worst {np.log2(w):.1f}")
+    assert w > 2.0 ** -100
+    diff, _, _ = orc.exact_check(A, B, C.cpu().numpy())
+    assert np.all(diff <= cert[0].cpu().numpy() * (1 + 2.0 ** -50))
+
+
+def test_zero_lines_and_empty(mp):
+    import torch
+    m, n, k = 20, 18, 33
+    A, B = W.gen_pair("qd", m, n, k, E=8, seed=9)
+    A[:, :, 3] = 0.0   # row 3 of A
+    B[:, 5, :] = 0.0   # column 5 of B
+    C, cert, worst = mp.certify("qd", dev(A), dev(B))
+    beta, lam = cert[0].cpu().numpy(), cert[1].cpu().numpy()
+    assert np.all(beta[:, 3] == 0) and np.all(lam[:, 3] == 0)
+    assert np.all(beta[5, :] == 0) and np.all(lam[5, :] == 0)
+    assert float(worst.cpu()[0]) <= 2.0 ** -200
+    # k = 0: C = 0, nothing to bound
+    A0 = torch.zeros((4, 0, 6), dtype=torch.float64, device="cuda")
+    B0 = torch.zeros((4, 5, 0), dtype=torch.float64, device="cuda")
+    C0, cert0, worst0 = mp.certify("qd", A0, B0)
+    assert not C0.any() and not cert0.any() and float(worst0.cpu()[0]) == 0.0
+
+
+def test_unsupported_modes(mp):
+    A, B = W.gen_pair("dd", 8, 8, 8, E=0, seed=1)
+    dA, dB = dev(A), dev(B)
+    mp.set_mode("dd", "int8")
+    try:
+        with pytest.raises(mp.MpgemmError):  # the thread's INT8 form is in force
+            _certify_in_mode(mp, dA, dB)
+    finally:
+        mp.set_mode("dd", "float")
+    mp.set_last_slice("remainder")
+    try:
+        with pytest.raises(mp.MpgemmError):
+            mp.certify("dd", dA, dB)
+    finally:
+        mp.set_last_slice("extract")
+
+
+def _certify_in_mode(mp, dA, dB):
+    """Calls the C entry point directly, with the thread's (INT8) mode in force."""
+    import ctypes
+
+    import torch
+    m, k = dA.shape[2], dA.shape[1]
+    n = dB.shape[1]
+    C = torch.empty((2, n, m), dtype=torch.float64, device="cuda")
+    cert = torch.empty((2, n, m), dtype=torch.float64, device="cuda")
+    worst = torch.empty((1,), dtype=torch.float64, device="cuda")
+    P = ctypes.c_void_p
+    st = mp.lib().mpgemm_certify(mp.FORMATS["dd"], m, n, k, P(dA.data_ptr()), m, P(dB.data_ptr()), k,
+                                 P(C.data_ptr()), m, P(cert.data_ptr()), P(worst.data_ptr()),
+                                 P(torch.cuda.current_stream().cuda_stream))
+    if st != 0:
+        raise mp.MpgemmError(st, "mpgemm_certify")
