@@ -62,6 +62,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-int8", action="store_true", help="skip the INT8-slice form")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-certify", action="store_true", help="skip the certified calls")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows of C in the CPU sample (0: auto)")
@@ -258,6 +259,29 @@ def main():
                     (stages[f]["split_ms"] + stages[f]["gemm_kernel_ms"]) / call_ms, 3),
             }
 
+    certify = None
+    if not args.no_certify:
+        # the same products with the a-posteriori certificate (one call each,
+        # after a warm call), against the plain call's split + GEMM time
+        certify = {}
+        for f in fmts:
+            mp.certify(f, *inputs[f], outs[f])
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            _, _, worst = mp.certify(f, *inputs[f], outs[f])
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            plain = stages[f]["split_ms"] + stages[f]["gemm_kernel_ms"]
+            certify[f] = {
+                "certify_call_ms": round(ms, 3),
+                "plain_call_ms": round(plain, 3),
+                "overhead_frac": round(ms / plain - 1.0, 4),
+                "log2_worst_bound_ratio": round(float(np.log2(float(worst.cpu()[0]))), 2),
+            }
+            log(f"certify {f}: {certify[f]}")
+
     batched = None
     pool = None
     if not args.no_batched or not args.no_serving:
@@ -339,6 +363,7 @@ def main():
         },
         "stages": stages,
         "int8": int8,
+        "certify": certify,
         "batched": batched,
         "serving": serving,
         "roofline": roofline,
