@@ -215,9 +215,11 @@ size_t mpgemm_workspace_bytes(int fmt, int mode, int m, int n, int k, int D);
 int mpgemm_set_workspace(void *dev_ptr, size_t bytes);
 
 /*
- * C = AB with an a-posteriori certificate (binary64/binary32 slices).  Computes
- * C exactly as mpgemm_<fmt> does in the FLOAT form, with the thread's slice
- * count, then bounds its error from the same split (Algorithm 1, Section 3):
+ * C = AB with an a-posteriori certificate.  Computes C exactly as mpgemm_<fmt>
+ * does, in the thread's slice form and with its slice count, then bounds its
+ * error from the same split (Algorithm 1, Section 3; in the INT8 form digit
+ * plane s is the slice, at most 2^(E - 7 (s - 1)), the remainder at most
+ * 2^(E - 7 D)):
  * with A = A_s + RA (slices plus the remainder after D passes) and likewise B,
  * AB - C = (the pairs a + b > D + 1 that are not formed) + A_s RB + RA B + (the
  * rounding of the sum to c components).  Each part is bounded per entry from
@@ -233,8 +235,9 @@ int mpgemm_set_workspace(void *dev_ptr, size_t bytes);
  * entry if worst <= 2^-t (t = 100 / 150 / 200 / 66 for DD / TD / QD / TS).
  * Assumes |A||B| and the bounds stay in the normal binary64 range.
  *
- * Returns MPGEMM_ERR_UNSUPPORTED in the INT8 form, with the printed last slice
- * (mpgemm_set_last_slice(1)), and for TS with D = 1.  Argument codes as for
+ * Returns MPGEMM_ERR_UNSUPPORTED with the printed last slice
+ * (mpgemm_set_last_slice(1)), for TS with D = 1, and in the INT8 form with
+ * fewer than about 8 digits (their planes hold |A_0| and |B_0|).  Argument codes as for
  * mpgemm_<fmt>, shifted by one (fmt is argument 1); -11 / -12 for a NULL cert
  * (with m, n > 0) / worst.  Enqueued on `stream` like the other calls.
  */

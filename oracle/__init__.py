@@ -288,10 +288,13 @@ def bound_report(diff, absab, t: int):
     return ok, (float(np.log2(worst)) if worst > 0 else float("-inf"))
 
 
-def certificate_terms(A, B, D: int):
+def certificate_terms(A, B, D: int, form: str = "float"):
     """The truncation part of the a-posteriori error bound of the D-slice
     product (Algorithm 1 and the pairs a + b <= D + 1 of Section 3), in exact
-    rational arithmetic (small inputs only).
+    rational arithmetic (small inputs only).  ``form='int8'``: the slices are
+    the INT8 digit planes, slice s of vector v being d_s 2^(E_v - 6 - 7 (s - 1))
+    with |d_s| <= 64, so it is bounded by 2^(E_v - 7 (s - 1)), and the remainder
+    after D digits by 2^(E_v - 7 D) (1 + 2^-40).
 
     With A = A_s + RA and B = B_s + RB (slices plus the remainder of the D
     passes), AB - C_tri = (pairs a + b > D + 1) + A_s RB + RA B.  Per entry:
@@ -309,19 +312,36 @@ def certificate_terms(A, B, D: int):
     c, k, m = A.shape
     n = B.shape[1]
     r = rho(S, k)
-    sa, ea = split_plain(A, D, "rows")
-    sb, eb = split_plain(B, D, "cols")
-    Av = X.matrix_values(A)  # Av[i][p]
-    Bv = X.matrix_values(B)  # Bv[p][j]
-    SA = [[[Fraction(float(sa[a, p, i])) for p in range(k)] for i in range(m)] for a in range(D)]
-    SB = [[[Fraction(float(sb[b, j, p])) for p in range(k)] for j in range(n)] for b in range(D)]
 
     def p2(e):
         return Fraction(2) ** int(e)
 
-    rem = 1 + Fraction(2) ** (1 - r)
-    rA = [0 if ea[D - 1, i] == ZERO_EXP else p2(ea[D - 1, i] + r - S) * rem for i in range(m)]
-    rB = [0 if eb[D - 1, j] == ZERO_EXP else p2(eb[D - 1, j] + r - S) * rem for j in range(n)]
+    Av = X.matrix_values(A)  # Av[i][p]
+    Bv = X.matrix_values(B)  # Bv[p][j]
+    if form == "int8":
+        da, EA = split_int8(A, D, "rows")
+        db, EB = split_int8(B, D, "cols")
+
+        def unit(E, s):
+            return p2(E - 6 - 7 * s)  # 0-based digit s
+
+        SA = [[[0 if EA[i] == ZERO_EXP else int(da[a, p, i]) * unit(EA[i], a) for p in range(k)] for i in range(m)]
+              for a in range(D)]
+        SB = [[[0 if EB[j] == ZERO_EXP else int(db[b, j, p]) * unit(EB[j], b) for p in range(k)] for j in range(n)]
+              for b in range(D)]
+        ea = np.array([[ZERO_EXP if E == ZERO_EXP else E - 7 * a for E in EA] for a in range(D)], dtype=np.int64)
+        eb = np.array([[ZERO_EXP if E == ZERO_EXP else E - 7 * b for E in EB] for b in range(D)], dtype=np.int64)
+        margin = 1 + Fraction(2) ** -40
+        rA = [0 if EA[i] == ZERO_EXP else p2(EA[i] - 7 * D) * margin for i in range(m)]
+        rB = [0 if EB[j] == ZERO_EXP else p2(EB[j] - 7 * D) * margin for j in range(n)]
+    else:
+        sa, ea = split_plain(A, D, "rows")
+        sb, eb = split_plain(B, D, "cols")
+        SA = [[[Fraction(float(sa[a, p, i])) for p in range(k)] for i in range(m)] for a in range(D)]
+        SB = [[[Fraction(float(sb[b, j, p])) for p in range(k)] for j in range(n)] for b in range(D)]
+        rem = 1 + Fraction(2) ** (1 - r)
+        rA = [0 if ea[D - 1, i] == ZERO_EXP else p2(ea[D - 1, i] + r - S) * rem for i in range(m)]
+        rB = [0 if eb[D - 1, j] == ZERO_EXP else p2(eb[D - 1, j] + r - S) * rem for j in range(n)]
     rs = [sum((abs(Av[i][p]) for p in range(k)), Fraction(0)) for i in range(m)]
     cs = [sum((abs(Bv[p][j]) for p in range(k)), Fraction(0)) for j in range(n)]
     trunc, T1, T23, absab = [], [], [], []

@@ -291,8 +291,8 @@ def gemm(fmt, A, B, C=None, *, mode=None, slices=None, stream=None):
     return C
 
 
-def certify(fmt, A, B, C=None, *, slices=None, stream=None):
-    """C = A B (binary64/binary32 slices) with its a-posteriori certificate.
+def certify(fmt, A, B, C=None, *, mode="float", slices=None, stream=None):
+    """C = A B in the given slice form with its a-posteriori certificate.
 
     Returns ``(C, cert, worst)``: cert ``(2, n, m)`` float64 holding, per entry,
     an upper bound of |C - AB| (plane 0) and a lower bound of (|A||B|)_ij (plane
@@ -315,7 +315,7 @@ def certify(fmt, A, B, C=None, *, slices=None, stream=None):
         C = torch.empty((c, n, m), dtype=dtype, device=A.device)
     cert = torch.empty((2, n, m), dtype=torch.float64, device=A.device)
     worst = torch.empty((1,), dtype=torch.float64, device=A.device)
-    with _options(f, _mode("float"), slices):
+    with _options(f, _mode(mode), slices):
         st = lib().mpgemm_certify(f, m, n, k, _P(A.data_ptr()), max(1, m), _P(B.data_ptr()), max(1, k),
                                   _P(C.data_ptr()), max(1, m), _P(cert.data_ptr()), _P(worst.data_ptr()),
                                   _stream(stream))

@@ -532,10 +532,11 @@ int certify_t(int fmt, int m, int n, int k, const T *A, int lda, const T *B, int
   if (!cert && m > 0 && n > 0) return -11;
   if (!worst) return -12;
   if ((s = check_device_cached())) return s;
-  if (g_opt.mode[fmt] != MPGEMM_MODE_FLOAT || g_opt.last_slice != 0) return MPGEMM_ERR_UNSUPPORTED;
-  const int D = slices_for(fmt, MPGEMM_MODE_FLOAT, k);
+  const int mode = g_opt.mode[fmt];
+  if (mode == MPGEMM_MODE_FLOAT && g_opt.last_slice != 0) return MPGEMM_ERR_UNSUPPORTED;
+  const int D = slices_for(fmt, mode, k);
   g_opt.last_slices = D;
-  if (sizeof(T) == 4 && D < 2) return MPGEMM_ERR_UNSUPPORTED;  // plane 0 of the binary32 slices holds |A_0|
+  if (mode == MPGEMM_MODE_FLOAT && sizeof(T) == 4 && D < 2) return MPGEMM_ERR_UNSUPPORTED;  // plane 0 holds |A_0|
   if (m == 0 || n == 0 || k == 0) {
     hipError_t e = launch_fill32(worst, 2, 0u, st);
     if (e == hipSuccess && m > 0 && n > 0) e = launch_fill32(cert, (int64_t)4 * m * n, 0u, st);
@@ -543,14 +544,29 @@ int certify_t(int fmt, int m, int n, int k, const T *A, int lda, const T *B, int
       e = launch_zero_matrix(Cm, sizeof(T), C, m, n, ldc, (int64_t)ldc * n, st);
     return hip_status(e);
   }
-  const Plan p = make_plan(fmt, MPGEMM_MODE_FLOAT, m, n, k, D);
+  const Plan p = make_plan(fmt, mode, m, n, k, D);
+  // |A_0| and |B_0| go into the slice buffers in the binary64 packed layout
+  SplitOperand<T> ca{}, cb{};
+  ca.nbp = nblocks_padded(m);
+  cb.nbp = nblocks_padded(n);
+  ca.kbp = cb.kbp = kblocks_padded(k);
+  if (mode == MPGEMM_MODE_INT8 &&
+      ((size_t)D * p.mbp * p.kbp * 1024 < (size_t)ca.nbp * ca.kbp * 256 * 8 ||
+       (size_t)D * p.nbp * p.kbp * 1024 < (size_t)cb.nbp * cb.kbp * 256 * 8))
+    return MPGEMM_ERR_UNSUPPORTED;  // fewer than about 8 digit planes
   Workspace ws;
   if ((s = acquire(ws, p.total, st))) return s;
   const SplitOperand<T> a = operand_a(A, m, k, lda, p, ws.base), b = operand_b(B, k, n, ldb, p, ws.base);
   hipError_t e = split_both<T, C>(a, b, p, st);
   if (e == hipSuccess) e = gemm_launch<T, C>(p, ws.base, m, n, k, Cm, ldc, -1, nullptr, 0, st);
+  ca = a;
+  cb = b;
+  ca.nbp = nblocks_padded(m);
+  cb.nbp = nblocks_padded(n);
+  ca.kbp = cb.kbp = kblocks_padded(k);
   if (e == hipSuccess)
-    e = launch_certify<T>(a, b, m, n, k, D, p.rho, C, cert, worst, reinterpret_cast<double *>(ws.base + p.off_pack_a),
+    e = launch_certify<T>(ca, cb, m, n, k, D, p.rho, C, mode == MPGEMM_MODE_INT8 ? 1 : 0, cert, worst,
+                          reinterpret_cast<double *>(ws.base + p.off_pack_a),
                           reinterpret_cast<double *>(ws.base + p.off_pack_b),
                           reinterpret_cast<double *>(ws.base + p.off_mu_a),
                           reinterpret_cast<double *>(ws.base + p.off_mu_b), 1, st);

@@ -1,4 +1,4 @@
-// A-posteriori error certificate of the binary64/binary32-slice product.
+// A-posteriori error certificate of the slice product (binary64/binary32 or INT8 slices).
 //
 // With D slices per row of A and column of B (Algorithm 1, Section 3), write
 // A = A_s + RA and B = B_s + RB, where A_s is the sum of the slices and RA the
@@ -7,14 +7,15 @@
 //   AB - C_tri = sum_{a,b <= D, a + b > D + 1} A_a B_b + A_s RB + RA B,
 // and the computed C differs from C_tri by the rounding of the accumulation to
 // c components.  Per entry (i, j) this file bounds each part from quantities
-// the split already produced, and bounds (|A||B|)_ij from below:
+// the split already produced (in either slice form: an INT8 digit plane is a
+// slice on the fixed grid of E - 6 - 7 (s - 1)), and bounds (|A||B|)_ij from below:
 //   T1 = k sum_{dropped (a, b)} 2^(eA_a,i + eB_b,j)      |A_a,ip| <= 2^eA_a,i
 //   T2 = rB_j (rsA_i + k rA_i)                             |A_s| <= |A| + |RA|
 //   T3 = rA_i csB_j
 //   T4 = 2^(4 - S c) UB_ij                                 final rounding of C
-// with rA_i = 2^(eA_D,i + rho - S) (1 + 2^(1 - rho)) the bound on the remainder
-// after the last pass, rsA_i / csB_j upper bounds of the row sums of |A| and
-// column sums of |B|, and UB_ij / LB_ij upper / lower bounds of (|A||B|)_ij
+// with rA_i the bound on the remainder after the last slice (remainder_bound),
+// rsA_i / csB_j upper bounds of the row sums of |A| and column sums of |B|, and
+// UB_ij / LB_ij upper / lower bounds of (|A||B|)_ij
 // from one binary64 product of the absolute leading components |A_0| |B_0|
 // (run on the slice-product kernel as a single pair).  Entry (i, j) is
 // certified when T1 + T2 + T3 + T4 <= 2^-t LB_ij.
@@ -57,12 +58,36 @@ __global__ __launch_bounds__(kCertThreads) void k_abs_sums(SplitOperand<T> op, d
 
 __device__ __forceinline__ double pow2d(int e) { return ldexp(1.0, e); }
 
+// Exponent bounding slice a (1-based) of vector v: FLOAT form, the pass's
+// ceil(log2 mu) (exps holds D x nvec); INT8 form, E_v - 7 (a - 1), since a digit
+// is at most 64 units u_a = 2^(E_v - 6 - 7 (a - 1)) (exps holds E per vector).
+__device__ __forceinline__ int slice_exp(const int *exps, int nvec, int v, int a, bool int8) {
+  if (!int8) return exps[(int64_t)(a - 1) * nvec + v];
+  const int E = exps[v];
+  return E == kZeroExp ? kZeroExp : E - 7 * (a - 1);
+}
+
+// Bound of the remainder after D slices: FLOAT form, 2^(e_D + rho - S)
+// (1 + 2^(1 - rho)) (half a grid step of the last pass, and the rounding of the
+// grid to the sum); INT8 form, u_D / 2 = 2^(E - 7 D), with a margin for the
+// components below the leading one.
+__device__ __forceinline__ double remainder_bound(const int *exps, int nvec, int v, int D, int rho, int S,
+                                                  bool int8) {
+  if (int8) {
+    const int E = exps[v];
+    return E == kZeroExp ? 0.0 : ldexp(1.0, E - 7 * D) * (1.0 + ldexp(1.0, -40));
+  }
+  const int e = exps[(int64_t)(D - 1) * nvec + v];
+  return e == kZeroExp ? 0.0 : ldexp(1.0, e + rho - S) * (1.0 + ldexp(1.0, 1 - rho));
+}
+
 // Per entry: reads the single-pair product of |A_0| |B_0| from plane 0 of
 // `cert`, writes the error bound there and the lower bound of (|A||B|)_ij to
 // plane 1, and raises *worst to the largest ratio (bit patterns of
 // non-negative doubles order like the values).
 __global__ __launch_bounds__(kCertThreads) void k_certify(int m, int n, int k, int D, int rho, int S, int comps,
-                                                          const int *__restrict__ eA, const int *__restrict__ eB,
+                                                          int int8, const int *__restrict__ eA,
+                                                          const int *__restrict__ eB,
                                                           const double *__restrict__ rsA,
                                                           const double *__restrict__ csB, double *cert,
                                                           unsigned long long *worst) {
@@ -70,7 +95,6 @@ __global__ __launch_bounds__(kCertThreads) void k_certify(int m, int n, int k, i
   const double u = ldexp(1.0, -52);
   const double sum_up = 1.0 + (k + 2) * u;  // |computed sum - exact| <= (k - 1) u' (sum), u' = 2^-53
   const double lead_lo = 1.0 - ldexp(1.0, 2 - S), lead_hi = 1.0 + ldexp(1.0, 2 - S);  // |x_0| vs |x|
-  const double rem = 1.0 + ldexp(1.0, 1 - rho);
   unsigned long long local = 0;
   for (int64_t idx = blockIdx.x * (int64_t)kCertThreads + threadIdx.x; idx < mn;
        idx += (int64_t)gridDim.x * kCertThreads) {
@@ -81,18 +105,17 @@ __global__ __launch_bounds__(kCertThreads) void k_certify(int m, int n, int k, i
     // T1: the pairs outside the triangle (both indices >= 2)
     double t1 = 0.0;
     for (int a = 2; a <= D; ++a) {
-      const int ea = eA[(int64_t)(a - 1) * m + i];
-      if (ea == kZeroExp) break;  // later passes are zero too
+      const int ea = slice_exp(eA, m, i, a, int8 != 0);
+      if (ea == kZeroExp) break;  // later slices are zero too
       for (int b = D + 2 - a; b <= D; ++b) {
-        const int eb = eB[(int64_t)(b - 1) * n + j];
+        const int eb = slice_exp(eB, n, j, b, int8 != 0);
         if (eb == kZeroExp) break;
         t1 += pow2d(ea + eb);
       }
     }
     t1 *= (double)k;
-    const int eAD = eA[(int64_t)(D - 1) * m + i], eBD = eB[(int64_t)(D - 1) * n + j];
-    const double rA = eAD == kZeroExp ? 0.0 : pow2d(eAD + rho - S) * rem;
-    const double rB = eBD == kZeroExp ? 0.0 : pow2d(eBD + rho - S) * rem;
+    const double rA = remainder_bound(eA, m, i, D, rho, S, int8 != 0);
+    const double rB = remainder_bound(eB, n, j, D, rho, S, int8 != 0);
     const double rs = rsA[i] * sum_up * lead_hi, cs = csB[j] * sum_up * lead_hi;
     const double t2 = rB * (rs + (double)k * rA);
     const double t3 = rA * cs;
@@ -116,8 +139,8 @@ __global__ __launch_bounds__(kCertThreads) void k_certify(int m, int n, int k, i
 
 template <typename T>
 hipError_t launch_certify(const SplitOperand<T> &a, const SplitOperand<T> &b, int m, int n, int k, int D, int rho,
-                          int comps, double *cert, double *worst, double *pack_a, double *pack_b, double *rs_a,
-                          double *cs_b, int layout, hipStream_t st) {
+                          int comps, int int8, double *cert, double *worst, double *pack_a, double *pack_b,
+                          double *rs_a, double *cs_b, int layout, hipStream_t st) {
   const int S = sizeof(T) == 8 ? 53 : 24;
   hipError_t e = launch_fill32(worst, 2, 0u, st);
   if (e != hipSuccess) return e;
@@ -132,15 +155,15 @@ hipError_t launch_certify(const SplitOperand<T> &a, const SplitOperand<T> &b, in
                                    0, layout, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_certify, dim3(grid_of((int64_t)m * n)), dim3(kCertThreads), 0, st, m, n, k, D, rho, S, comps,
-                     a.exps, b.exps, rs_a, cs_b, cert, reinterpret_cast<unsigned long long *>(worst));
+                     int8, a.exps, b.exps, rs_a, cs_b, cert, reinterpret_cast<unsigned long long *>(worst));
   return hipGetLastError();
 }
 
 template hipError_t launch_certify<double>(const SplitOperand<double> &, const SplitOperand<double> &, int, int, int,
-                                           int, int, int, double *, double *, double *, double *, double *, double *,
-                                           int, hipStream_t);
+                                           int, int, int, int, double *, double *, double *, double *, double *,
+                                           double *, int, hipStream_t);
 template hipError_t launch_certify<float>(const SplitOperand<float> &, const SplitOperand<float> &, int, int, int, int,
-                                          int, int, double *, double *, double *, double *, double *, double *, int,
-                                          hipStream_t);
+                                          int, int, int, double *, double *, double *, double *, double *, double *,
+                                          int, hipStream_t);
 
 }  // namespace mp

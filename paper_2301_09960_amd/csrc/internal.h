@@ -153,10 +153,12 @@ inline int int8_tile_blocks(int cfg) { return cfg == 1 ? 4 : 8; }
 // into plane 1 (m x n each, column-major, leading dimension m), and the largest
 // ratio of the two into *worst.  pack_a / pack_b (the packed slice planes,
 // reused) and rs_a / cs_b (m and n doubles) are scratch.
+// int8: the split was the INT8 digit split (exps: E per vector); a and b then
+// carry the binary64 packed geometry (nbp, kbp) for |A_0| and |B_0|.
 template <typename T>
 hipError_t launch_certify(const SplitOperand<T> &a, const SplitOperand<T> &b, int m, int n, int k, int D, int rho,
-                          int comps, double *cert, double *worst, double *pack_a, double *pack_b, double *rs_a,
-                          double *cs_b, int layout, hipStream_t st);
+                          int comps, int int8, double *cert, double *worst, double *pack_a, double *pack_b,
+                          double *rs_a, double *cs_b, int layout, hipStream_t st);
 
 // Debug: unpack D packed slices into planes of rows x cols (column-major, ld rows).
 hipError_t launch_unpack(int elem_bytes, const void *packed, int64_t nbp, int64_t kbp, int D, int orient, int rows,

@@ -40,20 +40,21 @@ def say(*a):
     print(*a, flush=True)
 
 
-@pytest.mark.parametrize("fmt", ["dd", "td", "qd", "ts"])
-def test_certificate_against_oracle(mp, orc, fmt):
+@pytest.mark.parametrize("fmt,mode", [("dd", "float"), ("td", "float"), ("qd", "float"), ("ts", "float"),
+                                      ("dd", "int8"), ("td", "int8"), ("qd", "int8")])
+def test_certificate_against_oracle(mp, orc, fmt, mode):
     import torch
     m, n, k = 9, 7, 37
     A, B = W.gen_pair(fmt, m, n, k, E=16, seed=41)
     dA, dB = dev(A), dev(B)
-    C, cert, worst = mp.certify(fmt, dA, dB)
+    C, cert, worst = mp.certify(fmt, dA, dB, mode=mode)
     D = mp.last_num_slices()
-    say(f"certify {fmt} m={m} n={n} k={k} D={D}")
-    ref = mp.gemm(fmt, dA, dB)
+    say(f"certify {fmt} {mode} m={m} n={n} k={k} D={D}")
+    ref = mp.gemm(fmt, dA, dB, mode=mode)
     torch.cuda.synchronize()
     assert torch.equal(C, ref)
     beta, lam = cert[0].cpu().numpy(), cert[1].cpu().numpy()  # (n, m)
-    tr, t1, t23, absab = orc.certificate_terms(A, B, D)
+    tr, t1, t23, absab = orc.certificate_terms(A, B, D, form=mode)
     diff, _, _ = orc.exact_check(A, B, C.cpu().numpy())  # (n, m): |C - AB| rounded once
     ratios = []
     for i in range(m):
@@ -72,19 +73,23 @@ def test_certificate_against_oracle(mp, orc, fmt):
     say(f"  log2 worst beta/lambda {np.log2(w):.1f} (t = {T_BITS[fmt]})")
 
 
-@pytest.mark.parametrize("fmt,m,n,k,extra", [("dd", 300, 200, 1000, 0), ("td", 130, 70, 600, 0),
-                                             ("qd", 200, 150, 333, 0), ("ts", 256, 129, 700, 1),
-                                             ("dd", 4096, 4096, 4096, 0)])
-def test_certified_at_automatic_slices(mp, orc, fmt, m, n, k, extra):
+@pytest.mark.parametrize("fmt,mode,m,n,k,extra", [("dd", "float", 300, 200, 1000, 0), ("td", "float", 130, 70, 600, 0),
+                                                  ("qd", "float", 200, 150, 333, 0), ("ts", "float", 256, 129, 700, 1),
+                                                  ("dd", "float", 4096, 4096, 4096, 0),
+                                                  ("dd", "int8", 300, 200, 1000, 0), ("td", "int8", 130, 70, 600, 0),
+                                                  ("qd", "int8", 200, 150, 333, 0),
+                                                  ("qd", "int8", 4096, 4096, 4096, 1)])
+def test_certified_at_automatic_slices(mp, orc, fmt, mode, m, n, k, extra):
     """The automatic slice counts certify DD / TD / QD on the workload; TS (7 to
-    9 bits per binary32 slice) needs one slice more, since the bound takes every
-    left-out pair at its largest.  The bound also holds against the exact error
-    on sampled rows."""
+    9 bits per binary32 slice) and INT8 QD at k = 4096 need one slice more,
+    since the bound takes every left-out pair at its largest.  The bound also
+    holds against the exact error on sampled rows."""
     A, B = W.gen_pair(fmt, m, n, k, E=16, seed=m + k)
-    D = mp.num_slices(fmt, "float", k) + extra
-    C, cert, worst = mp.certify(fmt, dev(A), dev(B), slices=D)
+    D = mp.num_slices(fmt, mode, k) + extra
+    C, cert, worst = mp.certify(fmt, dev(A), dev(B), mode=mode, slices=D)
     w = float(worst.cpu()[0])
-    say(f"certify {fmt} {m}x{n}x{k} D={mp.last_num_slices()}: log2 worst {np.log2(w):.1f} (t = {T_BITS[fmt]})")
+    say(f"certify {fmt} {mode} {m}x{n}x{k} D={mp.last_num_slices()}: log2 worst {np.log2(w):.1f} "
+        f"(t = {T_BITS[fmt]})")
     assert w <= 2.0 ** -T_BITS[fmt]
     rows = [0, m // 2, m - 1]
     diff, _, _ = orc.exact_check(A, B, C.cpu().numpy(), rows=rows)
@@ -124,13 +129,18 @@ def test_zero_lines_and_empty(mp):
     assert not C0.any() and not cert0.any() and float(worst0.cpu()[0]) == 0.0
 
 
-def test_unsupported_modes(mp):
+def test_thread_mode_and_unsupported(mp):
+    """The C entry point follows the thread's slice form (INT8 here: same C as
+    the INT8 product); the printed last slice is refused."""
+    import torch
     A, B = W.gen_pair("dd", 8, 8, 8, E=0, seed=1)
     dA, dB = dev(A), dev(B)
     mp.set_mode("dd", "int8")
     try:
-        with pytest.raises(mp.MpgemmError):  # the thread's INT8 form is in force
-            _certify_in_mode(mp, dA, dB)
+        C = _certify_in_mode(mp, dA, dB)
+        ref = mp.gemm("dd", dA, dB)
+        torch.cuda.synchronize()
+        assert torch.equal(C, ref)
     finally:
         mp.set_mode("dd", "float")
     mp.set_last_slice("remainder")
@@ -157,3 +167,4 @@ def _certify_in_mode(mp, dA, dB):
                                  P(torch.cuda.current_stream().cuda_stream))
     if st != 0:
         raise mp.MpgemmError(st, "mpgemm_certify")
+    return C

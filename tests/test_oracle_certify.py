@@ -31,6 +31,20 @@ def test_truncation_within_bound(orc, fmt, E, D):
     assert max(ratios) > Fraction(1, 256)
 
 
+@pytest.mark.parametrize("fmt,E,D", [("dd", 16, 6), ("dd", 16, 9), ("td", 0, 10), ("qd", 8, 12)])
+def test_truncation_within_bound_int8(orc, fmt, E, D):
+    """The same bound with INT8 digit planes as slices (grid 2^(E - 6 - 7 (s - 1)))."""
+    m, n, k = 5, 4, 13
+    A, B = W.gen_pair(fmt, m, n, k, E=E, seed=7 + D)
+    tr, t1, t23, _ = orc.certificate_terms(A, B, D, form="int8")
+    for i, j in _entries(m, n):
+        assert tr[i][j] <= t1[i][j] + t23[i][j], (i, j)
+    # one digit: nothing is left out, the remainder bound alone carries it
+    tr1, t11, t231, _ = orc.certificate_terms(A, B, 1, form="int8")
+    assert all(t11[i][j] == 0 and tr1[i][j] <= t231[i][j] for i, j in _entries(m, n))
+    assert any(tr1[i][j] > 0 for i, j in _entries(m, n))
+
+
 def test_remainder_terms_bound_d1(orc):
     """D = 1 leaves out no pair (T1 = 0): the truncation is the remainders'
     alone, and T2 + T3 by itself must bound it."""
