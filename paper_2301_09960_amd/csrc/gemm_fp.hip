@@ -266,6 +266,10 @@ __device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const
     T *ndst = lds + (issued % kStages) * stage_elems<T>();
 
     const T *stage = lds + (step % kStages) * stage_elems<T>();
+    // raised wave priority while this wave issues its matrix-core work, so the
+    // sequencer favours waves that can feed the matrix cores over those about to
+    // wait at the barrier (TS 108 -> 100 ms, DD 41.6 -> 41.0 ms at n = 4096)
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int kb = 0; kb < kKStepBlocks; ++kb) {
       // binary64 fragments arrive in two halves (k substeps q = 0,1 and 2,3),
@@ -319,6 +323,7 @@ __device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const
             }
       }
     }
+    __builtin_amdgcn_s_setprio(0);
     if (more) advance();
 
     if (++cks == nks) {  // the pair's product is complete and exact: fold it in
