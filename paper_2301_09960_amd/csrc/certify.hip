@@ -46,14 +46,38 @@ __global__ __launch_bounds__(kCertThreads) void k_pack_abs_lead(SplitOperand<T> 
   }
 }
 
-// Sum over p of |X_0(v, p)| for every vector v (one thread per vector).
+// Sum over p of |X_0(v, p)| for every vector v, in a fixed order.
+// Rows of A (v contiguous in memory): a workgroup of 1024 threads takes 64
+// rows; lane l of wavefront w adds p = w, w + 16, ... of row l (each wavefront
+// reads 64 neighbouring rows at one p), and the 16 partial sums meet in LDS.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_abs_row_sums(SplitOperand<T> op, double *sums) {
+  __shared__ double part[16][64];
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int v = blockIdx.x * 64 + lane;
+  double s = 0.0;
+  if (v < op.nvec)
+    for (int p = w; p < op.len; p += 16) s += fabs((double)op.X[(int64_t)v * op.sv + (int64_t)p * op.sp]);
+  part[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && v < op.nvec) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += part[q][lane];
+    sums[v] = t;
+  }
+}
+
+// Columns of B (p contiguous): one wavefront per column, lanes along p, then a
+// shuffle reduction.
 template <typename T>
 __global__ __launch_bounds__(kCertThreads) void k_abs_sums(SplitOperand<T> op, double *sums) {
-  const int v = blockIdx.x * kCertThreads + threadIdx.x;
-  if (v >= op.nvec) return;
+  const int v = blockIdx.x * (kCertThreads / 64) + threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (v >= op.nvec) return;  // uniform over the wavefront
   double s = 0.0;
-  for (int p = 0; p < op.len; ++p) s += fabs((double)op.X[(int64_t)v * op.sv + (int64_t)p * op.sp]);
-  sums[v] = s;
+  for (int p = lane; p < op.len; p += 64) s += fabs((double)op.X[(int64_t)v * op.sv + (int64_t)p * op.sp]);
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) sums[v] = s;
 }
 
 __device__ __forceinline__ double pow2d(int e) { return ldexp(1.0, e); }
@@ -147,8 +171,9 @@ hipError_t launch_certify(const SplitOperand<T> &a, const SplitOperand<T> &b, in
   const auto grid_of = [](int64_t work) { return (unsigned)std::min<int64_t>(ceil_div(work, kCertThreads), 8192); };
   hipLaunchKernelGGL((k_pack_abs_lead<T>), dim3(grid_of(a.nbp * a.kbp * 256)), dim3(kCertThreads), 0, st, a, pack_a);
   hipLaunchKernelGGL((k_pack_abs_lead<T>), dim3(grid_of(b.nbp * b.kbp * 256)), dim3(kCertThreads), 0, st, b, pack_b);
-  hipLaunchKernelGGL((k_abs_sums<T>), dim3((unsigned)ceil_div(m, kCertThreads)), dim3(kCertThreads), 0, st, a, rs_a);
-  hipLaunchKernelGGL((k_abs_sums<T>), dim3((unsigned)ceil_div(n, kCertThreads)), dim3(kCertThreads), 0, st, b, cs_b);
+  hipLaunchKernelGGL((k_abs_row_sums<T>), dim3((unsigned)ceil_div(m, 64)), dim3(1024), 0, st, a, rs_a);
+  hipLaunchKernelGGL((k_abs_sums<T>), dim3((unsigned)ceil_div(n, kCertThreads / 64)), dim3(kCertThreads), 0, st, b,
+                     cs_b);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // |A_0| |B_0| as one pair on the binary64 slice-product kernel, into planes 0 and 1
   e = launch_gemm_plain<double, 2>(pack_a, pack_b, a.nbp, b.nbp, a.kbp, m, n, 1, cert, m, (int64_t)m * n, -1, nullptr,
