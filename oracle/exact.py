@@ -178,3 +178,52 @@ def int8_digits_py(comps_list, D: int):
             R = renorm_py(R)
         out.append(digs)
     return out, E
+
+
+def lu_backward_error(A, LU) -> float:
+    """Largest |A - L U|_ij / (|L||U|)_ij over the entries, exactly: A and LU
+    are ``(c, n, n)`` expansions (component planes, column-major), LU holding
+    the unit lower L below its diagonal and U on and above it (the blocked LU
+    of Section 4.6).  Small n only."""
+    n = A.shape[2]
+    Av = matrix_values(A)   # Av[i][j]
+    F = matrix_values(LU)
+    L = [[(Fraction(1) if i == j else (F[i][j] if i > j else Fraction(0))) for j in range(n)] for i in range(n)]
+    U = [[(F[i][j] if j >= i else Fraction(0)) for j in range(n)] for i in range(n)]
+    worst = Fraction(0)
+    for i in range(n):
+        for j in range(n):
+            s, a = Fraction(0), Fraction(0)
+            for q in range(min(i, j) + 1):
+                s += L[i][q] * U[q][j]
+                a += abs(L[i][q] * U[q][j])
+            d = abs(Av[i][j] - s)
+            if a > 0:
+                worst = max(worst, d / a)
+            elif d > 0:
+                return math.inf
+    return float(worst)
+
+
+def solve_exact(A, b) -> list:
+    """Exact solution of A x = b (Gaussian elimination in rationals, no
+    pivoting needed for the nonsingular test matrices used); A ``(c, n, n)``,
+    b ``(c, n)``.  Returns a list of Fractions."""
+    n = A.shape[2]
+    M = [row[:] for row in matrix_values(A)]
+    y = [value(b[:, i]) for i in range(n)]
+    for j in range(n):
+        p = next(i for i in range(j, n) if M[i][j] != 0)
+        if p != j:
+            M[j], M[p] = M[p], M[j]
+            y[j], y[p] = y[p], y[j]
+        for i in range(j + 1, n):
+            f = M[i][j] / M[j][j]
+            if f:
+                for q in range(j, n):
+                    M[i][q] -= f * M[j][q]
+                y[i] -= f * y[j]
+    x = [Fraction(0)] * n
+    for i in range(n - 1, -1, -1):
+        x[i] = (y[i] - sum((M[i][q] * x[q] for q in range(i + 1, n)), Fraction(0))) / M[i][i]
+    return x

@@ -79,6 +79,8 @@ def lib():
                 L.mpgemm_debug_split.argtypes = [_I, _I, _I, _I, _I, _P, _I, _I, _P, _P, _P]
                 L.mpgemm_debug_products.argtypes = [_I, _I, _I, _I, _I, _P, _I, _P, _I, _I, _I, _I, _P, _I, _P]
                 L.mpgemm_certify.argtypes = [_I, _I, _I, _I, _P, _I, _P, _I, _P, _I, _P, _P, _P]
+                L.mpgemm_dd_lu.argtypes = [_I, _P, _I, _I, _P]
+                L.mpgemm_dd_lu_solve.argtypes = [_I, _P, _I, _P, _P]
                 L.mpgemm_profile_enable.argtypes = [_I]
                 L.mpgemm_profile_read.argtypes = [_P, _P, _I]
                 L.mpgemm_load_tune_file.argtypes = [ctypes.c_char_p]
@@ -321,6 +323,36 @@ def certify(fmt, A, B, C=None, *, mode="float", slices=None, stream=None):
                                   _stream(stream))
     _check(st, "mpgemm_certify")
     return C, cert, worst
+
+
+def dd_lu(A, K: int, *, mode=None, stream=None):
+    """In-place blocked LU (no pivoting) of a DD matrix ``A`` of shape
+    ``(2, n, n)`` (component planes, column-major: A[r, j, i] is component r of
+    a_ij) with block width K; Schur updates by the DD product in ``mode``
+    ('float' or 'int8', default the thread's).  Returns A (now L and U)."""
+    import torch
+    _check_tensor(A, 2, torch.float64, "A")
+    n = A.shape[2]
+    if A.shape[1] != n:
+        raise ValueError("A must be square")
+    with _options(FORMATS["dd"], None if mode is None else _mode(mode), None):
+        st = lib().mpgemm_dd_lu(n, _P(A.data_ptr()), max(1, n), int(K), _stream(stream))
+    _check(st, "mpgemm_dd_lu")
+    return A
+
+
+def dd_lu_solve(LU, b, *, stream=None):
+    """Solve L U x = b with the factors from ``dd_lu``; b is ``(2, n)`` float64
+    (hi, lo).  Returns x as a new ``(2, n)`` tensor."""
+    import torch
+    _check_tensor(LU, 2, torch.float64, "LU")
+    n = LU.shape[2]
+    x = b.detach().clone().contiguous()
+    if tuple(x.shape) != (2, n) or x.dtype != torch.float64 or x.device != LU.device:
+        raise ValueError(f"b must be a float64 tensor of shape (2, {n}) on the device of LU")
+    _check(lib().mpgemm_dd_lu_solve(n, _P(LU.data_ptr()), max(1, n), _P(x.data_ptr()), _stream(stream)),
+           "mpgemm_dd_lu_solve")
+    return x
 
 
 def gemm_batched(fmt, As, Bs, Cs=None, *, mode=None, slices=None, stream=None):

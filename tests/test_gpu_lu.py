@@ -1,0 +1,102 @@
+"""GPU: blocked DD LU with the Schur updates by the slice-product GEMM
+(Section 4.6), against exact rational checks: the backward error
+|A - L U| / (|L||U|) in every entry, and the solution of A x = b against the
+exact one.  Diagonally dominant matrices (no pivoting, as in the paper), block
+widths spanning one, several and ragged blocks, both slice forms."""
+import numpy as np
+import pytest
+
+import oracle.exact as X
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2301_09960_amd as mp
+    mp.lib()
+    assert mp.check_device() == 0, "device is not gfx950"
+    return mp
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dd_dominant(n, seed):
+    """(2, n, n) DD matrix: uniform [0, 1) entries with a lo part, n added on the diagonal."""
+    rng = np.random.default_rng(seed)
+    hi = rng.random((n, n)) + n * np.eye(n)
+    lo = (rng.random((n, n)) - 0.5) * np.spacing(hi)  # |lo| <= ulp(hi) / 2
+    A = np.zeros((2, n, n))
+    A[0] = hi.T  # column-major planes: A[r, j, i]
+    A[1] = lo.T
+    return A
+
+
+@pytest.mark.parametrize("n,K,mode", [(40, 16, "float"), (40, 8, "float"), (40, 64, "float"), (40, 1, "float"),
+                                      (37, 16, "int8"), (33, 32, "float")])
+def test_lu_backward_error(mp, n, K, mode):
+    import torch
+    A = dd_dominant(n, seed=n + K)
+    dA = torch.from_numpy(A.copy()).cuda()
+    mp.dd_lu(dA, K, mode=mode)
+    LU = dA.cpu().numpy()
+    err = X.lu_backward_error(A, LU)
+    say(f"dd_lu n={n} K={K} {mode}: log2 backward error {np.log2(err) if err > 0 else -np.inf:.1f}")
+    assert np.isfinite(LU).all()
+    assert err <= 2.0 ** -92
+
+
+@pytest.mark.parametrize("n,K", [(40, 16), (24, 24)])
+def test_lu_solve(mp, n, K):
+    import torch
+    A = dd_dominant(n, seed=7 * n)
+    b = np.zeros((2, n))
+    b[0] = 1.0 / np.arange(1, n + 1)  # the paper's right-hand side [1, 1/2, ..., 1/n]
+    b[1] = [float(X.Fraction(1, i) - X.Fraction(float(b[0, i - 1]))) for i in range(1, n + 1)]
+    dA = torch.from_numpy(A.copy()).cuda()
+    mp.dd_lu(dA, K)
+    x = mp.dd_lu_solve(dA, torch.from_numpy(b).cuda()).cpu().numpy()
+    exact = X.solve_exact(A, b)
+    rel = max(abs(X.Fraction(float(x[0, i])) + X.Fraction(float(x[1, i])) - exact[i]) / abs(exact[i])
+              for i in range(n) if exact[i] != 0)
+    say(f"dd_lu_solve n={n} K={K}: log2 max relative error {np.log2(float(rel)):.1f}")
+    assert rel <= X.Fraction(2) ** -88
+
+
+@pytest.mark.parametrize("mode", ["float", "int8"])
+def test_lu_residual_n512(mp, orc, mode):
+    """n = 512, K = 128 (three Schur updates): the exact residual of the solve,
+    |b - A x| against |A||x| in every row."""
+    import torch
+    n, K = 512, 128
+    A = dd_dominant(n, seed=3)
+    b = np.zeros((2, n))
+    b[0] = 1.0 / np.arange(1, n + 1)
+    dA = torch.from_numpy(A.copy()).cuda()
+    mp.dd_lu(dA, K, mode=mode)
+    x = mp.dd_lu_solve(dA, torch.from_numpy(b).cuda()).cpu().numpy()
+    # A x as the product of A (c, k=n, m=n) and x as an n x 1 matrix (c, 1, n)
+    diff, absab, _ = orc.exact_check(A, x.reshape(2, 1, n), b.reshape(2, 1, n))
+    worst = float(np.max(diff / absab))
+    say(f"dd_lu n={n} K={K} {mode}: log2 max |b - A x| / (|A||x|) {np.log2(worst):.1f}")
+    assert worst <= 2.0 ** -95
+
+
+def test_lu_edge_cases(mp):
+    import torch
+    # 1 x 1, and K larger than n
+    A = torch.tensor([[[3.0]], [[2.0 ** -60]]], dtype=torch.float64, device="cuda")
+    mp.dd_lu(A, 4)
+    assert A[0, 0, 0].item() == 3.0 and A[1, 0, 0].item() == 2.0 ** -60
+    x = mp.dd_lu_solve(A, torch.tensor([[6.0], [0.0]], dtype=torch.float64, device="cuda"))
+    assert abs(x[0, 0].item() - 2.0) < 1e-15
+    # n = 0 is a no-op; bad arguments are refused
+    E = torch.zeros((2, 0, 0), dtype=torch.float64, device="cuda")
+    mp.dd_lu(E, 8)
+    with pytest.raises(mp.MpgemmError):
+        mp.dd_lu(torch.zeros((2, 4, 4), dtype=torch.float64, device="cuda"), 0)
