@@ -48,6 +48,20 @@ def test_argument_codes(L):
     assert f(4, 4, 4, x, 4, x, 4, x, 3, None) == -9
     assert L.mpgemm_ts(4, 4, 4, x, 4, x, 4, x, 2, None) == -9
     assert f(1 << 21, 4, 4, x, 1 << 21, x, 4, x, 1 << 21, None) == 5  # beyond the size limit
+    # certified product: fmt first, then the product's codes shifted by one
+    c = L.mpgemm_certify
+    assert c(7, 4, 4, 4, x, 4, x, 4, x, 4, x, x, None) == -1
+    assert c(0, -1, 4, 4, x, 4, x, 4, x, 4, x, x, None) == -2
+    assert c(0, 4, 4, 4, x, 3, x, 4, x, 4, x, x, None) == -6
+    assert c(0, 4, 4, 4, x, 4, x, 4, x, 4, None, x, None) == -11
+    assert c(0, 4, 4, 4, x, 4, x, 4, x, 4, x, None, None) == -12
+    # DD LU and its solve
+    assert L.mpgemm_dd_lu(-1, x, 1, 8, None) == -1
+    assert L.mpgemm_dd_lu(4, None, 4, 8, None) == -2
+    assert L.mpgemm_dd_lu(4, x, 3, 8, None) == -3
+    assert L.mpgemm_dd_lu(4, x, 4, 0, None) == -4
+    assert L.mpgemm_dd_lu_solve(-1, x, 1, x, None) == -1
+    assert L.mpgemm_dd_lu_solve(4, x, 4, None, None) == -4
 
 
 def test_options_and_policy(L):
