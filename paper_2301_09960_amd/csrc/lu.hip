@@ -74,6 +74,55 @@ __global__ __launch_bounds__(256) void k_trsm_upper(DDMat A, int j0, int K, int 
   }
 }
 
+// The same two solves with one wavefront per column (row), for K <= kSweepMax:
+// the vector sits in LDS and is swept left to right; at step q the lanes
+// update the entries after q with x_q.  Every entry receives the same DD
+// operations in the same order as in the kernels above (the subtractions for
+// q = 0, 1, ... and then, for U, the division), so the results are identical;
+// the chain per wavefront is K steps instead of K^2 / 2.
+constexpr int kSweepMax = 512;
+constexpr int kSweepWaves = 4;
+
+__global__ __launch_bounds__(64 * kSweepWaves) void k_trsm_lower_sweep(DDMat A, int j0, int K, int n) {
+  __shared__ dd col[kSweepWaves][kSweepMax];
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int l = j0 + K + blockIdx.x * kSweepWaves + w;
+  const bool live = l < n;
+  if (live)
+    for (int i = lane; i < K; i += 64) col[w][i] = A.get(j0 + i, l);
+  __syncthreads();
+  for (int q = 0; q < K - 1; ++q) {
+    if (live) {
+      const dd xq = col[w][q];
+      for (int i = q + 1 + lane; i < K; i += 64) col[w][i] = dd_sub(col[w][i], dd_mul(A.get(j0 + i, j0 + q), xq));
+    }
+    __syncthreads();
+  }
+  if (live)
+    for (int i = lane; i < K; i += 64) A.put(j0 + i, l, col[w][i]);
+}
+
+__global__ __launch_bounds__(64 * kSweepWaves) void k_trsm_upper_sweep(DDMat A, int j0, int K, int n) {
+  __shared__ dd row[kSweepWaves][kSweepMax];
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int i = j0 + K + blockIdx.x * kSweepWaves + w;
+  const bool live = i < n;
+  if (live)
+    for (int t = lane; t < K; t += 64) row[w][t] = A.get(i, j0 + t);
+  __syncthreads();
+  for (int q = 0; q < K; ++q) {
+    if (live && lane == 0) row[w][q] = dd_div(row[w][q], A.get(j0 + q, j0 + q));
+    __syncthreads();
+    if (live) {
+      const dd xq = row[w][q];
+      for (int t = q + 1 + lane; t < K; t += 64) row[w][t] = dd_sub(row[w][t], dd_mul(xq, A.get(j0 + q, j0 + t)));
+    }
+    __syncthreads();
+  }
+  if (live)
+    for (int t = lane; t < K; t += 64) A.put(i, j0 + t, row[w][t]);
+}
+
 // out = A[r0 .. r0 + rows, c0 .. c0 + cols) as a contiguous DD matrix
 // (leading dimension rows, lo plane rows * cols later).
 __global__ __launch_bounds__(256) void k_copy_block(DDMat A, int r0, int c0, int rows, int cols, double *out) {
@@ -95,47 +144,61 @@ __global__ __launch_bounds__(256) void k_sub_block(DDMat A, int r0, int c0, int 
   }
 }
 
-// Sum of one DD value per thread over the workgroup, in a fixed tree order.
-__device__ dd block_sum(dd v, dd *red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = kLuThreads / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = dd_add(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  const dd out = red[0];
-  __syncthreads();
-  return out;
+// Blocked solve of L U x = b (x holds b on entry): blocks of kSolveB rows.
+// Forward: one wavefront solves the block's rows against the unit lower
+// diagonal block (lane per row, x_q passed by shuffle), then every later row
+// subtracts the block's contribution (thread per row, q ascending).  Backward:
+// the same from the last block up, with the division by U's diagonal.  Each
+// entry's subtractions come in a fixed order, so the solve is reproducible.
+constexpr int kSolveB = 64;
+
+__device__ __forceinline__ dd shfl_dd(dd v, int src) {
+  return dd{__shfl(v.hi, src, 64), __shfl(v.lo, src, 64)};
 }
 
-// Solve L U x = b in place (x holds b on entry; hi plane, then lo plane of n),
-// one workgroup: forward substitution with the unit lower L, then backward
-// with U, each inner product split over the threads and summed in a tree.
-__global__ __launch_bounds__(kLuThreads) void k_lu_solve(DDMat A, int n, double *x) {
-  __shared__ dd red[kLuThreads];
-  for (int i = 0; i < n; ++i) {
-    dd part{0.0, 0.0};
-    for (int q = threadIdx.x; q < i; q += kLuThreads) part = dd_add(part, dd_mul(A.get(i, q), dd{x[q], x[n + q]}));
-    const dd s = block_sum(part, red);
-    if (threadIdx.x == 0) {
-      const dd y = dd_sub(dd{x[i], x[n + i]}, s);
-      x[i] = y.hi;
-      x[n + i] = y.lo;
-    }
-    __syncthreads();
+__global__ __launch_bounds__(64) void k_solve_fwd_diag(DDMat A, int n, double *x, int b0, int B) {
+  const int lane = threadIdx.x, i = b0 + lane;
+  dd xi = lane < B ? dd{x[i], x[n + i]} : dd{0.0, 0.0};
+  for (int q = 0; q < B - 1; ++q) {
+    const dd xq = shfl_dd(xi, q);
+    if (lane > q && lane < B) xi = dd_sub(xi, dd_mul(A.get(i, b0 + q), xq));
   }
-  for (int i = n - 1; i >= 0; --i) {
-    dd part{0.0, 0.0};
-    for (int q = i + 1 + (int)threadIdx.x; q < n; q += kLuThreads)
-      part = dd_add(part, dd_mul(A.get(i, q), dd{x[q], x[n + q]}));
-    const dd s = block_sum(part, red);
-    if (threadIdx.x == 0) {
-      const dd v = dd_div(dd_sub(dd{x[i], x[n + i]}, s), A.get(i, i));
-      x[i] = v.hi;
-      x[n + i] = v.lo;
-    }
-    __syncthreads();
+  if (lane < B) {
+    x[i] = xi.hi;
+    x[n + i] = xi.lo;
   }
+}
+
+__global__ __launch_bounds__(256) void k_solve_fwd_update(DDMat A, int n, double *x, int b0, int B) {
+  const int i = b0 + B + blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  dd s{x[i], x[n + i]};
+  for (int q = b0; q < b0 + B; ++q) s = dd_sub(s, dd_mul(A.get(i, q), dd{x[q], x[n + q]}));
+  x[i] = s.hi;
+  x[n + i] = s.lo;
+}
+
+__global__ __launch_bounds__(64) void k_solve_bwd_diag(DDMat A, int n, double *x, int b0, int B) {
+  const int lane = threadIdx.x, i = b0 + lane;
+  dd xi = lane < B ? dd{x[i], x[n + i]} : dd{0.0, 0.0};
+  for (int q = B - 1; q >= 0; --q) {
+    if (lane == q) xi = dd_div(xi, A.get(i, i));
+    const dd xq = shfl_dd(xi, q);
+    if (lane < q) xi = dd_sub(xi, dd_mul(A.get(i, b0 + q), xq));
+  }
+  if (lane < B) {
+    x[i] = xi.hi;
+    x[n + i] = xi.lo;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_solve_bwd_update(DDMat A, int n, double *x, int b0, int B) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= b0) return;
+  dd s{x[i], x[n + i]};
+  for (int q = b0; q < b0 + B; ++q) s = dd_sub(s, dd_mul(A.get(i, q), dd{x[q], x[n + q]}));
+  x[i] = s.hi;
+  x[n + i] = s.lo;
 }
 
 unsigned grid_for(int64_t work) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(work, 256), 8192)); }
@@ -145,7 +208,11 @@ unsigned grid_for(int64_t work) { return (unsigned)std::max<int64_t>(1, std::min
 hipError_t launch_lu_panel(double *A, int64_t ld, int64_t plane, int j0, int K, int n, hipStream_t st) {
   const DDMat M{A, ld, plane};
   hipLaunchKernelGGL(k_lu_diag, dim3(1), dim3(kLuThreads), 0, st, M, j0, K);
-  if (j0 + K < n) {
+  if (j0 + K < n && K <= kSweepMax) {
+    const dim3 grid((unsigned)ceil_div(n - j0 - K, kSweepWaves));
+    hipLaunchKernelGGL(k_trsm_lower_sweep, grid, dim3(64 * kSweepWaves), 0, st, M, j0, K, n);
+    hipLaunchKernelGGL(k_trsm_upper_sweep, grid, dim3(64 * kSweepWaves), 0, st, M, j0, K, n);
+  } else if (j0 + K < n) {
     hipLaunchKernelGGL(k_trsm_lower, dim3((unsigned)ceil_div(n - j0 - K, 256)), dim3(256), 0, st, M, j0, K, n);
     hipLaunchKernelGGL(k_trsm_upper, dim3((unsigned)ceil_div(n - j0 - K, 256)), dim3(256), 0, st, M, j0, K, n);
   }
@@ -167,7 +234,20 @@ hipError_t launch_lu_sub(double *A, int64_t ld, int64_t plane, int r0, int c0, i
 }
 
 hipError_t launch_lu_solve(const double *A, int64_t ld, int64_t plane, int n, double *x, hipStream_t st) {
-  hipLaunchKernelGGL(k_lu_solve, dim3(1), dim3(kLuThreads), 0, st, DDMat{const_cast<double *>(A), ld, plane}, n, x);
+  const DDMat M{const_cast<double *>(A), ld, plane};
+  for (int b0 = 0; b0 < n; b0 += kSolveB) {
+    const int B = std::min(kSolveB, n - b0);
+    hipLaunchKernelGGL(k_solve_fwd_diag, dim3(1), dim3(64), 0, st, M, n, x, b0, B);
+    if (b0 + B < n)
+      hipLaunchKernelGGL(k_solve_fwd_update, dim3((unsigned)ceil_div(n - b0 - B, 256)), dim3(256), 0, st, M, n, x,
+                         b0, B);
+  }
+  for (int b0 = (n - 1) / kSolveB * kSolveB; b0 >= 0; b0 -= kSolveB) {
+    const int B = std::min(kSolveB, n - b0);
+    hipLaunchKernelGGL(k_solve_bwd_diag, dim3(1), dim3(64), 0, st, M, n, x, b0, B);
+    if (b0 > 0)
+      hipLaunchKernelGGL(k_solve_bwd_update, dim3((unsigned)ceil_div(b0, 256)), dim3(256), 0, st, M, n, x, b0, B);
+  }
   return hipGetLastError();
 }
 
