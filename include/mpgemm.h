@@ -245,25 +245,28 @@ int mpgemm_certify(int fmt, int m, int n, int k, const void *A, int lda, const v
                    double *cert, double *worst, hipStream_t stream);
 
 /*
- * LU factorization of a DD matrix with the Schur updates done by this
- * library's DD product (Section 4.6).  A (device; two planes, hi then lo, each
- * n x n column-major with leading dimension lda, the lo plane lda * n doubles
- * after the hi plane) is overwritten by L (unit lower, diagonal not stored)
- * and U.  Block width K (the paper's MIN_DIM): the K x K diagonal block is
- * factored in DD arithmetic, the panels U12 = L11^-1 A12 and L21 = A21 U11^-1
- * are solved in DD, and A22 -= L21 U12 goes through mpgemm_dd in the thread's
- * slice form and slice count (for k = K).  No pivoting, as in the paper: a
+ * LU factorization of a DD (TD) matrix with the Schur updates done by this
+ * library's DD (TD) product (Section 4.6).  A (device; two (three) planes of
+ * components, each n x n column-major with leading dimension lda, lda * n
+ * doubles apart) is overwritten by L (unit lower, diagonal not stored) and U.
+ * Block width K (the paper's MIN_DIM): the K x K diagonal block is factored in
+ * DD (TD) arithmetic, the panels U12 = L11^-1 A12 and L21 = A21 U11^-1 are
+ * solved in it, and A22 -= L21 U12 goes through mpgemm_dd (mpgemm_td) in the
+ * thread's slice form and slice count (for k = K).  No pivoting, as in the paper: a
  * zero pivot gives infinities or NaNs.  Allocates its panel and product
  * buffers on the stream (and the GEMM's workspace, unless one is attached).
  *
- * mpgemm_dd_lu_solve: solves L U x = b with the factors in LU; x (device, two
- * planes of n doubles) holds b on entry and x on return.  Forward and backward
+ * mpgemm_dd_lu_solve (mpgemm_td_lu_solve): solves L U x = b with the factors
+ * in LU; x (device, two (three) planes of n doubles) holds b on entry and x on
+ * return.  Forward and backward
  * substitution in DD, each inner product summed in a fixed order.
  * Argument codes: -i for argument i (n < 0, NULL pointers, lda < max(1, n),
  * K < 1).
  */
 int mpgemm_dd_lu(int n, double *A, int lda, int K, hipStream_t stream);
 int mpgemm_dd_lu_solve(int n, const double *LU, int lda, double *x, hipStream_t stream);
+int mpgemm_td_lu(int n, double *A, int lda, int K, hipStream_t stream);
+int mpgemm_td_lu_solve(int n, const double *LU, int lda, double *x, hipStream_t stream);
 
 /*
  * Parity hooks (used by the tests to compare intermediate results bit for bit).

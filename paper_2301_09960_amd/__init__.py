@@ -79,8 +79,10 @@ def lib():
                 L.mpgemm_debug_split.argtypes = [_I, _I, _I, _I, _I, _P, _I, _I, _P, _P, _P]
                 L.mpgemm_debug_products.argtypes = [_I, _I, _I, _I, _I, _P, _I, _P, _I, _I, _I, _I, _P, _I, _P]
                 L.mpgemm_certify.argtypes = [_I, _I, _I, _I, _P, _I, _P, _I, _P, _I, _P, _P, _P]
-                L.mpgemm_dd_lu.argtypes = [_I, _P, _I, _I, _P]
-                L.mpgemm_dd_lu_solve.argtypes = [_I, _P, _I, _P, _P]
+                for name in ("mpgemm_dd_lu", "mpgemm_td_lu"):
+                    getattr(L, name).argtypes = [_I, _P, _I, _I, _P]
+                for name in ("mpgemm_dd_lu_solve", "mpgemm_td_lu_solve"):
+                    getattr(L, name).argtypes = [_I, _P, _I, _P, _P]
                 L.mpgemm_profile_enable.argtypes = [_I]
                 L.mpgemm_profile_read.argtypes = [_P, _P, _I]
                 L.mpgemm_load_tune_file.argtypes = [ctypes.c_char_p]
@@ -325,34 +327,53 @@ def certify(fmt, A, B, C=None, *, mode="float", slices=None, stream=None):
     return C, cert, worst
 
 
-def dd_lu(A, K: int, *, mode=None, stream=None):
-    """In-place blocked LU (no pivoting) of a DD matrix ``A`` of shape
-    ``(2, n, n)`` (component planes, column-major: A[r, j, i] is component r of
-    a_ij) with block width K; Schur updates by the DD product in ``mode``
-    ('float' or 'int8', default the thread's).  Returns A (now L and U)."""
+def lu(fmt, A, K: int, *, mode=None, stream=None):
+    """In-place blocked LU (no pivoting, Section 4.6) of a DD or TD matrix ``A``
+    of shape ``(c, n, n)`` (component planes, column-major: A[r, j, i] is
+    component r of a_ij) with block width K; Schur updates by the library's
+    product in ``mode`` ('float' or 'int8', default the thread's).  Returns A
+    (now L and U)."""
     import torch
-    _check_tensor(A, 2, torch.float64, "A")
+    name = {0: "dd", 1: "td"}.get(_fmt(fmt))
+    if name is None:
+        raise ValueError("lu: DD or TD only")
+    c = COMPONENTS[name]
+    _check_tensor(A, c, torch.float64, "A")
     n = A.shape[2]
     if A.shape[1] != n:
         raise ValueError("A must be square")
-    with _options(FORMATS["dd"], None if mode is None else _mode(mode), None):
-        st = lib().mpgemm_dd_lu(n, _P(A.data_ptr()), max(1, n), int(K), _stream(stream))
-    _check(st, "mpgemm_dd_lu")
+    with _options(FORMATS[name], None if mode is None else _mode(mode), None):
+        st = getattr(lib(), f"mpgemm_{name}_lu")(n, _P(A.data_ptr()), max(1, n), int(K), _stream(stream))
+    _check(st, f"mpgemm_{name}_lu")
     return A
 
 
-def dd_lu_solve(LU, b, *, stream=None):
-    """Solve L U x = b with the factors from ``dd_lu``; b is ``(2, n)`` float64
-    (hi, lo).  Returns x as a new ``(2, n)`` tensor."""
+def lu_solve(fmt, LU, b, *, stream=None):
+    """Solve L U x = b with the factors from ``lu``; b is ``(c, n)`` float64
+    (component planes).  Returns x as a new ``(c, n)`` tensor."""
     import torch
-    _check_tensor(LU, 2, torch.float64, "LU")
+    name = {0: "dd", 1: "td"}.get(_fmt(fmt))
+    if name is None:
+        raise ValueError("lu_solve: DD or TD only")
+    c = COMPONENTS[name]
+    _check_tensor(LU, c, torch.float64, "LU")
     n = LU.shape[2]
     x = b.detach().clone().contiguous()
-    if tuple(x.shape) != (2, n) or x.dtype != torch.float64 or x.device != LU.device:
-        raise ValueError(f"b must be a float64 tensor of shape (2, {n}) on the device of LU")
-    _check(lib().mpgemm_dd_lu_solve(n, _P(LU.data_ptr()), max(1, n), _P(x.data_ptr()), _stream(stream)),
-           "mpgemm_dd_lu_solve")
+    if tuple(x.shape) != (c, n) or x.dtype != torch.float64 or x.device != LU.device:
+        raise ValueError(f"b must be a float64 tensor of shape ({c}, {n}) on the device of LU")
+    _check(getattr(lib(), f"mpgemm_{name}_lu_solve")(n, _P(LU.data_ptr()), max(1, n), _P(x.data_ptr()),
+                                                      _stream(stream)), f"mpgemm_{name}_lu_solve")
     return x
+
+
+def dd_lu(A, K: int, *, mode=None, stream=None):
+    """``lu('dd', ...)``."""
+    return lu("dd", A, K, mode=mode, stream=stream)
+
+
+def dd_lu_solve(LU, b, *, stream=None):
+    """``lu_solve('dd', ...)``."""
+    return lu_solve("dd", LU, b, stream=stream)
 
 
 def gemm_batched(fmt, As, Bs, Cs=None, *, mode=None, slices=None, stream=None):

@@ -573,6 +573,56 @@ int certify_t(int fmt, int m, int n, int k, const T *A, int lda, const T *B, int
   return hip_status(e);
 }
 
+// Blocked LU (Section 4.6) of a DD (C = 2) or TD (C = 3) matrix: panels on the
+// LU kernels, Schur updates as products of this library in the thread's slice
+// form.
+template <int C>
+int lu_t(int fmt, int n, double *A, int lda, int K, hipStream_t stream) {
+  if (n < 0) return -1;
+  if (n > 0 && !A) return -2;
+  if (lda < std::max(1, n)) return -3;
+  if (K < 1) return -4;
+  int s = check_device_cached();
+  if (s) return s;
+  if (n == 0) return 0;
+  const int64_t plane = (int64_t)lda * n;
+  const int Kmax = std::min(K, n);
+  const int rmax = n - std::min(Kmax, n);
+  void *buf = nullptr;
+  const size_t bytes = rmax > 0 ? (size_t)C * 8 * ((size_t)2 * rmax * Kmax + (size_t)rmax * rmax) : 0;
+  if (bytes && (hipMallocAsync(&buf, bytes, stream) != hipSuccess || !buf)) {
+    (void)hipGetLastError();
+    return MPGEMM_ERR_WORKSPACE;
+  }
+  double *bl = static_cast<double *>(buf), *bu = bl + (size_t)C * rmax * Kmax, *P = bu + (size_t)C * rmax * Kmax;
+  hipError_t e = hipSuccess;
+  const int mode = g_opt.mode[fmt];
+  for (int j0 = 0; j0 < n && e == hipSuccess && s == 0; j0 += K) {
+    const int Kb = std::min(K, n - j0), r = n - j0 - Kb;
+    e = launch_lu_panel(C, A, lda, plane, j0, Kb, n, stream);
+    if (e != hipSuccess || r == 0) break;
+    // A22 -= L21 U12, with L21 (r x Kb) and U12 (Kb x r) copied contiguous
+    if ((e = launch_lu_copy(C, A, lda, plane, j0 + Kb, j0, r, Kb, bl, stream)) != hipSuccess) break;
+    if ((e = launch_lu_copy(C, A, lda, plane, j0, j0 + Kb, Kb, r, bu, stream)) != hipSuccess) break;
+    s = run_with<double, C>(fmt, mode, slices_for(fmt, mode, Kb), r, r, Kb, bl, r, bu, Kb, P, r, stream);
+    if (s == 0) e = launch_lu_sub(C, A, lda, plane, j0 + Kb, j0 + Kb, r, r, P, stream);
+  }
+  if (buf) (void)hipFreeAsync(buf, stream);
+  if (s) return s;
+  return hip_status(e);
+}
+
+int lu_solve_t(int comps, int n, const double *LU, int lda, double *x, hipStream_t stream) {
+  if (n < 0) return -1;
+  if (n > 0 && !LU) return -2;
+  if (lda < std::max(1, n)) return -3;
+  if (n > 0 && !x) return -4;
+  const int s = check_device_cached();
+  if (s) return s;
+  if (n == 0) return 0;
+  return hip_status(launch_lu_solve(comps, LU, lda, (int64_t)lda * n, n, x, stream));
+}
+
 }  // namespace host
 }  // namespace mp
 
@@ -810,52 +860,17 @@ int mpgemm_debug_products(int fmt, int mode, int m, int n, int k, const void *A,
   }
 }
 
-// Blocked DD LU (Section 4.6): panels on the LU kernels, Schur updates as DD
-// products of this library in the thread's slice form.
 int mpgemm_dd_lu(int n, double *A, int lda, int K, hipStream_t stream) {
-  if (n < 0) return -1;
-  if (n > 0 && !A) return -2;
-  if (lda < std::max(1, n)) return -3;
-  if (K < 1) return -4;
-  int s = check_device_cached();
-  if (s) return s;
-  if (n == 0) return 0;
-  const int64_t plane = (int64_t)lda * n;
-  const int Kmax = std::min(K, n);
-  const int rmax = n - std::min(Kmax, n);
-  void *buf = nullptr;
-  const size_t bytes = rmax > 0 ? (size_t)2 * 8 * ((size_t)2 * rmax * Kmax + (size_t)rmax * rmax) : 0;
-  if (bytes && (hipMallocAsync(&buf, bytes, stream) != hipSuccess || !buf)) {
-    (void)hipGetLastError();
-    return MPGEMM_ERR_WORKSPACE;
-  }
-  double *bl = static_cast<double *>(buf), *bu = bl + (size_t)2 * rmax * Kmax, *P = bu + (size_t)2 * rmax * Kmax;
-  hipError_t e = hipSuccess;
-  const int mode = g_opt.mode[MPGEMM_DD];
-  for (int j0 = 0; j0 < n && e == hipSuccess && s == 0; j0 += K) {
-    const int Kb = std::min(K, n - j0), r = n - j0 - Kb;
-    e = launch_lu_panel(A, lda, plane, j0, Kb, n, stream);
-    if (e != hipSuccess || r == 0) break;
-    // A22 -= L21 U12, with L21 (r x Kb) and U12 (Kb x r) copied contiguous
-    if ((e = launch_lu_copy(A, lda, plane, j0 + Kb, j0, r, Kb, bl, stream)) != hipSuccess) break;
-    if ((e = launch_lu_copy(A, lda, plane, j0, j0 + Kb, Kb, r, bu, stream)) != hipSuccess) break;
-    s = run_with<double, 2>(MPGEMM_DD, mode, slices_for(MPGEMM_DD, mode, Kb), r, r, Kb, bl, r, bu, Kb, P, r, stream);
-    if (s == 0) e = launch_lu_sub(A, lda, plane, j0 + Kb, j0 + Kb, r, r, P, stream);
-  }
-  if (buf) (void)hipFreeAsync(buf, stream);
-  if (s) return s;
-  return hip_status(e);
+  return lu_t<2>(MPGEMM_DD, n, A, lda, K, stream);
 }
-
+int mpgemm_td_lu(int n, double *A, int lda, int K, hipStream_t stream) {
+  return lu_t<3>(MPGEMM_TD, n, A, lda, K, stream);
+}
 int mpgemm_dd_lu_solve(int n, const double *LU, int lda, double *x, hipStream_t stream) {
-  if (n < 0) return -1;
-  if (n > 0 && !LU) return -2;
-  if (lda < std::max(1, n)) return -3;
-  if (n > 0 && !x) return -4;
-  const int s = check_device_cached();
-  if (s) return s;
-  if (n == 0) return 0;
-  return hip_status(launch_lu_solve(LU, lda, (int64_t)lda * n, n, x, stream));
+  return lu_solve_t(2, n, LU, lda, x, stream);
+}
+int mpgemm_td_lu_solve(int n, const double *LU, int lda, double *x, hipStream_t stream) {
+  return lu_solve_t(3, n, LU, lda, x, stream);
 }
 
 int mpgemm_certify(int fmt, int m, int n, int k, const void *A, int lda, const void *B, int ldb, void *C, int ldc,

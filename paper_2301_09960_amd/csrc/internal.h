@@ -160,15 +160,17 @@ hipError_t launch_certify(const SplitOperand<T> &a, const SplitOperand<T> &b, in
                           int comps, int int8, double *cert, double *worst, double *pack_a, double *pack_b,
                           double *rs_a, double *cs_b, int layout, hipStream_t st);
 
-// LU of a DD matrix (two planes of ld x n, lo plane `plane` doubles later):
-// panel step at column j0 with width K (diagonal block, then U12 and L21),
-// block copy into a contiguous DD matrix, A22 -= P, and the solve of L U x = b.
-hipError_t launch_lu_panel(double *A, int64_t ld, int64_t plane, int j0, int K, int n, hipStream_t st);
-hipError_t launch_lu_copy(double *A, int64_t ld, int64_t plane, int r0, int c0, int rows, int cols, double *out,
-                          hipStream_t st);
-hipError_t launch_lu_sub(double *A, int64_t ld, int64_t plane, int r0, int c0, int rows, int cols, const double *P,
-                         hipStream_t st);
-hipError_t launch_lu_solve(const double *A, int64_t ld, int64_t plane, int n, double *x, hipStream_t st);
+// LU of a DD (comps = 2) or TD (comps = 3) matrix (comps planes of ld x n,
+// `plane` doubles apart): panel step at column j0 with width K (diagonal block,
+// then U12 and L21), block copy into a contiguous matrix, A22 -= P, and the
+// solve of L U x = b.
+hipError_t launch_lu_panel(int comps, double *A, int64_t ld, int64_t plane, int j0, int K, int n, hipStream_t st);
+hipError_t launch_lu_copy(int comps, double *A, int64_t ld, int64_t plane, int r0, int c0, int rows, int cols,
+                          double *out, hipStream_t st);
+hipError_t launch_lu_sub(int comps, double *A, int64_t ld, int64_t plane, int r0, int c0, int rows, int cols,
+                         const double *P, hipStream_t st);
+hipError_t launch_lu_solve(int comps, const double *A, int64_t ld, int64_t plane, int n, double *x,
+                           hipStream_t st);
 
 // Debug: unpack D packed slices into planes of rows x cols (column-major, ld rows).
 hipError_t launch_unpack(int elem_bytes, const void *packed, int64_t nbp, int64_t kbp, int D, int orient, int rows,

@@ -62,6 +62,8 @@ def test_argument_codes(L):
     assert L.mpgemm_dd_lu(4, x, 4, 0, None) == -4
     assert L.mpgemm_dd_lu_solve(-1, x, 1, x, None) == -1
     assert L.mpgemm_dd_lu_solve(4, x, 4, None, None) == -4
+    assert L.mpgemm_td_lu(4, x, 4, 0, None) == -4
+    assert L.mpgemm_td_lu_solve(4, None, 4, x, None) == -2
 
 
 def test_options_and_policy(L):

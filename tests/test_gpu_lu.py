@@ -26,46 +26,62 @@ def say(*a):
     print(*a, flush=True)
 
 
-def dd_dominant(n, seed):
-    """(2, n, n) DD matrix: uniform [0, 1) entries with a lo part, n added on the diagonal."""
+def dd_dominant(n, seed, c=2):
+    """(c, n, n) DD (TD) matrix: uniform [0, 1) entries with lower components,
+    n added on the diagonal."""
     rng = np.random.default_rng(seed)
     hi = rng.random((n, n)) + n * np.eye(n)
-    lo = (rng.random((n, n)) - 0.5) * np.spacing(hi)  # |lo| <= ulp(hi) / 2
-    A = np.zeros((2, n, n))
+    A = np.zeros((c, n, n))
     A[0] = hi.T  # column-major planes: A[r, j, i]
-    A[1] = lo.T
+    prev = hi
+    for r in range(1, c):
+        nxt = (rng.random((n, n)) - 0.5) * np.spacing(prev)  # below half an ulp of the previous component
+        A[r] = nxt.T
+        prev = np.abs(nxt) + np.finfo(float).tiny
     return A
 
 
-@pytest.mark.parametrize("n,K,mode", [(40, 16, "float"), (40, 8, "float"), (40, 64, "float"), (40, 1, "float"),
-                                      (37, 16, "int8"), (33, 32, "float")])
-def test_lu_backward_error(mp, n, K, mode):
+# bounds: the Schur products meet 2^-t |L21||U12| (t = 100 / 150), the panels
+# are DD (TD) arithmetic; a few bits of margin for the sums over blocks
+BACKWARD = {"dd": 2.0 ** -92, "td": 2.0 ** -140}
+SOLVE = {"dd": 2.0 ** -88, "td": 2.0 ** -135}
+
+
+@pytest.mark.parametrize("fmt,n,K,mode", [("dd", 40, 16, "float"), ("dd", 40, 8, "float"), ("dd", 40, 64, "float"),
+                                          ("dd", 40, 1, "float"), ("dd", 37, 16, "int8"), ("dd", 33, 32, "float"),
+                                          ("td", 40, 16, "float"), ("td", 37, 8, "int8"), ("td", 30, 64, "float")])
+def test_lu_backward_error(mp, fmt, n, K, mode):
     import torch
-    A = dd_dominant(n, seed=n + K)
+    c = 2 if fmt == "dd" else 3
+    A = dd_dominant(n, seed=n + K, c=c)
     dA = torch.from_numpy(A.copy()).cuda()
-    mp.dd_lu(dA, K, mode=mode)
+    mp.lu(fmt, dA, K, mode=mode)
     LU = dA.cpu().numpy()
     err = X.lu_backward_error(A, LU)
-    say(f"dd_lu n={n} K={K} {mode}: log2 backward error {np.log2(err) if err > 0 else -np.inf:.1f}")
+    say(f"{fmt}_lu n={n} K={K} {mode}: log2 backward error {np.log2(err) if err > 0 else -np.inf:.1f}")
     assert np.isfinite(LU).all()
-    assert err <= 2.0 ** -92
+    assert err <= BACKWARD[fmt]
 
 
-@pytest.mark.parametrize("n,K", [(40, 16), (24, 24)])
-def test_lu_solve(mp, n, K):
+@pytest.mark.parametrize("fmt,n,K", [("dd", 40, 16), ("dd", 24, 24), ("td", 40, 16)])
+def test_lu_solve(mp, fmt, n, K):
     import torch
-    A = dd_dominant(n, seed=7 * n)
-    b = np.zeros((2, n))
-    b[0] = 1.0 / np.arange(1, n + 1)  # the paper's right-hand side [1, 1/2, ..., 1/n]
-    b[1] = [float(X.Fraction(1, i) - X.Fraction(float(b[0, i - 1]))) for i in range(1, n + 1)]
+    c = 2 if fmt == "dd" else 3
+    A = dd_dominant(n, seed=7 * n, c=c)
+    b = np.zeros((c, n))
+    # the paper's right-hand side [1, 1/2, ..., 1/n], rounded to c components
+    for i in range(1, n + 1):
+        rest = X.Fraction(1, i)
+        for r in range(c):
+            b[r, i - 1] = float(rest)
+            rest -= X.Fraction(b[r, i - 1])
     dA = torch.from_numpy(A.copy()).cuda()
-    mp.dd_lu(dA, K)
-    x = mp.dd_lu_solve(dA, torch.from_numpy(b).cuda()).cpu().numpy()
+    mp.lu(fmt, dA, K)
+    x = mp.lu_solve(fmt, dA, torch.from_numpy(b).cuda()).cpu().numpy()
     exact = X.solve_exact(A, b)
-    rel = max(abs(X.Fraction(float(x[0, i])) + X.Fraction(float(x[1, i])) - exact[i]) / abs(exact[i])
-              for i in range(n) if exact[i] != 0)
-    say(f"dd_lu_solve n={n} K={K}: log2 max relative error {np.log2(float(rel)):.1f}")
-    assert rel <= X.Fraction(2) ** -88
+    rel = max(abs(X.value(x[:, i]) - exact[i]) / abs(exact[i]) for i in range(n) if exact[i] != 0)
+    say(f"{fmt}_lu_solve n={n} K={K}: log2 max relative error {np.log2(float(rel)):.1f}")
+    assert rel <= X.Fraction(SOLVE[fmt])
 
 
 @pytest.mark.parametrize("mode", ["float", "int8"])
