@@ -328,6 +328,13 @@ int mpgemm_nd(int c, int D, int m, int n, int k, const double *A, int lda, const
               int ldc, hipStream_t stream);
 int mpgemm_nd_num_slices(int c, int k);
 size_t mpgemm_nd_workspace_bytes(int c, int D, int m, int n, int k);
+/*
+ * mpgemm_nd_certify: mpgemm_nd with the a-posteriori certificate of
+ * mpgemm_certify (INT8 form, c components; the target is 2^-(50 c)).  Codes as
+ * for mpgemm_nd; -12 / -13 for a NULL cert (with m, n > 0) / worst.
+ */
+int mpgemm_nd_certify(int c, int D, int m, int n, int k, const double *A, int lda, const double *B, int ldb,
+                      double *C, int ldc, double *cert, double *worst, hipStream_t stream);
 int mpgemm_nd_debug_split(int c, int operand, int rows, int cols, const double *X, int ldx, int D, int8_t *digits,
                           int *exps, hipStream_t stream);
 int mpgemm_nd_debug_products(int c, int m, int n, int k, const double *A, int lda, const double *B, int ldb, int D,

@@ -88,6 +88,7 @@ def lib():
                 L.mpgemm_load_tune_file.argtypes = [ctypes.c_char_p]
                 L.mpgemm_nd.restype = _I
                 L.mpgemm_nd.argtypes = [_I, _I, _I, _I, _I, _P, _I, _P, _I, _P, _I, _P]
+                L.mpgemm_nd_certify.argtypes = [_I, _I, _I, _I, _I, _P, _I, _P, _I, _P, _I, _P, _P, _P]
                 L.mpgemm_nd_num_slices.argtypes = [_I, _I]
                 L.mpgemm_nd_workspace_bytes.restype = ctypes.c_size_t
                 L.mpgemm_nd_workspace_bytes.argtypes = [_I, _I, _I, _I, _I]
@@ -473,6 +474,30 @@ def gemm_nd(A, B, C=None, *, slices: int = 0, stream=None):
     _check(lib().mpgemm_nd(c, int(slices), m, n, k, _P(A.data_ptr()), max(1, m), _P(B.data_ptr()), max(1, k),
                            _P(C.data_ptr()), max(1, m), _stream(stream)), "mpgemm_nd")
     return C
+
+
+def nd_certify(A, B, C=None, *, slices: int = 0, stream=None):
+    """``gemm_nd`` with its a-posteriori certificate: returns ``(C, cert,
+    worst)`` as ``certify`` does (the result meets 2^-(50 c) |A||B| wherever
+    cert[0] <= 2^-(50 c) cert[1], everywhere when worst <= 2^-(50 c))."""
+    import torch
+    _check_nd(A, "A")
+    _check_nd(B, "B")
+    c = A.shape[0]
+    if B.shape[0] != c:
+        raise ValueError("A and B must have the same number of components")
+    k, m = A.shape[1], A.shape[2]
+    n, kb = B.shape[1], B.shape[2]
+    if kb != k:
+        raise ValueError(f"inner dimensions differ: A has k={k}, B has k={kb}")
+    if C is None:
+        C = torch.empty((c, n, m), dtype=torch.float64, device=A.device)
+    cert = torch.empty((2, n, m), dtype=torch.float64, device=A.device)
+    worst = torch.empty((1,), dtype=torch.float64, device=A.device)
+    _check(lib().mpgemm_nd_certify(c, int(slices), m, n, k, _P(A.data_ptr()), max(1, m), _P(B.data_ptr()),
+                                   max(1, k), _P(C.data_ptr()), max(1, m), _P(cert.data_ptr()),
+                                   _P(worst.data_ptr()), _stream(stream)), "mpgemm_nd_certify")
+    return C, cert, worst
 
 
 def nd_num_slices(c: int, k: int) -> int:

@@ -525,16 +525,10 @@ int debug_products_t(int fmt, int mode, int m, int n, int k, const T *A, int lda
 // C = AB as run() computes it in the binary64/binary32 form, then the
 // a-posteriori certificate (certify.hip) from the same split.
 template <typename T, int C>
-int certify_t(int fmt, int m, int n, int k, const T *A, int lda, const T *B, int ldb, T *Cm, int ldc, double *cert,
-              double *worst, hipStream_t st) {
-  int s = validate(m, n, k, A, lda, B, ldb, Cm, ldc);
-  if (s) return s < 0 ? s - 1 : s;  // shifted past fmt
-  if (!cert && m > 0 && n > 0) return -11;
-  if (!worst) return -12;
-  if ((s = check_device_cached())) return s;
-  const int mode = g_opt.mode[fmt];
+int certify_run(int fmt, int mode, int D, int m, int n, int k, const T *A, int lda, const T *B, int ldb, T *Cm,
+                int ldc, double *cert, double *worst, hipStream_t st) {
+  int s;
   if (mode == MPGEMM_MODE_FLOAT && g_opt.last_slice != 0) return MPGEMM_ERR_UNSUPPORTED;
-  const int D = slices_for(fmt, mode, k);
   g_opt.last_slices = D;
   if (mode == MPGEMM_MODE_FLOAT && sizeof(T) == 4 && D < 2) return MPGEMM_ERR_UNSUPPORTED;  // plane 0 holds |A_0|
   if (m == 0 || n == 0 || k == 0) {
@@ -571,6 +565,31 @@ int certify_t(int fmt, int m, int n, int k, const T *A, int lda, const T *B, int
                           reinterpret_cast<double *>(ws.base + p.off_mu_a),
                           reinterpret_cast<double *>(ws.base + p.off_mu_b), 1, st);
   return hip_status(e);
+}
+
+template <typename T, int C>
+int certify_t(int fmt, int m, int n, int k, const T *A, int lda, const T *B, int ldb, T *Cm, int ldc, double *cert,
+              double *worst, hipStream_t st) {
+  int s = validate(m, n, k, A, lda, B, ldb, Cm, ldc);
+  if (s) return s < 0 ? s - 1 : s;  // shifted past fmt
+  if (!cert && m > 0 && n > 0) return -11;
+  if (!worst) return -12;
+  if ((s = check_device_cached())) return s;
+  const int mode = g_opt.mode[fmt];
+  return certify_run<T, C>(fmt, mode, slices_for(fmt, mode, k), m, n, k, A, lda, B, ldb, Cm, ldc, cert, worst, st);
+}
+
+// Longer expansions (c components, INT8 form), as mpgemm_nd computes them.
+template <int C>
+int certify_nd_t(int D, int m, int n, int k, const double *A, int lda, const double *B, int ldb, double *Cm, int ldc,
+                 double *cert, double *worst, hipStream_t st) {
+  int s = validate(m, n, k, A, lda, B, ldb, Cm, ldc);
+  if (s) return s < 0 ? s - 2 : s;  // shifted past (c, D)
+  if (!cert && m > 0 && n > 0) return -12;
+  if (!worst) return -13;
+  if ((s = check_device_cached())) return s;
+  return certify_run<double, C>(MPGEMM_QD, MPGEMM_MODE_INT8, D > 0 ? D : nd_auto_slices(C, k), m, n, k, A, lda, B,
+                                ldb, Cm, ldc, cert, worst, st);
 }
 
 // Blocked LU (Section 4.6) of a DD (C = 2) or TD (C = 3) matrix: panels on the
@@ -692,6 +711,20 @@ int mpgemm_nd(int c, int D, int m, int n, int k, const double *A, int lda, const
 #define MP_CASE(CC) \
   case CC:          \
     return run_nd<CC>(D, m, n, k, A, lda, B, ldb, C, ldc, stream);
+    MP_ND_CASES(MP_CASE)
+#undef MP_CASE
+  }
+  return -1;
+}
+
+int mpgemm_nd_certify(int c, int D, int m, int n, int k, const double *A, int lda, const double *B, int ldb,
+                      double *C, int ldc, double *cert, double *worst, hipStream_t stream) {
+  if (c < 2 || c > kMaxNd) return -1;
+  if (D < 0 || D > kMaxDNd) return -2;
+  switch (c) {
+#define MP_CASE(CC) \
+  case CC:          \
+    return certify_nd_t<CC>(D, m, n, k, A, lda, B, ldb, C, ldc, cert, worst, stream);
     MP_ND_CASES(MP_CASE)
 #undef MP_CASE
   }

@@ -63,6 +63,11 @@ def test_argument_codes(L):
     assert L.mpgemm_dd_lu_solve(-1, x, 1, x, None) == -1
     assert L.mpgemm_dd_lu_solve(4, x, 4, None, None) == -4
     assert L.mpgemm_td_lu(4, x, 4, 0, None) == -4
+    nc = L.mpgemm_nd_certify
+    assert nc(1, 0, 4, 4, 4, x, 4, x, 4, x, 4, x, x, None) == -1
+    assert nc(6, -1, 4, 4, 4, x, 4, x, 4, x, 4, x, x, None) == -2
+    assert nc(6, 0, 4, 4, 4, x, 4, x, 4, x, 4, None, x, None) == -12
+    assert nc(6, 0, 4, 4, 4, x, 4, x, 4, x, 4, x, None, None) == -13
     assert L.mpgemm_td_lu_solve(4, None, 4, x, None) == -2
 
 

@@ -168,3 +168,40 @@ def _certify_in_mode(mp, dA, dB):
     if st != 0:
         raise mp.MpgemmError(st, "mpgemm_certify")
     return C
+
+
+@pytest.mark.parametrize("c", [6, 10])
+def test_nd_certificate(mp, orc, c):
+    """Longer expansions (INT8 form, c components): the bound against the
+    oracle's exact terms and the exact error, and certification at the
+    automatic digit count (target 2^-(50 c))."""
+    import torch
+    m, n, k = 8, 7, 29
+    A, B = W.gen_pair(f"{c}d", m, n, k, E=8, seed=c)
+    dA, dB = dev(A), dev(B)
+    C, cert, worst = mp.nd_certify(dA, dB)
+    ref = mp.gemm_nd(dA, dB)
+    torch.cuda.synchronize()
+    assert torch.equal(C, ref)
+    D = mp.nd_num_slices(c, k)
+    beta, lam = cert[0].cpu().numpy(), cert[1].cpu().numpy()
+    _, t1, t23, absab = orc.certificate_terms(A, B, D, form="int8")
+    diff, _, _ = orc.exact_check(A, B, C.cpu().numpy())
+    for i in range(m):
+        for j in range(n):
+            b = Fraction(float(beta[j, i]))
+            T = t1[i][j] + t23[i][j]
+            assert T <= b <= T * (1 + Fraction(2) ** -30) + Fraction(2) ** (6 - 53 * c) * absab[i][j], (i, j)
+            assert float(lam[j, i]) <= absab[i][j]
+            assert diff[j, i] <= float(beta[j, i]) * (1 + 2.0 ** -50)
+    w = float(worst.cpu()[0])
+    say(f"nd certify c={c} D={D}: log2 worst {np.log2(w):.1f} (target {-50 * c})")
+    assert w <= 2.0 ** (-50 * c)
+    # a larger shape with a wider spread: certified with one digit more than
+    # the automatic count (the bound takes every left-out pair at its largest)
+    A2, B2 = W.gen_pair(f"{c}d", 130, 90, 300, E=16, seed=c + 1)
+    D2 = mp.nd_num_slices(c, 300) + 1
+    _, _, worst2 = mp.nd_certify(dev(A2), dev(B2), slices=D2)
+    w2 = float(worst2.cpu()[0])
+    say(f"nd certify c={c} 130x90x300 D={D2}: log2 worst {np.log2(w2):.1f}")
+    assert w2 <= 2.0 ** (-50 * c)
