@@ -205,3 +205,21 @@ def test_nd_certificate(mp, orc, c):
     w2 = float(worst2.cpu()[0])
     say(f"nd certify c={c} 130x90x300 D={D2}: log2 worst {np.log2(w2):.1f}")
     assert w2 <= 2.0 ** (-50 * c)
+
+
+@pytest.mark.parametrize("mode", ["float", "int8"])
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (1, 5, 3), (6, 1, 70), (3, 4, 1)])
+def test_certificate_thin_shapes(mp, orc, mode, m, n, k):
+    """Single rows, columns and k = 1: the bound still dominates the oracle's
+    exact terms and the exact error."""
+    A, B = W.gen_pair("dd", m, n, k, E=8, seed=m * 100 + n * 10 + k)
+    C, cert, worst = mp.certify("dd", dev(A), dev(B), mode=mode)
+    D = mp.last_num_slices()
+    beta = cert[0].cpu().numpy()
+    _, t1, t23, _ = orc.certificate_terms(A, B, D, form=mode)
+    diff, _, _ = orc.exact_check(A, B, C.cpu().numpy())
+    for i in range(m):
+        for j in range(n):
+            assert t1[i][j] + t23[i][j] <= Fraction(float(beta[j, i]))
+            assert diff[j, i] <= float(beta[j, i]) * (1 + 2.0 ** -50)
+    assert float(worst.cpu()[0]) <= 2.0 ** -100
