@@ -22,7 +22,7 @@
  *     relative error over the elements of C; the exact product needed for it
  *     is oracle_gemm_exact_check (a long fixed-point accumulator).
  *
- * Readings where the paper is silent (each also listed in the design doc):
+ * Readings where the paper is silent:
  *   - Layout: component-planar, column-major.  Matrix X with `rows` rows and
  *     `cols` columns stores component r of element (i, p) at
  *     X[r*rows*cols + i + p*rows].
