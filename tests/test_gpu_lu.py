@@ -49,7 +49,8 @@ SOLVE = {"dd": 2.0 ** -88, "td": 2.0 ** -135}
 
 @pytest.mark.parametrize("fmt,n,K,mode", [("dd", 40, 16, "float"), ("dd", 40, 8, "float"), ("dd", 40, 64, "float"),
                                           ("dd", 40, 1, "float"), ("dd", 37, 16, "int8"), ("dd", 33, 32, "float"),
-                                          ("td", 40, 16, "float"), ("td", 37, 8, "int8"), ("td", 30, 64, "float")])
+                                          ("td", 40, 16, "float"), ("td", 37, 8, "int8"), ("td", 30, 64, "float"),
+                                          ("dd", 150, 100, "float"), ("td", 120, 96, "float")])
 def test_lu_backward_error(mp, fmt, n, K, mode):
     import torch
     c = 2 if fmt == "dd" else 3
