@@ -31,6 +31,10 @@ __device__ __forceinline__ td nadd(const td &a, const td &b) { return mc_add<3>(
 __device__ __forceinline__ td nsub(const td &a, const td &b) { return mc_sub<3>(a, b); }
 __device__ __forceinline__ td nmul(const td &a, const td &b) { return mc_mul<3>(a, b); }
 __device__ __forceinline__ td ndiv(const td &a, const td &b) { return mc_div<3>(a, b); }
+// 1 / b, by the division above: a solve multiplies by it so that the division
+// leaves the chain of dependent steps.
+__device__ __forceinline__ dd ninv(dd b) { return dd_div(dd{1.0, 0.0}, b); }
+__device__ __forceinline__ td ninv(const td &b) { return mc_div<3>(td{{1.0, 0.0, 0.0}}, b); }
 
 template <typename Num>
 struct Comps;
@@ -119,7 +123,7 @@ __global__ __launch_bounds__(256) void k_trsm_lower(Mat<Num> A, int j0, int K, i
 }
 
 // L21 = A21 U11^-1 in place: thread per row i of A21, solving x U11 = a left to
-// right.
+// right; x_q is the remaining sum times the reciprocal of u_qq.
 template <typename Num>
 __global__ __launch_bounds__(256) void k_trsm_upper(Mat<Num> A, int j0, int K, int n) {
   const int i = j0 + K + blockIdx.x * 256 + threadIdx.x;
@@ -127,16 +131,17 @@ __global__ __launch_bounds__(256) void k_trsm_upper(Mat<Num> A, int j0, int K, i
   for (int q = 0; q < K; ++q) {
     Num s = A.get(i, j0 + q);
     for (int r = 0; r < q; ++r) s = nsub(s, nmul(A.get(i, j0 + r), A.get(j0 + r, j0 + q)));
-    A.put(i, j0 + q, ndiv(s, A.get(j0 + q, j0 + q)));
+    A.put(i, j0 + q, nmul(s, ninv(A.get(j0 + q, j0 + q))));
   }
 }
 
 // The same two solves with one wavefront per column (row), for K <= kSweepMax:
 // the vector sits in LDS and is swept left to right; at step q the lanes
-// update the entries after q with x_q.  Every entry receives the same DD
+// update the entries after q with x_q.  Every entry receives the same
 // operations in the same order as in the kernels above (the subtractions for
-// q = 0, 1, ... and then, for U, the division), so the results are identical;
-// the chain per wavefront is K steps instead of K^2 / 2.
+// q = 0, 1, ... and then, for U, the product with 1 / u_qq), so the results
+// are identical; the chain per wavefront is K steps instead of K^2 / 2, and
+// the reciprocals of U's diagonal are formed before it, all at once.
 constexpr int kSweepMax = 512;
 constexpr int kSweepWaves = 4;
 
@@ -163,17 +168,19 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_trsm_lower_sweep(Mat<Num> 
 template <typename Num>
 __global__ __launch_bounds__(64 * kSweepWaves) void k_trsm_upper_sweep(Mat<Num> A, int j0, int K, int n) {
   __shared__ Num row[kSweepWaves][kSweepMax];
+  __shared__ Num inv[kSweepMax];
   const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int i = j0 + K + blockIdx.x * kSweepWaves + w;
   const bool live = i < n;
+  for (int t = threadIdx.x; t < K; t += 64 * kSweepWaves) inv[t] = ninv(A.get(j0 + t, j0 + t));
   if (live)
     for (int t = lane; t < K; t += 64) row[w][t] = A.get(i, j0 + t);
   __syncthreads();
   for (int q = 0; q < K; ++q) {
-    if (live && lane == 0) row[w][q] = ndiv(row[w][q], A.get(j0 + q, j0 + q));
-    __syncthreads();
     if (live) {
-      const Num xq = row[w][q];
+      // every lane forms x_q; lane 0 stores it
+      const Num xq = nmul(row[w][q], inv[q]);
+      if (lane == 0) row[w][q] = xq;
       for (int t = q + 1 + lane; t < K; t += 64) row[w][t] = nsub(row[w][t], nmul(xq, A.get(j0 + q, j0 + t)));
     }
     __syncthreads();
@@ -227,7 +234,8 @@ __global__ __launch_bounds__(256) void k_sub_block(Mat<Num> A, int r0, int c0, i
 // Forward: one wavefront solves the block's rows against the unit lower
 // diagonal block (lane per row, x_q passed by shuffle), then every later row
 // subtracts the block's contribution (thread per row, q ascending).  Backward:
-// the same from the last block up, with the division by U's diagonal.  Each
+// the same from the last block up, with the product by the reciprocal of U's
+// diagonal entry (each lane forms its own before the chain).  Each
 // entry's subtractions come in a fixed order, so the solve is reproducible.
 constexpr int kSolveB = 64;
 
@@ -263,8 +271,10 @@ template <typename Num>
 __global__ __launch_bounds__(64) void k_solve_bwd_diag(Mat<Num> A, int n, double *x, int b0, int B) {
   const int lane = threadIdx.x, i = b0 + lane;
   Num xi = lane < B ? vget<Num>(x, n, i) : nzero<Num>();
+  Num inv = nzero<Num>();
+  if (lane < B) inv = ninv(A.get(i, i));
   for (int q = B - 1; q >= 0; --q) {
-    if (lane == q) xi = ndiv(xi, A.get(i, i));
+    if (lane == q) xi = nmul(xi, inv);
     const Num xq = shfl_num(xi, q);
     if (lane < q) xi = nsub(xi, nmul(A.get(i, b0 + q), xq));
   }

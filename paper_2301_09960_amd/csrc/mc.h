@@ -4,8 +4,8 @@
 // them by decreasing magnitude, renormalizes them with `renorm` (mp_device.h:
 // only TwoSum, so the sum is unchanged) and keeps the leading C components.
 // Division takes C + 1 quotient digits, each from the remainder of the
-// previous ones.  Must be compiled with -ffp-contract=off (only the explicit
-// fma of TwoProd is fused).
+// previous ones (the remainder formed in a single renormalization).  Must be
+// compiled with -ffp-contract=off (only the explicit fma of TwoProd is fused).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -90,6 +90,24 @@ __device__ __forceinline__ mc<C> mc_mul(const mc<C> &a, const mc<C> &b) {
   return mc_from_terms<C, 2 * kExact + kPlain>(t);
 }
 
+// r - q b for a binary64 q, in one renormalization: the terms of r, and q b_i
+// exact (TwoProd) below the last order, plain on it.
+template <int C>
+__device__ __forceinline__ mc<C> mc_sub_scaled(const mc<C> &r, double q, const mc<C> &b) {
+  double t[C + 2 * (C - 1) + 1];
+  int w = 0;
+#pragma unroll
+  for (int i = 0; i < C; ++i) t[w++] = r.x[i];
+#pragma unroll
+  for (int i = 0; i < C - 1; ++i) {
+    const double p = q * b.x[i];
+    t[w++] = -p;
+    t[w++] = -fma(q, b.x[i], -p);
+  }
+  t[w++] = -(q * b.x[C - 1]);
+  return mc_from_terms<C, C + 2 * (C - 1) + 1>(t);
+}
+
 template <int C>
 __device__ __forceinline__ mc<C> mc_div(const mc<C> &a, const mc<C> &b) {
   double q[C + 1];
@@ -97,11 +115,7 @@ __device__ __forceinline__ mc<C> mc_div(const mc<C> &a, const mc<C> &b) {
 #pragma unroll
   for (int d = 0; d <= C; ++d) {
     q[d] = r.x[0] / b.x[0];
-    if (d < C) {
-      mc<C> qd{};
-      qd.x[0] = q[d];
-      r = mc_sub<C>(r, mc_mul<C>(qd, b));
-    }
+    if (d < C) r = mc_sub_scaled<C>(r, q[d], b);
   }
   return mc_from_terms<C, C + 1>(q);
 }
