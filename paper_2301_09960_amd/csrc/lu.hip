@@ -26,11 +26,14 @@ __device__ __forceinline__ dd nadd(dd a, dd b) { return dd_add(a, b); }
 __device__ __forceinline__ dd nsub(dd a, dd b) { return dd_sub(a, b); }
 __device__ __forceinline__ dd nmul(dd a, dd b) { return dd_mul(a, b); }
 __device__ __forceinline__ dd ndiv(dd a, dd b) { return dd_div(a, b); }
+__device__ __forceinline__ dd nfms(dd s, dd a, dd b) { return dd_sub(s, dd_mul(a, b)); }
 using td = mc<3>;
 __device__ __forceinline__ td nadd(const td &a, const td &b) { return mc_add<3>(a, b); }
 __device__ __forceinline__ td nsub(const td &a, const td &b) { return mc_sub<3>(a, b); }
 __device__ __forceinline__ td nmul(const td &a, const td &b) { return mc_mul<3>(a, b); }
 __device__ __forceinline__ td ndiv(const td &a, const td &b) { return mc_div<3>(a, b); }
+// s - a b (TD: one renormalization of 8 terms)
+__device__ __forceinline__ td nfms(const td &s, const td &a, const td &b) { return mc_fms<3>(s, a, b); }
 // 1 / b, by the division above: a solve multiplies by it so that the division
 // leaves the chain of dependent steps.
 __device__ __forceinline__ dd ninv(dd b) { return dd_div(dd{1.0, 0.0}, b); }
@@ -103,7 +106,7 @@ __global__ __launch_bounds__(kLuThreads) void k_lu_diag(Mat<Num> A, int j0, int 
     const int r = K - j - 1;
     for (int idx = threadIdx.x; idx < r * r; idx += kLuThreads) {
       const int i = j + 1 + idx % r, l = j + 1 + idx / r;
-      A.put(j0 + i, j0 + l, nsub(A.get(j0 + i, j0 + l), nmul(A.get(j0 + i, j0 + j), A.get(j0 + j, j0 + l))));
+      A.put(j0 + i, j0 + l, nfms(A.get(j0 + i, j0 + l), A.get(j0 + i, j0 + j), A.get(j0 + j, j0 + l)));
     }
     __syncthreads();
   }
@@ -117,7 +120,7 @@ __global__ __launch_bounds__(256) void k_trsm_lower(Mat<Num> A, int j0, int K, i
   if (l >= n) return;
   for (int i = 1; i < K; ++i) {
     Num s = A.get(j0 + i, l);
-    for (int q = 0; q < i; ++q) s = nsub(s, nmul(A.get(j0 + i, j0 + q), A.get(j0 + q, l)));
+    for (int q = 0; q < i; ++q) s = nfms(s, A.get(j0 + i, j0 + q), A.get(j0 + q, l));
     A.put(j0 + i, l, s);
   }
 }
@@ -130,7 +133,7 @@ __global__ __launch_bounds__(256) void k_trsm_upper(Mat<Num> A, int j0, int K, i
   if (i >= n) return;
   for (int q = 0; q < K; ++q) {
     Num s = A.get(i, j0 + q);
-    for (int r = 0; r < q; ++r) s = nsub(s, nmul(A.get(i, j0 + r), A.get(j0 + r, j0 + q)));
+    for (int r = 0; r < q; ++r) s = nfms(s, A.get(i, j0 + r), A.get(j0 + r, j0 + q));
     A.put(i, j0 + q, nmul(s, ninv(A.get(j0 + q, j0 + q))));
   }
 }
@@ -157,7 +160,7 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_trsm_lower_sweep(Mat<Num> 
   for (int q = 0; q < K - 1; ++q) {
     if (live) {
       const Num xq = col[w][q];
-      for (int i = q + 1 + lane; i < K; i += 64) col[w][i] = nsub(col[w][i], nmul(A.get(j0 + i, j0 + q), xq));
+      for (int i = q + 1 + lane; i < K; i += 64) col[w][i] = nfms(col[w][i], A.get(j0 + i, j0 + q), xq);
     }
     __syncthreads();
   }
@@ -181,7 +184,7 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_trsm_upper_sweep(Mat<Num> 
       // every lane forms x_q; lane 0 stores it
       const Num xq = nmul(row[w][q], inv[q]);
       if (lane == 0) row[w][q] = xq;
-      for (int t = q + 1 + lane; t < K; t += 64) row[w][t] = nsub(row[w][t], nmul(xq, A.get(j0 + q, j0 + t)));
+      for (int t = q + 1 + lane; t < K; t += 64) row[w][t] = nfms(row[w][t], xq, A.get(j0 + q, j0 + t));
     }
     __syncthreads();
   }
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(256) void k_rank_update(Mat<Num> A, int r0, int c0,
   for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256) {
     const int i = r0 + (int)(idx % rows), l = c0 + (int)(idx / rows);
     Num s = A.get(i, l);
-    for (int q = q0; q < q0 + kb; ++q) s = nsub(s, nmul(A.get(i, q), A.get(q, l)));
+    for (int q = q0; q < q0 + kb; ++q) s = nfms(s, A.get(i, q), A.get(q, l));
     A.put(i, l, s);
   }
 }
@@ -253,7 +256,7 @@ __global__ __launch_bounds__(64) void k_solve_fwd_diag(Mat<Num> A, int n, double
   Num xi = lane < B ? vget<Num>(x, n, i) : nzero<Num>();
   for (int q = 0; q < B - 1; ++q) {
     const Num xq = shfl_num(xi, q);
-    if (lane > q && lane < B) xi = nsub(xi, nmul(A.get(i, b0 + q), xq));
+    if (lane > q && lane < B) xi = nfms(xi, A.get(i, b0 + q), xq);
   }
   if (lane < B) vput<Num>(x, n, i, xi);
 }
@@ -263,7 +266,7 @@ __global__ __launch_bounds__(256) void k_solve_fwd_update(Mat<Num> A, int n, dou
   const int i = b0 + B + blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   Num s = vget<Num>(x, n, i);
-  for (int q = b0; q < b0 + B; ++q) s = nsub(s, nmul(A.get(i, q), vget<Num>(x, n, q)));
+  for (int q = b0; q < b0 + B; ++q) s = nfms(s, A.get(i, q), vget<Num>(x, n, q));
   vput<Num>(x, n, i, s);
 }
 
@@ -276,7 +279,7 @@ __global__ __launch_bounds__(64) void k_solve_bwd_diag(Mat<Num> A, int n, double
   for (int q = B - 1; q >= 0; --q) {
     if (lane == q) xi = nmul(xi, inv);
     const Num xq = shfl_num(xi, q);
-    if (lane < q) xi = nsub(xi, nmul(A.get(i, b0 + q), xq));
+    if (lane < q) xi = nfms(xi, A.get(i, b0 + q), xq);
   }
   if (lane < B) vput<Num>(x, n, i, xi);
 }
@@ -286,7 +289,7 @@ __global__ __launch_bounds__(256) void k_solve_bwd_update(Mat<Num> A, int n, dou
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= b0) return;
   Num s = vget<Num>(x, n, i);
-  for (int q = b0; q < b0 + B; ++q) s = nsub(s, nmul(A.get(i, q), vget<Num>(x, n, q)));
+  for (int q = b0; q < b0 + B; ++q) s = nfms(s, A.get(i, q), vget<Num>(x, n, q));
   vput<Num>(x, n, i, s);
 }
 

@@ -1,7 +1,8 @@
 // Multi-component scalar arithmetic for the TD LU (Section 4.6 factorizes TD
 // matrices as well as DD ones).  A value is C binary64 components, largest
-// first.  Each operation gathers its exact terms (TwoSum / TwoProd), sorts
-// them by decreasing magnitude, renormalizes them with `renorm` (mp_device.h:
+// first.  Each operation gathers its terms (exact ones from TwoSum / TwoProd,
+// and for a product a plain tail at the lowest order kept), sorts them by
+// decreasing magnitude, renormalizes them with `renorm` (mp_device.h:
 // only TwoSum, so the sum is unchanged) and keeps the leading C components.
 // Division takes C + 1 quotient digits, each from the remainder of the
 // previous ones (the remainder formed in a single renormalization).  Must be
@@ -67,27 +68,58 @@ __device__ __forceinline__ mc<C> mc_sub(const mc<C> &a, const mc<C> &b) {
   return mc_add<C>(a, mc_neg<C>(b));
 }
 
-// Products a_i b_j with i + j < C: exact (TwoProd) below the last order, plain
-// on it; the terms beyond are below the precision kept.
+// The terms of a b, from the products a_i b_j with i + j < C.  Below order
+// C - 2 they are exact (TwoProd); on order C - 2 the product is kept and its
+// error joins a plain binary64 tail with the products of order C - 1, which
+// lie about 2^-106 |ab| below the lead (for C = 3), so the tail's rounding is
+// near 2^-159 |ab|.  The terms beyond are below the precision kept.  C = 3
+// gives 5 terms instead of the 9 of an exact gathering.
 template <int C>
-__device__ __forceinline__ mc<C> mc_mul(const mc<C> &a, const mc<C> &b) {
-  constexpr int kExact = (C - 1) * C / 2;  // pairs with i + j < C - 1
-  constexpr int kPlain = C;                // pairs with i + j == C - 1
-  double t[2 * kExact + kPlain];
+constexpr int mul_terms() {
+  return 2 * ((C - 2) * (C - 1) / 2) + (C - 1) + 1;
+}
+
+template <int C>
+__device__ __forceinline__ void gather_mul_terms(const mc<C> &a, const mc<C> &b, double (&t)[mul_terms<C>()]) {
+  double tail = 0.0;
   int w = 0;
 #pragma unroll
   for (int i = 0; i < C; ++i)
 #pragma unroll
     for (int j = 0; j + i < C; ++j) {
-      if (i + j < C - 1) {
-        const double p = a.x[i] * b.x[j];
+      const double p = a.x[i] * b.x[j];
+      if (i + j < C - 2) {
         t[w++] = p;
         t[w++] = fma(a.x[i], b.x[j], -p);
+      } else if (i + j == C - 2) {
+        t[w++] = p;
+        tail += fma(a.x[i], b.x[j], -p);
       } else {
-        t[w++] = a.x[i] * b.x[j];
+        tail += p;
       }
     }
-  return mc_from_terms<C, 2 * kExact + kPlain>(t);
+  t[w] = tail;
+}
+
+template <int C>
+__device__ __forceinline__ mc<C> mc_mul(const mc<C> &a, const mc<C> &b) {
+  double t[mul_terms<C>()];
+  gather_mul_terms<C>(a, b, t);
+  return mc_from_terms<C, mul_terms<C>()>(t);
+}
+
+// s - a b in one renormalization: the terms of s and of -(a b) as above.
+template <int C>
+__device__ __forceinline__ mc<C> mc_fms(const mc<C> &s, const mc<C> &a, const mc<C> &b) {
+  constexpr int M = mul_terms<C>();
+  double p[M];
+  gather_mul_terms<C>(a, b, p);
+  double t[C + M];
+#pragma unroll
+  for (int i = 0; i < C; ++i) t[i] = s.x[i];
+#pragma unroll
+  for (int i = 0; i < M; ++i) t[C + i] = -p[i];
+  return mc_from_terms<C, C + M>(t);
 }
 
 // r - q b for a binary64 q, in one renormalization: the terms of r, and q b_i
