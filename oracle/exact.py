@@ -180,28 +180,31 @@ def int8_digits_py(comps_list, D: int):
     return out, E
 
 
-def lu_backward_error(A, LU) -> float:
+def lu_backward_error(A, LU, entries=None) -> float:
     """Largest |A - L U|_ij / (|L||U|)_ij over the entries, exactly: A and LU
     are ``(c, n, n)`` expansions (component planes, column-major), LU holding
     the unit lower L below its diagonal and U on and above it (the blocked LU
-    of Section 4.6).  Small n only."""
+    of Section 4.6).  ``entries``: the (i, j) pairs to check, else every entry
+    (small n only)."""
     n = A.shape[2]
-    Av = matrix_values(A)   # Av[i][j]
-    F = matrix_values(LU)
-    L = [[(Fraction(1) if i == j else (F[i][j] if i > j else Fraction(0))) for j in range(n)] for i in range(n)]
-    U = [[(F[i][j] if j >= i else Fraction(0)) for j in range(n)] for i in range(n)]
+    if entries is None:
+        entries = [(i, j) for i in range(n) for j in range(n)]
+
+    def l_of(i, q):
+        return Fraction(1) if i == q else value(LU[:, q, i])
+
     worst = Fraction(0)
-    for i in range(n):
-        for j in range(n):
-            s, a = Fraction(0), Fraction(0)
-            for q in range(min(i, j) + 1):
-                s += L[i][q] * U[q][j]
-                a += abs(L[i][q] * U[q][j])
-            d = abs(Av[i][j] - s)
-            if a > 0:
-                worst = max(worst, d / a)
-            elif d > 0:
-                return math.inf
+    for i, j in entries:
+        s, a = Fraction(0), Fraction(0)
+        for q in range(min(i, j) + 1):
+            t = l_of(i, q) * value(LU[:, j, q])  # L[i][q] U[q][j], q <= min(i, j)
+            s += t
+            a += abs(t)
+        d = abs(value(A[:, j, i]) - s)
+        if a > 0:
+            worst = max(worst, d / a)
+        elif d > 0:
+            return math.inf
     return float(worst)
 
 

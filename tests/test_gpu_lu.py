@@ -64,6 +64,31 @@ def test_lu_backward_error(mp, fmt, n, K, mode):
     assert err <= BACKWARD[fmt]
 
 
+@pytest.mark.parametrize("fmt", ["dd", "td"])
+def test_lu_wide_panel(mp, fmt):
+    """K = 520 > 512: the panel solves take the thread-per-vector kernels
+    (every step of the substitution in one thread) and the diagonal block is
+    factored in inner blocks.  Exact backward error on sampled entries of all
+    four blocks, their corners included."""
+    import torch
+    n, K = 600, 520
+    c = 2 if fmt == "dd" else 3
+    A = dd_dominant(n, seed=11, c=c)
+    dA = torch.from_numpy(A.copy()).cuda()
+    mp.lu(fmt, dA, K)
+    LU = dA.cpu().numpy()
+    assert np.isfinite(LU).all()
+    rng = np.random.default_rng(12)
+    corners = [(0, 0), (K - 1, K - 1), (n - 1, n - 1), (n - 1, 0), (0, n - 1), (K, K - 1), (K - 1, K),
+               (n - 1, K - 1), (K - 1, n - 1), (K, K)]
+    blocks = [(0, K, 0, K), (K, n, 0, K), (0, K, K, n), (K, n, K, n)]
+    entries = corners + [(int(rng.integers(r0, r1)), int(rng.integers(c0, c1)))
+                         for r0, r1, c0, c1 in blocks for _ in range(40)]
+    err = X.lu_backward_error(A, LU, entries=entries)
+    say(f"{fmt}_lu n={n} K={K}: log2 backward error (sampled) {np.log2(err) if err > 0 else -np.inf:.1f}")
+    assert err <= BACKWARD[fmt]
+
+
 @pytest.mark.parametrize("fmt,n,K", [("dd", 40, 16), ("dd", 24, 24), ("td", 40, 16)])
 def test_lu_solve(mp, fmt, n, K):
     import torch

@@ -39,6 +39,26 @@ def test_backward_error_exact_and_planted():
     assert got == float(want)
 
 
+def test_backward_error_sampled_entries():
+    """The sampled form agrees with the full one: zero off the planted column,
+    the planted ratio on it, and every entry listed gives the full result."""
+    rng = np.random.default_rng(4)
+    n = 7
+    L = np.tril(rng.integers(-4, 5, size=(n, n)) / 8.0, -1) + np.eye(n)
+    U = np.triu(rng.integers(1, 9, size=(n, n)) / 4.0)
+    A = _dd_matrix((L @ U).tolist())
+    LUd = _dd_matrix((np.tril(L, -1) + U).tolist())
+    LUd[1, 5, 3] = 2.0 ** -70  # U[3][5] + 2^-70: entries (i, 5) with i >= 3 change
+    full = X.lu_backward_error(A, LUd)
+    assert full > 0
+    every = [(i, j) for i in range(n) for j in range(n)]
+    assert X.lu_backward_error(A, LUd, entries=every) == full
+    assert X.lu_backward_error(A, LUd, entries=[(i, j) for i, j in every if j != 5]) == 0.0
+    col = [(i, 5) for i in range(n)]
+    assert X.lu_backward_error(A, LUd, entries=col) == full
+    assert X.lu_backward_error(A, LUd, entries=[(0, 5), (1, 5), (2, 5)]) == 0.0
+
+
 def test_solve_exact_satisfies_system():
     rng = np.random.default_rng(5)
     n = 7
