@@ -245,6 +245,24 @@ int mpgemm_certify(int fmt, int m, int n, int k, const void *A, int lda, const v
                    double *cert, double *worst, hipStream_t stream);
 
 /*
+ * mpgemm_certify with the slice count chosen from the data (the paper leaves the
+ * number of splits to be found by running the calculation, Section 3): runs
+ * the certified product at D = d_first, d_first + 1, ..., d_last in the
+ * thread's slice form and stops at the first D whose worst ratio is at most
+ * 2^-t (t as above).  C, cert and *worst hold that attempt's results, and
+ * *d_used (host) its D; if no D up to d_last is certified they hold the
+ * d_last attempt's, and the caller sees it in *worst.  A D the certificate does
+ * not support is skipped (MPGEMM_ERR_UNSUPPORTED if none was).  Synchronizes
+ * `stream` after each attempt to read *worst back, so it cannot be captured
+ * in a graph.  The thread's slice-count option is not changed.  Argument codes
+ * as for mpgemm_certify; -13 for d_first outside [1, the form's maximum D],
+ * -14 for d_last outside [d_first, that maximum], -15 for a NULL d_used.
+ */
+int mpgemm_certify_adaptive(int fmt, int m, int n, int k, const void *A, int lda, const void *B, int ldb, void *C,
+                            int ldc, double *cert, double *worst, int d_first, int d_last, int *d_used,
+                            hipStream_t stream);
+
+/*
  * LU factorization of a DD (TD) matrix with the Schur updates done by this
  * library's DD (TD) product (Section 4.6).  A (device; two (three) planes of
  * components, each n x n column-major with leading dimension lda, lda * n

@@ -79,6 +79,8 @@ def lib():
                 L.mpgemm_debug_split.argtypes = [_I, _I, _I, _I, _I, _P, _I, _I, _P, _P, _P]
                 L.mpgemm_debug_products.argtypes = [_I, _I, _I, _I, _I, _P, _I, _P, _I, _I, _I, _I, _P, _I, _P]
                 L.mpgemm_certify.argtypes = [_I, _I, _I, _I, _P, _I, _P, _I, _P, _I, _P, _P, _P]
+                L.mpgemm_certify_adaptive.argtypes = [_I, _I, _I, _I, _P, _I, _P, _I, _P, _I, _P, _P, _I, _I, _P,
+                                                      _P]
                 for name in ("mpgemm_dd_lu", "mpgemm_td_lu"):
                     getattr(L, name).argtypes = [_I, _P, _I, _I, _P]
                 for name in ("mpgemm_dd_lu_solve", "mpgemm_td_lu_solve"):
@@ -326,6 +328,36 @@ def certify(fmt, A, B, C=None, *, mode="float", slices=None, stream=None):
                                   _stream(stream))
     _check(st, "mpgemm_certify")
     return C, cert, worst
+
+
+def certify_adaptive(fmt, A, B, C=None, *, d_first: int, d_last: int, mode="float", stream=None):
+    """``certify`` with the slice count found from the data: the certified
+    product at D = d_first, d_first + 1, ... d_last, stopping at the first D
+    whose worst ratio meets 2^-t.  Returns ``(C, cert, worst, D)`` for that
+    attempt (the d_last attempt's if none is certified: see ``worst``).
+    Synchronizes ``stream`` after each attempt."""
+    import torch
+    f = _fmt(fmt)
+    name = [k for k, v in FORMATS.items() if v == f][0]
+    c = COMPONENTS[name]
+    dtype = torch.float32 if name == "ts" else torch.float64
+    _check_tensor(A, c, dtype, "A")
+    _check_tensor(B, c, dtype, "B")
+    k, m = A.shape[1], A.shape[2]
+    n, kb = B.shape[1], B.shape[2]
+    if kb != k:
+        raise ValueError(f"inner dimensions differ: A has k={k}, B has k={kb}")
+    if C is None:
+        C = torch.empty((c, n, m), dtype=dtype, device=A.device)
+    cert = torch.empty((2, n, m), dtype=torch.float64, device=A.device)
+    worst = torch.empty((1,), dtype=torch.float64, device=A.device)
+    used = ctypes.c_int(0)
+    with _options(f, _mode(mode), None):
+        st = lib().mpgemm_certify_adaptive(f, m, n, k, _P(A.data_ptr()), max(1, m), _P(B.data_ptr()), max(1, k),
+                                           _P(C.data_ptr()), max(1, m), _P(cert.data_ptr()), _P(worst.data_ptr()),
+                                           int(d_first), int(d_last), ctypes.byref(used), _stream(stream))
+    _check(st, "mpgemm_certify_adaptive")
+    return C, cert, worst, used.value
 
 
 def lu(fmt, A, K: int, *, mode=None, stream=None):

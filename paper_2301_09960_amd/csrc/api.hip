@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <array>
 #include <climits>
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -579,6 +580,43 @@ int certify_t(int fmt, int m, int n, int k, const T *A, int lda, const T *B, int
   return certify_run<T, C>(fmt, mode, slices_for(fmt, mode, k), m, n, k, A, lda, B, ldb, Cm, ldc, cert, worst, st);
 }
 
+// The certified product at D = d_first, d_first + 1, ... d_last, stopping at
+// the first D whose certificate meets 2^-t (|A||B|): the slice count chosen
+// from the data rather than from the a-priori estimate.  Reads *worst back
+// after each attempt (synchronizing the stream).  A D that the certificate
+// does not support (TS at D = 1, INT8 with too few digit planes) is skipped.
+template <typename T, int C>
+int certify_adaptive_t(int fmt, int m, int n, int k, const T *A, int lda, const T *B, int ldb, T *Cm, int ldc,
+                       double *cert, double *worst, int d_first, int d_last, int *d_used, hipStream_t st) {
+  int s = validate(m, n, k, A, lda, B, ldb, Cm, ldc);
+  if (s) return s < 0 ? s - 1 : s;  // shifted past fmt
+  if (!cert && m > 0 && n > 0) return -11;
+  if (!worst) return -12;
+  const int mode = g_opt.mode[fmt];
+  const int dmax = mode == MPGEMM_MODE_FLOAT ? kMaxDFloat : kMaxDInt8;
+  if (d_first < 1 || d_first > dmax) return -13;
+  if (d_last < d_first || d_last > dmax) return -14;
+  if (!d_used) return -15;
+  if ((s = check_device_cached())) return s;
+  const double target = std::ldexp(1.0, -kBoundBits[fmt]);
+  int status = MPGEMM_ERR_UNSUPPORTED;
+  for (int D = d_first; D <= d_last; ++D) {
+    s = certify_run<T, C>(fmt, mode, D, m, n, k, A, lda, B, ldb, Cm, ldc, cert, worst, st);
+    if (s == MPGEMM_ERR_UNSUPPORTED) continue;
+    if (s) return s;
+    *d_used = D;
+    status = 0;
+    double w = 0.0;
+    if (hipMemcpyAsync(&w, worst, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      (void)hipGetLastError();
+      return MPGEMM_ERR_HIP;
+    }
+    if (w <= target) break;
+  }
+  return status;
+}
+
 // Longer expansions (c components, INT8 form), as mpgemm_nd computes them.
 template <int C>
 int certify_nd_t(int D, int m, int n, int k, const double *A, int lda, const double *B, int ldb, double *Cm, int ldc,
@@ -922,6 +960,26 @@ int mpgemm_certify(int fmt, int m, int n, int k, const void *A, int lda, const v
     default:
       return certify_t<float, 3>(fmt, m, n, k, (const float *)A, lda, (const float *)B, ldb, (float *)C, ldc, cert,
                                  worst, stream);
+  }
+}
+
+int mpgemm_certify_adaptive(int fmt, int m, int n, int k, const void *A, int lda, const void *B, int ldb, void *C,
+                            int ldc, double *cert, double *worst, int d_first, int d_last, int *d_used,
+                            hipStream_t stream) {
+  if (!fmt_ok(fmt)) return -1;
+  switch (fmt) {
+    case MPGEMM_DD:
+      return certify_adaptive_t<double, 2>(fmt, m, n, k, (const double *)A, lda, (const double *)B, ldb, (double *)C,
+                                           ldc, cert, worst, d_first, d_last, d_used, stream);
+    case MPGEMM_TD:
+      return certify_adaptive_t<double, 3>(fmt, m, n, k, (const double *)A, lda, (const double *)B, ldb, (double *)C,
+                                           ldc, cert, worst, d_first, d_last, d_used, stream);
+    case MPGEMM_QD:
+      return certify_adaptive_t<double, 4>(fmt, m, n, k, (const double *)A, lda, (const double *)B, ldb, (double *)C,
+                                           ldc, cert, worst, d_first, d_last, d_used, stream);
+    default:
+      return certify_adaptive_t<float, 3>(fmt, m, n, k, (const float *)A, lda, (const float *)B, ldb, (float *)C, ldc,
+                                          cert, worst, d_first, d_last, d_used, stream);
   }
 }
 

@@ -55,6 +55,17 @@ def test_argument_codes(L):
     assert c(0, 4, 4, 4, x, 3, x, 4, x, 4, x, x, None) == -6
     assert c(0, 4, 4, 4, x, 4, x, 4, x, 4, None, x, None) == -11
     assert c(0, 4, 4, 4, x, 4, x, 4, x, 4, x, None, None) == -12
+    # adaptive certified product: the certify codes, then the D range and d_used
+    ca = L.mpgemm_certify_adaptive
+    assert ca(7, 4, 4, 4, x, 4, x, 4, x, 4, x, x, 2, 4, x, None) == -1
+    assert ca(0, 4, 4, 4, x, 3, x, 4, x, 4, x, x, 2, 4, x, None) == -6
+    assert ca(0, 4, 4, 4, x, 4, x, 4, x, 4, None, x, 2, 4, x, None) == -11
+    assert ca(0, 4, 4, 4, x, 4, x, 4, x, 4, x, None, 2, 4, x, None) == -12
+    assert ca(0, 4, 4, 4, x, 4, x, 4, x, 4, x, x, 0, 4, x, None) == -13
+    assert ca(0, 4, 4, 4, x, 4, x, 4, x, 4, x, x, 17, 17, x, None) == -13  # beyond the binary64 form's 16
+    assert ca(0, 4, 4, 4, x, 4, x, 4, x, 4, x, x, 5, 4, x, None) == -14
+    assert ca(0, 4, 4, 4, x, 4, x, 4, x, 4, x, x, 5, 17, x, None) == -14
+    assert ca(0, 4, 4, 4, x, 4, x, 4, x, 4, x, x, 2, 4, None, None) == -15
     # DD LU and its solve
     assert L.mpgemm_dd_lu(-1, x, 1, 8, None) == -1
     assert L.mpgemm_dd_lu(4, None, 4, 8, None) == -2

@@ -223,3 +223,47 @@ def test_certificate_thin_shapes(mp, orc, mode, m, n, k):
             assert t1[i][j] + t23[i][j] <= Fraction(float(beta[j, i]))
             assert diff[j, i] <= float(beta[j, i]) * (1 + 2.0 ** -50)
     assert float(worst.cpu()[0]) <= 2.0 ** -100
+
+
+@pytest.mark.parametrize("fmt,mode,E", [("dd", "float", 0), ("dd", "float", 16), ("qd", "float", 0),
+                                        ("td", "int8", 0), ("dd", "int8", 16)])
+def test_adaptive_slice_count(mp, orc, fmt, mode, E):
+    """mpgemm_certify_adaptive stops at the first certified D: its C, cert and
+    worst equal mpgemm_certify's at that D, worst meets 2^-t, one slice fewer
+    does not, and |C - AB| (exact) is within the certificate in every entry."""
+    import torch
+    m, n, k = 48, 40, 300
+    A, B = W.gen_pair(fmt, m, n, k, E=E, seed=61)
+    dA, dB = dev(A), dev(B)
+    auto = mp.num_slices(fmt, mode, k)
+    d_first = 2 if mode == "float" else 8
+    C, cert, worst, D = mp.certify_adaptive(fmt, dA, dB, d_first=d_first, d_last=auto + 2, mode=mode)
+    target = 2.0 ** -T_BITS[fmt]
+    w = float(worst.cpu()[0])
+    say(f"adaptive {fmt} {mode} E={E} m={m} n={n} k={k}: D = {D} (a-priori {auto}), log2 worst {np.log2(w):.1f}")
+    assert d_first <= D <= auto + 2
+    assert w <= target
+    C2, cert2, worst2 = mp.certify(fmt, dA, dB, mode=mode, slices=D)
+    torch.cuda.synchronize()
+    assert torch.equal(C, C2) and torch.equal(cert, cert2) and torch.equal(worst, worst2)
+    if D > d_first:
+        _, _, w1 = mp.certify(fmt, dA, dB, mode=mode, slices=D - 1)
+        assert float(w1.cpu()[0]) > target
+    beta, lam = cert[0].cpu().numpy(), cert[1].cpu().numpy()
+    diff, _, _ = orc.exact_check(A, B, C.cpu().numpy())
+    assert (diff <= beta * (1 + 2.0 ** -50)).all()
+    assert (beta <= target * lam).all()
+
+
+def test_adaptive_not_certified(mp):
+    """A range that ends too early returns its last attempt, uncertified."""
+    import torch
+    m, n, k = 33, 17, 200
+    A, B = W.gen_pair("dd", m, n, k, E=16, seed=62)
+    dA, dB = dev(A), dev(B)
+    C, cert, worst, D = mp.certify_adaptive("dd", dA, dB, d_first=2, d_last=3)
+    assert D == 3
+    assert float(worst.cpu()[0]) > 2.0 ** -100
+    C2, _, worst2 = mp.certify("dd", dA, dB, slices=3)
+    torch.cuda.synchronize()
+    assert torch.equal(C, C2) and torch.equal(worst, worst2)
