@@ -236,10 +236,10 @@ __global__ __launch_bounds__(256) void k_sub_block(Mat<Num> A, int r0, int c0, i
 // Blocked solve of L U x = b (x holds b on entry): blocks of kSolveB rows.
 // Forward: one wavefront solves the block's rows against the unit lower
 // diagonal block (lane per row, x_q passed by shuffle), then every later row
-// subtracts the block's contribution (thread per row, q ascending).  Backward:
-// the same from the last block up, with the product by the reciprocal of U's
-// diagonal entry (each lane forms its own before the chain).  Each
-// entry's subtractions come in a fixed order, so the solve is reproducible.
+// subtracts the block's contribution (k_solve_update).  Backward: the same
+// from the last block up, with the product by the reciprocal of U's diagonal
+// entry (each lane forms its own before the chain).  Every entry's operations
+// come in a fixed order, so the solve is reproducible.
 constexpr int kSolveB = 64;
 
 template <typename Num>
@@ -262,15 +262,6 @@ __global__ __launch_bounds__(64) void k_solve_fwd_diag(Mat<Num> A, int n, double
 }
 
 template <typename Num>
-__global__ __launch_bounds__(256) void k_solve_fwd_update(Mat<Num> A, int n, double *x, int b0, int B) {
-  const int i = b0 + B + blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  Num s = vget<Num>(x, n, i);
-  for (int q = b0; q < b0 + B; ++q) s = nfms(s, A.get(i, q), vget<Num>(x, n, q));
-  vput<Num>(x, n, i, s);
-}
-
-template <typename Num>
 __global__ __launch_bounds__(64) void k_solve_bwd_diag(Mat<Num> A, int n, double *x, int b0, int B) {
   const int lane = threadIdx.x, i = b0 + lane;
   Num xi = lane < B ? vget<Num>(x, n, i) : nzero<Num>();
@@ -284,13 +275,32 @@ __global__ __launch_bounds__(64) void k_solve_bwd_diag(Mat<Num> A, int n, double
   if (lane < B) vput<Num>(x, n, i, xi);
 }
 
+// x_i -= sum over q in [b0, b0 + B) of A(i, q) x_q for the rows i in
+// [r0, r0 + rows): the sum in kSolveChunks runs of consecutive q, one thread
+// each (32 rows per workgroup), then added to x_i in run order.
+constexpr int kSolveChunks = 8;
+constexpr int kSolveRows = 256 / kSolveChunks;
+
 template <typename Num>
-__global__ __launch_bounds__(256) void k_solve_bwd_update(Mat<Num> A, int n, double *x, int b0, int B) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= b0) return;
-  Num s = vget<Num>(x, n, i);
-  for (int q = b0; q < b0 + B; ++q) s = nfms(s, A.get(i, q), vget<Num>(x, n, q));
-  vput<Num>(x, n, i, s);
+__global__ __launch_bounds__(256) void k_solve_update(Mat<Num> A, int n, double *x, int b0, int B, int r0,
+                                                      int rows) {
+  __shared__ Num part[kSolveChunks][kSolveRows];
+  const int rl = threadIdx.x % kSolveRows, c = threadIdx.x / kSolveRows;
+  const int i = r0 + blockIdx.x * kSolveRows + rl;
+  const bool live = i < r0 + rows;
+  const int per = (B + kSolveChunks - 1) / kSolveChunks;
+  const int q0 = b0 + c * per, q1 = std::min(b0 + B, q0 + per);
+  Num p = nzero<Num>();  // minus the run's sum
+  if (live)
+    for (int q = q0; q < q1; ++q) p = nfms(p, A.get(i, q), vget<Num>(x, n, q));
+  part[c][rl] = p;
+  __syncthreads();
+  if (live && c == 0) {
+    Num s = vget<Num>(x, n, i);
+#pragma unroll
+    for (int r = 0; r < kSolveChunks; ++r) s = nadd(s, part[r][rl]);
+    vput<Num>(x, n, i, s);
+  }
 }
 
 unsigned grid_for(int64_t work) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(work, 256), 8192)); }
@@ -340,15 +350,15 @@ hipError_t lu_solve(const double *A, int64_t ld, int64_t plane, int n, double *x
     const int B = std::min(kSolveB, n - b0);
     hipLaunchKernelGGL((k_solve_fwd_diag<Num>), dim3(1), dim3(64), 0, st, M, n, x, b0, B);
     if (b0 + B < n)
-      hipLaunchKernelGGL((k_solve_fwd_update<Num>), dim3((unsigned)ceil_div(n - b0 - B, 256)), dim3(256), 0, st, M, n,
-                         x, b0, B);
+      hipLaunchKernelGGL((k_solve_update<Num>), dim3((unsigned)ceil_div(n - b0 - B, kSolveRows)), dim3(256), 0, st, M,
+                         n, x, b0, B, b0 + B, n - b0 - B);
   }
   for (int b0 = (n - 1) / kSolveB * kSolveB; b0 >= 0; b0 -= kSolveB) {
     const int B = std::min(kSolveB, n - b0);
     hipLaunchKernelGGL((k_solve_bwd_diag<Num>), dim3(1), dim3(64), 0, st, M, n, x, b0, B);
     if (b0 > 0)
-      hipLaunchKernelGGL((k_solve_bwd_update<Num>), dim3((unsigned)ceil_div(b0, 256)), dim3(256), 0, st, M, n, x, b0,
-                         B);
+      hipLaunchKernelGGL((k_solve_update<Num>), dim3((unsigned)ceil_div(b0, kSolveRows)), dim3(256), 0, st, M, n, x,
+                         b0, B, 0, b0);
   }
   return hipGetLastError();
 }
