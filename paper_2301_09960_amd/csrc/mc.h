@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include "mp_device.h"
+#include "sortnet.h"
 
 namespace mp {
 
@@ -20,18 +21,19 @@ struct mc {
   double x[C];
 };
 
-// Insertion sort by decreasing magnitude (fully unrolled, selects only).
+// Sort by decreasing magnitude with the comparator network of sortnet.h
+// (fully unrolled: compile-time indices, selects only).
 template <int N>
 __device__ __forceinline__ void sort_by_magnitude(double (&t)[N]) {
+  constexpr SortNet<N> net{};
 #pragma unroll
-  for (int i = 1; i < N; ++i)
-#pragma unroll
-    for (int j = i; j > 0; --j) {
-      const double a = t[j - 1], b = t[j];
-      const bool swap = fabs(b) > fabs(a);
-      t[j - 1] = swap ? b : a;
-      t[j] = swap ? a : b;
-    }
+  for (int c = 0; c < net.count; ++c) {
+    const int lo = net.lo[c], hi = net.hi[c];
+    const double a = t[lo], b = t[hi];
+    const bool swap = fabs(b) > fabs(a);
+    t[lo] = swap ? b : a;
+    t[hi] = swap ? a : b;
+  }
 }
 
 // The leading C components of the renormalized sum of N exact terms.
