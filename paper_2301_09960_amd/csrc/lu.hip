@@ -112,6 +112,38 @@ __global__ __launch_bounds__(kLuThreads) void k_lu_diag(Mat<Num> A, int j0, int 
   }
 }
 
+// The same factorization with the block held in LDS (K <= kDiagLds): the
+// operations and their order are those of k_lu_diag, so the factors are
+// identical; each column's chain waits on LDS instead of the L2.
+constexpr int kDiagLds = 32;
+
+template <typename Num>
+__global__ __launch_bounds__(kLuThreads) void k_lu_diag_lds(Mat<Num> A, int j0, int K) {
+  __shared__ Num blk[kDiagLds * kDiagLds];  // column-major, leading dimension K
+  for (int idx = threadIdx.x; idx < K * K; idx += kLuThreads) blk[idx] = A.get(j0 + idx % K, j0 + idx / K);
+  __syncthreads();
+  for (int j = 0; j < K; ++j) {
+    const Num piv = blk[j + j * K];
+    for (int i = j + 1 + (int)threadIdx.x; i < K; i += kLuThreads) blk[i + j * K] = ndiv(blk[i + j * K], piv);
+    __syncthreads();
+    const int r = K - j - 1;
+    for (int idx = threadIdx.x; idx < r * r; idx += kLuThreads) {
+      const int i = j + 1 + idx % r, l = j + 1 + idx / r;
+      blk[i + l * K] = nfms(blk[i + l * K], blk[i + j * K], blk[j + l * K]);
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < K * K; idx += kLuThreads) A.put(j0 + idx % K, j0 + idx / K, blk[idx]);
+}
+
+template <typename Num>
+void launch_lu_diag(const Mat<Num> &M, int j0, int K, hipStream_t st) {
+  if (K <= kDiagLds)
+    hipLaunchKernelGGL((k_lu_diag_lds<Num>), dim3(1), dim3(kLuThreads), 0, st, M, j0, K);
+  else
+    hipLaunchKernelGGL((k_lu_diag<Num>), dim3(1), dim3(kLuThreads), 0, st, M, j0, K);
+}
+
 // U12 = L11^-1 A12 in place: thread per column l of A12, forward substitution
 // down the column with the unit lower L11.
 template <typename Num>
@@ -316,12 +348,12 @@ template <typename Num>
 hipError_t lu_panel(double *A, int64_t ld, int64_t plane, int j0, int K, int n, hipStream_t st) {
   const Mat<Num> M{A, ld, plane};
   if (K <= 2 * kInner) {
-    hipLaunchKernelGGL((k_lu_diag<Num>), dim3(1), dim3(kLuThreads), 0, st, M, j0, K);
+    launch_lu_diag<Num>(M, j0, K, st);
   } else {
     const int end = j0 + K;
     for (int jj = j0; jj < end; jj += kInner) {
       const int kb = std::min(kInner, end - jj), r = end - jj - kb;
-      hipLaunchKernelGGL((k_lu_diag<Num>), dim3(1), dim3(kLuThreads), 0, st, M, jj, kb);
+      launch_lu_diag<Num>(M, jj, kb, st);
       if (r == 0) break;
       const dim3 grid((unsigned)ceil_div(r, kSweepWaves));
       hipLaunchKernelGGL((k_trsm_lower_sweep<Num>), grid, dim3(64 * kSweepWaves), 0, st, M, jj, kb, end);
