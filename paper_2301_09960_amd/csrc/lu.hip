@@ -180,19 +180,33 @@ __global__ __launch_bounds__(256) void k_trsm_upper(Mat<Num> A, int j0, int K, i
 constexpr int kSweepMax = 512;
 constexpr int kSweepWaves = 4;
 
-template <typename Num>
+// KMAX: the largest K of the instance.  With KMAX <= kDiagLds the K x K
+// diagonal block is also staged in LDS, so each step of the chain reads it
+// there; the operations are the same either way.
+template <typename Num, int KMAX>
 __global__ __launch_bounds__(64 * kSweepWaves) void k_trsm_lower_sweep(Mat<Num> A, int j0, int K, int n) {
-  __shared__ Num col[kSweepWaves][kSweepMax];
+  constexpr bool kStage = KMAX <= kDiagLds;
+  __shared__ Num col[kSweepWaves][KMAX];
+  __shared__ Num blk[kStage ? KMAX * KMAX : 1];
   const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int l = j0 + K + blockIdx.x * kSweepWaves + w;
   const bool live = l < n;
+  if constexpr (kStage)
+    for (int idx = threadIdx.x; idx < K * K; idx += 64 * kSweepWaves) blk[idx] = A.get(j0 + idx % K, j0 + idx / K);
   if (live)
     for (int i = lane; i < K; i += 64) col[w][i] = A.get(j0 + i, l);
   __syncthreads();
   for (int q = 0; q < K - 1; ++q) {
     if (live) {
       const Num xq = col[w][q];
-      for (int i = q + 1 + lane; i < K; i += 64) col[w][i] = nfms(col[w][i], A.get(j0 + i, j0 + q), xq);
+      for (int i = q + 1 + lane; i < K; i += 64) {
+        Num lq;
+        if constexpr (kStage)
+          lq = blk[i + q * K];
+        else
+          lq = A.get(j0 + i, j0 + q);
+        col[w][i] = nfms(col[w][i], lq, xq);
+      }
     }
     __syncthreads();
   }
@@ -200,13 +214,17 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_trsm_lower_sweep(Mat<Num> 
     for (int i = lane; i < K; i += 64) A.put(j0 + i, l, col[w][i]);
 }
 
-template <typename Num>
+template <typename Num, int KMAX>
 __global__ __launch_bounds__(64 * kSweepWaves) void k_trsm_upper_sweep(Mat<Num> A, int j0, int K, int n) {
-  __shared__ Num row[kSweepWaves][kSweepMax];
-  __shared__ Num inv[kSweepMax];
+  constexpr bool kStage = KMAX <= kDiagLds;
+  __shared__ Num row[kSweepWaves][KMAX];
+  __shared__ Num inv[KMAX];
+  __shared__ Num blk[kStage ? KMAX * KMAX : 1];
   const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int i = j0 + K + blockIdx.x * kSweepWaves + w;
   const bool live = i < n;
+  if constexpr (kStage)
+    for (int idx = threadIdx.x; idx < K * K; idx += 64 * kSweepWaves) blk[idx] = A.get(j0 + idx % K, j0 + idx / K);
   for (int t = threadIdx.x; t < K; t += 64 * kSweepWaves) inv[t] = ninv(A.get(j0 + t, j0 + t));
   if (live)
     for (int t = lane; t < K; t += 64) row[w][t] = A.get(i, j0 + t);
@@ -216,12 +234,33 @@ __global__ __launch_bounds__(64 * kSweepWaves) void k_trsm_upper_sweep(Mat<Num> 
       // every lane forms x_q; lane 0 stores it
       const Num xq = nmul(row[w][q], inv[q]);
       if (lane == 0) row[w][q] = xq;
-      for (int t = q + 1 + lane; t < K; t += 64) row[w][t] = nfms(row[w][t], xq, A.get(j0 + q, j0 + t));
+      for (int t = q + 1 + lane; t < K; t += 64) {
+        Num uq;
+        if constexpr (kStage)
+          uq = blk[q + t * K];
+        else
+          uq = A.get(j0 + q, j0 + t);
+        row[w][t] = nfms(row[w][t], xq, uq);
+      }
     }
     __syncthreads();
   }
   if (live)
     for (int t = lane; t < K; t += 64) A.put(i, j0 + t, row[w][t]);
+}
+
+// Both panel sweeps for a K x K diagonal block at (j0, j0), rows and columns up
+// to `end`.
+template <typename Num>
+void launch_sweeps(const Mat<Num> &M, int j0, int K, int end, hipStream_t st) {
+  const dim3 grid((unsigned)ceil_div(end - j0 - K, kSweepWaves));
+  if (K <= kDiagLds) {
+    hipLaunchKernelGGL((k_trsm_lower_sweep<Num, kDiagLds>), grid, dim3(64 * kSweepWaves), 0, st, M, j0, K, end);
+    hipLaunchKernelGGL((k_trsm_upper_sweep<Num, kDiagLds>), grid, dim3(64 * kSweepWaves), 0, st, M, j0, K, end);
+  } else {
+    hipLaunchKernelGGL((k_trsm_lower_sweep<Num, kSweepMax>), grid, dim3(64 * kSweepWaves), 0, st, M, j0, K, end);
+    hipLaunchKernelGGL((k_trsm_upper_sweep<Num, kSweepMax>), grid, dim3(64 * kSweepWaves), 0, st, M, j0, K, end);
+  }
 }
 
 // A[r0 + i, c0 + l] -= sum over q in [q0, q0 + kb) of A[r0 + i, q] A[q, c0 + l]
@@ -337,17 +376,17 @@ __global__ __launch_bounds__(256) void k_solve_update(Mat<Num> A, int n, double 
 
 unsigned grid_for(int64_t work) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(work, 256), 8192)); }
 
-// Diagonal blocks wider than 2 kInner are factored in inner blocks of kInner:
-// the unblocked kernel on the inner diagonal block, the two panel solves
-// restricted to the diagonal block, and a rank-kInner update of its rest (DD at
-// n = 2048: K = 512 170 -> 13.6 ms; up to K = 64 the one-workgroup kernel is
-// as fast or faster).
+// Diagonal blocks wider than kInner are factored in inner blocks of kInner:
+// the unblocked kernel on the inner diagonal block (in LDS), the two panel
+// solves restricted to the diagonal block, and a rank-kInner update of its
+// rest (DD at n = 2048: K = 512 170 -> 13.6 ms, and K = 64 12.0 -> 10.7 ms
+// once blocks of up to kInner were held in LDS).
 constexpr int kInner = 32;
 
 template <typename Num>
 hipError_t lu_panel(double *A, int64_t ld, int64_t plane, int j0, int K, int n, hipStream_t st) {
   const Mat<Num> M{A, ld, plane};
-  if (K <= 2 * kInner) {
+  if (K <= kInner) {
     launch_lu_diag<Num>(M, j0, K, st);
   } else {
     const int end = j0 + K;
@@ -355,17 +394,13 @@ hipError_t lu_panel(double *A, int64_t ld, int64_t plane, int j0, int K, int n, 
       const int kb = std::min(kInner, end - jj), r = end - jj - kb;
       launch_lu_diag<Num>(M, jj, kb, st);
       if (r == 0) break;
-      const dim3 grid((unsigned)ceil_div(r, kSweepWaves));
-      hipLaunchKernelGGL((k_trsm_lower_sweep<Num>), grid, dim3(64 * kSweepWaves), 0, st, M, jj, kb, end);
-      hipLaunchKernelGGL((k_trsm_upper_sweep<Num>), grid, dim3(64 * kSweepWaves), 0, st, M, jj, kb, end);
+      launch_sweeps<Num>(M, jj, kb, end, st);
       hipLaunchKernelGGL((k_rank_update<Num>), dim3(grid_for((int64_t)r * r)), dim3(256), 0, st, M, jj + kb, jj + kb,
                          r, r, jj, kb);
     }
   }
   if (j0 + K < n && K <= kSweepMax) {
-    const dim3 grid((unsigned)ceil_div(n - j0 - K, kSweepWaves));
-    hipLaunchKernelGGL((k_trsm_lower_sweep<Num>), grid, dim3(64 * kSweepWaves), 0, st, M, j0, K, n);
-    hipLaunchKernelGGL((k_trsm_upper_sweep<Num>), grid, dim3(64 * kSweepWaves), 0, st, M, j0, K, n);
+    launch_sweeps<Num>(M, j0, K, n, st);
   } else if (j0 + K < n) {
     hipLaunchKernelGGL((k_trsm_lower<Num>), dim3((unsigned)ceil_div(n - j0 - K, 256)), dim3(256), 0, st, M, j0, K,
                        n);
