@@ -4,8 +4,8 @@
 // and for a product a plain tail at the lowest order kept), sorts them by
 // decreasing magnitude, renormalizes them with `renorm` (mp_device.h:
 // only TwoSum, so the sum is unchanged) and keeps the leading C components.
-// Division takes C + 1 quotient digits, each from the remainder of the
-// previous ones (the remainder formed in a single renormalization).  Must be
+// Division takes C quotient digits, each from the remainder of the previous
+// ones (the remainder formed in a single renormalization).  Must be
 // compiled with -ffp-contract=off (only the explicit fma of TwoProd is fused).
 #pragma once
 
@@ -142,16 +142,19 @@ __device__ __forceinline__ mc<C> mc_sub_scaled(const mc<C> &r, double q, const m
   return mc_from_terms<C, C + 2 * (C - 1) + 1>(t);
 }
 
+// C quotient digits: after them the remainder is near 2^(-53 C) |a|, so the
+// next digit would only move the result by about the rounding of its last
+// component.
 template <int C>
 __device__ __forceinline__ mc<C> mc_div(const mc<C> &a, const mc<C> &b) {
-  double q[C + 1];
+  double q[C];
   mc<C> r = a;
 #pragma unroll
-  for (int d = 0; d <= C; ++d) {
+  for (int d = 0; d < C; ++d) {
     q[d] = r.x[0] / b.x[0];
-    if (d < C) r = mc_sub_scaled<C>(r, q[d], b);
+    if (d < C - 1) r = mc_sub_scaled<C>(r, q[d], b);
   }
-  return mc_from_terms<C, C + 1>(q);
+  return mc_from_terms<C, C>(q);
 }
 
 }  // namespace mp
