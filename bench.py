@@ -114,17 +114,8 @@ def cpu_baseline(n, E, rows_req):
 
 def run_batched(mp, torch, pool, fmt, count=512, seed=31, mode="float"):
     """One graph launch of `count` products with sizes log-uniform in [64, 1024]."""
-    import workload as W
-    m = W.log_uniform_sizes(seed, count, 64, 1024, draw=0)
-    n = W.log_uniform_sizes(seed, count, 64, 1024, draw=1)
-    k = W.log_uniform_sizes(seed, count, 64, 1024, draw=2)
-    offs = W.uniform_int(seed, 5, 0, 2 * count, 0, pool.elements - 1)
-    As, Bs = [], []
-    for i in range(count):
-        ao = int(offs[2 * i]) % (pool.elements - int(m[i] * k[i]))
-        bo = int(offs[2 * i + 1]) % (pool.elements - int(k[i] * n[i]))
-        As.append(pool.operand(fmt, int(m[i]), int(k[i]), ao))
-        Bs.append(pool.operand(fmt, int(k[i]), int(n[i]), bo))
+    from paper_2301_09960_amd import serve
+    As, Bs, m, n, k = serve.batch_operands(pool, fmt, count, seed)
     Cs = mp.gemm_batched(fmt, As, Bs, mode=mode)  # captures the graph
     torch.cuda.synchronize()
     reps = 3

@@ -51,6 +51,7 @@ def lib():
         L.oracle_split_plain_f.argtypes = [_I, _I, _I, _P, _L, _L, _L, _I, _I, _I, _P, _P, _P]
         L.oracle_slice_product.argtypes = [_I, _I, _I, _P, _P, _P, _P, _I, _I, _P]
         L.oracle_gemm_exact_check.argtypes = [_I, _I, _I, _I, _I, _P, _P, _P, _I, _P, _I, _P, _P, _P]
+        L.oracle_gemm_exact_check_many.argtypes = [_I, _I, _I, _I, _I, _P, _P, _I, _P, _I, _P, _I, _P, _P, _P]
         L.oracle_exact_sum.argtypes = [_P, _L, _I, _I, _P]
         L.oracle_ozaki_gemm.argtypes = [_I, _I, _I, _I, _I, _P, _P, _I, _P, _I, _P, _P]
         L.oracle_split_int8.argtypes = [_I, _I, _I, _P, _L, _L, _L, _I, _P, _P]
@@ -181,6 +182,32 @@ def exact_check(A, B, C, rows=None):
     _check(lib().oracle_gemm_exact_check(c, int(f32), m, n, k, _ptr(A), _ptr(B), _ptr(C), ldc, _ptr(rows_arr),
                                          nrows, _ptr(diff), _ptr(absab), _ptr(cex)), "exact_check")
     return diff, absab, cex
+
+
+def exact_check_many(A, B, Cs, rows=None):
+    """``exact_check`` of several results of the same product at once: the
+    exact AB of each listed entry is formed once and compared with every C in
+    ``Cs`` (all of one shape).  Returns ``(diffs, absab, cex)`` with diffs a
+    list of ``(n, nrows)`` arrays, one per C."""
+    A = np.ascontiguousarray(A)
+    B = np.ascontiguousarray(B)
+    Cs = [np.ascontiguousarray(C) for C in Cs]
+    c, k, m = A.shape
+    n = B.shape[1]
+    f32 = A.dtype == np.float32
+    if any(C.shape != Cs[0].shape or C.dtype != A.dtype for C in Cs):
+        raise ValueError("every C must have one shape and the dtype of A")
+    rows_arr = None if rows is None else np.ascontiguousarray(rows, dtype=np.int32)
+    nrows = m if rows is None else len(rows_arr)
+    ldc = Cs[0].shape[2]
+    diff = np.zeros((len(Cs), n, nrows))
+    absab = np.zeros((n, nrows))
+    cex = np.zeros((n, nrows))
+    ptrs = (ctypes.c_void_p * max(1, len(Cs)))(*[C.ctypes.data for C in Cs])
+    _check(lib().oracle_gemm_exact_check_many(c, int(f32), m, n, k, _ptr(A), _ptr(B), len(Cs), ptrs, ldc,
+                                              _ptr(rows_arr), nrows, _ptr(diff), _ptr(absab), _ptr(cex)),
+           "exact_check_many")
+    return list(diff), absab, cex
 
 
 def exact_sum(values, c: int, f32: bool = False) -> np.ndarray:

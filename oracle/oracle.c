@@ -539,29 +539,33 @@ static void sa_to_expansion(sacc *s, double *x, int c, int p, int emin)
 
 /*
  * For the listed rows of C = A B (all rows if rows == NULL, nrows = m):
- *   diff[t + j*nrows] = RN(|C_test - A B|) (exact difference, rounded once),
+ *   diff[u*n*nrows + t + j*nrows] = RN(|C_u - A B|) for each of the nc
+ *                       matrices under test (exact difference, rounded once),
  *   absab[...]        = sum_p |a_ip0| |b_pj0| in binary64 (leading components;
  *                       relative error below (k + 2) 2^-52 of sum |a||b|),
  *   cex[...]          = RN(A B), the exact product rounded once.
- * A: c planes of k x m (col-major), B: c planes of n x k, C_test: c planes of
- * n x ldc.  is_f32 selects binary32 component arrays.
+ * A: c planes of k x m (col-major), B: c planes of n x k, each C_u (Cs[u]): c
+ * planes of n x ldc.  is_f32 selects binary32 component arrays.  The exact
+ * product is formed once per entry and compared with every C_u.
  */
-int oracle_gemm_exact_check(int c, int is_f32, int m, int n, int k, const void *Av, const void *Bv, const void *Cv,
-                            int ldc, const int *rows, int nrows, double *diff, double *absab, double *cex)
+int oracle_gemm_exact_check_many(int c, int is_f32, int m, int n, int k, const void *Av, const void *Bv, int nc,
+                                 const void *const *Cs, int ldc, const int *rows, int nrows, double *diff,
+                                 double *absab, double *cex)
 {
-    if (c < 1 || c > ORC_MAXC || m < 0 || n < 0 || k < 0)
+    if (c < 1 || c > ORC_MAXC || m < 0 || n < 0 || k < 0 || nc < 0 || (nc > 0 && (!Cs || !diff)))
         return ORC_EINVAL;
     const long pa = (long)m * k, pb = (long)k * n, pc = (long)ldc * n;
     int status = ORC_OK;
 #pragma omp parallel
     {
         sacc *s = malloc(sizeof(sacc));
-        if (!s)
+        sacc *w = malloc(sizeof(sacc));
+        if (!s || !w)
             status = ORC_ENOMEM;
 #pragma omp for schedule(dynamic, 1) collapse(2)
         for (int t = 0; t < nrows; ++t) {
             for (int j = 0; j < n; ++j) {
-                if (!s)
+                if (!s || !w)
                     continue;
                 int i = rows ? rows[t] : t;
                 sa_clear(s);
@@ -587,22 +591,34 @@ int oracle_gemm_exact_check(int c, int is_f32, int m, int n, int k, const void *
                 sa_norm(s);
                 if (cex)
                     cex[t + (long)j * nrows] = sa_round(s, 53, -1074);
-                if (diff) {
+                for (int u = 0; u < nc; ++u) {
+                    const void *Cv = Cs[u];
+                    *w = *s;
                     for (int r = 0; r < c; ++r) {
                         double cv = is_f32 ? (double)((const float *)Cv)[r * pc + i + (long)j * ldc]
                                            : ((const double *)Cv)[r * pc + i + (long)j * ldc];
-                        sa_add(s, -cv);
+                        sa_add(w, -cv);
                     }
-                    sa_norm(s);
-                    diff[t + (long)j * nrows] = fabs(sa_round(s, 53, -1074));
+                    sa_norm(w);
+                    diff[(long)u * n * nrows + t + (long)j * nrows] = fabs(sa_round(w, 53, -1074));
                 }
                 if (absab)
                     absab[t + (long)j * nrows] = ab;
             }
         }
         free(s);
+        free(w);
     }
     return status;
+}
+
+/* The single-matrix form: diff (if not NULL) for C_test = Cv. */
+int oracle_gemm_exact_check(int c, int is_f32, int m, int n, int k, const void *Av, const void *Bv, const void *Cv,
+                            int ldc, const int *rows, int nrows, double *diff, double *absab, double *cex)
+{
+    const void *cs[1] = {Cv};
+    return oracle_gemm_exact_check_many(c, is_f32, m, n, k, Av, Bv, diff ? 1 : 0, cs, ldc, rows, nrows, diff, absab,
+                                        cex);
 }
 
 /* Exact sum of a list of binary64 values, returned as a c-term greedy expansion. */

@@ -11,6 +11,9 @@ Tensor conventions (component-planar, column-major planes):
     B (k x n)  -> tensor of shape (c, n, k)
     C (m x n)  -> tensor of shape (c, n, m)
 with c = 2 (DD), 3 (TD), 4 (QD) float64 components, or 3 float32 (TS).
+``gemm``, ``certify`` and ``gemm_batched`` also take views ``X[:, :, :rows]``
+of a (c, cols, ld) buffer: the buffer's ld is passed as the leading dimension
+(planes ld * cols elements apart), and C's rows beyond m are left untouched.
 Row-major users get C^T = B^T A^T by swapping operands.
 """
 from __future__ import annotations
@@ -139,6 +142,28 @@ def _check_tensor(t, c, dtype, name):
         raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+
+
+def _planes_ld(t, c, dtype, name) -> int:
+    """Leading dimension of a (c, cols, rows) tensor of column-major component
+    planes: a contiguous tensor has ld = rows; a view ``X[:, :, :rows]`` of a
+    contiguous (c, cols, ld) buffer (strides (ld * cols, ld, 1), ld >= rows)
+    passes its buffer's ld, as the C-ABI's plane addressing expects."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dim() != 3 or t.shape[0] != c:
+        raise ValueError(f"{name} must have shape (c={c}, cols, rows), got {tuple(t.shape)}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    cols, rows = t.shape[1], t.shape[2]
+    if t.is_contiguous():
+        return max(1, rows)
+    s0, s1, s2 = t.stride()
+    if s2 != 1 or s1 < max(1, rows) or (c > 1 and s0 != s1 * cols):
+        raise ValueError(f"{name}: planes must be column-major with plane stride ld * cols "
+                         f"(strides (ld * {cols}, ld, 1)), got strides {t.stride()}")
+    return s1
 
 
 def set_mode(fmt, mode):
@@ -278,22 +303,20 @@ def gemm(fmt, A, B, C=None, *, mode=None, slices=None, stream=None):
     name = [k for k, v in FORMATS.items() if v == f][0]
     c = COMPONENTS[name]
     dtype = torch.float32 if name == "ts" else torch.float64
-    _check_tensor(A, c, dtype, "A")
-    _check_tensor(B, c, dtype, "B")
+    lda = _planes_ld(A, c, dtype, "A")
+    ldb = _planes_ld(B, c, dtype, "B")
     k, m = A.shape[1], A.shape[2]
     n, kb = B.shape[1], B.shape[2]
     if kb != k:
         raise ValueError(f"inner dimensions differ: A has k={k}, B has k={kb}")
     if C is None:
         C = torch.empty((c, n, m), dtype=dtype, device=A.device)
-    else:
-        _check_tensor(C, c, dtype, "C")
-        if tuple(C.shape) != (c, n, m):
-            raise ValueError(f"C must have shape {(c, n, m)}")
+    if tuple(C.shape) != (c, n, m):
+        raise ValueError(f"C must have shape {(c, n, m)}")
+    ldc = _planes_ld(C, c, dtype, "C")
     fn = getattr(lib(), "mpgemm_" + name)
     with _options(f, None if mode is None else _mode(mode), slices):
-        st = fn(m, n, k, _P(A.data_ptr()), max(1, m), _P(B.data_ptr()), max(1, k), _P(C.data_ptr()), max(1, m),
-                _stream(stream))
+        st = fn(m, n, k, _P(A.data_ptr()), lda, _P(B.data_ptr()), ldb, _P(C.data_ptr()), ldc, _stream(stream))
     _check(st, "mpgemm_" + name)
     return C
 
@@ -312,19 +335,22 @@ def certify(fmt, A, B, C=None, *, mode="float", slices=None, stream=None):
     name = [k for k, v in FORMATS.items() if v == f][0]
     c = COMPONENTS[name]
     dtype = torch.float32 if name == "ts" else torch.float64
-    _check_tensor(A, c, dtype, "A")
-    _check_tensor(B, c, dtype, "B")
+    lda = _planes_ld(A, c, dtype, "A")
+    ldb = _planes_ld(B, c, dtype, "B")
     k, m = A.shape[1], A.shape[2]
     n, kb = B.shape[1], B.shape[2]
     if kb != k:
         raise ValueError(f"inner dimensions differ: A has k={k}, B has k={kb}")
     if C is None:
         C = torch.empty((c, n, m), dtype=dtype, device=A.device)
+    if tuple(C.shape) != (c, n, m):
+        raise ValueError(f"C must have shape {(c, n, m)}")
+    ldc = _planes_ld(C, c, dtype, "C")
     cert = torch.empty((2, n, m), dtype=torch.float64, device=A.device)
     worst = torch.empty((1,), dtype=torch.float64, device=A.device)
     with _options(f, _mode(mode), slices):
-        st = lib().mpgemm_certify(f, m, n, k, _P(A.data_ptr()), max(1, m), _P(B.data_ptr()), max(1, k),
-                                  _P(C.data_ptr()), max(1, m), _P(cert.data_ptr()), _P(worst.data_ptr()),
+        st = lib().mpgemm_certify(f, m, n, k, _P(A.data_ptr()), lda, _P(B.data_ptr()), ldb,
+                                  _P(C.data_ptr()), ldc, _P(cert.data_ptr()), _P(worst.data_ptr()),
                                   _stream(stream))
     _check(st, "mpgemm_certify")
     return C, cert, worst
@@ -421,10 +447,10 @@ def gemm_batched(fmt, As, Bs, Cs=None, *, mode=None, slices=None, stream=None):
     count = len(As)
     if len(Bs) != count or (Cs is not None and len(Cs) != count):
         raise ValueError("As, Bs and Cs must have the same length")
-    ms, ns, ks = [], [], []
+    ms, ns, ks, ldas, ldbs, ldcs = [], [], [], [], [], []
     for i, (A, B) in enumerate(zip(As, Bs)):
-        _check_tensor(A, c, dtype, f"A[{i}]")
-        _check_tensor(B, c, dtype, f"B[{i}]")
+        ldas.append(_planes_ld(A, c, dtype, f"A[{i}]"))
+        ldbs.append(_planes_ld(B, c, dtype, f"B[{i}]"))
         if B.shape[2] != A.shape[1]:
             raise ValueError(f"product {i}: inner dimensions differ")
         ms.append(A.shape[2])
@@ -433,14 +459,16 @@ def gemm_batched(fmt, As, Bs, Cs=None, *, mode=None, slices=None, stream=None):
     if Cs is None:
         Cs = [torch.empty((c, n, m), dtype=dtype, device=A.device) for A, m, n in zip(As, ms, ns)]
     for i, Cm in enumerate(Cs):
-        _check_tensor(Cm, c, dtype, f"C[{i}]")
+        if tuple(Cm.shape) != (c, ns[i], ms[i]):
+            raise ValueError(f"C[{i}] must have shape {(c, ns[i], ms[i])}")
+        ldcs.append(_planes_ld(Cm, c, dtype, f"C[{i}]"))
     IA = ctypes.c_int * max(count, 1)
     PA = ctypes.c_void_p * max(count, 1)
     fn = getattr(lib(), f"mpgemm_{name}_batched")
     with _options(f, None if mode is None else _mode(mode), slices):
-        st = fn(count, IA(*ms), IA(*ns), IA(*ks), PA(*[A.data_ptr() for A in As]), IA(*[max(1, m) for m in ms]),
-                PA(*[B.data_ptr() for B in Bs]), IA(*[max(1, k) for k in ks]), PA(*[Cm.data_ptr() for Cm in Cs]),
-                IA(*[max(1, m) for m in ms]), _stream(stream))
+        st = fn(count, IA(*ms), IA(*ns), IA(*ks), PA(*[A.data_ptr() for A in As]), IA(*ldas),
+                PA(*[B.data_ptr() for B in Bs]), IA(*ldbs), PA(*[Cm.data_ptr() for Cm in Cs]), IA(*ldcs),
+                _stream(stream))
     _check(st, f"mpgemm_{name}_batched")
     return Cs
 

@@ -114,6 +114,27 @@ class DevicePool:
         return P[:, offset:offset + rows * cols].reshape(P.shape[0], cols, rows).contiguous()
 
 
+def batch_operands(pool: DevicePool, fmt: str, count: int = 512, seed: int = 31, lo: int = 64, hi: int = 1024,
+                   first: int = 0):
+    """Operands of a batch of ``count`` independent products with m, n, k each
+    log-uniform in [lo, hi] (seeded), sliced out of the pool at seeded
+    offsets.  Products ``first .. first + count - 1`` of the seed's sequence.
+    Returns ``(As, Bs, m, n, k)`` (device tensors and integer arrays)."""
+    from workload import log_uniform_sizes, uniform_int
+    total = first + count
+    m = log_uniform_sizes(seed, total, lo, hi, draw=0)[first:]
+    n = log_uniform_sizes(seed, total, lo, hi, draw=1)[first:]
+    k = log_uniform_sizes(seed, total, lo, hi, draw=2)[first:]
+    offs = uniform_int(seed, 5, 0, 2 * total, 0, pool.elements - 1)[2 * first:]
+    As, Bs = [], []
+    for i in range(count):
+        ao = int(offs[2 * i]) % (pool.elements - int(m[i] * k[i]))
+        bo = int(offs[2 * i + 1]) % (pool.elements - int(k[i] * n[i]))
+        As.append(pool.operand(fmt, int(m[i]), int(k[i]), ao))
+        Bs.append(pool.operand(fmt, int(k[i]), int(n[i]), bo))
+    return As, Bs, m, n, k
+
+
 class Server:
     """Admits requests under an HBM budget onto a fixed set of streams."""
 

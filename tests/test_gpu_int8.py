@@ -109,22 +109,6 @@ def test_int8_zero_rows_and_chunking(mp, orc):
     assert ok
 
 
-@pytest.mark.parametrize("fmt,E,rows", [("dd", 16, [0, 4095]), ("qd", 16, [1234]), ("td", 16, [99]),
-                                        ("qd", 0, [4000]), ("dd", 0, [1])])
-def test_int8_full_size_sampled(mp, orc, fmt, E, rows):
-    """The same n = 4096 products as the binary64-slice form (e ~ U{0..16} and
-    e ~ U{0..0}), in the INT8 form: sampled rows against the exact product."""
-    n = 4096
-    A, B = W.gen_pair(fmt, n, n, n, E=E, seed=4096 + E)
-    say(f"int8 full {fmt} n={n} E={E}")
-    C = host(mp.gemm(fmt, dev(A), dev(B), mode="int8"))
-    say(f"  D={mp.last_num_slices()}")
-    diff, absab, _ = orc.exact_check(A, B, np.ascontiguousarray(C), rows=rows)
-    ok, worst = orc.bound_report(diff, absab, T_BITS[fmt])
-    say(f"  worst log2 ratio {worst:.1f}")
-    assert ok
-
-
 @pytest.mark.parametrize("cfg", [1, 2, 3, 4])
 def test_int8_every_tile_config(mp, orc, cfg):
     """Each INT8 tile configuration gives the exact diagonal sums and a C within

@@ -263,39 +263,6 @@ def test_attached_workspace(mp):
     assert np.array_equal(C1, C2)
 
 
-@pytest.mark.parametrize("fmt,rows", [("dd", [0, 1111, 4095]), ("qd", [5, 2048]), ("ts", [17, 4000])])
-def test_full_size_sampled(mp, orc, fmt, rows):
-    """n = 4096 (the benchmark's size and launch path), E = 16: sampled rows of C
-    against the exact product."""
-    n = 4096
-    A, B = W.gen_pair(fmt, n, n, n, E=16, seed=4096)
-    say(f"full {fmt} n={n} rows={rows}")
-    C = host(mp.gemm(fmt, dev(A), dev(B)))
-    say(f"  D={mp.last_num_slices()}")
-    ok, worst = _check_bound(orc, fmt, A, B, np.ascontiguousarray(C), rows=rows)
-    say(f"  worst log2 ratio {worst:.1f} (bound -{T_BITS[fmt]})")
-    assert ok
-
-
-@pytest.mark.parametrize("fmt,n,E,rows", [
-    ("td", 4096, 16, [3, 3000]),
-    ("ts", 4096, 0, [100]),
-    ("dd", 2048, 0, [0, 2047]),
-    ("qd", 2048, 16, [777]),
-    ("td", 1024, 0, [512]),
-    ("qd", 1024, 0, [0, 1023]),
-])
-def test_square_grid_sampled(mp, orc, fmt, n, E, rows):
-    """The square products of the benchmark grid (n in {1024, 2048, 4096},
-    e ~ U{0..E} with E in {0, 16}): sampled rows of C against the exact product."""
-    A, B = W.gen_pair(fmt, n, n, n, E=E, seed=n + E)
-    say(f"grid {fmt} n={n} E={E} rows={rows}")
-    C = host(mp.gemm(fmt, dev(A), dev(B)))
-    ok, worst = _check_bound(orc, fmt, A, B, np.ascontiguousarray(C), rows=rows)
-    say(f"  D={mp.last_num_slices()} worst log2 ratio {worst:.1f} (bound -{T_BITS[fmt]})")
-    assert ok
-
-
 @pytest.mark.parametrize("layout", [1, 2, 3])
 @pytest.mark.parametrize("fmt", ["dd", "qd", "ts"])
 def test_every_tile_layout(mp, orc, fmt, layout):

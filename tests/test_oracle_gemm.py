@@ -49,6 +49,40 @@ def test_exact_check_against_fractions(orc, fmt):
             assert abs(Fraction(absab[j, i]) - ab) <= ab * Fraction(2) ** -48
 
 
+@pytest.mark.parametrize("fmt", ["dd", "qd", "ts"])
+def test_exact_check_many_against_fractions(orc, fmt):
+    """Several results compared with one exact product: each difference equals
+    the rational |C_u - AB| rounded once, on a subset of rows (the row index
+    must map to the right row of every C), and an exactly rounded C_u gives
+    the rational rounding error of its own components."""
+    m, n, k = 5, 3, 7
+    A, B = W.gen_pair(fmt, m, n, k, E=16, seed=9)
+    c = A.shape[0]
+    Cf = X.matmul_fraction(A, B)
+    Cs = []
+    for u in range(3):
+        C = np.zeros((c, n, m), dtype=A.dtype)
+        for i in range(m):
+            for j in range(n):
+                C[0, j, i] = float(Cf[i][j]) * (1 + u * 2.0 ** -20) + u * (i - j)
+                if c > 1 and u == 1:
+                    C[1, j, i] = 2.0 ** -30 * (i + 1)
+        Cs.append(C)
+    rows = [4, 0, 2]
+    diffs, absab, cex = orc.exact_check_many(A, B, Cs, rows=rows)
+    assert len(diffs) == 3
+    for u, C in enumerate(Cs):
+        for t, i in enumerate(rows):
+            for j in range(n):
+                got = sum(Fraction(float(C[r, j, i])) for r in range(c))
+                assert diffs[u][j, t] == float(abs(got - Cf[i][j])), (u, i, j)
+                assert cex[j, t] == float(Cf[i][j])
+    # the same arrays as the single-matrix form, entry for entry
+    for u, C in enumerate(Cs):
+        d1, a1, _ = orc.exact_check(A, B, C, rows=rows)
+        assert np.array_equal(d1, diffs[u]) and np.array_equal(a1, absab)
+
+
 def test_slice_product_exact_non_square(orc):
     """C_ab from exact int64 dot products equals the rational product (a 5x3 times 3x7
     shape, so a transposed operand cannot pass)."""
