@@ -358,6 +358,26 @@ int mpgemm_nd_debug_split(int c, int operand, int rows, int cols, const double *
 int mpgemm_nd_debug_products(int c, int m, int n, int k, const double *A, int lda, const double *B, int ldb, int D,
                              int g, int64_t *out, int ldo, hipStream_t stream);
 
+/*
+ * mpgemm_dd without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same product as mpgemm_dd (the thread's slice form
+ * and slice count, the same kernels, the same C bit for bit), with its
+ * workspace in a fixed device array of MPGEMM_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each device it runs on until the process ends.  A shape
+ * whose workspace (mpgemm_workspace_bytes(MPGEMM_DD, mode, m, n, k, 0)) exceeds
+ * it returns MPGEMM_ERR_TOO_LARGE without enqueuing work (for example
+ * m = n = k = 1024 needs 128 MiB with binary64 slices).  Every call on a device
+ * shares that device's array: calls that overlap on one device (on different
+ * streams, or from different threads) race and must be serialized by the
+ * caller; calls queued on one stream are ordered and safe.  The first call on
+ * each device looks up the array's address (hipGetSymbolAddress) and keeps it.
+ * Argument codes as mpgemm_dd.
+ */
+#define MPGEMM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int mpgemm_dd_noalloc(int m, int n, int k, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+                      hipStream_t stream);
+
 /* Text for a return code. */
 const char *mpgemm_status_string(int status);
 

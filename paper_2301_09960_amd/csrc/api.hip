@@ -416,6 +416,33 @@ hipError_t gemm_launch(const Plan &p, char *base, int m, int n, int k, T *Cout, 
   return hipErrorInvalidValue;
 }
 
+// The launch sequence of one product (split, then the fused slice products
+// and accumulation) on the workspace at `base`, laid out by plan p.  With
+// `profile`, records the thread's stage-timing events if they are enabled.
+template <typename T, int C>
+hipError_t launch_product(const Plan &p, char *base, int m, int n, int k, const T *A, int lda, const T *B, int ldb,
+                          T *Cm, int ldc, bool profile, hipStream_t st) {
+  const SplitOperand<T> a = operand_a(A, m, k, lda, p, base), b = operand_b(B, k, n, ldb, p, base);
+  const bool prof = profile && g_prof.on;
+  std::array<hipEvent_t, 3> ev{nullptr, nullptr, nullptr};
+  if (prof) {
+    for (auto &x : ev) x = g_prof.take();
+    if (ev[0]) (void)hipEventRecord(ev[0], st);
+  }
+  hipError_t e = split_both<T, C>(a, b, p, st);
+  if (ev[1]) (void)hipEventRecord(ev[1], st);
+  if (e == hipSuccess) e = gemm_launch<T, C>(p, base, m, n, k, Cm, ldc, -1, nullptr, 0, st);
+  if (ev[2]) (void)hipEventRecord(ev[2], st);
+  if (prof) {
+    if (ev[0] && ev[1] && ev[2])
+      g_prof.marks.push_back(ev);
+    else
+      for (auto x : ev)
+        if (x) g_prof.pool.push_back(x);
+  }
+  return e;
+}
+
 // One product in the given form with D slices (arguments already validated).
 template <typename T, int C>
 int run_with(int fmt, int mode, int D, int m, int n, int k, const T *A, int lda, const T *B, int ldb, T *Cm, int ldc,
@@ -427,24 +454,52 @@ int run_with(int fmt, int mode, int D, int m, int n, int k, const T *A, int lda,
   const Plan p = make_plan(fmt, mode, m, n, k, D);
   Workspace ws;
   if ((s = acquire(ws, p.total, st))) return s;
-  const SplitOperand<T> a = operand_a(A, m, k, lda, p, ws.base), b = operand_b(B, k, n, ldb, p, ws.base);
-  std::array<hipEvent_t, 3> ev{nullptr, nullptr, nullptr};
-  if (g_prof.on) {
-    for (auto &x : ev) x = g_prof.take();
-    if (ev[0]) (void)hipEventRecord(ev[0], st);
+  return hip_status(launch_product<T, C>(p, ws.base, m, n, k, A, lda, B, ldb, Cm, ldc, true, st));
+}
+
+// Scratch of the allocation-free DD entry point: a fixed device array, one
+// copy per device, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the symbol):
+// its device address is looked up once per device with hipGetSymbolAddress
+// and that address is what the kernels receive.
+constexpr size_t kScratchBytes = MPGEMM_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[64] = {};
+
+int scratch_of_current_device(char **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return MPGEMM_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return MPGEMM_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = static_cast<char *>(ptr);
   }
-  hipError_t e = split_both<T, C>(a, b, p, st);
-  if (ev[1]) (void)hipEventRecord(ev[1], st);
-  if (e == hipSuccess) e = gemm_launch<T, C>(p, ws.base, m, n, k, Cm, ldc, -1, nullptr, 0, st);
-  if (ev[2]) (void)hipEventRecord(ev[2], st);
-  if (g_prof.on) {
-    if (ev[0] && ev[1] && ev[2])
-      g_prof.marks.push_back(ev);
-    else
-      for (auto x : ev)
-        if (x) g_prof.pool.push_back(x);
-  }
-  return hip_status(e);
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+
+// mpgemm_dd with its workspace in the device's scratch array instead of an
+// allocation: the same plan and kernels, so the same result bit for bit.
+int run_dd_noalloc(int m, int n, int k, const double *A, int lda, const double *B, int ldb, double *Cm, int ldc,
+                   hipStream_t st) {
+  int s = validate(m, n, k, A, lda, B, ldb, Cm, ldc);
+  if (s) return s;
+  if ((s = check_device_cached())) return s;
+  const int mode = g_opt.mode[MPGEMM_DD];
+  const int D = slices_for(MPGEMM_DD, mode, k);
+  g_opt.last_slices = D;
+  if (m == 0 || n == 0) return 0;
+  if (k == 0) return hip_status(launch_zero_matrix(Cm, sizeof(double), 2, m, n, ldc, (int64_t)ldc * n, st));
+  const Plan p = make_plan(MPGEMM_DD, mode, m, n, k, D);
+  if (p.total > kScratchBytes) return MPGEMM_ERR_TOO_LARGE;
+  char *base = nullptr;
+  if ((s = scratch_of_current_device(&base))) return s;
+  return hip_status(launch_product<double, 2>(p, base, m, n, k, A, lda, B, ldb, Cm, ldc, false, st));
 }
 
 template <typename T, int C>
@@ -725,6 +780,10 @@ extern "C" {
 int mpgemm_dd(int m, int n, int k, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
               hipStream_t stream) {
   return run<double, 2>(MPGEMM_DD, m, n, k, A, lda, B, ldb, C, ldc, stream);
+}
+int mpgemm_dd_noalloc(int m, int n, int k, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
+                      hipStream_t stream) {
+  return run_dd_noalloc(m, n, k, A, lda, B, ldb, C, ldc, stream);
 }
 int mpgemm_td(int m, int n, int k, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
               hipStream_t stream) {
