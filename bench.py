@@ -52,7 +52,7 @@ def log(msg):
 
 
 def parse():
-    ap = argparse.ArgumentParser()
+    ap = argparse.ArgumentParser(epilog=MODES_HELP, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -68,7 +68,41 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows of C in the CPU sample (0: auto)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 1 GiB (for scaling HBM counters)")
+    # other measurement modes (each prints its own lines and exits)
+    ap.add_argument("--sweep", choices=("grid", "nd", "simple"), default="",
+                    help="grid: the square grid of products; nd: longer expansions; "
+                         "simple: the simple in-format products against the Ozaki products")
+    ap.add_argument("--sizes", default="", help="sweep sizes, comma separated")
+    ap.add_argument("--reps", type=int, default=3, help="sweep repetitions per case")
+    ap.add_argument("--traffic", action="store_true", help="summarize two rocprofv3 --pmc runs (no GPU)")
+    ap.add_argument("--fetch", help="rocprofv3 -d folder of the FETCH_SIZE run")
+    ap.add_argument("--write", help="rocprofv3 -d folder of the WRITE_SIZE run")
+    ap.add_argument("--kernel", help="substring of the kernel's name")
+    ap.add_argument("--label", default="", help="name written into the summary (default: --kernel)")
+    ap.add_argument("--algorithmic-bytes", type=float)
+    ap.add_argument("--source", help="the kernel's source file (hashed)")
+    ap.add_argument("--command", action="append", default=[], help="command of a run, recorded as given")
+    ap.add_argument("--out", default="")
     return ap.parse_args()
+
+
+MODES_HELP = """measurement modes besides the benchmark line:
+  python bench.py --sweep grid [--sizes 1024,2048,4096] [--reps 3]
+      square products n x {DD, TD, QD} x e ~ U{0..0}, U{0..16} (binary64
+      slices), TS at the largest n, the INT8 form at the largest n: one JSON
+      line per case with split / slice-product milliseconds from the library's
+      own HIP events on the launch stream
+  python bench.py --sweep nd [--sizes 1024,2048]
+      longer binary64 expansions (4 .. 14 components), INT8 form
+  python bench.py --sweep simple [--sizes 512,1024,...,4096]
+      the simple in-format products (DD, TS, D+S; with and without LDS
+      staging; Section 4.4) beside the Ozaki products of the same inputs
+  python bench.py --traffic --fetch DIR1 --write DIR2 --kernel NAME
+      --algorithmic-bytes B --source FILE [--out traffic.json]
+      HBM bytes per launch of one kernel from two rocprofv3 --pmc runs
+      (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by what the
+      counter reads for the plain 1 GiB copies of --copy-calibration
+"""
 
 
 def source_hash(path):
@@ -145,8 +179,195 @@ def run_batched(mp, torch, pool, fmt, count=512, seed=31, mode="float"):
     }
 
 
+# ---------------------------------------------------------------------------
+# sweeps (--sweep)
+# ---------------------------------------------------------------------------
+
+SWEEP_PEAK = {"float64": FP64_MFMA_PEAK_TFLOPS, "float32": FP32_MFMA_PEAK_TFLOPS, "int8": INT8_MFMA_PEAK_TOPS}
+
+
+def _timed_calls(torch, mp, call, reps):
+    """Median split and GEMM milliseconds of `reps` calls (library events)."""
+    call()
+    torch.cuda.synchronize()
+    mp.profile_enable(True)
+    for _ in range(reps):
+        call()
+    torch.cuda.synchronize()
+    mp.profile_enable(False)
+    sp, gm = mp.profile_read()
+    return float(np.median(sp)), float(np.median(gm))
+
+
+def _event_ms(torch, call, reps):
+    """Median milliseconds of `reps` calls, HIP events on the current stream."""
+    call()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        call()
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return float(np.median(out))
+
+
+def sweep_grid(torch, mp, sizes, reps):
+    import workload as W
+    cases = [(f, n, E, "float") for n in sizes for f in ("dd", "td", "qd") for E in (0, 16)]
+    big = max(sizes)
+    cases += [("ts", big, E, "float") for E in (0, 16)]
+    cases += [(f, big, E, "int8") for f in ("dd", "td", "qd") for E in (0, 16)]
+    for fmt, n, E, mode in cases:
+        A, B = W.gen_pair(fmt, n, n, n, E=E, seed=n + E)
+        dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        del A, B
+        C = torch.empty((W.FORMATS[fmt][0], n, n), dtype=dA.dtype, device="cuda")
+        split_ms, gemm_ms = _timed_calls(torch, mp, lambda: mp.gemm(fmt, dA, dB, C, mode=mode), reps)
+        D = mp.last_num_slices()
+        ops = D * (D + 1) / 2 * 2.0 * n ** 3
+        kind = "int8" if mode == "int8" else ("float32" if fmt == "ts" else "float64")
+        rate = ops / (gemm_ms * 1e-3) / 1e12
+        print(json.dumps({
+            "fmt": fmt, "n": n, "E": E, "mode": mode, "D": D,
+            "split_ms": round(split_ms, 3), "gemm_ms": round(gemm_ms, 3),
+            "effective_gflops": round(2.0 * n ** 3 / ((split_ms + gemm_ms) * 1e-3) / 1e9, 1),
+            "slice_rate": round(rate, 2), "slice_rate_unit": "TOP/s" if mode == "int8" else "TFLOP/s",
+            "peak_frac": round(rate / SWEEP_PEAK[kind], 4)}), flush=True)
+        del dA, dB, C
+
+
+def sweep_nd(torch, mp, sizes, reps, E=16):
+    import workload as W
+    for n in sizes:
+        for c in (4, 5, 6, 8, 10, 12, 14):
+            fmt = f"{c}d" if c > 4 else {2: "dd", 3: "td", 4: "qd"}[c]
+            A, B = W.gen_pair(fmt, n, n, n, E=E, seed=n + c)
+            dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+            del A, B
+            C = torch.empty((c, n, n), dtype=torch.float64, device="cuda")
+            split_ms, gemm_ms = _timed_calls(torch, mp, lambda: mp.gemm_nd(dA, dB, C), reps)
+            D = mp.nd_num_slices(c, n)
+            ops = D * (D + 1) / 2 * 2.0 * n ** 3
+            print(json.dumps({
+                "components": c, "bits": 53 * c, "n": n, "E": E, "mode": "int8", "D": D,
+                "split_ms": round(split_ms, 3), "gemm_ms": round(gemm_ms, 3),
+                "effective_gflops": round(2.0 * n ** 3 / ((split_ms + gemm_ms) * 1e-3) / 1e9, 1),
+                "slice_rate": round(ops / (gemm_ms * 1e-3) / 1e12, 2), "slice_rate_unit": "TOP/s",
+                "peak_frac": round(ops / (gemm_ms * 1e-3) / 1e12 / INT8_MFMA_PEAK_TOPS, 4)}), flush=True)
+            del dA, dB, C
+
+
+def sweep_simple(torch, mp, sizes, reps, E=16):
+    """Section 4.4's GPU comparison at square n: the simple in-format products
+    of DD, TS and D+S with and without LDS staging, and the Ozaki products of
+    the same inputs (DD and TS with binary64 / binary32 slices, DD with INT8
+    slices, D+S through the DD product), milliseconds per call (HIP events)."""
+    import workload as W
+    for n in sizes:
+        rows = []
+        for fmt in ("dd", "ts"):
+            A, B = W.gen_pair(fmt, n, n, n, E=E, seed=n + E)
+            dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+            del A, B
+            C = torch.empty((W.FORMATS[fmt][0], n, n), dtype=dA.dtype, device="cuda")
+            for staging in (1, 0):
+                ms = _event_ms(torch, lambda: mp.simple(fmt, dA, dB, C, staging=staging), reps)
+                rows.append({"fmt": fmt, "method": "simple", "lds": bool(staging), "ms": ms})
+            ms = _event_ms(torch, lambda: mp.gemm(fmt, dA, dB, C, mode="float"), reps)
+            rows.append({"fmt": fmt, "method": "ozaki", "mode": "float", "D": mp.last_num_slices(), "ms": ms})
+            if fmt == "dd":
+                ms = _event_ms(torch, lambda: mp.gemm(fmt, dA, dB, C, mode="int8"), reps)
+                rows.append({"fmt": fmt, "method": "ozaki", "mode": "int8", "D": mp.last_num_slices(), "ms": ms})
+            del dA, dB, C
+        Ahi, Alo = W.gen_ds(n, n, E=E, seed=n + E, operand="A")
+        Bhi, Blo = W.gen_ds(n, n, E=E, seed=n + E, operand="B")
+        d = [torch.from_numpy(x).cuda() for x in (Ahi, Alo, Bhi, Blo)]
+        Chi = torch.empty((1, n, n), dtype=torch.float64, device="cuda")
+        Clo = torch.empty((1, n, n), dtype=torch.float32, device="cuda")
+        for staging in (1, 0):
+            ms = _event_ms(torch, lambda: mp.ds_simple(*d, Chi, Clo, staging=staging), reps)
+            rows.append({"fmt": "ds", "method": "simple", "lds": bool(staging), "ms": ms})
+        ms = _event_ms(torch, lambda: mp.ds_gemm(*d, Chi, Clo), reps)
+        rows.append({"fmt": "ds", "method": "ozaki", "mode": "float", "D": mp.last_num_slices(), "ms": ms})
+        del d, Chi, Clo
+        for r in rows:
+            r["n"] = n
+            r["ms"] = round(r["ms"], 3)
+            r["effective_gflops"] = round(2.0 * n ** 3 / (r["ms"] * 1e-3) / 1e9, 1)
+            print(json.dumps(r), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# HBM traffic from rocprofv3 counters (--traffic)
+# ---------------------------------------------------------------------------
+
+COPY_KERNEL = "copyBuffer"
+GIB_KIB = 1 << 20
+
+
+def counter_values(folder, counter):
+    """{kernel name: [counter value per dispatch]} from every counter CSV below `folder`."""
+    import csv
+    import glob
+    per = {}
+    for path in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+        with open(path, newline="") as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                key = (r["Kernel_Name"], r["Dispatch_Id"])
+                per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    out = {}
+    for (name, _), v in per.items():
+        out.setdefault(name, []).append(v)
+    return out
+
+
+def traffic_summary(fetch_dir, write_dir, kernel, algorithmic_bytes, source, label, commands=()):
+    """HBM bytes per launch of `kernel`: each counter's mean per dispatch,
+    scaled by 1 GiB over what the counter reads for a plain 1 GiB copy."""
+    def mean_of(values, sub):
+        vals = [v for name, vs in values.items() if sub in name for v in vs]
+        if not vals:
+            raise SystemExit(f"no dispatch of a kernel matching {sub!r}")
+        return sum(vals) / len(vals)
+
+    def copy_reading(values):
+        vals = [v for name, vs in values.items() if COPY_KERNEL in name for v in vs if v >= GIB_KIB / 4]
+        if not vals:
+            raise SystemExit("no 1 GiB copy dispatch found (run the command with --copy-calibration)")
+        return sum(vals) / len(vals)
+
+    fv, wv = counter_values(fetch_dir, "FETCH_SIZE"), counter_values(write_dir, "WRITE_SIZE")
+    fk, wk = mean_of(fv, kernel), mean_of(wv, kernel)
+    cf, cw = copy_reading(fv), copy_reading(wv)
+    ff, wf = GIB_KIB / cf, GIB_KIB / cw
+    fb, wb = fk * 1024 * ff, wk * 1024 * wf
+    return {
+        "kernel": label, "kernel_match": kernel, "source_sha256_16": source_hash(source),
+        "fetch_kib_counter": fk, "write_kib_counter": wk,
+        "copy_fetch_kib_per_gib": cf, "copy_write_kib_per_gib": cw,
+        "fetch_factor": ff, "write_factor": wf, "fetch_bytes": fb, "write_bytes": wb,
+        "bytes_per_launch": fb + wb, "algorithmic_bytes": algorithmic_bytes, "commands": list(commands),
+    }
+
+
 def main():
     args = parse()
+    if args.traffic:
+        if not (args.fetch and args.write and args.kernel and args.source and args.algorithmic_bytes):
+            raise SystemExit("--traffic needs --fetch, --write, --kernel, --algorithmic-bytes and --source")
+        summ = traffic_summary(args.fetch, args.write, args.kernel, args.algorithmic_bytes, args.source,
+                               args.label or args.kernel, args.command)
+        text = json.dumps(summ, indent=1)
+        if args.out:
+            with open(args.out, "w") as f:
+                f.write(text + "\n")
+        print(text)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path.",
               file=sys.stderr)
@@ -160,6 +381,11 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     mp.lib()
     torch.cuda.set_device(0)
+    if args.sweep:
+        default = {"grid": "1024,2048,4096", "nd": "1024,2048", "simple": "512,1024,1536,2048,2560,3072,3584,4096"}
+        sizes = [int(x) for x in (args.sizes or default[args.sweep]).split(",")]
+        {"grid": sweep_grid, "nd": sweep_nd, "simple": sweep_simple}[args.sweep](torch, mp, sizes, args.reps)
+        return
     n = args.n
     fmts = args.formats.split(",")
     log(f"generating inputs n={n} formats={fmts}")

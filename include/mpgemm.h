@@ -93,6 +93,49 @@ int mpgemm_ts(int m, int n, int k, const float *A, int lda, const float *B, int 
               hipStream_t stream);
 
 /*
+ * D+S: a binary64 leading part and a binary32 trailing part per element (the
+ * format of Section 4.4's GPU comparison; about 77 bits), stored as two
+ * planes: hi (binary64) and lo (binary32), each column-major with the same
+ * leading dimension (A: m x k with lda >= max(1, m), B: k x n with ldb >=
+ * max(1, k), C: m x n with ldc >= max(1, m)); |lo| <= ulp(hi) / 2.
+ *
+ * mpgemm_ds: C := A B through the DD Ozaki product (Section 3, Algorithm 1):
+ * each input read as the DD number (hi, lo) (exact), the DD product in the
+ * thread's DD slice form and slice count, and C rounded to D+S (hi = RN of
+ * the DD result, lo = its second part rounded to binary32), so that
+ * |C - AB| <= 2^-76 (|A||B|) elementwise where the DD product meets its bound.
+ * Takes workspace for the DD copies of A, B and C besides the DD product's.
+ * Argument codes: -1 .. -12 for m, n, k, Ahi, Alo, lda, Bhi, Blo, ldb, Chi,
+ * Clo, ldc; positive codes as above.
+ */
+int mpgemm_ds(int m, int n, int k, const double *Ahi, const float *Alo, int lda, const double *Bhi, const float *Blo,
+              int ldb, double *Chi, float *Clo, int ldc, hipStream_t stream);
+
+/*
+ * The simple matrix multiplication that Section 4.4 compares with the Ozaki
+ * scheme on the GPU: C := A B by the triple loop in the format's own
+ * arithmetic (no splitting), every term a_ip b_pj multiplied and added in
+ * order p = 0 .. k - 1.  DD: the classical double-double operations (TwoProd
+ * with an FMA, the cross terms, TwoSum of both parts, two renormalizations);
+ * TD, QD, TS: each term's exact and truncated partial products gathered with
+ * the accumulator, sorted by magnitude and renormalized to c components.
+ * D+S: DD arithmetic on the exact DD reading of the inputs, C rounded to D+S
+ * once.  The error grows with k: about k 2^-(L - 3) (|A||B|) for L = 106, 159,
+ * 212, 72 (DD, TD, QD, TS) bits (D+S: that of DD plus 2^-76 (|A||B|)).
+ * staging 0: each thread reads its operands from global memory; 1: 64 x 16
+ * operand panels pass through LDS (the paper's comparison with and without
+ * shared memory); both give the same C bit for bit.  Layout and return codes
+ * as mpgemm_<fmt> with the arguments shifted: -1 for fmt, -2 for staging,
+ * then -(i + 2) for argument i of the DD signature (mpgemm_ds_simple: -1 for
+ * staging, then -(i + 1) for argument i of mpgemm_ds).
+ */
+int mpgemm_simple(int fmt, int staging, int m, int n, int k, const void *A, int lda, const void *B, int ldb, void *C,
+                  int ldc, hipStream_t stream);
+int mpgemm_ds_simple(int staging, int m, int n, int k, const double *Ahi, const float *Alo, int lda,
+                     const double *Bhi, const float *Blo, int ldb, double *Chi, float *Clo, int ldc,
+                     hipStream_t stream);
+
+/*
  * Batched products: C_i := A_i B_i for i < count, independent products of
  * uneven sizes, each computed exactly as the single call computes it (the same
  * per-tile kernel code, so the results are identical bit for bit).  All

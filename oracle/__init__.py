@@ -58,6 +58,8 @@ def lib():
         L.oracle_int8_diag_sums.argtypes = [_I, _I, _I, _I, _P, _P, _P]
         L.oracle_int8_combine.argtypes = [_I, _I, _I, _I, _P, _P, _P, _P]
         L.oracle_gemm_naive.argtypes = [_I, _I, _I, _I, _I, _P, _P, _P, _I, _P]
+        L.oracle_ds_round.argtypes = [_I, _L, _L, _P, _P, _P]
+        L.oracle_gemm_naive_ds.argtypes = [_I, _I, _I, _P, _P, _P, _P, _P, _I, _P, _P]
         L.oracle_omp_threads.restype = _I
         _lib = L
     return _lib
@@ -291,6 +293,42 @@ def gemm_naive(A, B, rows=None) -> np.ndarray:
     _check(lib().oracle_gemm_naive(c, int(A.dtype == np.float32), m, n, k, _ptr(A), _ptr(B), _ptr(rows_arr), nrows,
                                    _ptr(C)), "gemm_naive")
     return C
+
+
+def ds_round(X):
+    """D+S rounding of exact sums: X ``(c, ...)`` float64 component planes;
+    returns ``(hi, lo)`` with the shape of one plane, hi = RN53(sum) (float64)
+    and lo = RN24(sum - hi) (float32), from the exact value."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    c = X.shape[0]
+    count = X[0].size
+    hi = np.zeros(X.shape[1:], dtype=np.float64)
+    lo = np.zeros(X.shape[1:], dtype=np.float32)
+    _check(lib().oracle_ds_round(c, count, count, _ptr(X), _ptr(hi), _ptr(lo)), "ds_round")
+    return hi, lo
+
+
+def gemm_naive_ds(Ahi, Alo, Bhi, Blo, rows=None):
+    """The simple triple loop in D+S (DD arithmetic on the exact DD reading of
+    each D+S input, C rounded to D+S once).  Inputs as ``workload.gen_ds``:
+    ``(1, k, m)`` / ``(1, n, k)`` planes.  Returns ``(Chi, Clo)`` of shape
+    ``(1, n, nrows)``."""
+    Ahi, Bhi = np.ascontiguousarray(Ahi, dtype=np.float64), np.ascontiguousarray(Bhi, dtype=np.float64)
+    Alo, Blo = np.ascontiguousarray(Alo, dtype=np.float32), np.ascontiguousarray(Blo, dtype=np.float32)
+    _, k, m = Ahi.shape
+    n = Bhi.shape[1]
+    rows_arr = None if rows is None else np.ascontiguousarray(rows, dtype=np.int32)
+    nrows = m if rows is None else len(rows_arr)
+    Chi = np.zeros((1, n, nrows), dtype=np.float64)
+    Clo = np.zeros((1, n, nrows), dtype=np.float32)
+    _check(lib().oracle_gemm_naive_ds(m, n, k, _ptr(Ahi), _ptr(Alo), _ptr(Bhi), _ptr(Blo), _ptr(rows_arr), nrows,
+                                      _ptr(Chi), _ptr(Clo)), "gemm_naive_ds")
+    return Chi, Clo
+
+
+def ds_as_dd(hi, lo):
+    """A D+S array pair as a two-component binary64 array (exact)."""
+    return np.concatenate([np.asarray(hi, dtype=np.float64), np.asarray(lo, dtype=np.float64)], axis=0)
 
 
 def bound_report(diff, absab, t: int):

@@ -1058,6 +1058,82 @@ int oracle_gemm_naive(int c, int is_f32, int m, int n, int k, const void *Av, co
     return ORC_OK;
 }
 
+/* ------------------------------------------------------------------------- */
+/* D+S (a binary64 leading part and a binary32 trailing part; Section 4.4's   */
+/* GPU comparison of D+S, DD and TS simple matrix multiplication).            */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * D+S rounding of exact sums: for each of `count` values given as c binary64
+ * components (planes `stride` apart), hi = RN53(v) and lo = RN24(v - hi), both
+ * from the exact value (a long fixed-point accumulator), ties to even.
+ */
+int oracle_ds_round(int c, long count, long stride, const double *x, double *hi, float *lo)
+{
+    if (c < 1 || c > ORC_MAXC || count < 0)
+        return ORC_EINVAL;
+    int status = ORC_OK;
+#pragma omp parallel
+    {
+        sacc *s = malloc(sizeof(sacc));
+        if (!s)
+            status = ORC_ENOMEM;
+#pragma omp for schedule(static)
+        for (long t = 0; t < count; ++t) {
+            if (!s)
+                continue;
+            sa_clear(s);
+            for (int r = 0; r < c; ++r)
+                sa_add(s, x[r * stride + t]);
+            sa_norm(s);
+            const double h = sa_round(s, 53, -1074);
+            sa_add(s, -h);
+            sa_norm(s);
+            hi[t] = h;
+            lo[t] = (float)sa_round(s, 24, -149);
+        }
+        free(s);
+    }
+    return status;
+}
+
+/*
+ * The simple matrix multiplication in D+S: each D+S input is read as the DD
+ * number (hi, (double)lo) (exact), the triple loop runs in the DD arithmetic
+ * of oracle_gemm_naive (c = 2), and each entry of C is rounded to D+S once
+ * at the end (oracle_ds_round of the DD accumulator).  Planes: A (k x m),
+ * B (n x k), C (n x nrows), leading dimension = rows.
+ */
+int oracle_gemm_naive_ds(int m, int n, int k, const double *Ahi, const float *Alo, const double *Bhi,
+                         const float *Blo, const int *rows, int nrows, double *Chi, float *Clo)
+{
+    if (m < 0 || n < 0 || k < 0)
+        return ORC_EINVAL;
+    const long pc = (long)nrows * n;
+    double *acc2 = malloc(sizeof(double) * (size_t)(2 * pc + 1));
+    if (!acc2)
+        return ORC_ENOMEM;
+#pragma omp parallel for schedule(static) collapse(2)
+    for (int j = 0; j < n; ++j)
+        for (int t = 0; t < nrows; ++t) {
+            const int i = rows ? rows[t] : t;
+            double acc[2] = {0.0, 0.0}, a[2], b[2], pr[2];
+            for (int p = 0; p < k; ++p) {
+                a[0] = Ahi[i + (long)p * m];
+                a[1] = (double)Alo[i + (long)p * m];
+                b[0] = Bhi[p + (long)j * k];
+                b[1] = (double)Blo[p + (long)j * k];
+                mc_mul(a, b, 2, pr);
+                mc_add(acc, pr, 2);
+            }
+            acc2[t + (long)j * nrows] = acc[0];
+            acc2[pc + t + (long)j * nrows] = acc[1];
+        }
+    const int st = oracle_ds_round(2, pc, pc, acc2, Chi, Clo);
+    free(acc2);
+    return st;
+}
+
 int oracle_omp_threads(void)
 {
 #ifdef _OPENMP

@@ -99,6 +99,10 @@ def lib():
                 L.mpgemm_nd_workspace_bytes.argtypes = [_I, _I, _I, _I, _I]
                 L.mpgemm_nd_debug_split.argtypes = [_I, _I, _I, _I, _P, _I, _I, _P, _P, _P]
                 L.mpgemm_nd_debug_products.argtypes = [_I, _I, _I, _I, _P, _I, _P, _I, _I, _I, _P, _I, _P]
+                L.mpgemm_simple.argtypes = [_I, _I, _I, _I, _I, _P, _I, _P, _I, _P, _I, _P]
+                L.mpgemm_ds_simple.argtypes = [_I, _I, _I, _I, _P, _P, _I, _P, _P, _I, _P, _P, _I, _P]
+                L.mpgemm_ds.argtypes = [_I, _I, _I, _P, _P, _I, _P, _P, _I, _P, _P, _I, _P]
+                L.mpgemm_dd_noalloc.argtypes = [_I, _I, _I, _P, _I, _P, _I, _P, _I, _P]
                 L.mpgemm_status_string.restype = ctypes.c_char_p
                 L.mpgemm_status_string.argtypes = [_I]
                 _lib = L
@@ -319,6 +323,77 @@ def gemm(fmt, A, B, C=None, *, mode=None, slices=None, stream=None):
         st = fn(m, n, k, _P(A.data_ptr()), lda, _P(B.data_ptr()), ldb, _P(C.data_ptr()), ldc, _stream(stream))
     _check(st, "mpgemm_" + name)
     return C
+
+
+def simple(fmt, A, B, C=None, *, staging: int = 1, stream=None):
+    """C = A B by the simple triple loop in the format's own arithmetic (the
+    non-Ozaki comparison of Section 4.4), tensors as in ``gemm``.
+    ``staging``: 1 stages operand panels through LDS, 0 reads them from
+    global memory (same C bit for bit)."""
+    import torch
+    f = _fmt(fmt)
+    name = [k for k, v in FORMATS.items() if v == f][0]
+    c = COMPONENTS[name]
+    dtype = torch.float32 if name == "ts" else torch.float64
+    lda = _planes_ld(A, c, dtype, "A")
+    ldb = _planes_ld(B, c, dtype, "B")
+    k, m = A.shape[1], A.shape[2]
+    n, kb = B.shape[1], B.shape[2]
+    if kb != k:
+        raise ValueError(f"inner dimensions differ: A has k={k}, B has k={kb}")
+    if C is None:
+        C = torch.empty((c, n, m), dtype=dtype, device=A.device)
+    if tuple(C.shape) != (c, n, m):
+        raise ValueError(f"C must have shape {(c, n, m)}")
+    ldc = _planes_ld(C, c, dtype, "C")
+    _check(lib().mpgemm_simple(f, int(staging), m, n, k, _P(A.data_ptr()), lda, _P(B.data_ptr()), ldb,
+                               _P(C.data_ptr()), ldc, _stream(stream)), "mpgemm_simple")
+    return C
+
+
+def _ds_args(Ahi, Alo, Bhi, Blo, Chi, Clo):
+    import torch
+    for X, dt, nm in ((Ahi, torch.float64, "Ahi"), (Alo, torch.float32, "Alo"), (Bhi, torch.float64, "Bhi"),
+                      (Blo, torch.float32, "Blo")):
+        if not isinstance(X, torch.Tensor) or not X.is_cuda or X.dtype != dt or X.dim() != 3 or X.shape[0] != 1 \
+                or not X.is_contiguous():
+            raise ValueError(f"{nm} must be a contiguous CUDA {dt} tensor of shape (1, cols, rows)")
+    if Alo.shape != Ahi.shape or Blo.shape != Bhi.shape:
+        raise ValueError("hi and lo planes must have one shape")
+    k, m = Ahi.shape[1], Ahi.shape[2]
+    n, kb = Bhi.shape[1], Bhi.shape[2]
+    if kb != k:
+        raise ValueError(f"inner dimensions differ: A has k={k}, B has k={kb}")
+    if Chi is None:
+        Chi = torch.empty((1, n, m), dtype=torch.float64, device=Ahi.device)
+    if Clo is None:
+        Clo = torch.empty((1, n, m), dtype=torch.float32, device=Ahi.device)
+    if tuple(Chi.shape) != (1, n, m) or tuple(Clo.shape) != (1, n, m) or not Chi.is_contiguous() \
+            or not Clo.is_contiguous():
+        raise ValueError(f"C planes must be contiguous of shape {(1, n, m)}")
+    return m, n, k, Chi, Clo
+
+
+def ds_gemm(Ahi, Alo, Bhi, Blo, Chi=None, Clo=None, *, mode=None, slices=None, stream=None):
+    """D+S product through the DD Ozaki product (``mpgemm_ds``): operands as
+    (hi, lo) planes of shapes (1, k, m) float64 / float32 and (1, n, k);
+    returns ``(Chi, Clo)`` of shape (1, n, m).  ``mode`` / ``slices`` as for DD."""
+    m, n, k, Chi, Clo = _ds_args(Ahi, Alo, Bhi, Blo, Chi, Clo)
+    with _options(FORMATS["dd"], None if mode is None else _mode(mode), slices):
+        st = lib().mpgemm_ds(m, n, k, _P(Ahi.data_ptr()), _P(Alo.data_ptr()), max(1, m), _P(Bhi.data_ptr()),
+                             _P(Blo.data_ptr()), max(1, k), _P(Chi.data_ptr()), _P(Clo.data_ptr()), max(1, m),
+                             _stream(stream))
+    _check(st, "mpgemm_ds")
+    return Chi, Clo
+
+
+def ds_simple(Ahi, Alo, Bhi, Blo, Chi=None, Clo=None, *, staging: int = 1, stream=None):
+    """D+S product by the simple triple loop (``mpgemm_ds_simple``)."""
+    m, n, k, Chi, Clo = _ds_args(Ahi, Alo, Bhi, Blo, Chi, Clo)
+    _check(lib().mpgemm_ds_simple(int(staging), m, n, k, _P(Ahi.data_ptr()), _P(Alo.data_ptr()), max(1, m),
+                                  _P(Bhi.data_ptr()), _P(Blo.data_ptr()), max(1, k), _P(Chi.data_ptr()),
+                                  _P(Clo.data_ptr()), max(1, m), _stream(stream)), "mpgemm_ds_simple")
+    return Chi, Clo
 
 
 def certify(fmt, A, B, C=None, *, mode="float", slices=None, stream=None):

@@ -457,6 +457,92 @@ int run_with(int fmt, int mode, int D, int m, int n, int k, const T *A, int lda,
   return hip_status(launch_product<T, C>(p, ws.base, m, n, k, A, lda, B, ldb, Cm, ldc, true, st));
 }
 
+// Simple in-format product (Section 4.4's comparison), planar formats.
+int run_simple(int fmt, int staging, int m, int n, int k, const void *A, int lda, const void *B, int ldb, void *Cm,
+               int ldc, hipStream_t st) {
+  if (fmt < 0 || fmt >= kNumFmt) return -1;
+  if (staging != 0 && staging != 1) return -2;
+  int s = validate(m, n, k, A, lda, B, ldb, Cm, ldc);
+  if (s) return s < 0 ? s - 2 : s;  // shifted past (fmt, staging)
+  if ((s = check_device_cached())) return s;
+  if (m == 0 || n == 0) return 0;
+  const int elem = fmt == MPGEMM_TS ? 4 : 8;
+  if (k == 0) return hip_status(launch_zero_matrix(Cm, elem, kComps[fmt], m, n, ldc, (int64_t)ldc * n, st));
+  const bool staged = staging == 1;
+  switch (fmt) {
+    case MPGEMM_DD: return hip_status(launch_simple<0>(m, n, k, A, lda, B, ldb, Cm, ldc, staged, st));
+    case MPGEMM_TD: return hip_status(launch_simple<1>(m, n, k, A, lda, B, ldb, Cm, ldc, staged, st));
+    case MPGEMM_QD: return hip_status(launch_simple<2>(m, n, k, A, lda, B, ldb, Cm, ldc, staged, st));
+    default: return hip_status(launch_simple<3>(m, n, k, A, lda, B, ldb, Cm, ldc, staged, st));
+  }
+}
+
+// D+S arguments: (m, n, k, Ahi, Alo, lda, Bhi, Blo, ldb, Chi, Clo, ldc) at
+// positions base + 1 ...; 0 if valid.
+int validate_ds(int base, int m, int n, int k, const void *Ahi, const void *Alo, int lda, const void *Bhi,
+                const void *Blo, int ldb, const void *Chi, const void *Clo, int ldc) {
+  if (m < 0) return -(base + 1);
+  if (n < 0) return -(base + 2);
+  if (k < 0) return -(base + 3);
+  if (!Ahi && m > 0 && k > 0) return -(base + 4);
+  if (!Alo && m > 0 && k > 0) return -(base + 5);
+  if (lda < (m > 1 ? m : 1)) return -(base + 6);
+  if (!Bhi && k > 0 && n > 0) return -(base + 7);
+  if (!Blo && k > 0 && n > 0) return -(base + 8);
+  if (ldb < (k > 1 ? k : 1)) return -(base + 9);
+  if (!Chi && m > 0 && n > 0) return -(base + 10);
+  if (!Clo && m > 0 && n > 0) return -(base + 11);
+  if (ldc < (m > 1 ? m : 1)) return -(base + 12);
+  if (m > kMaxDim || n > kMaxDim || k > kMaxDim) return MPGEMM_ERR_TOO_LARGE;
+  return 0;
+}
+
+int run_simple_ds(int staging, int m, int n, int k, const double *Ahi, const float *Alo, int lda, const double *Bhi,
+                  const float *Blo, int ldb, double *Chi, float *Clo, int ldc, hipStream_t st) {
+  if (staging != 0 && staging != 1) return -1;
+  int s = validate_ds(1, m, n, k, Ahi, Alo, lda, Bhi, Blo, ldb, Chi, Clo, ldc);
+  if (s) return s;
+  if ((s = check_device_cached())) return s;
+  if (m == 0 || n == 0) return 0;
+  if (k == 0) {
+    hipError_t e = launch_zero_matrix(Chi, 8, 1, m, n, ldc, 0, st);
+    if (e == hipSuccess) e = launch_zero_matrix(Clo, 4, 1, m, n, ldc, 0, st);
+    return hip_status(e);
+  }
+  return hip_status(launch_simple_ds(m, n, k, Ahi, Alo, lda, Bhi, Blo, ldb, Chi, Clo, ldc, staging == 1, st));
+}
+
+// D+S through the DD Ozaki product: the inputs read as DD (exact), the DD
+// product in the thread's DD slice form and slice count, C rounded to D+S.
+int run_ds(int m, int n, int k, const double *Ahi, const float *Alo, int lda, const double *Bhi, const float *Blo,
+           int ldb, double *Chi, float *Clo, int ldc, hipStream_t st) {
+  int s = validate_ds(0, m, n, k, Ahi, Alo, lda, Bhi, Blo, ldb, Chi, Clo, ldc);
+  if (s) return s;
+  if ((s = check_device_cached())) return s;
+  const int mode = g_opt.mode[MPGEMM_DD];
+  const int D = slices_for(MPGEMM_DD, mode, k);
+  g_opt.last_slices = D;
+  if (m == 0 || n == 0) return 0;
+  if (k == 0) {
+    hipError_t e = launch_zero_matrix(Chi, 8, 1, m, n, ldc, 0, st);
+    if (e == hipSuccess) e = launch_zero_matrix(Clo, 4, 1, m, n, ldc, 0, st);
+    return hip_status(e);
+  }
+  const Plan p = make_plan(MPGEMM_DD, mode, m, n, k, D);
+  const size_t a_bytes = align256((size_t)2 * m * k * 8), b_bytes = align256((size_t)2 * k * n * 8);
+  const size_t c_bytes = align256((size_t)2 * m * n * 8);
+  Workspace ws;
+  if ((s = acquire(ws, p.total + a_bytes + b_bytes + c_bytes, st))) return s;
+  double *Add = reinterpret_cast<double *>(ws.base + p.total);
+  double *Bdd = reinterpret_cast<double *>(ws.base + p.total + a_bytes);
+  double *Cdd = reinterpret_cast<double *>(ws.base + p.total + a_bytes + b_bytes);
+  hipError_t e = launch_ds_to_dd(m, k, Ahi, Alo, lda, Add, st);
+  if (e == hipSuccess) e = launch_ds_to_dd(k, n, Bhi, Blo, ldb, Bdd, st);
+  if (e == hipSuccess) e = launch_product<double, 2>(p, ws.base, m, n, k, Add, m, Bdd, k, Cdd, m, true, st);
+  if (e == hipSuccess) e = launch_dd_to_ds(m, n, Cdd, Chi, Clo, ldc, st);
+  return hip_status(e);
+}
+
 // Scratch of the allocation-free DD entry point: a fixed device array, one
 // copy per device, held until the process ends.  Host code never passes the
 // array's name to a kernel (on the host it is only a stand-in for the symbol):
@@ -796,6 +882,22 @@ int mpgemm_qd(int m, int n, int k, const double *A, int lda, const double *B, in
 int mpgemm_ts(int m, int n, int k, const float *A, int lda, const float *B, int ldb, float *C, int ldc,
               hipStream_t stream) {
   return run<float, 3>(MPGEMM_TS, m, n, k, A, lda, B, ldb, C, ldc, stream);
+}
+
+int mpgemm_ds(int m, int n, int k, const double *Ahi, const float *Alo, int lda, const double *Bhi, const float *Blo,
+              int ldb, double *Chi, float *Clo, int ldc, hipStream_t stream) {
+  return run_ds(m, n, k, Ahi, Alo, lda, Bhi, Blo, ldb, Chi, Clo, ldc, stream);
+}
+
+int mpgemm_simple(int fmt, int staging, int m, int n, int k, const void *A, int lda, const void *B, int ldb, void *C,
+                  int ldc, hipStream_t stream) {
+  return run_simple(fmt, staging, m, n, k, A, lda, B, ldb, C, ldc, stream);
+}
+
+int mpgemm_ds_simple(int staging, int m, int n, int k, const double *Ahi, const float *Alo, int lda,
+                     const double *Bhi, const float *Blo, int ldb, double *Chi, float *Clo, int ldc,
+                     hipStream_t stream) {
+  return run_simple_ds(staging, m, n, k, Ahi, Alo, lda, Bhi, Blo, ldb, Chi, Clo, ldc, stream);
 }
 
 #define MP_ND_CASES(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)

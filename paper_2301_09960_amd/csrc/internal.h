@@ -180,6 +180,22 @@ hipError_t launch_unpack(int elem_bytes, const void *packed, int64_t nbp, int64_
 // sequence stays capturable in a graph).
 hipError_t launch_fill32(void *p, int64_t nwords, uint32_t value, hipStream_t st);
 
+// Simple (non-Ozaki) in-format products: C = A B by the triple loop in the
+// format's arithmetic (F = 0 DD, 1 TD, 2 QD, 3 TS), operands planar as the
+// C-ABI's; staged: operand panels through LDS, else read from global memory.
+template <int F>
+hipError_t launch_simple(int m, int n, int k, const void *A, int lda, const void *B, int ldb, void *Cm, int ldc,
+                         bool staged, hipStream_t st);
+// The same for D+S (binary64 hi plane, binary32 lo plane): DD arithmetic, C
+// rounded to D+S.
+hipError_t launch_simple_ds(int m, int n, int k, const double *Ahi, const float *Alo, int lda, const double *Bhi,
+                            const float *Blo, int ldb, double *Chi, float *Clo, int ldc, bool staged,
+                            hipStream_t st);
+// D+S (leading dimension ld) <-> two compact binary64 planes (rows x cols).
+hipError_t launch_ds_to_dd(int rows, int cols, const double *hi, const float *lo, int ld, double *out,
+                           hipStream_t st);
+hipError_t launch_dd_to_ds(int rows, int cols, const double *in, double *hi, float *lo, int ld, hipStream_t st);
+
 // C := 0 for an m x n multi-component matrix.
 hipError_t launch_zero_matrix(void *C, int elem_bytes, int comps, int m, int n, int ldc, int64_t c_stride,
                               hipStream_t st);

@@ -1,6 +1,7 @@
 // Multi-component scalar arithmetic for the TD LU (Section 4.6 factorizes TD
-// matrices as well as DD ones).  A value is C binary64 components, largest
-// first.  Each operation gathers its terms (exact ones from TwoSum / TwoProd,
+// matrices as well as DD ones) and the simple in-format matrix multiplication
+// of TS, TD and QD (Section 4.4).  A value is C components of type T (binary64,
+// or binary32 for TS), largest first.  Each operation gathers its terms (exact ones from TwoSum / TwoProd,
 // and for a product a plain tail at the lowest order kept), sorts them by
 // decreasing magnitude, renormalizes them with `renorm` (mp_device.h:
 // only TwoSum, so the sum is unchanged) and keeps the leading C components.
@@ -16,20 +17,20 @@
 
 namespace mp {
 
-template <int C>
+template <int C, typename T = double>
 struct mc {
-  double x[C];
+  T x[C];
 };
 
 // Sort by decreasing magnitude with the comparator network of sortnet.h
 // (fully unrolled: compile-time indices, selects only).
-template <int N>
-__device__ __forceinline__ void sort_by_magnitude(double (&t)[N]) {
+template <int N, typename T>
+__device__ __forceinline__ void sort_by_magnitude(T (&t)[N]) {
   constexpr SortNet<N> net{};
 #pragma unroll
   for (int c = 0; c < net.count; ++c) {
     const int lo = net.lo[c], hi = net.hi[c];
-    const double a = t[lo], b = t[hi];
+    const T a = t[lo], b = t[hi];
     const bool swap = fabs(b) > fabs(a);
     t[lo] = swap ? b : a;
     t[hi] = swap ? a : b;
@@ -37,26 +38,26 @@ __device__ __forceinline__ void sort_by_magnitude(double (&t)[N]) {
 }
 
 // The leading C components of the renormalized sum of N exact terms.
-template <int C, int N>
-__device__ __forceinline__ mc<C> mc_from_terms(double (&t)[N]) {
+template <int C, int N, typename T>
+__device__ __forceinline__ mc<C, T> mc_from_terms(T (&t)[N]) {
   sort_by_magnitude<N>(t);
-  renorm<double, N>(t);
-  mc<C> r;
+  renorm<T, N>(t);
+  mc<C, T> r;
 #pragma unroll
   for (int i = 0; i < C; ++i) r.x[i] = t[i];
   return r;
 }
 
-template <int C>
-__device__ __forceinline__ mc<C> mc_neg(mc<C> a) {
+template <int C, typename T>
+__device__ __forceinline__ mc<C, T> mc_neg(mc<C, T> a) {
 #pragma unroll
   for (int i = 0; i < C; ++i) a.x[i] = -a.x[i];
   return a;
 }
 
-template <int C>
-__device__ __forceinline__ mc<C> mc_add(const mc<C> &a, const mc<C> &b) {
-  double t[2 * C];
+template <int C, typename T>
+__device__ __forceinline__ mc<C, T> mc_add(const mc<C, T> &a, const mc<C, T> &b) {
+  T t[2 * C];
 #pragma unroll
   for (int i = 0; i < C; ++i) {
     t[2 * i] = a.x[i];
@@ -65,8 +66,8 @@ __device__ __forceinline__ mc<C> mc_add(const mc<C> &a, const mc<C> &b) {
   return mc_from_terms<C, 2 * C>(t);
 }
 
-template <int C>
-__device__ __forceinline__ mc<C> mc_sub(const mc<C> &a, const mc<C> &b) {
+template <int C, typename T>
+__device__ __forceinline__ mc<C, T> mc_sub(const mc<C, T> &a, const mc<C, T> &b) {
   return mc_add<C>(a, mc_neg<C>(b));
 }
 
@@ -81,15 +82,15 @@ constexpr int mul_terms() {
   return 2 * ((C - 2) * (C - 1) / 2) + (C - 1) + 1;
 }
 
-template <int C>
-__device__ __forceinline__ void gather_mul_terms(const mc<C> &a, const mc<C> &b, double (&t)[mul_terms<C>()]) {
-  double tail = 0.0;
+template <int C, typename T>
+__device__ __forceinline__ void gather_mul_terms(const mc<C, T> &a, const mc<C, T> &b, T (&t)[mul_terms<C>()]) {
+  T tail = T(0);
   int w = 0;
 #pragma unroll
   for (int i = 0; i < C; ++i)
 #pragma unroll
     for (int j = 0; j + i < C; ++j) {
-      const double p = a.x[i] * b.x[j];
+      const T p = a.x[i] * b.x[j];
       if (i + j < C - 2) {
         t[w++] = p;
         t[w++] = fma(a.x[i], b.x[j], -p);
@@ -103,24 +104,38 @@ __device__ __forceinline__ void gather_mul_terms(const mc<C> &a, const mc<C> &b,
   t[w] = tail;
 }
 
-template <int C>
-__device__ __forceinline__ mc<C> mc_mul(const mc<C> &a, const mc<C> &b) {
-  double t[mul_terms<C>()];
+template <int C, typename T>
+__device__ __forceinline__ mc<C, T> mc_mul(const mc<C, T> &a, const mc<C, T> &b) {
+  T t[mul_terms<C>()];
   gather_mul_terms<C>(a, b, t);
   return mc_from_terms<C, mul_terms<C>()>(t);
 }
 
 // s - a b in one renormalization: the terms of s and of -(a b) as above.
-template <int C>
-__device__ __forceinline__ mc<C> mc_fms(const mc<C> &s, const mc<C> &a, const mc<C> &b) {
+template <int C, typename T>
+__device__ __forceinline__ mc<C, T> mc_fms(const mc<C, T> &s, const mc<C, T> &a, const mc<C, T> &b) {
   constexpr int M = mul_terms<C>();
-  double p[M];
+  T p[M];
   gather_mul_terms<C>(a, b, p);
-  double t[C + M];
+  T t[C + M];
 #pragma unroll
   for (int i = 0; i < C; ++i) t[i] = s.x[i];
 #pragma unroll
   for (int i = 0; i < M; ++i) t[C + i] = -p[i];
+  return mc_from_terms<C, C + M>(t);
+}
+
+// s + a b in one renormalization: the terms of s and of a b as above.
+template <int C, typename T>
+__device__ __forceinline__ mc<C, T> mc_fma(const mc<C, T> &s, const mc<C, T> &a, const mc<C, T> &b) {
+  constexpr int M = mul_terms<C>();
+  T t[C + M];
+#pragma unroll
+  for (int i = 0; i < C; ++i) t[i] = s.x[i];
+  T p[M];
+  gather_mul_terms<C>(a, b, p);
+#pragma unroll
+  for (int i = 0; i < M; ++i) t[C + i] = p[i];
   return mc_from_terms<C, C + M>(t);
 }
 

@@ -48,6 +48,27 @@ def test_argument_codes(L):
     assert f(4, 4, 4, x, 4, x, 4, x, 3, None) == -9
     assert L.mpgemm_ts(4, 4, 4, x, 4, x, 4, x, 2, None) == -9
     assert f(1 << 21, 4, 4, x, 1 << 21, x, 4, x, 1 << 21, None) == 5  # beyond the size limit
+    # allocation-free DD product: the codes of mpgemm_dd
+    assert L.mpgemm_dd_noalloc(4, 4, 4, x, 3, x, 4, x, 4, None) == -5
+    # simple in-format product: fmt, staging, then the product's codes shifted by two
+    sp = L.mpgemm_simple
+    assert sp(9, 1, 4, 4, 4, x, 4, x, 4, x, 4, None) == -1
+    assert sp(0, 2, 4, 4, 4, x, 4, x, 4, x, 4, None) == -2
+    assert sp(0, 1, -1, 4, 4, x, 4, x, 4, x, 4, None) == -3
+    assert sp(3, 0, 4, 4, 4, x, 4, x, 3, x, 4, None) == -9
+    assert sp(1, 1, 4, 4, 4, x, 4, x, 4, x, 3, None) == -11
+    # D+S: (m, n, k, Ahi, Alo, lda, Bhi, Blo, ldb, Chi, Clo, ldc); the simple form takes staging first
+    ds = L.mpgemm_ds
+    assert ds(-1, 4, 4, x, x, 4, x, x, 4, x, x, 4, None) == -1
+    assert ds(4, 4, 4, x, None, 4, x, x, 4, x, x, 4, None) == -5
+    assert ds(4, 4, 4, x, x, 3, x, x, 4, x, x, 4, None) == -6
+    assert ds(4, 4, 4, x, x, 4, x, None, 4, x, x, 4, None) == -8
+    assert ds(4, 4, 4, x, x, 4, x, x, 4, x, None, 4, None) == -11
+    assert ds(4, 4, 4, x, x, 4, x, x, 4, x, x, 3, None) == -12
+    dss = L.mpgemm_ds_simple
+    assert dss(3, 4, 4, 4, x, x, 4, x, x, 4, x, x, 4, None) == -1
+    assert dss(0, 4, -1, 4, x, x, 4, x, x, 4, x, x, 4, None) == -3
+    assert dss(1, 4, 4, 4, x, x, 4, x, x, 3, x, x, 4, None) == -10
     # certified product: fmt first, then the product's codes shifted by one
     c = L.mpgemm_certify
     assert c(7, 4, 4, 4, x, 4, x, 4, x, 4, x, x, None) == -1

@@ -18,6 +18,8 @@ uniform integer instead of a log-normal factor, so the spread is a parameter):
   so ``|x_r| <= 2**-54 |x_{r-1}| < ulp(x_{r-1}) / 2`` (a normalized expansion).
 * TS (c = 3 binary32 components): the same with a ``2**-23`` grid for ``u``
   and ``x_r = RN_f32(x_{r-1} * 2**-24 * v_r)``.
+* D+S (``gen_ds``): the DD leading component with the second component
+  rounded to binary32.
 * ``eq1`` spread: ``x0 = (ru - 0.5) * exp(rn)`` with ``ru`` uniform on
   ``[0, 1)`` and ``rn`` standard normal (Box-Muller on two uniforms), the
   paper's own distribution, with lower components drawn as above.
@@ -109,6 +111,16 @@ def gen_matrix(fmt: str, rows: int, cols: int, *, E: int = 8, seed: int = 0, ope
         v = (uniform01(seed, op, 8 + r, count) - 0.5).astype(dt)
         out[r] = (out[r - 1] * scale) * v
     return out.reshape(c, cols, rows)
+
+
+def gen_ds(rows: int, cols: int, *, E: int = 8, seed: int = 0, operand: str = "A", spread: str = "uniform"):
+    """D+S matrix (a binary64 leading part and a binary32 trailing part):
+    ``(hi, lo)`` of shapes ``(1, cols, rows)`` float64 and float32, hi drawn as
+    the DD generator's leading component and ``lo = RN_f32(hi * 2**-53 * v)``
+    with ``v`` uniform on ``[-0.5, 0.5)`` (so ``|lo| <= ulp(hi) / 2``)."""
+    X = gen_matrix("dd", rows, cols, E=E, seed=seed, operand=operand, spread=spread)
+    hi = np.ascontiguousarray(X[:1])
+    return hi, X[1:2].astype(np.float32)
 
 
 def gen_pair(fmt: str, m: int, n: int, k: int, *, E: int = 8, seed: int = 0, spread: str = "uniform"):
