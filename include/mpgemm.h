@@ -74,9 +74,15 @@ extern "C" {
 /*
  * C := A B in DD / TD / QD (Section 3, Algorithm 1; the product set is the
  * triangle a + b <= D + 1 and every slice product is exact).  Arguments as in
- * the layout paragraph above.  The result satisfies, elementwise,
- * |C - A B| <= 2^-t (|A||B|) with t = 100 (DD), 150 (TD), 200 (QD) for inputs
- * in range when D is left at its automatic value.
+ * the layout paragraph above.  Target: |C - A B| <= 2^-t (|A||B|) elementwise,
+ * t = 100 (DD), 150 (TD), 200 (QD).  The automatic D meets it when the largest
+ * entry of each row of A (column of B) is not far above the entries that
+ * carry (|A||B|)_ij: tested on exponents spread uniformly over up to 60 bits.
+ * It is an estimate, not a guarantee: a row whose grid is set by one entry
+ * 2^40 above the rest needs more slices.  For any input in range, choose the
+ * slices from the data (MPGEMM_SLICES_DATA below), which meets the target by
+ * construction (up to 16 slices, enough for about 16 b - t bits of such
+ * excess with b-bit slices), or check a product with mpgemm_certify.
  */
 int mpgemm_dd(int m, int n, int k, const double *A, int lda, const double *B, int ldb, double *C, int ldc,
               hipStream_t stream);
@@ -174,11 +180,32 @@ int mpgemm_batched_cache_clear(void);
  * mpgemm_set_mode selects the slice form (returns MPGEMM_ERR_UNSUPPORTED for
  * INT8 with TS).  mpgemm_set_num_slices sets D for (fmt, mode); 0 restores the
  * automatic choice (Section 3 ties the attainable accuracy to the number of
- * divisions; the automatic D is the smallest that meets the bound above with
- * guard bits on inputs with an exponent spread of up to 16 bits within a row or
- * column).  mpgemm_num_slices returns the D a call with inner dimension k would
- * use.  mpgemm_last_num_slices returns the D used by this thread's last call.
+ * divisions; the automatic D is the smallest that met the bound above with
+ * guard bits on the tested inputs, see mpgemm_dd).  mpgemm_num_slices returns
+ * the D a call with inner dimension k would use.  mpgemm_last_num_slices
+ * returns the D used by this thread's last call.
+ *
+ * D = MPGEMM_SLICES_DATA (binary64/binary32 slices only; INT8 returns
+ * MPGEMM_ERR_UNSUPPORTED): the slice products are chosen from the data, as
+ * Section 3 says the number of divisions must be found by running the
+ * calculation and that more of the low-order products can be dropped.  The
+ * split makes 16 slices; the certificate's quantities (see mpgemm_certify:
+ * the slice exponents, the remainders, the row and column sums of |A_0| and
+ * |B_0| and the product |A_0| |B_0|) are formed before the slice products;
+ * then each 64 x 64 tile of C forms only the pairs (a, b) whose slices are
+ * large enough to matter: those with the largest bounds k 2^(e_a + e_b),
+ * taken until the bounds of all pairs left out, with the remainder and
+ * rounding terms, fit 2^-t times the tile's smallest lower bound of |A||B|
+ * (exponents relative to each row's and column's first slice, so the rows'
+ * and columns' scales do not matter).  Every entry then meets the target,
+ * and mpgemm_certify in this mode returns the certificate of the same C.
+ * Zero slices, zero rows and tiles with |A||B| = 0 take no pairs.  Applies to
+ * mpgemm_dd/td/qd/ts and mpgemm_certify; the batched, allocation-free, D+S
+ * and LU calls use the automatic D.  Workspace: mpgemm_workspace_bytes with
+ * D = MPGEMM_SLICES_DATA (or 0 while the thread is in this mode).  Stage
+ * timing records the split with the pair selection as the split stage.
  */
+#define MPGEMM_SLICES_DATA (-1)
 int mpgemm_set_mode(int fmt, int mode);
 int mpgemm_get_mode(int fmt);
 
@@ -351,6 +378,16 @@ int mpgemm_td_lu_solve(int n, const double *LU, int lda, double *x, hipStream_t 
  */
 int mpgemm_debug_split(int fmt, int mode, int operand, int rows, int cols, const void *X, int ldx, int D,
                        void *slices, int *exps, hipStream_t stream);
+/*
+ * mpgemm_debug_pair_sets: the pair sets the data-chosen slice mode
+ * (MPGEMM_SLICES_DATA) takes for C = AB: for tile (tm, tn) of 64 x 64 entries
+ * (tiles_m = ceil(m / 64), tiles_n = ceil(n / 64)), 16 bytes at
+ * sets + (tn * tiles_m + tm) * 16, byte a (0-based slice of A) holding how many
+ * slices of B (0-based b < count) pair with it.  Device pointer sets.  Codes:
+ * -1 fmt, then the DD signature's codes shifted by one, -10 for a NULL sets.
+ */
+int mpgemm_debug_pair_sets(int fmt, int m, int n, int k, const void *A, int lda, const void *B, int ldb,
+                           int8_t *sets, hipStream_t stream);
 int mpgemm_debug_products(int fmt, int mode, int m, int n, int k, const void *A, int lda, const void *B, int ldb,
                           int D, int a, int b, void *out, int ldo, hipStream_t stream);
 
@@ -373,9 +410,11 @@ int mpgemm_profile_read(double *split_ms, double *gemm_ms, int max_calls);
  * c = 2 .. 14 binary64 components per element, planes as for DD/TD/QD
  * (normalized expansions, each component below half an ulp of the one above).
  * The product uses the INT8-slice form with D digit slices (D = 0: automatic,
- * mpgemm_nd_num_slices) and meets |C - AB| <= 2^-(50 c) (|A||B|) elementwise
- * for the automatic D on inputs whose exponents spread up to 16 bits within a
- * row or column (c = 2, 3, 4 give the DD, TD and QD bounds).  At most 112
+ * mpgemm_nd_num_slices), targeting |C - AB| <= 2^-(50 c) (|A||B|) elementwise
+ * (c = 2, 3, 4 give the DD, TD and QD bounds); the automatic D met it on the
+ * tested inputs (exponents spread up to 16 bits), with the same caveat as
+ * mpgemm_dd for rows or columns dominated by one entry: mpgemm_nd_certify
+ * checks a product.  At most 112
  * digits.  Return codes: -1 bad c, -2 bad D, then -(i + 2) for argument i of
  * the DD signature; positive codes as above.  Workspace as for the other
  * calls (mpgemm_nd_workspace_bytes; 0 for an invalid or empty shape).

@@ -103,6 +103,7 @@ def lib():
                 L.mpgemm_ds_simple.argtypes = [_I, _I, _I, _I, _P, _P, _I, _P, _P, _I, _P, _P, _I, _P]
                 L.mpgemm_ds.argtypes = [_I, _I, _I, _P, _P, _I, _P, _P, _I, _P, _P, _I, _P]
                 L.mpgemm_dd_noalloc.argtypes = [_I, _I, _I, _P, _I, _P, _I, _P, _I, _P]
+                L.mpgemm_debug_pair_sets.argtypes = [_I, _I, _I, _I, _P, _I, _P, _I, _P, _P]
                 L.mpgemm_status_string.restype = ctypes.c_char_p
                 L.mpgemm_status_string.argtypes = [_I]
                 _lib = L
@@ -670,6 +671,26 @@ def nd_debug_products(A, B, g: int, D: int = 0, stream=None):
     _check(lib().mpgemm_nd_debug_products(c, m, n, k, _P(A.data_ptr()), max(1, m), _P(B.data_ptr()), max(1, k),
                                           int(D), int(g), _P(out.data_ptr()), max(1, m), _stream(stream)),
            "nd_debug_products")
+    return out
+
+
+def debug_pair_sets(fmt, A, B, stream=None):
+    """The pair sets of the data-chosen slice mode for C = A B: an int8 tensor
+    ``(tiles_n, tiles_m, 16)``; entry ``[tn, tm, a]`` is how many slices of B
+    pair with slice a of A in that 64 x 64 tile of C."""
+    import torch
+    f = _fmt(fmt)
+    name = [k for k, v in FORMATS.items() if v == f][0]
+    c = COMPONENTS[name]
+    dtype = torch.float32 if name == "ts" else torch.float64
+    _check_tensor(A, c, dtype, "A")
+    _check_tensor(B, c, dtype, "B")
+    k, m = A.shape[1], A.shape[2]
+    n = B.shape[1]
+    tm, tn = (m + 63) // 64, (n + 63) // 64
+    out = torch.zeros((tn, tm, 16), dtype=torch.int8, device=A.device)
+    _check(lib().mpgemm_debug_pair_sets(f, m, n, k, _P(A.data_ptr()), max(1, m), _P(B.data_ptr()), max(1, k),
+                                        _P(out.data_ptr()), _stream(stream)), "debug_pair_sets")
     return out
 
 

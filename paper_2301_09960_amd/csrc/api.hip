@@ -457,6 +457,140 @@ int run_with(int fmt, int mode, int D, int m, int n, int k, const T *A, int lda,
   return hip_status(launch_product<T, C>(p, ws.base, m, n, k, A, lda, B, ldb, Cm, ldc, true, st));
 }
 
+// Slice counts chosen from the data (mpgemm_set_num_slices(fmt, FLOAT,
+// MPGEMM_SLICES_DATA)): kMaxPairLim slices are made, the certificate's
+// quantities (the slice exponents, the remainders after the last slice, the
+// row and column sums of |A_0| and |B_0| and the product |A_0| |B_0|) are
+// formed before the slice products, and each 64 x 64 tile of C takes only
+// the pairs its entries need to meet 2^-t (|A||B|) (launch_tile_pairs).
+constexpr int kSlicesData = -1;
+
+bool data_mode(int fmt, int mode) { return mode == MPGEMM_MODE_FLOAT && g_opt.slices[fmt][mode] == kSlicesData; }
+
+struct DataPlan {
+  Plan p;
+  size_t off_abs_a, off_abs_b, off_rs, off_cs, off_raw, off_lims, total;
+  int64_t tiles_m, tiles_n;
+};
+
+DataPlan make_data_plan(int fmt, int64_t m, int64_t n, int64_t k, bool raw_outside) {
+  DataPlan d{};
+  d.p = make_plan(fmt, MPGEMM_MODE_FLOAT, m, n, k, kMaxPairLim);
+  size_t o = d.p.total;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  const int64_t kbp = kblocks_padded(k);
+  d.tiles_m = nblocks_padded(m) / kTileBlocks;
+  d.tiles_n = nblocks_padded(n) / kTileBlocks;
+  d.off_abs_a = take((size_t)nblocks_padded(m) * kbp * 256 * 8);
+  d.off_abs_b = take((size_t)nblocks_padded(n) * kbp * 256 * 8);
+  d.off_rs = take((size_t)m * 8);
+  d.off_cs = take((size_t)n * 8);
+  d.off_raw = take(raw_outside ? 0 : (size_t)2 * m * n * 8);
+  d.off_lims = take((size_t)d.tiles_m * d.tiles_n * kMaxPairLim);
+  d.total = o;
+  return d;
+}
+
+// C = AB with the pairs chosen per tile; with cert (2 m n doubles) and worst,
+// also the certificate of that C (its plane 0 first holds |A_0| |B_0|).
+template <typename T, int C>
+int run_data(int fmt, int m, int n, int k, const T *A, int lda, const T *B, int ldb, T *Cm, int ldc, double *cert,
+             double *worst, hipStream_t st) {
+  int s;
+  const int D = kMaxPairLim;
+  g_opt.last_slices = D;
+  if (cert && g_opt.last_slice != 0) return MPGEMM_ERR_UNSUPPORTED;
+  if (m == 0 || n == 0 || k == 0) {
+    hipError_t e = hipSuccess;
+    if (worst) e = launch_fill32(worst, 2, 0u, st);
+    if (e == hipSuccess && cert && m > 0 && n > 0) e = launch_fill32(cert, (int64_t)4 * m * n, 0u, st);
+    if (e == hipSuccess && m > 0 && n > 0) e = launch_zero_matrix(Cm, sizeof(T), C, m, n, ldc, (int64_t)ldc * n, st);
+    return hip_status(e);
+  }
+  const DataPlan d = make_data_plan(fmt, m, n, k, cert != nullptr);
+  const Plan &p = d.p;
+  Workspace ws;
+  if ((s = acquire(ws, d.total, st))) return s;
+  char *base = ws.base;
+  const SplitOperand<T> a = operand_a(A, m, k, lda, p, base), b = operand_b(B, k, n, ldb, p, base);
+  double *raw = cert ? cert : reinterpret_cast<double *>(base + d.off_raw);
+  double *rs = reinterpret_cast<double *>(base + d.off_rs), *cs = reinterpret_cast<double *>(base + d.off_cs);
+  int8_t *lims = reinterpret_cast<int8_t *>(base + d.off_lims);
+  const int S = sizeof(T) == 8 ? 53 : 24;
+  const int layout = layout_for(fmt);
+  std::array<hipEvent_t, 3> ev{nullptr, nullptr, nullptr};
+  if (g_prof.on) {
+    for (auto &x : ev) x = g_prof.take();
+    if (ev[0]) (void)hipEventRecord(ev[0], st);
+  }
+  hipError_t e = split_both<T, C>(a, b, p, st);
+  // |A_0| and |B_0| in the binary64 packed layout (the geometry of the binary64 slices)
+  SplitOperand<T> ca = a, cb = b;
+  ca.nbp = nblocks_padded(m);
+  cb.nbp = nblocks_padded(n);
+  ca.kbp = cb.kbp = kblocks_padded(k);
+  if (e == hipSuccess)
+    e = launch_abs_lead_product<T>(ca, cb, m, n, raw, reinterpret_cast<double *>(base + d.off_abs_a),
+                                   reinterpret_cast<double *>(base + d.off_abs_b), rs, cs, layout, st);
+  if (e == hipSuccess)
+    e = launch_tile_pairs(m, n, k, D, p.rho, S, C, kBoundBits[fmt], a.exps, b.exps, rs, cs, raw, d.tiles_m, d.tiles_n,
+                          lims, st);
+  if (ev[1]) (void)hipEventRecord(ev[1], st);
+  if (e == hipSuccess)
+    e = launch_gemm_plain_pruned<T, C>(base + p.off_pack_a, base + p.off_pack_b, p.mbp, p.nbp, p.kbp, m, n, D, Cm,
+                                       ldc, (int64_t)ldc * n, lims, layout, st);
+  if (ev[2]) (void)hipEventRecord(ev[2], st);
+  if (g_prof.on) {
+    if (ev[0] && ev[1] && ev[2])
+      g_prof.marks.push_back(ev);
+    else
+      for (auto x : ev)
+        if (x) g_prof.pool.push_back(x);
+  }
+  if (e == hipSuccess && cert)
+    e = launch_certify<T>(ca, cb, m, n, k, D, p.rho, C, 0, cert, worst, nullptr, nullptr, rs, cs, layout, st, lims,
+                          true);
+  return hip_status(e);
+}
+
+// The pair sets run_data would use: split, |A_0| |B_0| and the selection,
+// then a copy of the sets (tiles_m x tiles_n x kMaxPairLim counts).
+template <typename T, int C>
+int debug_pair_sets_t(int fmt, int m, int n, int k, const T *A, int lda, const T *B, int ldb, int8_t *out,
+                      hipStream_t st) {
+  int s;
+  if (m == 0 || n == 0) return 0;
+  const DataPlan d = make_data_plan(fmt, m, n, k, false);
+  if (k == 0) return hip_status(launch_fill32(out, (int64_t)d.tiles_m * d.tiles_n * kMaxPairLim / 4, 0u, st));
+  const Plan &p = d.p;
+  Workspace ws;
+  if ((s = acquire(ws, d.total, st))) return s;
+  char *base = ws.base;
+  const SplitOperand<T> a = operand_a(A, m, k, lda, p, base), b = operand_b(B, k, n, ldb, p, base);
+  double *raw = reinterpret_cast<double *>(base + d.off_raw);
+  double *rs = reinterpret_cast<double *>(base + d.off_rs), *cs = reinterpret_cast<double *>(base + d.off_cs);
+  int8_t *lims = reinterpret_cast<int8_t *>(base + d.off_lims);
+  const int layout = layout_for(fmt);
+  hipError_t e = split_both<T, C>(a, b, p, st);
+  SplitOperand<T> ca = a, cb = b;
+  ca.nbp = nblocks_padded(m);
+  cb.nbp = nblocks_padded(n);
+  ca.kbp = cb.kbp = kblocks_padded(k);
+  if (e == hipSuccess)
+    e = launch_abs_lead_product<T>(ca, cb, m, n, raw, reinterpret_cast<double *>(base + d.off_abs_a),
+                                   reinterpret_cast<double *>(base + d.off_abs_b), rs, cs, layout, st);
+  if (e == hipSuccess)
+    e = launch_tile_pairs(m, n, k, kMaxPairLim, p.rho, sizeof(T) == 8 ? 53 : 24, C, kBoundBits[fmt], a.exps, b.exps,
+                          rs, cs, raw, d.tiles_m, d.tiles_n, lims, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, lims, (size_t)d.tiles_m * d.tiles_n * kMaxPairLim, hipMemcpyDeviceToDevice, st);
+  return hip_status(e);
+}
+
 // Simple in-format product (Section 4.4's comparison), planar formats.
 int run_simple(int fmt, int staging, int m, int n, int k, const void *A, int lda, const void *B, int ldb, void *Cm,
                int ldc, hipStream_t st) {
@@ -594,6 +728,7 @@ int run(int fmt, int m, int n, int k, const T *A, int lda, const T *B, int ldb, 
   if (s) return s;
   if ((s = check_device_cached())) return s;
   const int mode = g_opt.mode[fmt];
+  if (data_mode(fmt, mode)) return run_data<T, C>(fmt, m, n, k, A, lda, B, ldb, Cm, ldc, nullptr, nullptr, st);
   return run_with<T, C>(fmt, mode, slices_for(fmt, mode, k), m, n, k, A, lda, B, ldb, Cm, ldc, st);
 }
 
@@ -718,6 +853,7 @@ int certify_t(int fmt, int m, int n, int k, const T *A, int lda, const T *B, int
   if (!worst) return -12;
   if ((s = check_device_cached())) return s;
   const int mode = g_opt.mode[fmt];
+  if (data_mode(fmt, mode)) return run_data<T, C>(fmt, m, n, k, A, lda, B, ldb, Cm, ldc, cert, worst, st);
   return certify_run<T, C>(fmt, mode, slices_for(fmt, mode, k), m, n, k, A, lda, B, ldb, Cm, ldc, cert, worst, st);
 }
 
@@ -889,6 +1025,21 @@ int mpgemm_ds(int m, int n, int k, const double *Ahi, const float *Alo, int lda,
   return run_ds(m, n, k, Ahi, Alo, lda, Bhi, Blo, ldb, Chi, Clo, ldc, stream);
 }
 
+int mpgemm_debug_pair_sets(int fmt, int m, int n, int k, const void *A, int lda, const void *B, int ldb,
+                           int8_t *sets, hipStream_t stream) {
+  if (!fmt_ok(fmt)) return -1;
+  int s = validate(m, n, k, A, lda, B, ldb, sets, m > 1 ? m : 1);
+  if (s) return s < 0 ? (s == -8 ? -10 : s - 1) : s;  // shifted past fmt; sets is argument 10
+  if ((s = check_device_cached())) return s;
+  if (fmt == MPGEMM_TS)
+    return debug_pair_sets_t<float, 3>(fmt, m, n, k, (const float *)A, lda, (const float *)B, ldb, sets, stream);
+  if (fmt == MPGEMM_DD)
+    return debug_pair_sets_t<double, 2>(fmt, m, n, k, (const double *)A, lda, (const double *)B, ldb, sets, stream);
+  if (fmt == MPGEMM_TD)
+    return debug_pair_sets_t<double, 3>(fmt, m, n, k, (const double *)A, lda, (const double *)B, ldb, sets, stream);
+  return debug_pair_sets_t<double, 4>(fmt, m, n, k, (const double *)A, lda, (const double *)B, ldb, sets, stream);
+}
+
 int mpgemm_simple(int fmt, int staging, int m, int n, int k, const void *A, int lda, const void *B, int ldb, void *C,
                   int ldc, hipStream_t stream) {
   return run_simple(fmt, staging, m, n, k, A, lda, B, ldb, C, ldc, stream);
@@ -1027,6 +1178,11 @@ int mpgemm_set_num_slices(int fmt, int mode, int D) {
   if (!fmt_ok(fmt)) return -1;
   if (mode != MPGEMM_MODE_FLOAT && mode != MPGEMM_MODE_INT8) return -2;
   if (!mode_ok(fmt, mode)) return MPGEMM_ERR_UNSUPPORTED;
+  if (D == kSlicesData) {
+    if (mode != MPGEMM_MODE_FLOAT) return MPGEMM_ERR_UNSUPPORTED;
+    g_opt.slices[fmt][mode] = D;
+    return 0;
+  }
   if (D < 0 || D > (mode == MPGEMM_MODE_FLOAT ? kMaxDFloat : kMaxDInt8)) return -3;
   g_opt.slices[fmt][mode] = D;
   return 0;
@@ -1041,6 +1197,8 @@ int mpgemm_last_num_slices(void) { return g_opt.last_slices; }
 
 size_t mpgemm_workspace_bytes(int fmt, int mode, int m, int n, int k, int D) {
   if (!fmt_ok(fmt) || !mode_ok(fmt, mode) || m < 0 || n < 0 || k < 0) return 0;
+  if (D == kSlicesData || (D == 0 && data_mode(fmt, mode)))
+    return mode == MPGEMM_MODE_FLOAT ? make_data_plan(fmt, m, n, k, false).total : 0;
   if (D <= 0) D = slices_for(fmt, mode, k);
   return make_plan(fmt, mode, m, n, k, D).total;
 }

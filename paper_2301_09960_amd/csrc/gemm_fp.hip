@@ -151,12 +151,14 @@ __device__ __forceinline__ void wait_step(int64_t later) {
 
 // All slice products of one 64 x 64 tile (tm, tn) of one product, folded into
 // C.  `lds` is the workgroup's ring of stages_of<T>() staging buffers of
-// stage_elems<T>() elements each.
-template <typename T, int C, int LAYOUT>
+// stage_elems<T>() elements each.  The pairs are (a, b), 0-based, with
+// b < lim(a): the triangle a + b <= D - 1 (lim(a) = D - a), or with PRUNE the
+// tile's own staircase lim(a) = s_lim[a] (non-increasing in a, at most D).
+template <typename T, int C, int LAYOUT, bool PRUNE = false>
 __device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const T *__restrict__ Bpk, int64_t mbp, int64_t nbp,
                                 int64_t kbp, int m, int n, int D, T *__restrict__ Cout, int ldc, int64_t c_stride,
                                 int single_pair, double *__restrict__ Cdbg, int lddbg, int tm, int tn,
-                                T *lds) {
+                                T *lds, const int *s_lim = nullptr) {
   using M = Mma<T>;
   using acc_t = typename M::acc_t;
   constexpr int WM = Layout<LAYOUT>::WM, WN = Layout<LAYOUT>::WN;
@@ -176,7 +178,17 @@ __device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const
   const int wm = wave % WM, wn = wave / WM;
 
   const int nks = (int)(kbp / kKStepBlocks);
-  const int npairs = single_pair >= 0 ? 1 : D * (D + 1) / 2;
+  auto lim = [&](int a) -> int {
+    if constexpr (PRUNE)
+      return s_lim[a];
+    else
+      return D - a;
+  };
+  int npairs = single_pair >= 0 ? 1 : D * (D + 1) / 2;
+  if constexpr (PRUNE) {
+    npairs = 0;
+    for (int a = 0; a < D; ++a) npairs += s_lim[a];
+  }
   const int64_t total = (int64_t)npairs * nks;
 
   // this wavefront's share of a step: operand op_w and kL consecutive 1 KiB
@@ -214,7 +226,7 @@ __device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const
     ++issued;
     if (++lks == nks) {
       lks = 0;
-      if (single_pair < 0 && la + ++lb > D - 1) {
+      if (single_pair < 0 && ++lb >= lim(la)) {
         ++la;
         lb = 0;
       }
@@ -374,6 +386,25 @@ __global__ __launch_bounds__(64 * Layout<LAYOUT>::WM * Layout<LAYOUT>::WN, waves
                                 tn, &lds[0][0]);
 }
 
+// The same with the pairs of each tile chosen from the data: tile (tm, tn)
+// takes pairs (a, b) with b < lims[(tn * tiles_m + tm) * D + a] (a staircase
+// written by launch_tile_pairs).
+template <typename T, int C, int LAYOUT>
+__global__ __launch_bounds__(64 * Layout<LAYOUT>::WM * Layout<LAYOUT>::WN, waves_of(LAYOUT, C, (int)sizeof(T))) void k_gemm_plain_pruned(
+    const T *__restrict__ Apk, const T *__restrict__ Bpk, int64_t mbp, int64_t nbp, int64_t kbp, int m, int n, int D,
+    T *__restrict__ Cout, int ldc, int64_t c_stride, const int8_t *__restrict__ lims) {
+  __shared__ __attribute__((aligned(16))) T lds[stages_of<T>()][stage_elems<T>()];
+  __shared__ int s_lim[kMaxPairLim + 1];
+  int tm, tn;
+  const int tiles_m = (int)(mbp / kTileBlocks);
+  tile_coords(blockIdx.x, gridDim.x, tiles_m, (int)(nbp / kTileBlocks), tm, tn);
+  if (threadIdx.x <= kMaxPairLim)
+    s_lim[threadIdx.x] = (int)threadIdx.x < D ? (int)lims[((int64_t)tn * tiles_m + tm) * D + threadIdx.x] : 0;
+  __syncthreads();
+  gemm_plain_tile<T, C, LAYOUT, true>(Apk, Bpk, mbp, nbp, kbp, m, n, D, Cout, ldc, c_stride, -1, nullptr, 0, tm, tn,
+                                      &lds[0][0], s_lim);
+}
+
 // Persistent batched kernel: each workgroup takes (product, tile) work items
 // from a shared counter until the list is exhausted (items are ordered by
 // decreasing work, so the long tiles start first).
@@ -426,6 +457,31 @@ hipError_t launch_gemm_plain(const void *Apk, const void *Bpk, int64_t mbp, int6
 }
 
 template <typename T, int C>
+hipError_t launch_gemm_plain_pruned(const void *Apk, const void *Bpk, int64_t mbp, int64_t nbp, int64_t kbp, int m,
+                                    int n, int D, T *Cout, int ldc, int64_t c_stride, const int8_t *lims, int layout,
+                                    hipStream_t st) {
+  const int64_t tiles = (mbp / kTileBlocks) * (nbp / kTileBlocks);
+  if (tiles <= 0) return hipSuccess;
+  if (D < 1 || D > kMaxPairLim) return hipErrorInvalidValue;
+  const T *a = static_cast<const T *>(Apk);
+  const T *b = static_cast<const T *>(Bpk);
+  switch (layout) {
+    case 2:
+      hipLaunchKernelGGL((k_gemm_plain_pruned<T, C, 2>), dim3((unsigned)tiles), dim3(threads_of(2)), 0, st, a, b, mbp,
+                         nbp, kbp, m, n, D, Cout, ldc, c_stride, lims);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_gemm_plain_pruned<T, C, 3>), dim3((unsigned)tiles), dim3(threads_of(3)), 0, st, a, b, mbp,
+                         nbp, kbp, m, n, D, Cout, ldc, c_stride, lims);
+      break;
+    default:
+      hipLaunchKernelGGL((k_gemm_plain_pruned<T, C, 1>), dim3((unsigned)tiles), dim3(threads_of(1)), 0, st, a, b, mbp,
+                         nbp, kbp, m, n, D, Cout, ldc, c_stride, lims);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int C>
 hipError_t launch_gemm_plain_batched(const PlainGemmDesc *descs, const int2 *items, int nitems, int *counter,
                                      int grid, int layout, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
@@ -449,7 +505,9 @@ hipError_t launch_gemm_plain_batched(const PlainGemmDesc *descs, const int2 *ite
   template hipError_t launch_gemm_plain<T, C>(const void *, const void *, int64_t, int64_t, int64_t, int, int, int, \
                                               T *, int, int64_t, int, double *, int, int, hipStream_t);              \
   template hipError_t launch_gemm_plain_batched<T, C>(const PlainGemmDesc *, const int2 *, int, int *, int, int,    \
-                                                      hipStream_t);
+                                                      hipStream_t);                                                 \
+  template hipError_t launch_gemm_plain_pruned<T, C>(const void *, const void *, int64_t, int64_t, int64_t, int, int, \
+                                                     int, T *, int, int64_t, const int8_t *, int, hipStream_t);
 MP_GEMM_INST(double, 2)
 MP_GEMM_INST(double, 3)
 MP_GEMM_INST(double, 4)

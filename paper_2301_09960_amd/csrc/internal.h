@@ -131,6 +131,33 @@ hipError_t launch_gemm_plain(const void *Apk, const void *Bpk, int64_t mbp, int6
                              int D, T *Cout, int ldc, int64_t c_stride, int single_pair, double *Cdbg, int lddbg,
                              int layout, hipStream_t st);
 
+// The fused GEMM with a pair set per 64 x 64 tile: tile (tm, tn) forms the
+// pairs (a, b) (0-based) with b < lims[(tn * tiles_m + tm) * D + a], a
+// staircase within D x D (D <= kMaxPairLim), written by launch_tile_pairs.
+template <typename T, int C>
+hipError_t launch_gemm_plain_pruned(const void *Apk, const void *Bpk, int64_t mbp, int64_t nbp, int64_t kbp, int m,
+                                    int n, int D, T *Cout, int ldc, int64_t c_stride, const int8_t *lims, int layout,
+                                    hipStream_t st);
+
+// Pair sets from the data (binary64/binary32 slices, D passes done): for each
+// 64 x 64 tile of C, the fewest pairs whose left-out bounds, added to the
+// remainder and rounding terms of the certificate, keep every entry of the
+// tile within 2^-t of its lower bound of (|A||B|)_ij.  raw: the binary64
+// product |A_0| |B_0| (m x n, leading dimension m); rs_a / cs_b: row sums of
+// |A_0| and column sums of |B_0|.  Writes lims (tiles x D bytes, tile index
+// tn * tiles_m + tm).
+hipError_t launch_tile_pairs(int m, int n, int k, int D, int rho, int S, int comps, int t, const int *eA,
+                             const int *eB, const double *rs_a, const double *cs_b, const double *raw,
+                             int64_t tiles_m, int64_t tiles_n, int8_t *lims, hipStream_t st);
+
+// The certificate's pieces (certify.hip) without its final pass: |A_0| and
+// |B_0| packed into pack_a / pack_b, the row and column sums into rs_a / cs_b,
+// and the single-pair product |A_0| |B_0| into raw (two planes of m x n).
+template <typename T>
+hipError_t launch_abs_lead_product(const SplitOperand<T> &a, const SplitOperand<T> &b, int m, int n, double *raw,
+                                   double *pack_a, double *pack_b, double *rs_a, double *cs_b, int layout,
+                                   hipStream_t st);
+
 // INT8 form GEMM: diagonal sums S_g into Sws (D x nchunks planes of m x n
 // int32), then their exact combination into C.  debug_g > 0 writes S_g for
 // that g as int64 into Sdbg instead of forming C.
@@ -155,10 +182,15 @@ inline int int8_tile_blocks(int cfg) { return cfg == 1 ? 4 : 8; }
 // reused) and rs_a / cs_b (m and n doubles) are scratch.
 // int8: the split was the INT8 digit split (exps: E per vector); a and b then
 // carry the binary64 packed geometry (nbp, kbp) for |A_0| and |B_0|.
+// lims (may be NULL): the per-tile pair sets of launch_tile_pairs the product
+// was formed with (pairs outside them count as left out), else the triangle.
+// raw_ready: the |A_0| |B_0| product and the sums are already in cert plane 0
+// and rs_a / cs_b (the pair sets were chosen from them).
 template <typename T>
 hipError_t launch_certify(const SplitOperand<T> &a, const SplitOperand<T> &b, int m, int n, int k, int D, int rho,
                           int comps, int int8, double *cert, double *worst, double *pack_a, double *pack_b,
-                          double *rs_a, double *cs_b, int layout, hipStream_t st);
+                          double *rs_a, double *cs_b, int layout, hipStream_t st, const int8_t *lims = nullptr,
+                          bool raw_ready = false);
 
 // LU of a DD (comps = 2) or TD (comps = 3) matrix (comps planes of ld x n,
 // `plane` doubles apart): panel step at column j0 with width K (diagonal block,

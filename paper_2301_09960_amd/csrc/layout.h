@@ -33,6 +33,7 @@ constexpr int kTileBlocks8 = 8;   // largest INT8 tile: 8 blocks (256 rows); the
 constexpr int kKStepBlocks8 = 4;  // INT8 k padding unit: 4 k-blocks (128), a multiple of every k step
 constexpr int kTileBlocks = 4;  // GEMM tile = 4 x 4 blocks (64 x 64)
 constexpr int kKStepBlocks = 2; // GEMM k step = 2 k-blocks (32)
+constexpr int kMaxPairLim = 16; // most slices of the data-chosen pair sets (per-tile staircases)
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
