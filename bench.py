@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-certify", action="store_true", help="skip the certified calls")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
-    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-requests", type=int, default=2000, help="served requests timed (after a tenth as many)")
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows of C in the CPU sample (0: auto)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 1 GiB (for scaling HBM counters)")

@@ -159,7 +159,9 @@ __device__ __forceinline__ mc<C> mc_sub_scaled(const mc<C> &r, double q, const m
 
 // C quotient digits: after them the remainder is near 2^(-53 C) |a|, so the
 // next digit would only move the result by about the rounding of its last
-// component.
+// component.  For C = 3 the relative error stays below 2^-155 (a host test
+// checks it against exact rationals; 2^-158.7 at worst on random operands,
+// against about 2^-105 with two digits).
 template <int C>
 __device__ __forceinline__ mc<C> mc_div(const mc<C> &a, const mc<C> &b) {
   double q[C];

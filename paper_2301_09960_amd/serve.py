@@ -3,20 +3,25 @@
 Requests (format uniform over DD/TD/QD, m, n, k log-uniform in [lo, hi],
 entries with exponent spread e ~ U{0..8}) arrive by a seeded Poisson process.
 The server admits a waiting request as soon as a stream slot is free and its
-device memory fits the HBM budget; the ledger charges its inputs, output and
-library workspace (``mpgemm_workspace_bytes``) and releases them at
-completion.  Admitted requests run concurrently, one per HIP stream, so work
-of requests that arrive while others are on the GPU overlaps on the device;
-their operands, slices and results stay resident in HBM.  Latency is measured
-from arrival to the completion event.
+device memory fits the HBM budget.  Admitted requests run concurrently, one
+per HIP stream, so work of requests that arrive while others are on the GPU
+overlaps on the device.  Latency is measured from arrival to the completion
+event and includes staging the operands.
 
-Operands come from a device pool of synthetic values generated once: each
-request takes seeded offsets into the pool, and its operands and output are
-staged in HBM before the clock starts (requests arrive with their data already
-on the device).  Each stream slot owns a library workspace sized for the
-largest request, attached before each call (``set_workspace``): the request
-path holds no host work and no allocation (a stream-ordered allocation inside
-the library could otherwise wait for the other streams under load).
+Device memory and the ledger:
+* Operands come from a device pool of synthetic values generated once (the
+  requests' source data, outside the budget).  At admission a request's
+  operands are copied out of the pool and its output allocated, on its
+  stream; they are charged to the ledger in the caching allocator's 512-byte
+  units and released at completion.  Its slices and the product's other
+  temporaries live in the stream slot's workspace.
+* Each stream slot owns a library workspace sized for the largest request of
+  the run, allocated when the run starts and charged to the ledger for the
+  whole run (a stream-ordered allocation inside the library could otherwise
+  wait for the other streams under load).
+So the device memory the server holds beyond the pool never exceeds the
+ledger, and the ledger never exceeds the budget (a test checks
+torch.cuda.memory_allocated against it at every admission and completion).
 
 Run a rate sweep: ``python -m paper_2301_09960_amd.serve --sweep``.
 """
@@ -53,6 +58,7 @@ class Request:
     A: object = None
     B: object = None
     C: object = None
+    kept: object = None  # the result, when the run keeps results
     event: object = None
     stream_slot: int = -1
 
@@ -138,6 +144,8 @@ def batch_operands(pool: DevicePool, fmt: str, count: int = 512, seed: int = 31,
 class Server:
     """Admits requests under an HBM budget onto a fixed set of streams."""
 
+    UNIT = 512  # allocation granularity of torch's caching allocator
+
     def __init__(self, pool: DevicePool, budget_gb: float = 64.0, streams: int = 8, mode: str = "float"):
         import torch
         self.pool = pool
@@ -148,47 +156,67 @@ class Server:
         self.streams = [torch.cuda.Stream() for _ in range(streams)]
         self.free_slots = deque(range(streams))
         self.ws = [None] * streams  # per-slot library workspace
+        self.on_change = None  # called with the server after every admission and completion
+
+    @classmethod
+    def units(cls, nbytes: int) -> int:
+        return -(-max(int(nbytes), 1) // cls.UNIT) * cls.UNIT
 
     def cost(self, r: Request) -> int:
+        """Bytes a request holds while admitted: its operand copies and output."""
         c = COMPONENTS[r.fmt]
-        return 8 * c * (r.m * r.k + r.k * r.n + r.m * r.n) + workspace_bytes(r.fmt, self.mode, r.m, r.n, r.k)
+        return self.units(8 * c * r.m * r.k) + self.units(8 * c * r.k * r.n) + self.units(8 * c * r.m * r.n)
+
+    def reserve(self, reqs):
+        """One workspace per stream slot, for the largest request of the run,
+        charged to the ledger for the whole run."""
+        import torch
+        need = self.units(max(workspace_bytes(r.fmt, self.mode, r.m, r.n, r.k) for r in reqs))
+        if self.ledger + len(self.ws) * need > self.budget:
+            raise ValueError(f"slot workspaces of {len(self.ws) * need / GB:.2f} GB exceed the budget")
+        for i in range(len(self.ws)):
+            self.ws[i] = torch.empty(need, dtype=torch.uint8, device="cuda")
+            self.ledger += need
+        self.peak = max(self.peak, self.ledger)
 
     def stage(self, r: Request):
-        """Operands (compact copies out of the pool) and output in HBM."""
+        """Operands (compact copies out of the pool) and output in HBM, on the
+        current stream."""
         import torch
         r.A = self.pool.operand(r.fmt, r.m, r.k, r.a_off)
         r.B = self.pool.operand(r.fmt, r.k, r.n, r.b_off)
         r.C = torch.empty((COMPONENTS[r.fmt], r.n, r.m), dtype=r.A.dtype, device=r.A.device)
-        r.event = torch.cuda.Event()
 
     def launch(self, r: Request, now: float):
+        import torch
         slot = self.free_slots.popleft()
         st = self.streams[slot]
         r.stream_slot = slot
         r.start = now
-        set_workspace(self.ws[slot])
-        try:
-            gemm(r.fmt, r.A, r.B, r.C, mode=self.mode, stream=st)
-        finally:
-            set_workspace(None)
-        r.event.record(st)
         self.ledger += r.bytes
         self.peak = max(self.peak, self.ledger)
+        with torch.cuda.stream(st):
+            self.stage(r)
+            set_workspace(self.ws[slot])
+            try:
+                gemm(r.fmt, r.A, r.B, r.C, mode=self.mode, stream=st)
+            finally:
+                set_workspace(None)
+        r.event = torch.cuda.Event()
+        r.event.record(st)
+        if self.on_change:
+            self.on_change(self)
 
     def run(self, reqs, warmup: int = 0, keep_results: bool = False) -> ServeStats:
         """Replays the arrival trace in real time; returns latency statistics of
         the requests after the first ``warmup``."""
         import torch
+        self.reserve(reqs)
         for r in reqs:
             r.bytes = self.cost(r)
-            if r.bytes > self.budget:
-                raise ValueError(f"request {r.rid} needs {r.bytes / GB:.1f} GB, above the budget")
-        for r in reqs:
-            self.stage(r)
-        need = max(workspace_bytes(r.fmt, self.mode, r.m, r.n, r.k) for r in reqs)
-        for i in range(len(self.ws)):
-            if self.ws[i] is None or self.ws[i].numel() < need:
-                self.ws[i] = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+            if self.ledger + r.bytes > self.budget:
+                raise ValueError(f"request {r.rid} needs {r.bytes / GB:.1f} GB beside the slot workspaces, "
+                                 f"above the budget")
         waiting = deque()
         inflight = []
         pending = deque(reqs)
@@ -209,17 +237,23 @@ class Server:
             for r in inflight:
                 if r.event.query():
                     r.done = time.perf_counter() - t0
-                    self.ledger -= r.bytes
                     self.free_slots.append(r.stream_slot)
                     r.A = r.B = None
-                    if not keep_results:
-                        r.C = None
+                    if keep_results:
+                        r.kept = r.C  # held by the caller from here on, outside the ledger
+                    r.C = None
+                    self.ledger -= r.bytes
+                    if self.on_change:
+                        self.on_change(self)
                 else:
                     still.append(r)
             inflight = still
             if not inflight and not waiting and pending:
                 time.sleep(max(0.0, min(pending[0].arrival - (time.perf_counter() - t0), 0.001)))
         wall = time.perf_counter() - t0
+        for i in range(len(self.ws)):  # the run's reservation ends with it
+            self.ledger -= self.ws[i].numel()
+            self.ws[i] = None
         meas = reqs[warmup:]
         lat = np.array([(r.done - r.arrival) * 1e3 for r in meas])
         span = max(r.done for r in meas) - min(r.arrival for r in meas)
