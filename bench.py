@@ -16,9 +16,13 @@ Extra objects on the JSON line:
   int8         -- the same products with INT8 digit slices on the INT8 matrix
                   cores (precision form), timed the same way; speedup over
                   the binary64-slice form at the same error bound.
+  data_chosen_pairs -- the same products with the slice products chosen
+                  from the data (per-tile pair sets, certified by
+                  construction): call time, mean pairs per tile, certificate.
   batched      -- 512 independent DD (and QD) products with m, n, k each
                   log-uniform in [64, 1024], e ~ U{0..8}, as one graph launch:
-                  sum of 2mnk over the batch / launch time.
+                  sum of 2mnk over the batch / launch time; and 256 DD + 256
+                  QD products as two launches on one stream ("mixed").
   serving      -- Poisson arrivals of DD/TD/QD requests (m, n, k log-uniform in
                   [64, 2048]) under a 64 GB HBM budget at 0.75 of the measured
                   capacity: p50/p99 latency and throughput.
@@ -64,6 +68,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-certify", action="store_true", help="skip the certified calls")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-data", action="store_true", help="skip the data-chosen slice products")
     ap.add_argument("--serve-requests", type=int, default=2000, help="served requests timed (after a tenth as many)")
     ap.add_argument("--cpu-rows", type=int, default=0, help="rows of C in the CPU sample (0: auto)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -355,6 +360,28 @@ def traffic_summary(fetch_dir, write_dir, kernel, algorithmic_bytes, source, lab
     }
 
 
+def run_mixed_batch(mp, torch, pool, mode="float", seed=31):
+    """256 DD and 256 QD products (the first and second halves of the seeded
+    shape sequence), as two graph launches on one stream: sum of 2mnk over
+    the wall time of both."""
+    from paper_2301_09960_amd import serve
+    Ad, Bd, md, nd, kd = serve.batch_operands(pool, "dd", 256, seed)
+    Aq, Bq, mq, nq, kq = serve.batch_operands(pool, "qd", 256, seed, first=256)
+    Cd = mp.gemm_batched("dd", Ad, Bd, mode=mode)
+    Cq = mp.gemm_batched("qd", Aq, Bq, mode=mode)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mp.gemm_batched("dd", Ad, Bd, Cd, mode=mode)
+        mp.gemm_batched("qd", Aq, Bq, Cq, mode=mode)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    flops = float(np.sum(2.0 * md * nd * kd) + np.sum(2.0 * mq * nq * kq))
+    return {"products": "256 dd + 256 qd", "mode": mode, "sum_2mnk": flops, "wall_ms_per_batch": round(ms, 3),
+            "effective_gflops": round(flops / (ms * 1e-3) / 1e9, 1)}
+
+
 def main():
     args = parse()
     if args.traffic:
@@ -499,6 +526,42 @@ def main():
             }
             log(f"certify {f}: {certify[f]}")
 
+    data = None
+    if not args.no_data and all(f != "ts" for f in fmts):
+        # the same products with the slice products chosen from the data
+        # (16 slices, per-tile pair sets, certified by construction): call
+        # time, pairs formed against the automatic triangle, and the
+        # certificate of the result
+        data = {}
+        for f in fmts:
+            sets = mp.debug_pair_sets(f, *inputs[f]).cpu().numpy().astype(np.int64)
+            mp.set_num_slices(f, "float", -1)
+            try:
+                mp.gemm(f, *inputs[f], outs[f])
+                torch.cuda.synchronize()
+                mp.profile_enable(True)
+                for _ in range(2):
+                    mp.gemm(f, *inputs[f], outs[f])
+                torch.cuda.synchronize()
+                mp.profile_enable(False)
+                sp, gm = mp.profile_read()
+                _, _, worst = mp.certify(f, *inputs[f], outs[f])
+                torch.cuda.synchronize()
+            finally:
+                mp.set_num_slices(f, "float", 0)
+            D = slices[f]
+            pairs = float(sets.sum(axis=2).mean())
+            data[f] = {
+                "split_and_selection_ms": round(float(np.mean(sp)), 3),
+                "gemm_kernel_ms": round(float(np.mean(gm)), 3),
+                "call_ms": round(float(np.mean(sp)) + float(np.mean(gm)), 3),
+                "automatic_call_ms": round(stages[f]["split_ms"] + stages[f]["gemm_kernel_ms"], 3),
+                "pairs_per_tile_mean": round(pairs, 2),
+                "automatic_pairs": D * (D + 1) // 2,
+                "log2_worst_bound_ratio": round(float(np.log2(float(worst.cpu()[0]))), 2),
+            }
+            log(f"data-chosen pairs {f}: {data[f]}")
+
     batched = None
     pool = None
     if not args.no_batched or not args.no_serving:
@@ -509,11 +572,15 @@ def main():
         for f in ("dd", "qd"):
             batched[f] = run_batched(mp, torch, pool, f)
             log(f"batched {f}: {batched[f]}")
+        batched["mixed"] = run_mixed_batch(mp, torch, pool)
+        log(f"batched mixed: {batched['mixed']}")
         if not args.no_int8:
             batched["int8"] = {}
             for f in ("dd", "qd"):
                 batched["int8"][f] = run_batched(mp, torch, pool, f, mode="int8")
                 log(f"batched int8 {f}: {batched['int8'][f]}")
+            batched["int8"]["mixed"] = run_mixed_batch(mp, torch, pool, mode="int8")
+            log(f"batched int8 mixed: {batched['int8']['mixed']}")
         mp.batched_cache_clear()
 
     serving = None
@@ -581,6 +648,7 @@ def main():
         "stages": stages,
         "int8": int8,
         "certify": certify,
+        "data_chosen_pairs": data,
         "batched": batched,
         "serving": serving,
         "roofline": roofline,

@@ -107,8 +107,8 @@ def time_layouts(fmt: str, n: int, reps: int = 3, E: int = 16):
     return out
 
 
-def time_int8_tiles(fmt: str, n: int, reps: int = 3, E: int = 16):
-    """INT8-form tile configurations 1..4 (GEMM + combine milliseconds)."""
+def time_int8_tiles(fmt: str, n: int, reps: int = 3, E: int = 16, cfgs=(1, 2, 3, 4, 5)):
+    """INT8-form tile configurations (GEMM + combine milliseconds)."""
     import torch
 
     from workload import gen_pair
@@ -116,7 +116,7 @@ def time_int8_tiles(fmt: str, n: int, reps: int = 3, E: int = 16):
     dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
     C = torch.empty((COMPONENTS[fmt], n, n), dtype=dA.dtype, device="cuda")
     out = {}
-    for cfg in (1, 2, 3, 4):
+    for cfg in cfgs:
         set_int8_tile(cfg)
         gemm(fmt, dA, dB, C, mode="int8")
         torch.cuda.synchronize()

@@ -129,6 +129,67 @@ def test_lu_residual_n512(mp, orc, mode):
     assert worst <= 2.0 ** -95
 
 
+def paper_system(n, seed, c):
+    """Section 4.6's test system: a_ij uniform random on [0, 1) (here with
+    lower components below half an ulp), b = [1, 1/2, ..., 1/n] rounded to c
+    components.  Not diagonally dominant: without pivoting the pivots can be
+    small and the factors grow."""
+    rng = np.random.default_rng(seed)
+    hi = rng.random((n, n))
+    A = np.zeros((c, n, n))
+    A[0] = hi.T
+    prev = hi
+    for r in range(1, c):
+        nxt = (rng.random((n, n)) - 0.5) * np.spacing(prev)
+        A[r] = nxt.T
+        prev = np.abs(nxt) + np.finfo(float).tiny
+    b = np.zeros((c, n))
+    for i in range(1, n + 1):
+        rest = X.Fraction(1, i)
+        for r in range(c):
+            b[r, i - 1] = float(rest)
+            rest -= X.Fraction(b[r, i - 1])
+    return A, b
+
+
+@pytest.mark.parametrize("fmt,mode", [("dd", "float"), ("dd", "int8"), ("td", "float")])
+def test_lu_paper_system_n512(mp, orc, fmt, mode):
+    """Section 4.6's own system at n = 512, K = 128: the exact residual
+    |b - A x| in every row against the componentwise backward-error scale
+    (|L||U||x|)_i of an elimination without pivoting (the growth of the
+    factors included), and the paper's max relative error of x, for DD
+    against the TD solution of the same system."""
+    import torch
+    n, K = 512, 128
+    c = 2 if fmt == "dd" else 3
+    A, b = paper_system(n, seed=46, c=c)
+    dA = torch.from_numpy(A.copy()).cuda()
+    mp.lu(fmt, dA, K, mode=mode)
+    x = mp.lu_solve(fmt, dA, torch.from_numpy(b).cuda()).cpu().numpy()
+    LU = dA.cpu().numpy()[0].T  # leading components, row-major (i, j)
+    assert np.isfinite(LU).all() and np.isfinite(x).all()
+    L = np.tril(LU, -1) + np.eye(n)
+    U = np.triu(LU)
+    scale = np.abs(L) @ (np.abs(U) @ np.abs(x[0])) * (1 + 2.0 ** -40)  # float64: relative error ~ n 2^-53
+    growth = np.max(np.abs(U)) / np.max(np.abs(A[0]))
+    diff, _, _ = orc.exact_check(A, x.reshape(c, 1, n), b.reshape(c, 1, n))
+    ratio = float(np.max(diff[0] / scale))
+    t = {"dd": 100, "td": 150}[fmt]
+    rel = None
+    if fmt == "dd":
+        Ah, bh = paper_system(n, seed=46, c=3)
+        dT = torch.from_numpy(Ah.copy()).cuda()
+        mp.lu("td", dT, K)
+        xt = mp.lu_solve("td", dT, torch.from_numpy(bh).cuda()).cpu().numpy()
+        rel = float(np.max(np.abs((x[0] - xt[0]) + (x[1] - xt[1]) - xt[2]) / np.abs(xt[0])))
+    say(f"{fmt}_lu paper system n={n} K={K} {mode}: growth {growth:.3g}, log2 max |b - A x| / (|L||U||x|) "
+        f"{np.log2(ratio):.1f}" + (f", max relative error of x vs TD {rel:.3g}" if rel is not None else ""))
+    # the Schur products meet 2^-t |L21||U12| per update (n / K of them); the
+    # panels and the substitutions add up to about n roundings of the format
+    # (2^-106 / 2^-159 each, n / 16 in units of 2^-t)
+    assert ratio <= (n / K + n / 16) * 2.0 ** -t
+
+
 def test_lu_edge_cases(mp):
     import torch
     # 1 x 1, and K larger than n

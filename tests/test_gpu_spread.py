@@ -10,7 +10,8 @@
 * The data-chosen pair sets on the benchmark-like inputs of every format and
   on ragged shapes: C within the bound, certificate within it and above the
   exact error entry by entry; the sets are staircases, larger than the
-  automatic triangle where outliers need it and smaller where the data allow.
+  automatic triangle where outliers need it, and much smaller where the data
+  carry fewer bits than the format (lower components zero).
 """
 import numpy as np
 import pytest
@@ -147,23 +148,30 @@ def test_data_chosen_pairs_meet_the_bound(mp, orc, fmt, m, n, k, E):
         f"(automatic triangle {D * (D + 1) // 2})")
 
 
-def test_data_chosen_pairs_fewer_on_narrow_data(mp, orc):
-    """Inputs without exponent spread (e ~ U{0..0}) need fewer pairs than the
-    automatic triangle, whose guard bits cover spreads: the data-chosen sets
-    form fewer slice products, still certified."""
+@pytest.mark.parametrize("fmt,nonzero", [("dd", 1), ("qd", 2)])
+def test_data_chosen_pairs_fewer_on_short_data(mp, orc, fmt, nonzero):
+    """Values with fewer significant bits than the format (DD holding binary64
+    values, QD holding DD values: the lower components zero) run out of
+    slices early: their later slices are exactly zero, so the data-chosen
+    sets form far fewer slice products than the automatic triangle, still
+    certified and within the bound."""
     import torch
-    fmt, m, n, k = "dd", 256, 192, 1024
-    A, B = W.gen_pair(fmt, m, n, k, E=0, seed=77)
+    m, n, k = 256, 192, 1024
+    A, B = W.gen_pair(fmt, m, n, k, E=8, seed=77)
+    A[nonzero:] = 0.0
+    B[nonzero:] = 0.0
     dA, dB = dev(A), dev(B)
     sets = mp.debug_pair_sets(fmt, dA, dB).cpu().numpy().astype(np.int64)
     D = mp.num_slices(fmt, "float", k)
     mean = sets.sum(axis=2).mean()
-    say(f"narrow data: pairs per tile {mean:.1f} (automatic triangle {D * (D + 1) // 2})")
-    assert mean < D * (D + 1) // 2
+    say(f"short data {fmt} ({nonzero} nonzero components): pairs per tile {mean:.1f} "
+        f"(automatic triangle {D * (D + 1) // 2})")
+    assert mean <= 0.5 * D * (D + 1) // 2
     with data_slices(mp, fmt):
         C, cert, worst = mp.certify(fmt, dA, dB)
     torch.cuda.synchronize()
     ok, w, _ = bound(orc, fmt, A, B, C.cpu().numpy())
+    say(f"  worst {w:.1f}, certificate {np.log2(float(worst.cpu()[0])):.1f} (bound -{T_BITS[fmt]})")
     assert ok and float(worst.cpu()[0]) <= 2.0 ** -T_BITS[fmt]
 
 
