@@ -136,18 +136,29 @@ def cpu_baseline(n, E, rows_req):
     import workload as W
     A, B = W.gen_pair("dd", n, n, n, E=E, seed=2023)
     D = 6
-    rows = rows_req or 2 * oracle.threads()  # about 10 s of CPU work
+    cores = oracle.threads()
+    rows = rows_req or 2 * cores  # about 10 s of CPU work
     t0 = time.perf_counter()
     oracle.ozaki_gemm(A, B, D, rows=list(range(rows)))
     dt = time.perf_counter() - t0
     flops = 2.0 * rows * n * n
+    # the same on one core, on 2 rows
+    oracle.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        oracle.ozaki_gemm(A, B, D, rows=[0, 1])
+        dt1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(cores)
     return {
         "value": flops / dt / 1e9,
         "unit": "GFLOP/s (effective 2mnk/s)",
-        "cores": oracle.threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": f"DD n={n} E~U{{0..{E}}} D={D}: full split of B, split of {rows} rows of A, exact slice products "
                   f"and exact accumulation for {rows} x {n} entries of C ({dt:.1f} s)",
+        "one_core": {"value": 2.0 * 2 * n * n / dt1 / 1e9, "cores": 1,
+                     "sample": f"the same for 2 rows of C on one thread ({dt1:.1f} s)"},
     }
 
 

@@ -18,7 +18,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# ORACLE_LIB names another build of oracle.c (the sanitizer run of the oracle's tests)
+LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 ZERO_EXP = -(2 ** 31)
 C_OF = {"dd": 2, "td": 3, "qd": 4, "ts": 3}
 
@@ -61,6 +62,8 @@ def lib():
         L.oracle_ds_round.argtypes = [_I, _L, _L, _P, _P, _P]
         L.oracle_gemm_naive_ds.argtypes = [_I, _I, _I, _P, _P, _P, _P, _P, _I, _P, _P]
         L.oracle_omp_threads.restype = _I
+        L.oracle_set_threads.argtypes = [_I]
+        L.oracle_set_threads.restype = _I
         _lib = L
     return _lib
 
@@ -72,6 +75,11 @@ def _ptr(a):
 def _check(status, what):
     if status != 0:
         raise RuntimeError(f"oracle {what} failed with status {status}")
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's later parallel loops; returns the count in effect."""
+    return int(lib().oracle_set_threads(int(n)))
 
 
 def threads() -> int:

@@ -1142,3 +1142,16 @@ int oracle_omp_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the oracle's later parallel loops (for timing on one core). */
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
