@@ -361,7 +361,7 @@ def bound_report(diff, absab, t: int):
     return ok, (float(np.log2(worst)) if worst > 0 else float("-inf"))
 
 
-def certificate_terms(A, B, D: int, form: str = "float"):
+def certificate_terms(A, B, D: int, form: str = "float", pairs=None):
     """The truncation part of the a-posteriori error bound of the D-slice
     product (Algorithm 1 and the pairs a + b <= D + 1 of Section 3), in exact
     rational arithmetic (small inputs only).  ``form='int8'``: the slices are
@@ -376,6 +376,10 @@ def certificate_terms(A, B, D: int, form: str = "float"):
     rA_i = 2^(eA_D,i + rho - S) (1 + 2^(1 - rho)) bounding the remainder.
     Returns ``(trunc, T1, T23, absab)`` as lists ``[i][j]`` of Fractions: the
     exact |C_tri - AB| from this oracle's slices, T1, T2 + T3, and (|A||B|)_ij.
+
+    ``pairs(i, j)``: another pair set per entry instead of the triangle, given
+    as D counts (0-based slice a of A pairs with slices b < counts[a] of B);
+    C_tri is then the sum over that set, and T1 runs over every other pair.
     """
     from fractions import Fraction
 
@@ -422,14 +426,15 @@ def certificate_terms(A, B, D: int, form: str = "float"):
         tr, t1s, t23s, ab = [], [], [], []
         for j in range(n):
             exact = sum((Av[i][p] * Bv[p][j] for p in range(k)), Fraction(0))
+            # 0-based a + b <= D - 1 (1-based a + b <= D + 1), or the given set
+            counts = [D - a for a in range(D)] if pairs is None else list(pairs(i, j))
             ctri = Fraction(0)
-            for a in range(D):
-                for b in range(D - a):  # 0-based a + b <= D - 1, i.e. 1-based a + b <= D + 1
-                    ctri += sum((SA[a][i][p] * SB[b][j][p] for p in range(k)), Fraction(0))
             t1 = Fraction(0)
-            for a in range(1, D):
-                for b in range(D - a, D):
-                    if ea[a, i] != ZERO_EXP and eb[b, j] != ZERO_EXP:
+            for a in range(D):
+                for b in range(D):
+                    if b < counts[a]:
+                        ctri += sum((SA[a][i][p] * SB[b][j][p] for p in range(k)), Fraction(0))
+                    elif ea[a, i] != ZERO_EXP and eb[b, j] != ZERO_EXP:
                         t1 += p2(ea[a, i] + eb[b, j])
             t1s.append(t1 * k)
             t23s.append(rB[j] * (rs[i] + k * rA[i]) + rA[i] * cs[j])

@@ -1155,7 +1155,7 @@ int mpgemm_set_tile_layout(int fmt, int layout) {
 int mpgemm_tile_layout(int fmt) { return fmt_ok(fmt) ? layout_for(fmt) : -1; }
 
 int mpgemm_set_int8_tile(int cfg) {
-  if (cfg < 0 || cfg > 5) return -1;
+  if (cfg < 0 || cfg > 4) return -1;
   g_opt.int8_tile = cfg;
   return 0;
 }

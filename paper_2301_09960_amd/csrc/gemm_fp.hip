@@ -149,16 +149,25 @@ __device__ __forceinline__ void wait_step(int64_t later) {
   }
 }
 
+// A tile's pair staircase: count a (0..16) in byte a of two 64-bit words,
+// held in scalar registers (no memory access on the pair walk).
+struct Staircase {
+  uint64_t lo, hi;
+  __device__ __forceinline__ int operator()(int a) const {
+    return (int)(((a < 8 ? lo >> (8 * a) : hi >> (8 * (a - 8)))) & 0xff);
+  }
+};
+
 // All slice products of one 64 x 64 tile (tm, tn) of one product, folded into
 // C.  `lds` is the workgroup's ring of stages_of<T>() staging buffers of
 // stage_elems<T>() elements each.  The pairs are (a, b), 0-based, with
 // b < lim(a): the triangle a + b <= D - 1 (lim(a) = D - a), or with PRUNE the
-// tile's own staircase lim(a) = s_lim[a] (non-increasing in a, at most D).
+// tile's own staircase lim(a) = stair(a) (non-increasing in a, at most D).
 template <typename T, int C, int LAYOUT, bool PRUNE = false>
 __device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const T *__restrict__ Bpk, int64_t mbp, int64_t nbp,
                                 int64_t kbp, int m, int n, int D, T *__restrict__ Cout, int ldc, int64_t c_stride,
                                 int single_pair, double *__restrict__ Cdbg, int lddbg, int tm, int tn,
-                                T *lds, const int *s_lim = nullptr) {
+                                T *lds, Staircase stair = Staircase{0, 0}) {
   using M = Mma<T>;
   using acc_t = typename M::acc_t;
   constexpr int WM = Layout<LAYOUT>::WM, WN = Layout<LAYOUT>::WN;
@@ -180,14 +189,14 @@ __device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const
   const int nks = (int)(kbp / kKStepBlocks);
   auto lim = [&](int a) -> int {
     if constexpr (PRUNE)
-      return s_lim[a];
+      return stair(a);
     else
       return D - a;
   };
   int npairs = single_pair >= 0 ? 1 : D * (D + 1) / 2;
   if constexpr (PRUNE) {
     npairs = 0;
-    for (int a = 0; a < D; ++a) npairs += s_lim[a];
+    for (int a = 0; a < D; ++a) npairs += stair(a);
   }
   const int64_t total = (int64_t)npairs * nks;
 
@@ -394,15 +403,25 @@ __global__ __launch_bounds__(64 * Layout<LAYOUT>::WM * Layout<LAYOUT>::WN, waves
     const T *__restrict__ Apk, const T *__restrict__ Bpk, int64_t mbp, int64_t nbp, int64_t kbp, int m, int n, int D,
     T *__restrict__ Cout, int ldc, int64_t c_stride, const int8_t *__restrict__ lims) {
   __shared__ __attribute__((aligned(16))) T lds[stages_of<T>()][stage_elems<T>()];
-  __shared__ int s_lim[kMaxPairLim + 1];
   int tm, tn;
   const int tiles_m = (int)(mbp / kTileBlocks);
   tile_coords(blockIdx.x, gridDim.x, tiles_m, (int)(nbp / kTileBlocks), tm, tn);
-  if (threadIdx.x <= kMaxPairLim)
-    s_lim[threadIdx.x] = (int)threadIdx.x < D ? (int)lims[((int64_t)tn * tiles_m + tm) * D + threadIdx.x] : 0;
-  __syncthreads();
+  // the tile's D counts (uniform), packed a byte each
+  const int8_t *src = lims + ((int64_t)tn * tiles_m + tm) * D;
+  uint64_t lo = 0, hi = 0;
+  for (int a = 0; a < D; ++a) {
+    const uint64_t v = (uint64_t)(uint8_t)src[a];
+    if (a < 8)
+      lo |= v << (8 * a);
+    else
+      hi |= v << (8 * (a - 8));
+  }
+  lo = ((uint64_t)__builtin_amdgcn_readfirstlane((int)(lo >> 32)) << 32) |
+       (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)lo);
+  hi = ((uint64_t)__builtin_amdgcn_readfirstlane((int)(hi >> 32)) << 32) |
+       (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)hi);
   gemm_plain_tile<T, C, LAYOUT, true>(Apk, Bpk, mbp, nbp, kbp, m, n, D, Cout, ldc, c_stride, -1, nullptr, 0, tm, tn,
-                                      &lds[0][0], s_lim);
+                                      &lds[0][0], Staircase{lo, hi});
 }
 
 // Persistent batched kernel: each workgroup takes (product, tile) work items

@@ -82,9 +82,8 @@ __device__ __forceinline__ void wait_step(int64_t later) {
   }
 }
 
-// Tile configurations (in 32 x 32 blocks): TBM x TBN tile of C, WM x WN
-// wavefronts, KSB 32-wide k blocks per pipeline step, NS LDS stages, WPC
-// workgroups per CU the register and LDS budgets are made for.
+// Tile configurations (in 32 x 32 blocks): TB x TB tile of C, WM x WN
+// wavefronts, KSB 32-wide k blocks per pipeline step, NS LDS stages.
 //   config 1: 128 x 128 tile, 4 wavefronts of 64 x 64 (small products)
 //   config 2: 256 x 256 tile, 4 wavefronts of 128 x 128 (accumulators in AGPRs;
 //             LDS traffic per instruction halved)
@@ -93,49 +92,46 @@ __device__ __forceinline__ void wait_step(int64_t later) {
 //   config 3: 256 x 256 tile, 8 wavefronts of 128 x 64, k steps of 128 in a
 //             2-stage ring (half the barriers of 64-wide steps, and 64 KiB
 //             requested per step)
-//   config 5: 256 x 128 tile, 4 wavefronts of 128 x 64 (the wavefront tile of
-//             config 3), k steps of 64 in a 3-stage ring of 72 KiB, so two
-//             workgroups share a CU: one computes while the other waits at
-//             its step barrier or for its loads
 // KSB divides kKStepBlocks8, the k padding unit of the INT8 slices.
 template <int CFG> struct Int8Cfg;
-template <> struct Int8Cfg<1> { static constexpr int TBM = 4, TBN = 4, WM = 2, WN = 2, KSB = 2, NS = 4, WPC = 1; };
-template <> struct Int8Cfg<2> { static constexpr int TBM = 8, TBN = 8, WM = 2, WN = 2, KSB = 2, NS = 4, WPC = 1; };
-template <> struct Int8Cfg<3> { static constexpr int TBM = 8, TBN = 8, WM = 2, WN = 4, KSB = 4, NS = 2, WPC = 1; };
-template <> struct Int8Cfg<4> { static constexpr int TBM = 8, TBN = 8, WM = 4, WN = 4, KSB = 4, NS = 2, WPC = 1; };
-template <> struct Int8Cfg<5> { static constexpr int TBM = 8, TBN = 4, WM = 2, WN = 2, KSB = 2, NS = 3, WPC = 2; };
+template <> struct Int8Cfg<1> { static constexpr int TB = 4, WM = 2, WN = 2, KSB = 2, NS = 4; };
+template <> struct Int8Cfg<2> { static constexpr int TB = 8, WM = 2, WN = 2, KSB = 2, NS = 4; };
+template <> struct Int8Cfg<3> { static constexpr int TB = 8, WM = 2, WN = 4, KSB = 4, NS = 2; };
+template <> struct Int8Cfg<4> { static constexpr int TB = 8, WM = 4, WN = 4, KSB = 4, NS = 2; };
 
 template <int CFG>
 constexpr int int8_stage_bytes() {
-  return (Int8Cfg<CFG>::TBM + Int8Cfg<CFG>::TBN) * Int8Cfg<CFG>::KSB * 1024;  // A panel, then B panel
+  return 2 * Int8Cfg<CFG>::TB * Int8Cfg<CFG>::KSB * 1024;  // A panel, then B panel
 }
 
 // Diagonal sums S_g of one tile (tm, tn) and k chunk, as in the file comment:
-// operand panels (TBM, TBN blocks x KSB k blocks of A_s and of B_t) move
+// operand panels (TB blocks x KSB k blocks of A_s and of B_t) move
 // global -> LDS by direct loads into a ring of NS stages, NS - 1 steps ahead;
 // each step waits for its own loads and passes one barrier.
 //
-// Each wavefront moves kL 1 KiB pieces per step (of A's panel, then B's).
-// Their global offsets from the step's panel bases and their LDS offsets are
-// fixed for the whole tile, so a load costs one 64-bit add; and the loads of
-// the next step are spread evenly between this step's matrix-core
-// instructions, which keeps the matrix cores fed where a burst of LDS-direct
-// loads would stall them.
+// Each wavefront moves kL 1 KiB pieces of one operand per step.  Their global
+// offsets from the step's panel base and their LDS offsets are fixed for the
+// whole tile, so a load costs one 64-bit add; and the loads of the next step
+// are spread evenly between this step's matrix-core instructions (one per
+// kEvery), which keeps the matrix cores fed where a burst of LDS-direct loads
+// would stall them.
 template <int CFG>
 __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, const int8_t *__restrict__ Bpk,
                                                int64_t mbp, int64_t nbp, int64_t kbp, int64_t kb0, int nks, int D,
                                                int m, int n, int32_t *__restrict__ S, int64_t plane, int chunk,
                                                int nchunks, int tm, int tn, int g0, int g1, int8_t *lds) {
   using G = Int8Cfg<CFG>;
-  constexpr int TBM = G::TBM, TBN = G::TBN, WM = G::WM, WN = G::WN, KSB = G::KSB, NS = G::NS;
-  constexpr int BI = TBM / WM, BJ = TBN / WN;
+  constexpr int TB = G::TB, WM = G::WM, WN = G::WN, KSB = G::KSB, NS = G::NS;
+  constexpr int BI = TB / WM, BJ = TB / WN;
   constexpr int NW = WM * WN;
-  constexpr int kPanel = TBM * KSB * 1024;    // A panel bytes; the B panel follows it
-  constexpr int kInst = (TBM + TBN) * KSB;  // 1 KiB wavefront instructions per step
+  constexpr int kPanel = TB * KSB * 1024;
+  constexpr int kInst = 2 * TB * KSB;  // 1 KiB wavefront instructions per step
   constexpr int kL = kInst / NW;
   constexpr int kMma = KSB * BI * BJ;  // matrix-core instructions per wavefront per step
+  constexpr int kEvery = kMma / kL;
   static_assert(kInst % NW == 0, "staging split");
-  static_assert(kL <= kMma, "at most one load beside each matrix-core instruction");
+  static_assert((TB * KSB) % kL == 0, "a wavefront's loads of a step come from one operand");
+  static_assert(kMma % kL == 0, "one load per fixed number of matrix-core instructions");
   static_assert(kKStepBlocks8 % KSB == 0, "k steps tile the padded k");
 
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
@@ -143,30 +139,25 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
   // diagonals g0 .. g1 - 1 (g pairs each)
   const int64_t total = ((int64_t)(g1 - 1) * g1 / 2 - (int64_t)(g0 - 1) * g0 / 2) * nks;
 
-  // this wavefront's share of a step: pieces j = 0..kL-1, piece j of operand
-  // op[j] (the step's pieces are A's TBM x KSB, then B's TBN x KSB)
+  // this wavefront's share of a step: operand op_w, pieces j = 0..kL-1
   const int wave_u = __builtin_amdgcn_readfirstlane(wave);
-  uint32_t goff[kL];  // byte offset from the operand's step panel base (per lane; k <= 2^20 keeps it below 2^32)
+  const int op_w = (wave_u * kL) / (TB * KSB);
+  uint32_t goff[kL];  // byte offset from the step's panel base (per lane; k <= 2^20 keeps it below 2^32)
   int loff[kL];       // byte offset in the stage (uniform)
-  int op[kL];         // 0: A, 1: B (uniform)
 #pragma unroll
   for (int j = 0; j < kL; ++j) {
-    const int q = wave_u * kL + j;
-    op[j] = q >= TBM * KSB ? 1 : 0;
-    const int r = op[j] ? q - TBM * KSB : q;
+    const int r = (wave_u * kL + j) % (TB * KSB);
     const int blk = r / KSB, kb = r % KSB;
     goff[j] = (uint32_t)(((int64_t)blk * kbp + kb) * 1024) + 16u * (uint32_t)lane;
-    loff[j] = op[j] * kPanel + (blk * KSB + kb) * 1024;
+    loff[j] = op_w * kPanel + (blk * KSB + kb) * 1024;
   }
 
   int lg = g0, ls = 1, lks = 0;  // load cursor: diagonal, pair within it, k step
   int64_t issued = 0;
-  // panel bases of the step at the load cursor (A_ls and B_(lg+1-ls))
-  auto base_a = [&]() -> const int8_t * {
-    return Apk + (((int64_t)(ls - 1) * mbp + (int64_t)tm * TBM) * kbp + kb0 + (int64_t)lks * KSB) * 1024;
-  };
-  auto base_b = [&]() -> const int8_t * {
-    return Bpk + (((int64_t)(lg - ls) * nbp + (int64_t)tn * TBN) * kbp + kb0 + (int64_t)lks * KSB) * 1024;
+  // panel base of the step at the load cursor (A_ls or B_(lg+1-ls)), and its ring slot
+  auto panel_base = [&]() -> const int8_t * {
+    return op_w == 0 ? Apk + (((int64_t)(ls - 1) * mbp + (int64_t)tm * TB) * kbp + kb0 + (int64_t)lks * KSB) * 1024
+                     : Bpk + (((int64_t)(lg - ls) * nbp + (int64_t)tn * TB) * kbp + kb0 + (int64_t)lks * KSB) * 1024;
   };
   auto advance = [&]() {
     ++issued;
@@ -191,10 +182,10 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
 #pragma unroll
   for (int s0 = 0; s0 < NS - 1; ++s0)
     if (issued < total) {
-      const int8_t *sa = base_a(), *sb = base_b();
+      const int8_t *src = panel_base();
       int8_t *dst = lds + (issued % NS) * int8_stage_bytes<CFG>();
 #pragma unroll
-      for (int j = 0; j < kL; ++j) load_lds16((op[j] ? sb : sa) + goff[j], dst + loff[j]);
+      for (int j = 0; j < kL; ++j) load_lds16(src + goff[j], dst + loff[j]);
       advance();
     }
 
@@ -204,7 +195,7 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
     __builtin_amdgcn_s_barrier();
     // the step NS - 1 ahead goes into the slot computed in the previous step
     const bool more = issued < total;
-    const int8_t *nsa = more ? base_a() : Apk, *nsb = more ? base_b() : Bpk;
+    const int8_t *nsrc = more ? panel_base() : Apk;
     int8_t *ndst = lds + (issued % NS) * int8_stage_bytes<CFG>();
 
     const int8_t *stage = lds + (step % NS) * int8_stage_bytes<CFG>();
@@ -221,11 +212,8 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
       for (int y = 0; y < BJ; ++y)
 #pragma unroll
         for (int x = 0; x < BI; ++x) {
-          // load j goes beside instruction j kMma / kL (rounded down): evenly spread
           const int mma = (kb * BJ + y) * BI + x;
-          const int jl = (mma * kL + kMma - 1) / kMma;
-          if (jl < kL && (jl * kMma) / kL == mma && more)
-            load_lds16((op[jl] ? nsb : nsa) + goff[jl], ndst + loff[jl]);
+          if (mma % kEvery == 0 && more) load_lds16(nsrc + goff[mma / kEvery], ndst + loff[mma / kEvery]);
           acc[y][x] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fb[y], fa[x], acc[y][x], 0, 0, 0);
           __builtin_amdgcn_sched_barrier(0);  // keep the loads where they were placed
         }
@@ -239,7 +227,7 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
         for (int y = 0; y < BJ; ++y)
 #pragma unroll
           for (int x = 0; x < BI; ++x) {
-            const int64_t bi = (int64_t)tm * TBM + wm * BI + x, bj = (int64_t)tn * TBN + wn * BJ + y;
+            const int64_t bi = (int64_t)tm * TB + wm * BI + x, bj = (int64_t)tn * TB + wn * BJ + y;
             i4v *dst = reinterpret_cast<i4v *>(out + ((bj * mbp + bi) * 64 + lane) * 16);
 #pragma unroll
             for (int v = 0; v < 4; ++v) dst[v] = i4v{acc[y][x][4 * v], acc[y][x][4 * v + 1], acc[y][x][4 * v + 2],
@@ -272,12 +260,13 @@ __device__ __forceinline__ void diagonal_group(int D, int z, int groups, int &g0
 }
 
 template <int CFG>
-__global__ __launch_bounds__(64 * Int8Cfg<CFG>::WM * Int8Cfg<CFG>::WN, Int8Cfg<CFG>::WPC) void k_gemm_int8(
+__global__ __launch_bounds__(64 * Int8Cfg<CFG>::WM * Int8Cfg<CFG>::WN, 1) void k_gemm_int8(
     const int8_t *__restrict__ Apk, const int8_t *__restrict__ Bpk, int64_t mbp, int64_t nbp, int64_t kbp,
     int kb_chunk, int D, int m, int n, int32_t *__restrict__ S, int64_t plane) {
   __shared__ __attribute__((aligned(16))) int8_t lds[Int8Cfg<CFG>::NS * int8_stage_bytes<CFG>()];
+  constexpr int TB = Int8Cfg<CFG>::TB;
   int tm, tn;
-  tile_coords(blockIdx.x, gridDim.x, (int)(mbp / Int8Cfg<CFG>::TBM), (int)(nbp / Int8Cfg<CFG>::TBN), tm, tn);
+  tile_coords(blockIdx.x, gridDim.x, (int)(mbp / TB), (int)(nbp / TB), tm, tn);
   const int chunk = blockIdx.y, nchunks = gridDim.y;
   const int64_t kb0 = (int64_t)chunk * kb_chunk;
   const int64_t kb1 = kb0 + kb_chunk < kbp ? kb0 + kb_chunk : kbp;
@@ -361,8 +350,7 @@ __global__ __launch_bounds__(64 * Int8Cfg<CFG>::WM * Int8Cfg<CFG>::WN, 1) void k
     const Int8GemmDesc *__restrict__ descs, const int4 *__restrict__ items, int nitems, int *__restrict__ counter) {
   __shared__ __attribute__((aligned(16))) int8_t lds[Int8Cfg<CFG>::NS * int8_stage_bytes<CFG>()];
   __shared__ int next;
-  constexpr int TB = Int8Cfg<CFG>::TBM;
-  static_assert(Int8Cfg<CFG>::TBM == Int8Cfg<CFG>::TBN, "batched items address square tiles");
+  constexpr int TB = Int8Cfg<CFG>::TB;
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(counter, 1);
     __syncthreads();
@@ -418,7 +406,7 @@ int int8_kblocks_per_chunk(int D) {
 // the larger tile ran 1.6 to 2 times faster from n = 1024 up
 // (DD and QD at n = 1024, 2048, 3072).
 int int8_tile_config(int64_t m, int64_t n, int cfg) {
-  if (cfg >= 1 && cfg <= 5) return cfg;
+  if (cfg >= 1 && cfg <= 4) return cfg;
   const int64_t area3 = ceil_div(m, 256) * ceil_div(n, 256) * 4, area1 = ceil_div(m, 128) * ceil_div(n, 128);
   return area3 <= 2 * area1 ? 3 : 1;
 }
@@ -436,18 +424,6 @@ hipError_t launch_gemm_int8(const void *Apk, const void *Bpk, const int *EA, con
   const int use = int8_tile_config(m, n, cfg);
   const int tb = int8_tile_blocks(use);
   if (mbp % tb != 0 || nbp % tb != 0) return hipErrorInvalidValue;  // slices padded for another tile
-  if (use == 5) {
-    const int64_t wgs = (mbp / 8) * (nbp / 4) * nchunks;
-    const int groups = wgs >= 512 ? 1 : (int)std::min<int64_t>(D, ceil_div(512, wgs));
-    hipLaunchKernelGGL((k_gemm_int8<5>), dim3((unsigned)((mbp / 8) * (nbp / 4)), (unsigned)nchunks, (unsigned)groups),
-                       dim3(256), 0, st, a, b, mbp, nbp, kbp, kbc, D, m, n, Sws, plane);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    const int64_t blocks = ceil_div(mbp * nbp * 256, 256);
-    hipLaunchKernelGGL((k_int8_combine<C>), dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, st, Sws,
-                       plane, nchunks, D, EA, EB, mbp, nbp, m, n, Cout, ldc, c_stride, debug_g, Sdbg, lddbg);
-    return hipGetLastError();
-  }
   // small products: diagonals (independent sums, each with its own plane) spread
   // over gridDim.z so the grid still fills the chip (256 workgroups of the
   // 256 x 256 configuration, 512 of the smaller ones)

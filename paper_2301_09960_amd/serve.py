@@ -12,12 +12,13 @@ Device memory and the ledger:
 * Operands come from a device pool of synthetic values generated once (the
   requests' source data, outside the budget).  At admission a request's
   operands are copied out of the pool and its output allocated, on its
-  stream; they are charged to the ledger in the caching allocator's 512-byte
-  units and released at completion.  Its slices and the product's other
+  stream; they are charged to the ledger at an upper bound of what the
+  caching allocator holds for them (512-byte units plus a block's possible
+  slack) and released at completion.  Its slices and the product's other
   temporaries live in the stream slot's workspace.
 * Each stream slot owns a library workspace sized for the largest request of
-  the run, allocated when the run starts and charged to the ledger for the
-  whole run (a stream-ordered allocation inside the library could otherwise
+  the run, allocated when the run starts and charged to the ledger, as
+  allocated, for the whole run (a stream-ordered allocation inside the library could otherwise
   wait for the other streams under load).
 So the device memory the server holds beyond the pool never exceeds the
 ledger, and the ledger never exceeds the budget (a test checks
@@ -145,6 +146,7 @@ class Server:
     """Admits requests under an HBM budget onto a fixed set of streams."""
 
     UNIT = 512  # allocation granularity of torch's caching allocator
+    LARGE = 1 << 20  # a block of the allocator's large pool can carry up to this much unsplit slack
 
     def __init__(self, pool: DevicePool, budget_gb: float = 64.0, streams: int = 8, mode: str = "float"):
         import torch
@@ -156,11 +158,17 @@ class Server:
         self.streams = [torch.cuda.Stream() for _ in range(streams)]
         self.free_slots = deque(range(streams))
         self.ws = [None] * streams  # per-slot library workspace
+        self.ws_charge = [0] * streams
         self.on_change = None  # called with the server after every admission and completion
 
     @classmethod
     def units(cls, nbytes: int) -> int:
-        return -(-max(int(nbytes), 1) // cls.UNIT) * cls.UNIT
+        """An upper bound of the device memory torch's caching allocator holds
+        for one tensor of nbytes: rounded to 512 bytes, plus the remainder of
+        a cached block it may hand out unsplit (below 512 bytes in the small
+        pool, below 1 MiB in the large one)."""
+        n = -(-max(int(nbytes), 1) // cls.UNIT) * cls.UNIT
+        return n + (cls.LARGE if n > cls.LARGE else cls.UNIT)
 
     def cost(self, r: Request) -> int:
         """Bytes a request holds while admitted: its operand copies and output."""
@@ -171,12 +179,17 @@ class Server:
         """One workspace per stream slot, for the largest request of the run,
         charged to the ledger for the whole run."""
         import torch
-        need = self.units(max(workspace_bytes(r.fmt, self.mode, r.m, r.n, r.k) for r in reqs))
-        if self.ledger + len(self.ws) * need > self.budget:
+        need = max(workspace_bytes(r.fmt, self.mode, r.m, r.n, r.k) for r in reqs)
+        if self.ledger + len(self.ws) * self.units(need) > self.budget:
             raise ValueError(f"slot workspaces of {len(self.ws) * need / GB:.2f} GB exceed the budget")
         for i in range(len(self.ws)):
+            before = torch.cuda.memory_allocated()
             self.ws[i] = torch.empty(need, dtype=torch.uint8, device="cuda")
-            self.ledger += need
+            # charged as allocated (the allocator rounds and may add a block's slack)
+            self.ws_charge[i] = torch.cuda.memory_allocated() - before
+            self.ledger += self.ws_charge[i]
+        if self.ledger > self.budget:
+            raise ValueError(f"slot workspaces of {self.ledger / GB:.2f} GB exceed the budget")
         self.peak = max(self.peak, self.ledger)
 
     def stage(self, r: Request):
@@ -252,8 +265,9 @@ class Server:
                 time.sleep(max(0.0, min(pending[0].arrival - (time.perf_counter() - t0), 0.001)))
         wall = time.perf_counter() - t0
         for i in range(len(self.ws)):  # the run's reservation ends with it
-            self.ledger -= self.ws[i].numel()
+            self.ledger -= self.ws_charge[i]
             self.ws[i] = None
+            self.ws_charge[i] = 0
         meas = reqs[warmup:]
         lat = np.array([(r.done - r.arrival) * 1e3 for r in meas])
         span = max(r.done for r in meas) - min(r.arrival for r in meas)

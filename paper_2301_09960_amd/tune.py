@@ -107,7 +107,7 @@ def time_layouts(fmt: str, n: int, reps: int = 3, E: int = 16):
     return out
 
 
-def time_int8_tiles(fmt: str, n: int, reps: int = 3, E: int = 16, cfgs=(1, 2, 3, 4, 5)):
+def time_int8_tiles(fmt: str, n: int, reps: int = 3, E: int = 16, cfgs=(1, 2, 3, 4)):
     """INT8-form tile configurations (GEMM + combine milliseconds)."""
     import torch
 

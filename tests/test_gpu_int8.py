@@ -109,7 +109,7 @@ def test_int8_zero_rows_and_chunking(mp, orc):
     assert ok
 
 
-@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
 def test_int8_every_tile_config(mp, orc, cfg):
     """Each INT8 tile configuration gives the exact diagonal sums and a C within
     the bound (sizes span several 256-wide tiles with ragged edges)."""

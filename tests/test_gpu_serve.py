@@ -46,7 +46,7 @@ def test_mix_equals_alone(srv, orc):
 
 def reservation(serve, mp, reqs, streams, mode="float"):
     need = max(mp.workspace_bytes(r.fmt, mode, r.m, r.n, r.k) for r in reqs)
-    return streams * serve.Server.units(need)
+    return streams * serve.Server.units(need)  # an upper bound of the slot workspaces' charge
 
 
 def test_budget_limits_admission(srv):

@@ -76,3 +76,32 @@ def test_left_out_pairs_bounded_by_t1(orc):
     assert all(0 < tr[i][j] <= t1[i][j] for i, j in _entries(m, n))
     # and within a factor 2^6 of it (all second slices share one sign)
     assert all(tr[i][j] * 64 >= t1[i][j] for i, j in _entries(m, n))
+
+
+@pytest.mark.parametrize("fmt,E,D", [("dd", 16, 4), ("qd", 8, 5), ("ts", 16, 5)])
+def test_truncation_within_bound_any_staircase(orc, fmt, E, D):
+    """Pair sets other than the triangle (the per-tile sets chosen from the
+    data): for random staircases per entry, from the empty set to the full
+    D x D square, the exact |C_P - AB| stays within T1 (over every pair left
+    out) + T2 + T3; the full square leaves only the remainder terms, the empty
+    set only |AB| itself."""
+    m, n, k = 4, 3, 11
+    A, B = W.gen_pair(fmt, m, n, k, E=E, seed=31 + D)
+    rng = np.random.default_rng(D)
+    sets = {}
+    for i, j in _entries(m, n):
+        counts = np.sort(rng.integers(0, D + 1, D))[::-1]  # non-increasing: a staircase
+        sets[(i, j)] = [int(c) for c in counts]
+    sets[(0, 0)] = [D] * D
+    sets[(m - 1, n - 1)] = [0] * D
+    tr, t1, t23, absab = orc.certificate_terms(A, B, D, pairs=lambda i, j: sets[(i, j)])
+    for i, j in _entries(m, n):
+        assert tr[i][j] <= t1[i][j] + t23[i][j], (i, j, sets[(i, j)])
+    assert t1[0][0] == 0
+    import oracle.exact as X
+    Av, Bv = X.matrix_values(A), X.matrix_values(B)
+    ab = sum((Av[m - 1][p] * Bv[p][n - 1] for p in range(k)), Fraction(0))
+    assert tr[m - 1][n - 1] == abs(ab)
+    # the triangle given explicitly is the default
+    tri = orc.certificate_terms(A, B, D, pairs=lambda i, j: [D - a for a in range(D)])
+    assert tri == orc.certificate_terms(A, B, D)
