@@ -139,6 +139,7 @@ def main():
     ap.add_argument("--out", default="")
     ap.add_argument("--int8", action="store_true", help="time the INT8-form tile configurations instead")
     ap.add_argument("--slices", action="store_true", help="tune slice counts instead")
+    ap.add_argument("--cfgs", default="1,2,3,4", help="INT8 tile configurations to time (with --int8)")
     args = ap.parse_args()
     if args.slices:
         cases = [(f, "float") for f in ("dd", "td", "qd", "ts")] + [(f, "int8") for f in ("dd", "td", "qd")]
@@ -151,7 +152,8 @@ def main():
     if args.int8:
         for fmt in args.formats.split(","):
             for n in sizes:
-                print(json.dumps({"fmt": fmt, "n": n, "int8_gemm_and_combine_ms": time_int8_tiles(fmt, n, args.reps)}),
+                print(json.dumps({"fmt": fmt, "n": n, "int8_gemm_and_combine_ms": time_int8_tiles(
+                    fmt, n, args.reps, cfgs=[int(c) for c in args.cfgs.split(",")])}),
                       flush=True)
         return
     table = {}
