@@ -150,13 +150,20 @@ def split_vector_py(vec, D: int, f32: bool = False, last_remainder: bool = False
     return slices, exps, R
 
 
+def rne(q: Fraction) -> int:
+    """Nearest integer to the rational q, ties to even."""
+    fl = math.floor(q)
+    frac = q - fl
+    return fl + 1 if frac > Fraction(1, 2) or (frac == Fraction(1, 2) and fl % 2 == 1) else fl
+
+
 def int8_digits_py(comps_list, D: int):
     """INT8 digits of one row/column with exact rationals: ``(digits[len][D], E)``.
 
     Same written rule as the oracle: E = 1 + max ilogb of the leading
-    components; digit s is the leading component of the residual divided by
-    u_s = 2^(E - 6 - 7 (s - 1)) and rounded to nearest (ties to even); the
-    residual keeps the exact remainder and is renormalized after each digit.
+    components; digit s is the exact residual (the whole expansion at s = 1)
+    divided by u_s = 2^(E - 6 - 7 (s - 1)) and rounded to nearest (ties to
+    even), and the residual loses d_s u_s.
     """
     lead = [float(c[0]) for c in comps_list]
     nz = [x for x in lead if x != 0]
@@ -165,17 +172,13 @@ def int8_digits_py(comps_list, D: int):
     E = max(math.frexp(x)[1] for x in nz)  # frexp exponent = ilogb + 1
     out = []
     for comps in comps_list:
-        R = [float(v) for v in comps]
+        R = sum((Fraction(float(v)) for v in comps), Fraction(0))
         digs = []
         for s in range(1, D + 1):
             u = Fraction(2) ** (E - 6 - 7 * (s - 1))
-            q = Fraction(R[0]) / u
-            fl = math.floor(q)
-            frac = q - fl
-            d = fl + 1 if frac > Fraction(1, 2) or (frac == Fraction(1, 2) and fl % 2 == 1) else fl
+            d = rne(R / u)
             digs.append(d)
-            R[0] = float(Fraction(R[0]) - d * u)  # exact: the remainder is representable
-            R = renorm_py(R)
+            R -= d * u
         out.append(digs)
     return out, E
 

@@ -40,7 +40,8 @@
  *   - INT8 slices (not in the paper): E = 1 + max ilogb(x_0) over the row (or
  *     column); digit s (s = 1..D) is Algorithm 1's extraction (x + tau) - tau
  *     on the fixed grid u_s = 2^(E - 6 - 7 (s - 1)) instead of a grid set by
- *     the residual's maximum, i.e. the leading component rounded to nearest
+ *     the residual's maximum, applied to the exact residual (the whole
+ *     expansion, not its leading component): the residual rounded to nearest
  *     on that grid; |digit| <= 64; the rest is dropped.
  *
  * Built with: gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp -shared -fPIC
@@ -800,14 +801,36 @@ done:
 /* ------------------------------------------------------------------------- */
 
 /*
+ * RNE(R / 2^e) for the normalized accumulator R with |R| <= 64.5 * 2^e: the
+ * nearest integer, ties to even (symmetric in the sign).
+ */
+static int rne_quotient(const sacc *R, int e)
+{
+    int sg = sa_sign(R);
+    if (sg == 0)
+        return 0;
+    sacc mag;
+    sa_abs(R, &mag);
+    int q = 0;
+    for (int b = e + 7; b >= e; --b)
+        q = 2 * q + sa_bit(&mag, b);
+    if (sa_bit(&mag, e - 1) && (sa_sticky_below(&mag, e - 1) || (q & 1)))
+        q += 1;
+    return sg < 0 ? -q : q;
+}
+
+/*
  * Split `nvec` vectors (strides as in oracle_split_plain) into D int8 digit
  * planes.  E_v = 1 + max_p ilogb(x_p0) over nonzero leading components
- * (ZERO_EXP if none), so |x_p0| < 2^E_v.  Digit s (s = 1..D) uses the unit
- * u_s = 2^(E_v - 6 - 7 (s - 1)) and is Algorithm 1's extraction on that fixed
- * grid: d_s = RN(lead / u_s) (nearest, ties to even), lead := lead - d_s u_s
- * (exact), then the residual is renormalized as in the plain split.  Hence
- * |d_s| <= 64 and x = sum_s d_s u_s + R_D with |R_D| about u_D / 2.
- * Returns ORC_ENOTEXACT if a digit falls outside [-64, 64].
+ * (ZERO_EXP if none), so |x| < 2^E_v for a normalized expansion.  Digit s
+ * (s = 1..D) uses the unit u_s = 2^(E_v - 6 - 7 (s - 1)) and is the
+ * extraction step of Algorithm 1 on that fixed grid applied to the exact
+ * residual: with R the exact value of the element (the sum of its components)
+ * at s = 1, d_s = RN(R / u_s) (nearest, ties to even) and R := R - d_s u_s.
+ * Hence sum_{t <= s} d_t u_t = RN(x / u_s) u_s for every s, |d_s| <= 64 and
+ * the remainder after D digits is at most u_D / 2.  The residual is held
+ * exactly in the long accumulator.  Returns ORC_ENOTEXACT if a digit falls
+ * outside [-64, 64] (an input that is not a normalized expansion).
  */
 int oracle_split_int8(int nvec, int len, int c, const double *X, long s_vec, long s_elt, long s_comp, int D,
                       int8_t *digits, int *exps)
@@ -825,21 +848,24 @@ int oracle_split_int8(int nvec, int len, int c, const double *X, long s_vec, lon
                 E = ilogb(x0) + 1;
         }
         exps[v] = E;
+        sacc R;
         for (int p = 0; p < len; ++p) {
             int8_t *dst = digits + v * s_vec + p * s_elt;
-            double R[ORC_MAXC];
+            sa_clear(&R);
             for (int r = 0; r < c; ++r)
-                R[r] = X[r * s_comp + v * s_vec + p * s_elt];
+                sa_add(&R, X[r * s_comp + v * s_vec + p * s_elt]);
             for (int d = 1; d <= D; ++d) {
                 int val = 0;
                 if (E != ZERO_EXP) {
                     const int ue = E - 6 - 7 * (d - 1);
-                    const double q = nearbyint(ldexp(R[0], -ue));
-                    if (fabs(q) > 64.0)
+                    sa_norm(&R);
+                    val = rne_quotient(&R, ue);
+                    if (val < -64 || val > 64) {
+#pragma omp atomic write
                         status = ORC_ENOTEXACT;
-                    val = (int)q;
-                    R[0] = R[0] - ldexp(q, ue); /* exact */
-                    renorm(R, c);
+                        val = 0;
+                    }
+                    sa_dep_u64(&R, val > 0, (uint64_t)(val < 0 ? -val : val), ue); /* R -= val u_s, exact */
                 }
                 dst[(d - 1) * plane] = (int8_t)val;
             }

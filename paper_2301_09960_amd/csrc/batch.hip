@@ -456,7 +456,7 @@ int build_plan_int8(BatchPlan &p, int cfg_override) {
   hipError_t e = launch_split_int8_batched<C>(
       reinterpret_cast<const SplitOperand<double> *>(p.ws + p.off_ops),
       reinterpret_cast<const int *>(p.ws + p.off_prefix0), reinterpret_cast<const int *>(p.ws + p.off_prefixp),
-      p.nops, p.tiles0, p.blocks8, p.ws + p.off_mu, (int64_t)(p.mu_bytes / 4), cs);
+      p.nops, p.tiles0, p.blocks8, p.dmax, p.ws + p.off_mu, (int64_t)(p.mu_bytes / 4), cs);
   if (e == hipSuccess) e = launch_fill32(p.ws + p.off_counter, 2, 0u, cs);
   if (e == hipSuccess)
     e = launch_int8_batched<C>(reinterpret_cast<const Int8GemmDesc *>(p.ws + p.off_descs),

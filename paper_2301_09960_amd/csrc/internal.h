@@ -103,13 +103,13 @@ hipError_t launch_gemm_plain_batched(const PlainGemmDesc *descs, const int2 *ite
 template <int C>
 hipError_t launch_split_int8(const SplitOperand<double> &a, const SplitOperand<double> &b, int D, hipStream_t st);
 
-// INT8 digit split of many operands at once (operand i: ops[i].D digits).
-// prefix_max0: running sums of each operand's 64 x 64 max-kernel tiles;
-// prefix_blk: running sums of its 32 x 32 packed blocks (nbp * kbp).
+// INT8 digit split of many operands at once (operand i: ops[i].D digits, at
+// most dmax).  prefix_max0: running sums of each operand's 64 x 64 max-kernel
+// tiles; prefix_blk: running sums of its 32 x 32 packed blocks (nbp * kbp).
 template <int C>
 hipError_t launch_split_int8_batched(const SplitOperand<double> *ops, const int *prefix_max0, const int *prefix_blk,
-                                     int nops, int tiles_max0, int64_t blocks, void *mu_all, int64_t mu_words,
-                                     hipStream_t st);
+                                     int nops, int tiles_max0, int64_t blocks, int dmax, void *mu_all,
+                                     int64_t mu_words, hipStream_t st);
 
 // INT8-form batch: persistent GEMMs over items (product, tile, k chunk,
 // diagonal group): items[0, nitems1) in the 128 x 128 configuration (their

@@ -465,10 +465,23 @@ template hipError_t launch_split_plain<float, 3>(const SplitOperand<float> &, co
 
 // ---------------------------------------------------------------------------
 // INT8 digit split (the precision form).  Per vector: E = 1 + ilogb(max |x_0|)
-// (the frexp exponent of the maximum, so |x_0| < 2^E), then for s = 1..D the
-// extraction step of Algorithm 1 on the fixed grid u_s = 2^(E - 6 - 7 (s - 1)):
-// d_s = RN(lead / u_s), lead := lead - d_s u_s (exact), renormalize.  All D
-// digits of an element come from one read of its components.  |d_s| <= 64.
+// (the frexp exponent of the maximum, so |x| < 2^E), then digit s (s = 1..D)
+// is the extraction step of Algorithm 1 on the fixed grid
+// u_s = 2^(E - 6 - 7 (s - 1)) applied to the exact residual: with
+// W_s = RN(x / u_s) (nearest, ties to even) and W_0 = 0, d_s = W_s - 128 W_{s-1},
+// so |d_s| <= 64 and sum_{t <= s} d_t u_t = W_s u_s.
+//
+// No floating-point step is taken.  The element's value is formed exactly as
+// the two's complement integer N = floor(x / 2^P) in NW 32-bit words, with
+// P = E - 7 Dw (Dw >= D: the digits the window holds), and a flag for a
+// nonzero remainder below 2^P.  For a normalized expansion only the first
+// component whose last bit lies below 2^P has bits there, and the components
+// after it add less than that last bit, so the remainder is that component's
+// cut-off bits moved by the sign of the first nonzero component after it.
+// In window bits, digit s has its 7 bits b_s at 7 (Dw - s) + 1, its half bit
+// h_s at 7 (Dw - s), and rounds up (r_s = 1) when h_s is set and anything
+// below it is nonzero or b_s is odd; then d_s = b_s + r_s - 128 r_{s-1}, with
+// r_0 the sign bit (bit 7 Dw).
 //
 // One workgroup per 32 x 32 block of one operand.  Thread T owns bytes
 // 4T .. 4T+3 of the block in every digit plane: with l = T / 4 and q = T % 4
@@ -478,8 +491,110 @@ template hipError_t launch_split_plain<float, 3>(const SplitOperand<float> &, co
 // ---------------------------------------------------------------------------
 namespace {
 
-template <int C, int ORIENT>
-__device__ void int8_block(const SplitOperand<double> &op, int64_t blk, int D) {
+// Digits a window of NW words holds.
+template <int NW>
+constexpr int window_digits() {
+  return (32 * NW - 1) / 7;
+}
+
+// Smallest window (of the instantiated sizes) for D digits: 4..9 words for the
+// DD/TD/QD formats (D <= 41), 13 or 25 for longer expansions (D <= 114).
+int window_words(int D) {
+  for (int nw : {4, 5, 6, 7, 8, 9, 13, 25})
+    if ((32 * nw - 1) / 7 >= D) return nw;
+  return 0;
+}
+
+// x = M 2^q exactly, |M| < 2^53 (zero gives M = 0).
+__device__ __forceinline__ void binary64_parts(double x, int64_t &M, int &q) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const int ef = (int)((b >> 52) & 0x7ff);
+  const int64_t f = (int64_t)(b & 0xfffffffffffffULL);
+  const int64_t m = ef == 0 ? f : (f | (int64_t(1) << 52));
+  q = ef == 0 ? -1074 : ef - 1075;
+  M = (b >> 63) ? -m : m;
+}
+
+// w += M 2^off over all NW words (two's complement; off >= 0).
+template <int NW>
+__device__ __forceinline__ void window_add(uint32_t (&w)[NW], int64_t M, int off) {
+  uint32_t carry = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    const int t = 32 * i - off;  // bit of M at bit 0 of word i
+    uint32_t part;
+    if (t >= 64)
+      part = M < 0 ? 0xffffffffu : 0u;
+    else if (t >= 0)
+      part = (uint32_t)(M >> t);
+    else if (t > -32)
+      part = (uint32_t)((uint64_t)M << (-t));
+    else
+      part = 0u;
+    const uint64_t sum = (uint64_t)w[i] + part + carry;
+    w[i] = (uint32_t)sum;
+    carry = (uint32_t)(sum >> 32);
+  }
+}
+
+// N = floor(x / 2^P) of the c components R[0..c-1] (a normalized expansion)
+// into w, and whether x - N 2^P is nonzero.
+template <int CMAX, int NW>
+__device__ __forceinline__ void value_window(const double (&R)[CMAX], int c, int P, uint32_t (&w)[NW], bool &below) {
+#pragma unroll
+  for (int i = 0; i < NW; ++i) w[i] = 0u;
+  bool cut = false, cut_bits = false;
+  int tail = 0;  // sign of the first nonzero component after the cut one
+#pragma unroll
+  for (int r = 0; r < CMAX; ++r) {
+    if (r >= c) break;
+    const double x = R[r];
+    if (x == 0.0) continue;
+    if (cut) {
+      if (tail == 0) tail = x < 0.0 ? -1 : 1;
+      continue;
+    }
+    int64_t M;
+    int q;
+    binary64_parts(x, M, q);
+    int off = q - P;
+    if (off < 0) {  // bits below 2^P: floor, and whether any was cut off
+      const int sh = -off;
+      cut_bits = sh >= 64 ? true : (M & ((int64_t(1) << sh) - 1)) != 0;
+      M = sh >= 64 ? (M < 0 ? -1 : 0) : (M >> sh);
+      off = 0;
+      cut = true;
+    }
+    window_add<NW>(w, M, off);
+  }
+  below = false;
+  if (cut) {
+    if (!cut_bits && tail < 0) {  // a remainder of 0 moved below zero: borrow
+      window_add<NW>(w, -1, 0);
+      below = true;
+    } else {
+      below = cut_bits || tail != 0;
+    }
+  }
+}
+
+template <int NW>
+__device__ __forceinline__ uint32_t window_bit(const uint32_t (&w)[NW], int j) {
+  return (w[j >> 5] >> (j & 31)) & 1u;
+}
+
+// bits j .. j + 6
+template <int NW>
+__device__ __forceinline__ uint32_t window_bits7(const uint32_t (&w)[NW], int j) {
+  const int i = j >> 5, o = j & 31;
+  uint32_t v = w[i] >> o;
+  if (o > 25 && i + 1 < NW) v |= w[i + 1] << (32 - o);
+  return v & 127u;
+}
+
+template <int CMAX, int NW, int ORIENT>
+__device__ void int8_block(const SplitOperand<double> &op, int64_t blk, int D, int c) {
+  constexpr int Dw = window_digits<NW>();
   // A (rows, contiguous along the row index): walk row blocks fastest;
   // B (columns, contiguous along k): walk k blocks fastest.
   const int64_t vb = ORIENT == 0 ? blk % op.nbp : blk / op.kbp;
@@ -495,57 +610,106 @@ __device__ void int8_block(const SplitOperand<double> &op, int64_t blk, int D) {
     (void)frexp(from_bits(mu[v], 0.0), &ex);
     E = ex;
   }
-  double R[4][C];
-  bool live[4];
+  const int P = E != kZeroExp ? E - 7 * Dw : 0;
+  uint32_t w[4][NW];
+  bool below[4];
+  uint32_t anyw[4];  // bit i: a nonzero word below word i
+  int rprev[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int p = p0 + j;
-    live[j] = v < op.nvec && p < op.len && E != kZeroExp;
+    const bool live = v < op.nvec && p < op.len && E != kZeroExp;
+    double R[CMAX];
 #pragma unroll
-    for (int r = 0; r < C; ++r)
-      R[j][r] = live[j] ? op.X[r * op.comp_stride + (int64_t)v * op.sv + (int64_t)p * op.sp] : 0.0;
+    for (int r = 0; r < CMAX; ++r)
+      R[r] = live && r < c ? op.X[r * op.comp_stride + (int64_t)v * op.sv + (int64_t)p * op.sp] : 0.0;
+    value_window<CMAX, NW>(R, c, P, w[j], below[j]);
+    uint32_t run = 0u, m = 0u;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      m |= (run != 0u ? 1u : 0u) << i;
+      run |= w[j][i];
+    }
+    anyw[j] = m;
+    rprev[j] = (int)window_bit(w[j], 7 * Dw);  // the sign: W_0 = 0
   }
   int8_t *dst = static_cast<int8_t *>(op.packed) + (vb * op.kbp + kb) * 1024 + 4 * T;
   const int64_t plane = op.nbp * op.kbp * 1024;
-#pragma unroll 1
-  for (int s = 1; s <= D; ++s) {
-    const int ue = E - 6 - 7 * (s - 1);
+  // every digit the window holds is formed (the bit positions are then
+  // constants); the first D are stored
+#pragma unroll
+  for (int s = 1; s <= Dw; ++s) {
+    const int ph = 7 * (Dw - s);  // half bit of digit s
     unsigned int word = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      if (live[j]) {
-        const double qd = rint(ldexp(R[j][0], -ue));
-        word |= (unsigned int)(uint8_t)(int8_t)(int)qd << (8 * j);
-        R[j][0] = R[j][0] - ldexp(qd, ue);  // exact
-        renorm<double, C>(R[j]);
-      }
+      const uint32_t b = window_bits7(w[j], ph + 1);
+      const uint32_t h = window_bit(w[j], ph);
+      const bool st = below[j] || ((anyw[j] >> (ph >> 5)) & 1u) || (w[j][ph >> 5] & ((1u << (ph & 31)) - 1u)) != 0u;
+      const int r = (int)(h & ((st ? 1u : 0u) | (b & 1u)));
+      const int d = (int)b + r - 128 * rprev[j];
+      rprev[j] = r;
+      word |= (unsigned int)(uint8_t)(int8_t)d << (8 * j);
     }
-    *reinterpret_cast<unsigned int *>(dst + (int64_t)(s - 1) * plane) = word;
+    if (s <= D) *reinterpret_cast<unsigned int *>(dst + (int64_t)(s - 1) * plane) = word;
   }
   if (p0 == 0 && v < op.nvec) op.exps[v] = E;
 }
 
-template <int C>
+template <int CMAX, int NW>
 __global__ __launch_bounds__(kThreads) void k_split_int8(SplitOperand<double> a, SplitOperand<double> b,
-                                                         int64_t blocks_a, int D) {
+                                                         int64_t blocks_a, int D, int c) {
   const int64_t blk = (int64_t)blockIdx.x;
   if (blk < blocks_a)
-    int8_block<C, 0>(a, blk, D);
+    int8_block<CMAX, NW, 0>(a, blk, D, c);
   else
-    int8_block<C, 1>(b, blk - blocks_a, D);
+    int8_block<CMAX, NW, 1>(b, blk - blocks_a, D, c);
 }
 
-// Batched: workgroup b takes block b - prefix[i] of operand i.
-template <int C>
+// Batched: workgroup b takes block b - prefix[i] of operand i (ops[i].D digits;
+// the window holds the batch's largest D).
+template <int C, int NW>
 __global__ __launch_bounds__(kThreads) void k_split_int8_batched(const SplitOperand<double> *ops, const int *prefix,
                                                                  int nops) {
   const int i = find_operand(prefix, nops, blockIdx.x);
   const SplitOperand<double> &op = ops[i];
   const int64_t local = (int64_t)blockIdx.x - prefix[i];
   if (op.orient == 0)
-    int8_block<C, 0>(op, local, op.D);
+    int8_block<C, NW, 0>(op, local, op.D, C);
   else
-    int8_block<C, 1>(op, local, op.D);
+    int8_block<C, NW, 1>(op, local, op.D, C);
+}
+
+// Digit kernel for c components and D digits: the DD/TD/QD formats in their own
+// instantiations, longer expansions in one generic one (up to 14 components).
+template <int C>
+hipError_t launch_int8_digits(const SplitOperand<double> &a, const SplitOperand<double> &b, int64_t ba, int64_t bb,
+                              int D, hipStream_t st) {
+  constexpr int CM = C <= 4 ? C : 14;
+  const dim3 grid((unsigned)(ba + bb)), block(kThreads);
+  int nw = window_words(D);
+  if (C > 4 && nw > 0 && nw < 9) nw = 9;
+  switch (nw) {
+#define MP_DIGITS_CASE(NW)                                                                                  \
+  case NW:                                                                                                  \
+    if constexpr ((C <= 4 && NW <= 9) || (C > 4 && NW >= 9)) {                                              \
+      hipLaunchKernelGGL((k_split_int8<CM, NW>), grid, block, 0, st, a, b, ba, D, C);                       \
+      return hipGetLastError();                                                                             \
+    }                                                                                                       \
+    break;
+    MP_DIGITS_CASE(4)
+    MP_DIGITS_CASE(5)
+    MP_DIGITS_CASE(6)
+    MP_DIGITS_CASE(7)
+    MP_DIGITS_CASE(8)
+    MP_DIGITS_CASE(9)
+    MP_DIGITS_CASE(13)
+    MP_DIGITS_CASE(25)
+#undef MP_DIGITS_CASE
+    default:
+      break;
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -567,16 +731,15 @@ hipError_t launch_split_int8(const SplitOperand<double> &a, const SplitOperand<d
   const int64_t bb = b.nvec > 0 ? b.nbp * b.kbp : 0;
   if (ba + bb > 0) {
     if (ba + bb > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_split_int8<C>), dim3((unsigned)(ba + bb)), dim3(kThreads), 0, st, a, b, ba, D);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
+    return launch_int8_digits<C>(a, b, ba, bb, D, st);
   }
   return hipSuccess;
 }
 
 template <int C>
 hipError_t launch_split_int8_batched(const SplitOperand<double> *ops, const int *prefix_max0, const int *prefix_blk,
-                                     int nops, int tiles_max0, int64_t blocks, void *mu_all, int64_t mu_words,
-                                     hipStream_t st) {
+                                     int nops, int tiles_max0, int64_t blocks, int dmax, void *mu_all,
+                                     int64_t mu_words, hipStream_t st) {
   hipError_t err = launch_fill32(mu_all, mu_words, 0u, st);
   if (err != hipSuccess) return err;
   if (tiles_max0 > 0) {
@@ -586,19 +749,32 @@ hipError_t launch_split_int8_batched(const SplitOperand<double> *ops, const int 
   }
   if (blocks > 0) {
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_split_int8_batched<C>), dim3((unsigned)blocks), dim3(kThreads), 0, st, ops, prefix_blk,
-                       nops);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
+    switch (window_words(dmax)) {
+#define MP_DIGITS_BATCHED_CASE(NW)                                                                           \
+  case NW:                                                                                                   \
+    hipLaunchKernelGGL((k_split_int8_batched<C, NW>), dim3((unsigned)blocks), dim3(kThreads), 0, st, ops,     \
+                       prefix_blk, nops);                                                                    \
+    return hipGetLastError();
+      MP_DIGITS_BATCHED_CASE(4)
+      MP_DIGITS_BATCHED_CASE(5)
+      MP_DIGITS_BATCHED_CASE(6)
+      MP_DIGITS_BATCHED_CASE(7)
+      MP_DIGITS_BATCHED_CASE(8)
+      MP_DIGITS_BATCHED_CASE(9)
+#undef MP_DIGITS_BATCHED_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
   }
   return hipSuccess;
 }
 
 template hipError_t launch_split_int8_batched<2>(const SplitOperand<double> *, const int *, const int *, int, int,
-                                                 int64_t, void *, int64_t, hipStream_t);
+                                                 int64_t, int, void *, int64_t, hipStream_t);
 template hipError_t launch_split_int8_batched<3>(const SplitOperand<double> *, const int *, const int *, int, int,
-                                                 int64_t, void *, int64_t, hipStream_t);
+                                                 int64_t, int, void *, int64_t, hipStream_t);
 template hipError_t launch_split_int8_batched<4>(const SplitOperand<double> *, const int *, const int *, int, int,
-                                                 int64_t, void *, int64_t, hipStream_t);
+                                                 int64_t, int, void *, int64_t, hipStream_t);
 
 #define MP_SPLIT_INT8_LONG(C) \
   template hipError_t launch_split_int8<C>(const SplitOperand<double> &, const SplitOperand<double> &, int, hipStream_t);

@@ -54,6 +54,31 @@ def test_int8_split_bit_exact(mp, orc, fmt, E):
     assert np.array_equal(host(geb), eb)
 
 
+@pytest.mark.parametrize("fmt,c,D", [("dd", 2, 17), ("td", 3, 24), ("qd", 4, 31), ("qd", 4, 40)])
+def test_int8_digits_on_rounding_boundaries(mp, orc, fmt, c, D):
+    """Exact ties and ties moved by 2^-70 of a unit either way, at every digit
+    the expansion can carry, as rows of A and as columns of B (several rows
+    with different exponents, one of them all zero): the digits equal the
+    oracle's bit for bit (the rounding follows the whole expansion, not its
+    leading component)."""
+    from digit_cases import tie_cases
+    rows = [tie_cases(c, D, E, seed=c + E + 100) for E in (3, -40, 77)]
+    k = max(len(r) for r in rows)
+    A = np.zeros((c, k, len(rows) + 1))  # the last row stays zero
+    for i, cases in enumerate(rows):
+        for p, comps in enumerate(cases):
+            A[:, p, i] = comps
+    B = np.ascontiguousarray(np.transpose(A, (0, 2, 1)))  # the same values as columns of B
+    say(f"int8 digits on boundaries {fmt} D={D} k={k}")
+    da, ea = orc.split_int8(A, D, "rows")
+    db, eb = orc.split_int8(B, D, "cols")
+    ga, gea = mp.debug_split(fmt, dev(A), 0, D, mode="int8")
+    gb, geb = mp.debug_split(fmt, dev(B), 1, D, mode="int8")
+    assert np.array_equal(host(gea), ea) and np.array_equal(host(geb), eb)
+    assert np.array_equal(host(ga), da)
+    assert np.array_equal(host(gb), db)
+
+
 @pytest.mark.parametrize("fmt", ["dd", "qd"])
 def test_int8_diagonal_sums_bit_exact(mp, orc, fmt):
     m, n, k = 150, 130, 200

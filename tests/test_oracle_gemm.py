@@ -9,6 +9,7 @@ import pytest
 
 import oracle.exact as X
 import workload as W
+from digit_cases import tie_cases
 
 T_BITS = {"dd": 100, "td": 150, "qd": 200, "ts": 66}
 
@@ -242,8 +243,10 @@ def test_error_falls_with_D_and_saturates_on_eq1_data(orc):
 @pytest.mark.parametrize("fmt,D", [("dd", 17), ("qd", 17), ("8d", 61), ("14d", 104)])
 def test_int8_digits_against_python_rationals(orc, fmt, D):
     """INT8 digits: equal to an independent rational implementation of the same
-    rule; |d| <= 64; a = sum_s d_s u_s + r exactly with |r| <= u_D/2 (1 + 2^-40).
-    Long expansions (8 and 14 binary64 components) included."""
+    rule; |d| <= 64; and the closed form: for every s, sum_{t <= s} d_t u_t is
+    x rounded to nearest (ties to even) on the grid u_s, so the remainder after
+    D digits is at most u_D / 2.  Long expansions (8 and 14 binary64
+    components) included."""
     m, k = 4, 9
     A = W.gen_matrix(fmt, m, k, E=16, seed=31, operand="A")
     dg, E = orc.split_int8(A, D, "rows")
@@ -252,11 +255,38 @@ def test_int8_digits_against_python_rationals(orc, fmt, D):
         assert E[i] == Ew
         for p in range(k):
             assert list(dg[:, p, i]) == want[p]
-            assert np.all(np.abs(dg[:, p, i].astype(int)) <= 64)
-            x = X.value(A[:, p, i])
-            approx = sum(Fraction(int(dg[s, p, i])) * Fraction(2) ** (int(E[i]) - 6 - 7 * s) for s in range(D))
-            uD = Fraction(2) ** (int(E[i]) - 6 - 7 * (D - 1))
-            assert abs(x - approx) <= uD / 2 * (1 + Fraction(2) ** -40)
+            check_digit_closed_form(A[:, p, i], dg[:, p, i], int(E[i]))
+
+
+def check_digit_closed_form(comps, digits, E):
+    x = X.value(comps)
+    partial = Fraction(0)
+    for s, d in enumerate(digits, start=1):
+        assert -64 <= int(d) <= 64
+        u = Fraction(2) ** (E - 6 - 7 * (s - 1))
+        partial += int(d) * u
+        assert partial == X.rne(x / u) * u, (s, comps)
+    assert abs(x - partial) <= u / 2
+
+
+@pytest.mark.parametrize("c,D", [(2, 17), (3, 24), (4, 31), (8, 61)])
+def test_int8_digits_on_rounding_boundaries(orc, c, D):
+    """Exact ties and near-ties at every level: the digits follow the exact
+    value (a tie moved by 2^-70 of a unit rounds away from it; an exact tie
+    goes to the even neighbour), as the rational implementation and the closed
+    form say."""
+    E = 3
+    cases = tie_cases(c, D, E, seed=c)
+    k = len(cases)
+    A = np.zeros((c, k, 1))
+    for p, comps in enumerate(cases):
+        A[:, p, 0] = comps
+    dg, Eo = orc.split_int8(A, D, "rows")
+    assert Eo[0] == E
+    want, _ = X.int8_digits_py([tuple(A[:, p, 0]) for p in range(k)], D)
+    for p in range(k):
+        assert list(dg[:, p, 0]) == want[p], cases[p]
+        check_digit_closed_form(A[:, p, 0], dg[:, p, 0], E)
 
 
 def test_int8_diag_sums_and_combination(orc):
