@@ -537,26 +537,28 @@ __device__ __forceinline__ void window_add(uint32_t (&w)[NW], int64_t M, int off
   }
 }
 
-// N = floor(x / 2^P) of the c components R[0..c-1] (a normalized expansion)
-// into w, and whether x - N 2^P is nonzero.
+// N = floor(x / 2^P) of the c components x[r * stride] (a normalized
+// expansion) into w, and whether x - N 2^P is nonzero.  The loop over the
+// components is unrolled for the DD/TD/QD formats (CMAX <= 4) only.
 template <int CMAX, int NW>
-__device__ __forceinline__ void value_window(const double (&R)[CMAX], int c, int P, uint32_t (&w)[NW], bool &below) {
+__device__ __forceinline__ void value_window(const double *x, int64_t stride, int c, int P, uint32_t (&w)[NW],
+                                             bool &below) {
 #pragma unroll
   for (int i = 0; i < NW; ++i) w[i] = 0u;
   bool cut = false, cut_bits = false;
   int tail = 0;  // sign of the first nonzero component after the cut one
-#pragma unroll
-  for (int r = 0; r < CMAX; ++r) {
-    if (r >= c) break;
-    const double x = R[r];
-    if (x == 0.0) continue;
+  constexpr int kUnroll = CMAX <= 4 ? CMAX : 1;
+#pragma unroll kUnroll
+  for (int r = 0; r < c; ++r) {
+    const double xr = x[r * stride];
+    if (xr == 0.0) continue;
     if (cut) {
-      if (tail == 0) tail = x < 0.0 ? -1 : 1;
+      if (tail == 0) tail = xr < 0.0 ? -1 : 1;
       continue;
     }
     int64_t M;
     int q;
-    binary64_parts(x, M, q);
+    binary64_parts(xr, M, q);
     int off = q - P;
     if (off < 0) {  // bits below 2^P: floor, and whether any was cut off
       const int sh = -off;
@@ -611,47 +613,59 @@ __device__ void int8_block(const SplitOperand<double> &op, int64_t blk, int D, i
     E = ex;
   }
   const int P = E != kZeroExp ? E - 7 * Dw : 0;
-  uint32_t w[4][NW];
-  bool below[4];
-  uint32_t anyw[4];  // bit i: a nonzero word below word i
-  int rprev[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int p = p0 + j;
-    const bool live = v < op.nvec && p < op.len && E != kZeroExp;
-    double R[CMAX];
-#pragma unroll
-    for (int r = 0; r < CMAX; ++r)
-      R[r] = live && r < c ? op.X[r * op.comp_stride + (int64_t)v * op.sv + (int64_t)p * op.sp] : 0.0;
-    value_window<CMAX, NW>(R, c, P, w[j], below[j]);
-    uint32_t run = 0u, m = 0u;
-#pragma unroll
-    for (int i = 0; i < NW; ++i) {
-      m |= (run != 0u ? 1u : 0u) << i;
-      run |= w[j][i];
-    }
-    anyw[j] = m;
-    rprev[j] = (int)window_bit(w[j], 7 * Dw);  // the sign: W_0 = 0
-  }
   int8_t *dst = static_cast<int8_t *>(op.packed) + (vb * op.kbp + kb) * 1024 + 4 * T;
   const int64_t plane = op.nbp * op.kbp * 1024;
-  // every digit the window holds is formed (the bit positions are then
-  // constants); the first D are stored
+  // the thread's 4 elements in groups of G (fewer for wide windows, whose
+  // words would not all fit in registers); each group's digits are stored as
+  // G consecutive bytes of every plane
+  constexpr int G = NW <= 7 ? 4 : NW <= 13 ? 2 : 1;
+#pragma unroll 1
+  for (int j0 = 0; j0 < 4; j0 += G) {
+    uint32_t w[G][NW];
+    bool below[G];
+    uint32_t anyw[G];  // bit i: a nonzero word below word i
+    int rprev[G];
 #pragma unroll
-  for (int s = 1; s <= Dw; ++s) {
-    const int ph = 7 * (Dw - s);  // half bit of digit s
-    unsigned int word = 0;
+    for (int j = 0; j < G; ++j) {
+      const int p = p0 + j0 + j;
+      const bool live = v < op.nvec && p < op.len && E != kZeroExp;
+      value_window<CMAX, NW>(op.X + (live ? (int64_t)v * op.sv + (int64_t)p * op.sp : 0), op.comp_stride,
+                             live ? (CMAX <= 4 ? CMAX : c) : 0, P, w[j], below[j]);
+      uint32_t run = 0u, m = 0u;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint32_t b = window_bits7(w[j], ph + 1);
-      const uint32_t h = window_bit(w[j], ph);
-      const bool st = below[j] || ((anyw[j] >> (ph >> 5)) & 1u) || (w[j][ph >> 5] & ((1u << (ph & 31)) - 1u)) != 0u;
-      const int r = (int)(h & ((st ? 1u : 0u) | (b & 1u)));
-      const int d = (int)b + r - 128 * rprev[j];
-      rprev[j] = r;
-      word |= (unsigned int)(uint8_t)(int8_t)d << (8 * j);
+      for (int i = 0; i < NW; ++i) {
+        m |= (run != 0u ? 1u : 0u) << i;
+        run |= w[j][i];
+      }
+      anyw[j] = m;
+      rprev[j] = (int)window_bit(w[j], 7 * Dw);  // the sign: W_0 = 0
     }
-    if (s <= D) *reinterpret_cast<unsigned int *>(dst + (int64_t)(s - 1) * plane) = word;
+    // every digit the window holds is formed (the bit positions are then
+    // constants); the first D are stored
+#pragma unroll
+    for (int s = 1; s <= Dw; ++s) {
+      const int ph = 7 * (Dw - s);  // half bit of digit s
+      unsigned int word = 0;
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        const uint32_t b = window_bits7(w[j], ph + 1);
+        const uint32_t h = window_bit(w[j], ph);
+        const bool st = below[j] || ((anyw[j] >> (ph >> 5)) & 1u) || (w[j][ph >> 5] & ((1u << (ph & 31)) - 1u)) != 0u;
+        const int r = (int)(h & ((st ? 1u : 0u) | (b & 1u)));
+        const int d = (int)b + r - 128 * rprev[j];
+        rprev[j] = r;
+        word |= (unsigned int)(uint8_t)(int8_t)d << (8 * j);
+      }
+      if (s <= D) {
+        int8_t *out = dst + (int64_t)(s - 1) * plane + j0;
+        if constexpr (G == 4)
+          *reinterpret_cast<unsigned int *>(out) = word;
+        else if constexpr (G == 2)
+          *reinterpret_cast<unsigned short *>(out) = (unsigned short)word;
+        else
+          *out = (int8_t)word;
+      }
+    }
   }
   if (p0 == 0 && v < op.nvec) op.exps[v] = E;
 }

@@ -54,13 +54,15 @@ def test_int8_split_bit_exact(mp, orc, fmt, E):
     assert np.array_equal(host(geb), eb)
 
 
-@pytest.mark.parametrize("fmt,c,D", [("dd", 2, 17), ("td", 3, 24), ("qd", 4, 31), ("qd", 4, 40)])
+@pytest.mark.parametrize("fmt,c,D", [("dd", 2, 17), ("dd", 2, 21), ("td", 3, 24), ("td", 3, 35), ("qd", 4, 31),
+                                     ("qd", 4, 40)])
 def test_int8_digits_on_rounding_boundaries(mp, orc, fmt, c, D):
     """Exact ties and ties moved by 2^-70 of a unit either way, at every digit
     the expansion can carry, as rows of A and as columns of B (several rows
     with different exponents, one of them all zero): the digits equal the
     oracle's bit for bit (the rounding follows the whole expansion, not its
-    leading component)."""
+    leading component).  The D values use each integer width of the kernel
+    (4 to 9 words)."""
     from digit_cases import tie_cases
     rows = [tie_cases(c, D, E, seed=c + E + 100) for E in (3, -40, 77)]
     k = max(len(r) for r in rows)

@@ -65,6 +65,29 @@ def test_nd_digits_bit_exact(mp, orc, c):
     assert np.array_equal(host(geb), eb)
 
 
+@pytest.mark.parametrize("c,D", [(5, 41), (8, 59), (14, 112)])
+def test_nd_digits_on_rounding_boundaries(mp, orc, c, D):
+    """Exact and near ties at every digit the expansion carries (as in the
+    INT8 tests of the DD/TD/QD formats), with the digit counts that take the
+    9-, 13- and 25-word integers of the long-expansion kernel."""
+    from digit_cases import tie_cases
+    rows = [tie_cases(c, D, E, seed=c + E + 200) for E in (5, -33)]
+    k = max(len(r) for r in rows)
+    A = np.zeros((c, k, len(rows) + 1))
+    for i, cases in enumerate(rows):
+        for p, comps in enumerate(cases):
+            A[:, p, i] = comps
+    B = np.ascontiguousarray(np.transpose(A, (0, 2, 1)))
+    say(f"nd digits on boundaries c={c} D={D} k={k}")
+    da, ea = orc.split_int8(A, D, "rows")
+    db, eb = orc.split_int8(B, D, "cols")
+    ga, gea = mp.nd_debug_split(dev(A), 0, D)
+    gb, geb = mp.nd_debug_split(dev(B), 1, D)
+    assert np.array_equal(host(gea), ea) and np.array_equal(host(geb), eb)
+    assert np.array_equal(host(ga), da)
+    assert np.array_equal(host(gb), db)
+
+
 def test_nd_diagonal_sums_bit_exact(mp, orc):
     c, m, n, k = 9, 45, 38, 150
     A, B = W.gen_pair(fmt_of(c), m, n, k, E=8, seed=3)
