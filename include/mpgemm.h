@@ -206,6 +206,14 @@ int mpgemm_batched_cache_clear(void);
  * timing records the split with the pair selection as the split stage.
  */
 #define MPGEMM_SLICES_DATA (-1)
+/*
+ * Environment defaults, read once per process when a host thread first uses
+ * the library: MPGEMM_MODE=int8 starts every thread with the INT8 form for
+ * DD, TD and QD (TS stays FLOAT); MPGEMM_SLICES=N starts it with D = N for
+ * every format and form whose range holds N, and MPGEMM_SLICES=data with the
+ * data-chosen pairs of the FLOAT form.  Other values are ignored.  The
+ * per-thread setters override them.  (MPGEMM_TUNE_FILE: see below.)
+ */
 int mpgemm_set_mode(int fmt, int mode);
 int mpgemm_get_mode(int fmt);
 

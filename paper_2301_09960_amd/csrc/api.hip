@@ -34,7 +34,46 @@ constexpr int kBoundBits[kNumFmt] = {100, 150, 200, 66};  // 2^-t bound per form
 constexpr int kComps[kNumFmt] = {2, 3, 4, 3};
 const int kCompsH[kNumFmtH] = {2, 3, 4, 3};
 
+// Process-wide defaults of the per-thread options, read once from the
+// environment: MPGEMM_MODE ("float" or "int8"; TS stays FLOAT) and
+// MPGEMM_SLICES (a slice count for every format and form that allows it, or
+// "data" for the binary64/binary32 form's data-chosen pairs).  Values that do
+// not parse, or are out of a form's range, leave that default automatic.
+struct EnvDefaults {
+  int mode = MPGEMM_MODE_FLOAT;
+  int slices_float = 0, slices_int8 = 0;
+};
+const EnvDefaults &env_defaults() {
+  static const EnvDefaults d = [] {
+    EnvDefaults e;
+    const char *m = std::getenv("MPGEMM_MODE");
+    if (m && std::strcmp(m, "int8") == 0) e.mode = MPGEMM_MODE_INT8;
+    const char *s = std::getenv("MPGEMM_SLICES");
+    if (s && std::strcmp(s, "data") == 0) {
+      e.slices_float = MPGEMM_SLICES_DATA;
+    } else if (s && *s) {
+      char *end = nullptr;
+      const long v = std::strtol(s, &end, 10);
+      if (end && *end == '\0') {
+        if (v >= 1 && v <= kMaxDFloat) e.slices_float = (int)v;
+        if (v >= 1 && v <= kMaxDInt8) e.slices_int8 = (int)v;
+      }
+    }
+    return e;
+  }();
+  return d;
+}
+
 struct ThreadOptions {
+  ThreadOptions() {
+    const EnvDefaults &e = env_defaults();
+    for (int f = 0; f < kNumFmt; ++f) {
+      const bool int8_ok = f != MPGEMM_TS;
+      mode[f] = int8_ok ? e.mode : MPGEMM_MODE_FLOAT;
+      slices[f][MPGEMM_MODE_FLOAT] = e.slices_float;
+      slices[f][MPGEMM_MODE_INT8] = int8_ok ? e.slices_int8 : 0;
+    }
+  }
   int mode[kNumFmt] = {MPGEMM_MODE_FLOAT, MPGEMM_MODE_FLOAT, MPGEMM_MODE_FLOAT, MPGEMM_MODE_FLOAT};
   int layout[kNumFmt] = {0, 0, 0, 0};  // 0: tuned default
   int int8_tile = 0;                   // 0: automatic

@@ -200,3 +200,50 @@ def test_batched_argument_codes(L):
     assert L.mpgemm_dd_batched(1, None, IA(1), IA(1), x, IA(1), x, IA(1), x, IA(1), None) == -2
     assert L.mpgemm_dd_batched(1, IA(4), IA(4), IA(4), x, IA(3), x, IA(4), x, IA(4), None) == -6
     assert L.mpgemm_qd_batched(1, IA(4), IA(4), IA(4), x, IA(4), x, IA(4), x, IA(2), None) == -10
+
+
+ENV_PROBE = r"""
+import ctypes, json, sys
+sys.path.insert(0, sys.argv[1])
+import paper_2301_09960_amd as mp
+L = mp.lib()
+L.mpgemm_workspace_bytes.restype = ctypes.c_size_t
+out = {"mode": [L.mpgemm_get_mode(f) for f in range(4)],
+       "float": [L.mpgemm_num_slices(f, 0, 1024) for f in range(4)],
+       "int8": [L.mpgemm_num_slices(f, 1, 1024) for f in range(3)],
+       "ws0": L.mpgemm_workspace_bytes(0, 0, 100, 90, 80, 0),
+       "wsdata": L.mpgemm_workspace_bytes(0, 0, 100, 90, 80, -1)}
+L.mpgemm_set_mode(0, 0)
+out["after_set"] = L.mpgemm_get_mode(0)
+print(json.dumps(out))
+"""
+
+
+def env_probe(**env):
+    import json
+    import subprocess
+    import sys
+    e = dict(os.environ)
+    for k in ("MPGEMM_MODE", "MPGEMM_SLICES"):
+        e.pop(k, None)
+    e.update(env)
+    r = subprocess.run([sys.executable, "-c", ENV_PROBE, ROOT], env=e, capture_output=True, text=True, check=True)
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def test_environment_defaults(L):
+    """MPGEMM_MODE and MPGEMM_SLICES set the starting options of every host
+    thread; the setters override them; bad values are ignored."""
+    base = env_probe()
+    assert base["mode"] == [0, 0, 0, 0]
+    p = env_probe(MPGEMM_MODE="int8", MPGEMM_SLICES="7")
+    assert p["mode"] == [1, 1, 1, 0]  # TS has no INT8 form
+    assert p["float"] == [7, 7, 7, 7] and p["int8"] == [7, 7, 7]
+    assert p["after_set"] == 0
+    p = env_probe(MPGEMM_SLICES="30")  # beyond the FLOAT range: automatic there
+    assert p["float"] == base["float"] and p["int8"] == [30, 30, 30]
+    p = env_probe(MPGEMM_SLICES="data")
+    assert p["float"] == base["float"] and p["int8"] == base["int8"]
+    assert p["ws0"] == p["wsdata"] != base["ws0"]
+    p = env_probe(MPGEMM_MODE="fast", MPGEMM_SLICES="7x")
+    assert p == base
