@@ -94,10 +94,17 @@ __device__ __forceinline__ void wait_step(int64_t later) {
 //             requested per step)
 // KSB divides kKStepBlocks8, the k padding unit of the INT8 slices.
 template <int CFG> struct Int8Cfg;
-template <> struct Int8Cfg<1> { static constexpr int TB = 4, WM = 2, WN = 2, KSB = 2, NS = 4; };
-template <> struct Int8Cfg<2> { static constexpr int TB = 8, WM = 2, WN = 2, KSB = 2, NS = 4; };
-template <> struct Int8Cfg<3> { static constexpr int TB = 8, WM = 2, WN = 4, KSB = 4, NS = 2; };
-template <> struct Int8Cfg<4> { static constexpr int TB = 8, WM = 4, WN = 4, KSB = 4, NS = 2; };
+template <> struct Int8Cfg<1> { static constexpr int TB = 4, WM = 2, WN = 2, KSB = 2, NS = 4, SPACING = 0; };
+template <> struct Int8Cfg<2> { static constexpr int TB = 8, WM = 2, WN = 2, KSB = 2, NS = 4, SPACING = 0; };
+template <> struct Int8Cfg<3> { static constexpr int TB = 8, WM = 2, WN = 4, KSB = 4, NS = 2, SPACING = 3; };
+template <> struct Int8Cfg<4> { static constexpr int TB = 8, WM = 4, WN = 4, KSB = 4, NS = 2, SPACING = 0; };
+
+// Matrix-core instructions between two loads of the next step: spread over the
+// whole step by default, fewer where a configuration issues its loads earlier.
+template <typename G>
+constexpr int load_spacing(int even) {
+  return G::SPACING > 0 ? G::SPACING : even;
+}
 
 template <int CFG>
 constexpr int int8_stage_bytes() {
@@ -112,9 +119,11 @@ constexpr int int8_stage_bytes() {
 // Each wavefront moves kL 1 KiB pieces of one operand per step.  Their global
 // offsets from the step's panel base and their LDS offsets are fixed for the
 // whole tile, so a load costs one 64-bit add; and the loads of the next step
-// are spread evenly between this step's matrix-core instructions (one per
-// kEvery), which keeps the matrix cores fed where a burst of LDS-direct loads
-// would stall them.
+// are spread between this step's matrix-core instructions (one per kEvery),
+// which keeps the matrix cores fed where a burst of LDS-direct loads would
+// stall them.  The 256 x 256 configuration with its 2-stage ring issues them
+// over the first three quarters of the step (one per 3 instructions instead of
+// one per 4), so that the last ones land before the step ends.
 template <int CFG>
 __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, const int8_t *__restrict__ Bpk,
                                                int64_t mbp, int64_t nbp, int64_t kbp, int64_t kb0, int nks, int D,
@@ -128,10 +137,11 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
   constexpr int kInst = 2 * TB * KSB;  // 1 KiB wavefront instructions per step
   constexpr int kL = kInst / NW;
   constexpr int kMma = KSB * BI * BJ;  // matrix-core instructions per wavefront per step
-  constexpr int kEvery = kMma / kL;
+  constexpr int kEvery = load_spacing<G>(kMma / kL);
   static_assert(kInst % NW == 0, "staging split");
   static_assert((TB * KSB) % kL == 0, "a wavefront's loads of a step come from one operand");
   static_assert(kMma % kL == 0, "one load per fixed number of matrix-core instructions");
+  static_assert(kEvery * kL <= kMma, "every load of the next step is issued within this step");
   static_assert(kKStepBlocks8 % KSB == 0, "k steps tile the padded k");
 
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
@@ -213,7 +223,8 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
 #pragma unroll
         for (int x = 0; x < BI; ++x) {
           const int mma = (kb * BJ + y) * BI + x;
-          if (mma % kEvery == 0 && more) load_lds16(nsrc + goff[mma / kEvery], ndst + loff[mma / kEvery]);
+          if (mma % kEvery == 0 && mma / kEvery < kL && more)
+            load_lds16(nsrc + goff[mma / kEvery], ndst + loff[mma / kEvery]);
           acc[y][x] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fb[y], fa[x], acc[y][x], 0, 0, 0);
           __builtin_amdgcn_sched_barrier(0);  // keep the loads where they were placed
         }
