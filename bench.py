@@ -513,6 +513,12 @@ def main():
                 "speedup_vs_float_slices": round(
                     (stages[f]["split_ms"] + stages[f]["gemm_kernel_ms"]) / call_ms, 3),
             }
+            if not args.no_certify:
+                # equal accuracy: the certificate of the INT8 result (the same
+                # digits and sums; one untimed call)
+                _, _, worst8 = mp.certify(f, *inputs[f], outs[f], mode="int8")
+                torch.cuda.synchronize()
+                int8[f]["log2_worst_bound_ratio"] = round(float(np.log2(float(worst8.cpu()[0]))), 2)
 
     certify = None
     if not args.no_certify:
