@@ -360,3 +360,31 @@ def test_naive_loop_accuracy(orc, fmt):
     diff, absab, _ = orc.exact_check(A, B, C)
     L = {"dd": 106, "td": 159, "qd": 212, "ts": 72}[fmt]
     assert np.all(diff <= absab * k * 2.0 ** -(L - 3))
+
+
+def test_exponent_spread_beyond_the_automatic_slice_count(orc):
+    """Algorithm 1 at a fixed D loses accuracy when one row of A and one
+    column of B hold entries 2^40 apart that meet in the product (the slice
+    grid is set by the row's and column's largest entry): DD with k = 2,
+    A's row [x, 2^-40 u] and B's column [2^-40 v, y], all full-precision DD
+    values.  D = 5 (the a-priori count for k = 2) misses 2^-100 |A||B|; D = 6
+    meets it.  This is the case the automatic D does not cover and the
+    certificate or the data-chosen pair sets handle."""
+    rng = np.random.default_rng(5)
+
+    def dd(scale):
+        hi = rng.uniform(1.0, 2.0) * scale
+        return hi, hi * 2.0 ** -53 * rng.uniform(-0.5, 0.5)
+
+    worst5, worst6 = [], []
+    for _ in range(8):
+        A = np.zeros((2, 2, 1))
+        B = np.zeros((2, 1, 2))
+        A[:, 0, 0], A[:, 1, 0] = dd(1.0), dd(2.0 ** -40)
+        B[:, 0, 0], B[:, 0, 1] = dd(2.0 ** -40), dd(1.0)
+        for D, out in ((5, worst5), (6, worst6)):
+            C, _ = orc.ozaki_gemm(A, B, D)
+            diff, absab, _ = orc.exact_check(A, B, C)
+            out.append(orc.bound_report(diff, absab, 100)[1])
+    assert max(worst5) > -100  # the bound is missed at D = 5
+    assert max(worst6) <= -100  # and met at D = 6
