@@ -514,11 +514,33 @@ def main():
                     (stages[f]["split_ms"] + stages[f]["gemm_kernel_ms"]) / call_ms, 3),
             }
             if not args.no_certify:
-                # equal accuracy: the certificate of the INT8 result (the same
-                # digits and sums; one untimed call)
+                # equal accuracy: the certificate of the INT8 result (one
+                # untimed call), and the smallest digit count whose certificate
+                # meets 2^-t with its time and speedup (the certificate takes
+                # every left-out pair at its largest, so it can ask for a digit
+                # more than the exact error does)
                 _, _, worst8 = mp.certify(f, *inputs[f], outs[f], mode="int8")
                 torch.cuda.synchronize()
                 int8[f]["log2_worst_bound_ratio"] = round(float(np.log2(float(worst8.cpu()[0]))), 2)
+                _, _, wc, Dc = mp.certify_adaptive(f, *inputs[f], outs[f], mode="int8", d_first=D8, d_last=D8 + 3)
+                torch.cuda.synchronize()
+                mp.gemm(f, *inputs[f], outs[f], mode="int8", slices=Dc)
+                torch.cuda.synchronize()
+                mp.profile_enable(True)
+                for _ in range(3):
+                    mp.gemm(f, *inputs[f], outs[f], mode="int8", slices=Dc)
+                torch.cuda.synchronize()
+                mp.profile_enable(False)
+                csp, cgm = mp.profile_read()
+                cms = float(np.mean(csp)) + float(np.mean(cgm))
+                int8[f]["certified"] = {
+                    "D": Dc,
+                    "log2_worst_bound_ratio": round(float(np.log2(float(wc.cpu()[0]))), 2),
+                    "call_ms": round(cms, 3),
+                    "speedup_vs_float_slices": round(
+                        (stages[f]["split_ms"] + stages[f]["gemm_kernel_ms"]) / cms, 3),
+                }
+                log(f"int8 {f} certified: {int8[f]['certified']}")
 
     certify = None
     if not args.no_certify:
