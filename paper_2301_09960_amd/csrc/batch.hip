@@ -426,14 +426,19 @@ int build_plan_int8(BatchPlan &p, int cfg_override) {
     return MPGEMM_ERR_WORKSPACE;
   }
   if (hipEventCreateWithFlags(&p.stage_done, hipEventDisableTiming) != hipSuccess) return MPGEMM_ERR_HIP;
+  // the digit split writes only blocks that hold elements: the padding blocks
+  // of the packed planes are cleared here, once, and stay zero on every replay
+  if (hipMemset(p.ws, 0, p.total > 0 ? p.total : 256) != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess)
+    return MPGEMM_ERR_HIP;
 
   std::vector<int> pre0(p.nops + 1, 0), preb(p.nops + 1, 0), prec(p.live.size() + 1, 0);
   for (int slot = 0; slot < (int)p.live.size(); ++slot) {
     const ProductLayout &L = p.prod[p.live[slot]];
+    const int64_t kbl = ceil_div((int64_t)L.k, (int64_t)kKBlk8);
     pre0[2 * slot + 1] = pre0[2 * slot] + tiles64(L.m, L.k);
     pre0[2 * slot + 2] = pre0[2 * slot + 1] + tiles64(L.n, L.k);
-    preb[2 * slot + 1] = preb[2 * slot] + (int)(L.mbp * L.kbp);
-    preb[2 * slot + 2] = preb[2 * slot + 1] + (int)(L.nbp * L.kbp);
+    preb[2 * slot + 1] = preb[2 * slot] + (int)(ceil_div((int64_t)L.m, (int64_t)kBlk8) * kbl);
+    preb[2 * slot + 2] = preb[2 * slot + 1] + (int)(ceil_div((int64_t)L.n, (int64_t)kBlk8) * kbl);
     prec[slot + 1] = prec[slot] + (int)(L.mbp * L.nbp);
   }
   p.tiles0 = pre0[p.nops];

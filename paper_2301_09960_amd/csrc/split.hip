@@ -594,13 +594,18 @@ __device__ __forceinline__ uint32_t window_bits7(const uint32_t (&w)[NW], int j)
   return v & 127u;
 }
 
-template <int CMAX, int NW, int ORIENT>
+// LIVE: blk numbers only the blocks that hold an element of the operand (the
+// padding blocks of the packed planes were cleared once and are not written);
+// otherwise every packed block, padding included.
+template <int CMAX, int NW, int ORIENT, bool LIVE = false>
 __device__ void int8_block(const SplitOperand<double> &op, int64_t blk, int D, int c) {
   constexpr int Dw = window_digits<NW>();
+  const int64_t nb = LIVE ? ceil_div((int64_t)op.nvec, (int64_t)kBlk8) : op.nbp;
+  const int64_t kbn = LIVE ? ceil_div((int64_t)op.len, (int64_t)kKBlk8) : op.kbp;
   // A (rows, contiguous along the row index): walk row blocks fastest;
   // B (columns, contiguous along k): walk k blocks fastest.
-  const int64_t vb = ORIENT == 0 ? blk % op.nbp : blk / op.kbp;
-  const int64_t kb = ORIENT == 0 ? blk / op.nbp : blk % op.kbp;
+  const int64_t vb = ORIENT == 0 ? blk % nb : blk / kbn;
+  const int64_t kb = ORIENT == 0 ? blk / nb : blk % kbn;
   const int T = threadIdx.x, l = T >> 2, q = T & 3;
   const int v = (int)(vb * kBlk8) + (l & 31);
   const int p0 = (int)(kb * kKBlk8) + 16 * (l >> 5) + 4 * q;
@@ -680,8 +685,9 @@ __global__ __launch_bounds__(kThreads) void k_split_int8(SplitOperand<double> a,
     int8_block<CMAX, NW, 1>(b, blk - blocks_a, D, c);
 }
 
-// Batched: workgroup b takes block b - prefix[i] of operand i (ops[i].D digits;
-// the window holds the batch's largest D).
+// Batched: workgroup b takes live block b - prefix[i] of operand i (ops[i].D
+// digits; the window holds the batch's largest D).  The batch's packed planes
+// are cleared when its plan is built, so padding blocks are never written.
 template <int C, int NW>
 __global__ __launch_bounds__(kThreads) void k_split_int8_batched(const SplitOperand<double> *ops, const int *prefix,
                                                                  int nops) {
@@ -689,9 +695,9 @@ __global__ __launch_bounds__(kThreads) void k_split_int8_batched(const SplitOper
   const SplitOperand<double> &op = ops[i];
   const int64_t local = (int64_t)blockIdx.x - prefix[i];
   if (op.orient == 0)
-    int8_block<C, NW, 0>(op, local, op.D, C);
+    int8_block<C, NW, 0, true>(op, local, op.D, C);
   else
-    int8_block<C, NW, 1>(op, local, op.D, C);
+    int8_block<C, NW, 1, true>(op, local, op.D, C);
 }
 
 // Digit kernel for c components and D digits: the DD/TD/QD formats in their own
