@@ -92,7 +92,8 @@ __device__ __forceinline__ void wait_step(int64_t later) {
 //   config 3: 256 x 256 tile, 8 wavefronts of 128 x 64, k steps of 128 in a
 //             2-stage ring (half the barriers of 64-wide steps, and 64 KiB
 //             requested per step)
-// KSB divides kKStepBlocks8, the k padding unit of the INT8 slices.
+// KSB is 1 or 2 times kKStepBlocks8, the k padding unit of the INT8 slices (64
+// k): with 4-block steps a pair's last step in a k chunk may hold 2 blocks.
 template <int CFG> struct Int8Cfg;
 template <> struct Int8Cfg<1> { static constexpr int TB = 4, WM = 2, WN = 2, KSB = 2, NS = 4, SPACING = 0; };
 template <> struct Int8Cfg<2> { static constexpr int TB = 8, WM = 2, WN = 2, KSB = 2, NS = 4, SPACING = 0; };
@@ -126,8 +127,8 @@ constexpr int int8_stage_bytes() {
 // one per 4), so that the last ones land before the step ends.
 template <int CFG>
 __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, const int8_t *__restrict__ Bpk,
-                                               int64_t mbp, int64_t nbp, int64_t kbp, int64_t kb0, int nks, int D,
-                                               int m, int n, int32_t *__restrict__ S, int64_t plane, int chunk,
+                                               int64_t mbp, int64_t nbp, int64_t kbp, int64_t kb0, int nks, int last,
+                                               int D, int m, int n, int32_t *__restrict__ S, int64_t plane, int chunk,
                                                int nchunks, int tm, int tn, int g0, int g1, int8_t *lds) {
   using G = Int8Cfg<CFG>;
   constexpr int TB = G::TB, WM = G::WM, WN = G::WN, KSB = G::KSB, NS = G::NS;
@@ -142,7 +143,9 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
   static_assert((TB * KSB) % kL == 0, "a wavefront's loads of a step come from one operand");
   static_assert(kMma % kL == 0, "one load per fixed number of matrix-core instructions");
   static_assert(kEvery * kL <= kMma, "every load of the next step is issued within this step");
-  static_assert(kKStepBlocks8 % KSB == 0, "k steps tile the padded k");
+  // a pair's k blocks in the chunk are a multiple of kKStepBlocks8: its steps
+  // are full but the last, which holds `last` blocks (KSB / 2 or KSB)
+  static_assert(KSB % kKStepBlocks8 == 0 && KSB <= 2 * kKStepBlocks8, "k steps and the k padding unit");
 
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int wm = wave % WM, wn = wave / WM;
@@ -154,13 +157,19 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
   const int op_w = (wave_u * kL) / (TB * KSB);
   uint32_t goff[kL];  // byte offset from the step's panel base (per lane; k <= 2^20 keeps it below 2^32)
   int loff[kL];       // byte offset in the stage (uniform)
+  uint32_t beyond[kL];  // in a pair's short last step the piece lies past the pair's k: load piece kb - KSB / 2
 #pragma unroll
   for (int j = 0; j < kL; ++j) {
     const int r = (wave_u * kL + j) % (TB * KSB);
     const int blk = r / KSB, kb = r % KSB;
     goff[j] = (uint32_t)(((int64_t)blk * kbp + kb) * 1024) + 16u * (uint32_t)lane;
     loff[j] = op_w * kPanel + (blk * KSB + kb) * 1024;
+    beyond[j] = kb >= KSB / 2 ? (uint32_t)(KSB / 2) * 1024u : 0u;
   }
+  // every step loads kL pieces (the wait counts assume it): a pair's short
+  // last step re-loads pieces of its own range into stage slots that no
+  // matrix-core instruction reads
+  auto piece = [&](int j, int ks) -> uint32_t { return goff[j] - (ks == nks - 1 && last < KSB ? beyond[j] : 0u); };
 
   int lg = g0, ls = 1, lks = 0;  // load cursor: diagonal, pair within it, k step
   int64_t issued = 0;
@@ -195,7 +204,7 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
       const int8_t *src = panel_base();
       int8_t *dst = lds + (issued % NS) * int8_stage_bytes<CFG>();
 #pragma unroll
-      for (int j = 0; j < kL; ++j) load_lds16(src + goff[j], dst + loff[j]);
+      for (int j = 0; j < kL; ++j) load_lds16(src + piece(j, lks), dst + loff[j]);
       advance();
     }
 
@@ -209,23 +218,30 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
     int8_t *ndst = lds + (issued % NS) * int8_stage_bytes<CFG>();
 
     const int8_t *stage = lds + (step % NS) * int8_stage_bytes<CFG>();
+    // a pair's short last step holds the first KSB / 2 k blocks (the only
+    // short length): its second half is skipped, on a uniform branch
+    const bool short_step = cks == nks - 1 && last < KSB;
+    const uint32_t next_short = lks == nks - 1 && last < KSB ? 1u : 0u;  // the step being loaded is short
 #pragma unroll
     for (int kb = 0; kb < KSB; ++kb) {
+      const bool run = kb < KSB / 2 || !short_step;
       i4v fa[BI], fb[BJ];
+      if (run) {
 #pragma unroll
-      for (int x = 0; x < BI; ++x)
-        fa[x] = *reinterpret_cast<const i4v *>(stage + ((wm * BI + x) * KSB + kb) * 1024 + 16 * lane);
+        for (int x = 0; x < BI; ++x)
+          fa[x] = *reinterpret_cast<const i4v *>(stage + ((wm * BI + x) * KSB + kb) * 1024 + 16 * lane);
 #pragma unroll
-      for (int y = 0; y < BJ; ++y)
-        fb[y] = *reinterpret_cast<const i4v *>(stage + kPanel + ((wn * BJ + y) * KSB + kb) * 1024 + 16 * lane);
+        for (int y = 0; y < BJ; ++y)
+          fb[y] = *reinterpret_cast<const i4v *>(stage + kPanel + ((wn * BJ + y) * KSB + kb) * 1024 + 16 * lane);
+      }
 #pragma unroll
       for (int y = 0; y < BJ; ++y)
 #pragma unroll
         for (int x = 0; x < BI; ++x) {
           const int mma = (kb * BJ + y) * BI + x;
           if (mma % kEvery == 0 && mma / kEvery < kL && more)
-            load_lds16(nsrc + goff[mma / kEvery], ndst + loff[mma / kEvery]);
-          acc[y][x] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fb[y], fa[x], acc[y][x], 0, 0, 0);
+            load_lds16(nsrc + (goff[mma / kEvery] - next_short * beyond[mma / kEvery]), ndst + loff[mma / kEvery]);
+          if (run) acc[y][x] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fb[y], fa[x], acc[y][x], 0, 0, 0);
           __builtin_amdgcn_sched_barrier(0);  // keep the loads where they were placed
         }
     }
@@ -281,11 +297,13 @@ __global__ __launch_bounds__(64 * Int8Cfg<CFG>::WM * Int8Cfg<CFG>::WN, 1) void k
   const int chunk = blockIdx.y, nchunks = gridDim.y;
   const int64_t kb0 = (int64_t)chunk * kb_chunk;
   const int64_t kb1 = kb0 + kb_chunk < kbp ? kb0 + kb_chunk : kbp;
-  const int nks = (int)((kb1 - kb0) / Int8Cfg<CFG>::KSB);
+  constexpr int KSB = Int8Cfg<CFG>::KSB;
+  const int nks = (int)ceil_div(kb1 - kb0, KSB), last = (int)(kb1 - kb0) - (nks - 1) * KSB;
   // diagonal group blockIdx.z of gridDim.z
   int g0, g1;
   diagonal_group(D, blockIdx.z, gridDim.z, g0, g1);
-  gemm_int8_tile<CFG>(Apk, Bpk, mbp, nbp, kbp, kb0, nks, D, m, n, S, plane, chunk, nchunks, tm, tn, g0, g1, lds);
+  gemm_int8_tile<CFG>(Apk, Bpk, mbp, nbp, kbp, kb0, nks, last, D, m, n, S, plane, chunk, nchunks, tm, tn, g0, g1,
+                      lds);
 }
 
 // Diagonal-sum planes are blocked: the 32 x 32 block (bi, bj) of C holds, for
@@ -375,11 +393,12 @@ __global__ __launch_bounds__(64 * Int8Cfg<CFG>::WM * Int8Cfg<CFG>::WN, 1) void k
     const int chunk = w.z;
     const int64_t kb0 = (int64_t)chunk * d.kbc;
     const int64_t kb1 = kb0 + d.kbc < d.kbp ? kb0 + d.kbc : d.kbp;
-    const int nks = (int)((kb1 - kb0) / Int8Cfg<CFG>::KSB);
+    constexpr int KSB = Int8Cfg<CFG>::KSB;
+    const int nks = (int)ceil_div(kb1 - kb0, KSB), last = (int)(kb1 - kb0) - (nks - 1) * KSB;
     int g0, g1;
     diagonal_group(d.D, w.w, d.groups, g0, g1);
-    gemm_int8_tile<CFG>(d.Apk, d.Bpk, d.mbp, d.nbp, d.kbp, kb0, nks, d.D, d.m, d.n, d.S, d.plane, chunk, d.nchunks,
-                      tm, tn, g0, g1, lds);
+    gemm_int8_tile<CFG>(d.Apk, d.Bpk, d.mbp, d.nbp, d.kbp, kb0, nks, last, d.D, d.m, d.n, d.S, d.plane, chunk,
+                        d.nchunks, tm, tn, g0, g1, lds);
   }
 }
 

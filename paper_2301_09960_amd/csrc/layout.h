@@ -30,7 +30,7 @@ constexpr int kKBlk = 16;     // k per block (floating-point slices)
 constexpr int kBlk8 = 32;     // rows/cols per block (INT8 slices)
 constexpr int kKBlk8 = 32;    // k per block (INT8 slices)
 constexpr int kTileBlocks8 = 8;   // largest INT8 tile: 8 blocks (256 rows); the 128-row tile uses 4
-constexpr int kKStepBlocks8 = 4;  // INT8 k padding unit: 4 k-blocks (128), a multiple of every k step
+constexpr int kKStepBlocks8 = 2;  // INT8 k padding unit: 2 k-blocks (64); k steps are 2 or 4 blocks
 constexpr int kTileBlocks = 4;  // GEMM tile = 4 x 4 blocks (64 x 64)
 constexpr int kKStepBlocks = 2; // GEMM k step = 2 k-blocks (32)
 constexpr int kMaxPairLim = 16; // most slices of the data-chosen pair sets (per-tile staircases)

@@ -136,6 +136,35 @@ def test_int8_zero_rows_and_chunking(mp, orc):
     assert ok
 
 
+@pytest.mark.parametrize("cfg", [3, 4])
+@pytest.mark.parametrize("fmt,m,n,k,D", [("dd", 70, 90, 60, 0), ("td", 300, 40, 170, 0), ("qd", 33, 270, 420, 0),
+                                         ("dd", 20, 12, 14500, 37)])
+def test_int8_short_last_step(mp, orc, cfg, fmt, m, n, k, D):
+    """k padded to 64: with 128-deep steps (configurations 3 and 4) a pair's
+    last step in a k chunk holds 64 k when the chunk's 32-wide k blocks are 2
+    mod 4 (k = 60, 170, 420; and D = 37, whose 32-bit chunks are 442 blocks,
+    at k = 14500): diagonal sums bit-exact, C within the bound."""
+    A, B = W.gen_pair(fmt, m, n, k, E=8, seed=k + cfg)
+    D = D or mp.num_slices(fmt, "int8", k)
+    da, _ = orc.split_int8(A, D, "rows")
+    db, _ = orc.split_int8(B, D, "cols")
+    S = orc.int8_diag_sums(da, db)
+    dA, dB = dev(A), dev(B)
+    say(f"int8 short last step cfg={cfg} {fmt} {m}x{n}x{k} D={D}")
+    mp.set_int8_tile(cfg)
+    try:
+        for g in sorted({1, D // 2, D}):
+            got = host(mp.debug_products(fmt, dA, dB, g, 0, D, mode="int8"))
+            assert np.array_equal(got, S[g - 1]), g
+        C = host(mp.gemm(fmt, dA, dB, mode="int8", slices=D))
+    finally:
+        mp.set_int8_tile(0)
+    rows = None if m * n * k < 5e6 else [0, m // 2, m - 1]
+    diff, absab, _ = orc.exact_check(A, B, C, rows=rows)
+    ok, worst = orc.bound_report(diff, absab, T_BITS[fmt])
+    assert ok, worst
+
+
 @pytest.mark.parametrize("cfg", [1, 2, 3, 4])
 def test_int8_every_tile_config(mp, orc, cfg):
     """Each INT8 tile configuration gives the exact diagonal sums and a C within
