@@ -57,7 +57,13 @@ extern "C" {
 /* Slice forms.  FLOAT: binary64 slices on FP64 matrix cores (binary32 slices
  * on FP32 matrix cores for TS), Algorithm 1 as written.  INT8: signed 7-bit
  * digit slices on INT8 matrix cores with exact 32-bit integer sums (DD, TD, QD
- * only); more slices, each product far cheaper. */
+ * only); more slices, each product far cheaper.  Digit s (s = 1..D) of an
+ * element of a row of A (column of B) is the extraction step of Algorithm 1 on
+ * the fixed grid u_s = 2^(E - 6 - 7 (s - 1)), E = 1 + the largest ilogb of the
+ * row's (column's) leading components, applied to the exact value of the
+ * element: d_s = RN(x / u_s) - 128 RN(x / u_(s-1)) (nearest, ties to even;
+ * the first term for s = 0 taken as 0), so |d_s| <= 64 and the digits through
+ * s sum to x rounded to the grid u_s. */
 #define MPGEMM_MODE_FLOAT 0
 #define MPGEMM_MODE_INT8 1
 
