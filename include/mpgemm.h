@@ -62,8 +62,8 @@ extern "C" {
  * the fixed grid u_s = 2^(E - 6 - 7 (s - 1)), E = 1 + the largest ilogb of the
  * row's (column's) leading components, applied to the exact value of the
  * element: d_s = RN(x / u_s) - 128 RN(x / u_(s-1)) (nearest, ties to even;
- * the first term for s = 0 taken as 0), so |d_s| <= 64 and the digits through
- * s sum to x rounded to the grid u_s. */
+ * RN(x / u_0) taken as 0), so |d_s| <= 64 and the digits through s sum to x
+ * rounded to the grid u_s. */
 #define MPGEMM_MODE_FLOAT 0
 #define MPGEMM_MODE_INT8 1
 
