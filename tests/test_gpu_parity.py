@@ -243,6 +243,34 @@ def test_power_of_two_scaling_exact(mp):
     assert np.array_equal(C2, expect)
 
 
+@pytest.mark.parametrize("fmt,mode", [("dd", "float"), ("qd", "float"), ("dd", "int8"), ("qd", "int8"),
+                                      ("ts", "float")])
+def test_edges_of_the_magnitude_range(mp, orc, fmt, mode):
+    """Rows and columns scaled to the edges of the documented input range
+    (binary64 formats: |x| in [2^-400, 2^400]; TS: [2^-16, 2^40]), so that
+    slices, slice products and C sit near the ends of the exponent range:
+    every entry within the bound of the exact product, and rows scaled by a
+    power of two give results scaled by it, bit for bit."""
+    m, n, k = 70, 60, 150
+    A, B = W.gen_pair(fmt, m, n, k, E=8, seed=77)
+    hi, lo = (31, -6) if fmt == "ts" else (390, -390)
+    A[:, :, : m // 2] *= 2.0 ** hi  # products near 2^(hi - 10) for the top-left block
+    B[:, : n // 3, :] *= 2.0 ** (lo + 8)
+    A[:, :, m // 2:] *= 2.0 ** lo
+    C = host(mp.gemm(fmt, dev(A), dev(B), mode=mode))
+    ok, worst = _check_bound(orc, fmt, A, B, C)
+    say(f"magnitude edges {fmt} {mode}: worst {worst:.1f}")
+    assert ok, worst
+    assert np.all(np.isfinite(C))
+    if fmt != "ts":
+        A2 = A.copy()
+        A2[:, :, 5] *= 2.0 ** -7
+        C2 = host(mp.gemm(fmt, dev(A2), dev(B), mode=mode))
+        expect = C.copy()
+        expect[:, :, 5] *= 2.0 ** -7
+        assert np.array_equal(C2, expect)
+
+
 def test_attached_workspace(mp):
     import torch
     A, B = W.gen_pair("dd", 100, 90, 120, E=8, seed=2)
