@@ -154,7 +154,8 @@ int mpgemm_ds_simple(int staging, int m, int n, int k, const double *Ahi, const 
  * arguments after `count` are host arrays of count entries holding what the
  * single call takes (device matrix pointers, sizes, leading dimensions).
  * The split of all operands and one persistent slice-product kernel that takes
- * (product, tile) work items longest first run as one launch sequence.  That
+ * (product, tile) work items, longest first from one list per XCD, run as one
+ * launch sequence.  That
  * sequence is captured once per batch shape (format, count, every m, n, k and
  * slice count, device and stream) into a HIP graph and cached per host thread
  * (up to 6 shapes; releasing the least recently used one synchronizes the

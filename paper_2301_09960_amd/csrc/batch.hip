@@ -8,8 +8,7 @@
 //     descriptors (rewritten before every launch: they carry the caller's
 //     pointers),
 //   - prefix sums of the split tiles per operand and the (product, tile) work
-//     list of the persistent GEMM kernel, ordered by decreasing work
-//     (written once).
+//     items of the persistent GEMM kernel, in one list per XCD (written once).
 // The graph holds: clear the maxima, one max-exponent launch and dmax pass
 // launches covering all operands, clear the work counter, and one persistent
 // GEMM launch.  In the INT8 form: clear the maxima, the max-exponent launch,
@@ -62,7 +61,7 @@ struct BatchPlan {
   std::vector<int> live;  // products with m, n, k > 0
   char *ws = nullptr;
   size_t off_ops = 0, off_descs = 0, desc_bytes = 0, off_prefix0 = 0, off_prefixp = 0, off_prefixf = 0,
-         off_items = 0, off_counter = 0, off_mu = 0, mu_bytes = 0, off_prefixc = 0, total = 0;
+         off_items = 0, off_bounds = 0, off_counter = 0, off_mu = 0, mu_bytes = 0, off_prefixc = 0, total = 0;
   int nops = 0, tiles0 = 0, tilesp = 0, stripsf = 0, dmax = 0, nitems = 0, nitems3 = 0;
   int64_t blocks8 = 0, blocksc = 0;  // INT8 form: split blocks, combine blocks
   void *stage = nullptr;
@@ -100,6 +99,52 @@ BatchCache &cache() {
 }
 
 int tiles64(int64_t a, int64_t b) { return (int)(ceil_div(a, 64) * ceil_div(b, 64)); }
+
+// The work items of a persistent launch as kXcds per-XCD lists (take_item):
+// runs of items with the same key (the tiles of one product, or of one
+// product's k chunk and diagonal group) stay together in one list, so that the
+// workgroups of one XCD read the same operand panels through its L2.  Runs are
+// dealt out in decreasing total work, each to the list with the least work so
+// far, and every list is ordered by decreasing item work (longest first).
+// bounds receives the kXcds + 1 running offsets of the lists in the result.
+template <typename Item, typename Key>
+std::vector<Item> xcd_lists(const std::vector<Item> &items, Key key, int *bounds) {
+  struct Run {
+    int64_t key, item_cost, total;
+    std::vector<int> idx;
+  };
+  std::vector<Run> runs;
+  {
+    std::vector<std::pair<int64_t, int>> keyed(items.size());
+    for (size_t i = 0; i < items.size(); ++i) keyed[i] = {key(items[i]), (int)i};
+    std::stable_sort(keyed.begin(), keyed.end(),
+                     [](const std::pair<int64_t, int> &a, const std::pair<int64_t, int> &b) { return a.first < b.first; });
+    for (const auto &ki : keyed) {
+      if (runs.empty() || runs.back().key != ki.first) runs.push_back({ki.first, items[ki.second].cost, 0, {}});
+      runs.back().idx.push_back(ki.second);
+      runs.back().total += items[ki.second].cost;
+    }
+  }
+  std::stable_sort(runs.begin(), runs.end(), [](const Run &a, const Run &b) { return a.total > b.total; });
+  std::vector<std::vector<const Run *>> lists(kXcds);
+  int64_t load[kXcds] = {};
+  for (const Run &r : runs) {
+    const int q = (int)(std::min_element(load, load + kXcds) - load);
+    lists[q].push_back(&r);
+    load[q] += r.total;
+  }
+  std::vector<Item> out;
+  out.reserve(items.size());
+  bounds[0] = 0;
+  for (int q = 0; q < kXcds; ++q) {
+    std::stable_sort(lists[q].begin(), lists[q].end(),
+                     [](const Run *a, const Run *b) { return a->item_cost > b->item_cost; });
+    for (const Run *r : lists[q])
+      for (int i : r->idx) out.push_back(items[i]);
+    bounds[q + 1] = (int)out.size();
+  }
+  return out;
+}
 
 template <typename T, int C>
 int build_plan(BatchPlan &p, hipStream_t st) {
@@ -158,7 +203,7 @@ int build_plan(BatchPlan &p, hipStream_t st) {
   p.off_prefixp = take((size_t)(p.nops + 1) * 4);
   p.off_prefixf = take((size_t)(p.nops + 1) * 4);
 
-  // work list: (product slot, tile), longest first
+  // work items: (product slot, tile)
   struct Item {
     int slot, tile;
     int64_t cost;
@@ -170,10 +215,12 @@ int build_plan(BatchPlan &p, hipStream_t st) {
     const int64_t cost = (int64_t)L.D * (L.D + 1) / 2 * L.kbp;
     for (int t = 0; t < ntiles; ++t) items.push_back({slot, t, cost});
   }
-  std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
+  int bounds[kXcds + 1];
+  items = xcd_lists(items, [](const Item &it) { return (int64_t)it.slot; }, bounds);
   p.nitems = (int)items.size();
   p.off_items = take(items.size() * sizeof(int2));
-  p.off_counter = take(4);
+  p.off_bounds = take(sizeof(bounds));
+  p.off_counter = take(kXcds * 4);
   p.total = o;
 
   if (hipMalloc(&p.ws, p.total > 0 ? p.total : 256) != hipSuccess) {
@@ -214,7 +261,8 @@ int build_plan(BatchPlan &p, hipStream_t st) {
       hipMemcpy(p.ws + p.off_prefixp, prep.data(), prep.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p.ws + p.off_prefixf, pref.data(), pref.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
       (it2.size() && hipMemcpy(p.ws + p.off_items, it2.data(), it2.size() * sizeof(int2), hipMemcpyHostToDevice) !=
-                         hipSuccess))
+                         hipSuccess) ||
+      hipMemcpy(p.ws + p.off_bounds, bounds, sizeof(bounds), hipMemcpyHostToDevice) != hipSuccess)
     return MPGEMM_ERR_HIP;
 
   // capture the launch sequence on a private stream
@@ -226,10 +274,11 @@ int build_plan(BatchPlan &p, hipStream_t st) {
       reinterpret_cast<const SplitOperand<T> *>(p.ws + p.off_ops), reinterpret_cast<const int *>(p.ws + p.off_prefix0),
       reinterpret_cast<const int *>(p.ws + p.off_prefixp), reinterpret_cast<const int *>(p.ws + p.off_prefixf),
       p.nops, p.tiles0, p.tilesp, p.stripsf, dpass, p.ws + p.off_mu, (int64_t)(p.mu_bytes / 4), cs);
-  if (e == hipSuccess) e = launch_fill32(p.ws + p.off_counter, 1, 0u, cs);
+  if (e == hipSuccess) e = launch_fill32(p.ws + p.off_counter, kXcds, 0u, cs);
   if (e == hipSuccess)
     e = launch_gemm_plain_batched<T, C>(reinterpret_cast<const PlainGemmDesc *>(p.ws + p.off_descs),
-                                        reinterpret_cast<const int2 *>(p.ws + p.off_items), p.nitems,
+                                        reinterpret_cast<const int2 *>(p.ws + p.off_items),
+                                        reinterpret_cast<const int *>(p.ws + p.off_bounds),
                                         reinterpret_cast<int *>(p.ws + p.off_counter),
                                         std::min(p.nitems, kPersistentGrid), p.layout, cs);
   hipGraph_t graph = nullptr;
@@ -310,8 +359,8 @@ void write_descriptors(BatchPlan &p, const T *const *A, const int *lda, const T 
 }
 
 // INT8-form batch: the digit split of every operand, one persistent INT8
-// GEMM over (product, 128 x 128 tile, k chunk, diagonal group) items, longest
-// first, and one combine over every product's blocks.
+// GEMM per tile configuration over (product, tile, k chunk, diagonal group)
+// items in per-XCD lists, and one combine over every product's blocks.
 template <int C>
 int build_plan_int8(BatchPlan &p, int cfg_override) {
   const int count = (int)p.m.size();
@@ -405,14 +454,18 @@ int build_plan_int8(BatchPlan &p, int cfg_override) {
       }
     }
   }
-  auto longest_first = [](const Item &a, const Item &b) { return a.cost > b.cost; };
-  std::stable_sort(items.begin(), items.end(), longest_first);
-  std::stable_sort(items3.begin(), items3.end(), longest_first);
+  // one list per XCD for each configuration; a run is one (product, k chunk,
+  // diagonal group): its tiles
+  auto run_key = [](const Item &it) { return ((int64_t)it.slot << 32) | ((int64_t)it.chunk << 12) | it.group; };
+  int bounds[2 * (kXcds + 1)];
+  items = xcd_lists(items, run_key, bounds);
+  items3 = xcd_lists(items3, run_key, bounds + kXcds + 1);
   p.nitems = (int)items.size();
   p.nitems3 = (int)items3.size();
   items.insert(items.end(), items3.begin(), items3.end());
   p.off_items = take(items.size() * sizeof(int4));
-  p.off_counter = take(8);
+  p.off_bounds = take(sizeof(bounds));
+  p.off_counter = take(2 * kXcds * 4);
   p.total = o;
 
   if (hipMalloc(&p.ws, p.total > 0 ? p.total : 256) != hipSuccess) {
@@ -451,7 +504,8 @@ int build_plan_int8(BatchPlan &p, int cfg_override) {
       hipMemcpy(p.ws + p.off_prefixp, preb.data(), preb.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p.ws + p.off_prefixc, prec.data(), prec.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
       (it4.size() && hipMemcpy(p.ws + p.off_items, it4.data(), it4.size() * sizeof(int4), hipMemcpyHostToDevice) !=
-                         hipSuccess))
+                         hipSuccess) ||
+      hipMemcpy(p.ws + p.off_bounds, bounds, sizeof(bounds), hipMemcpyHostToDevice) != hipSuccess)
     return MPGEMM_ERR_HIP;
 
   BatchCache &bc = cache();
@@ -462,10 +516,11 @@ int build_plan_int8(BatchPlan &p, int cfg_override) {
       reinterpret_cast<const SplitOperand<double> *>(p.ws + p.off_ops),
       reinterpret_cast<const int *>(p.ws + p.off_prefix0), reinterpret_cast<const int *>(p.ws + p.off_prefixp),
       p.nops, p.tiles0, p.blocks8, p.dmax, p.ws + p.off_mu, (int64_t)(p.mu_bytes / 4), cs);
-  if (e == hipSuccess) e = launch_fill32(p.ws + p.off_counter, 2, 0u, cs);
+  if (e == hipSuccess) e = launch_fill32(p.ws + p.off_counter, 2 * kXcds, 0u, cs);
   if (e == hipSuccess)
     e = launch_int8_batched<C>(reinterpret_cast<const Int8GemmDesc *>(p.ws + p.off_descs),
                                reinterpret_cast<const int4 *>(p.ws + p.off_items), p.nitems, p.nitems3,
+                               reinterpret_cast<const int *>(p.ws + p.off_bounds),
                                reinterpret_cast<int *>(p.ws + p.off_counter),
                                reinterpret_cast<const int *>(p.ws + p.off_prefixc), (int)p.live.size(), p.blocksc,
                                cs);

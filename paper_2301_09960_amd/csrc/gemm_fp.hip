@@ -429,15 +429,16 @@ __global__ __launch_bounds__(64 * Layout<LAYOUT>::WM * Layout<LAYOUT>::WN, waves
 // decreasing work, so the long tiles start first).
 template <typename T, int C, int LAYOUT>
 __global__ __launch_bounds__(64 * Layout<LAYOUT>::WM * Layout<LAYOUT>::WN, waves_of(LAYOUT, C, (int)sizeof(T))) void k_gemm_plain_batched(
-    const PlainGemmDesc *__restrict__ descs, const int2 *__restrict__ items, int nitems, int *__restrict__ counter) {
+    const PlainGemmDesc *__restrict__ descs, const int2 *__restrict__ items, const int *__restrict__ bounds,
+    int *__restrict__ counters) {
   __shared__ __attribute__((aligned(16))) T lds[stages_of<T>()][stage_elems<T>()];
   __shared__ int next;
   for (;;) {
-    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    if (threadIdx.x == 0) next = take_item(counters, bounds, blockIdx.x);
     __syncthreads();
     const int it = next;
     __syncthreads();
-    if (it >= nitems) break;
+    if (it < 0) break;
     const int2 w = items[it];
     const PlainGemmDesc &d = descs[w.x];
     const int tiles_m = (int)(d.mbp / kTileBlocks);
@@ -501,21 +502,21 @@ hipError_t launch_gemm_plain_pruned(const void *Apk, const void *Bpk, int64_t mb
 }
 
 template <typename T, int C>
-hipError_t launch_gemm_plain_batched(const PlainGemmDesc *descs, const int2 *items, int nitems, int *counter,
-                                     int grid, int layout, hipStream_t st) {
-  if (nitems <= 0) return hipSuccess;
+hipError_t launch_gemm_plain_batched(const PlainGemmDesc *descs, const int2 *items, const int *bounds,
+                                     int *counters, int grid, int layout, hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
   switch (layout) {
     case 2:
       hipLaunchKernelGGL((k_gemm_plain_batched<T, C, 2>), dim3((unsigned)grid), dim3(threads_of(2)), 0, st, descs,
-                         items, nitems, counter);
+                         items, bounds, counters);
       break;
     case 3:
       hipLaunchKernelGGL((k_gemm_plain_batched<T, C, 3>), dim3((unsigned)grid), dim3(threads_of(3)), 0, st, descs,
-                         items, nitems, counter);
+                         items, bounds, counters);
       break;
     default:
       hipLaunchKernelGGL((k_gemm_plain_batched<T, C, 1>), dim3((unsigned)grid), dim3(threads_of(1)), 0, st, descs,
-                         items, nitems, counter);
+                         items, bounds, counters);
   }
   return hipGetLastError();
 }
@@ -523,8 +524,8 @@ hipError_t launch_gemm_plain_batched(const PlainGemmDesc *descs, const int2 *ite
 #define MP_GEMM_INST(T, C)                                                                                            \
   template hipError_t launch_gemm_plain<T, C>(const void *, const void *, int64_t, int64_t, int64_t, int, int, int, \
                                               T *, int, int64_t, int, double *, int, int, hipStream_t);              \
-  template hipError_t launch_gemm_plain_batched<T, C>(const PlainGemmDesc *, const int2 *, int, int *, int, int,    \
-                                                      hipStream_t);                                                 \
+  template hipError_t launch_gemm_plain_batched<T, C>(const PlainGemmDesc *, const int2 *, const int *, int *, int, \
+                                                      int, hipStream_t);                                            \
   template hipError_t launch_gemm_plain_pruned<T, C>(const void *, const void *, int64_t, int64_t, int64_t, int, int, \
                                                      int, T *, int, int64_t, const int8_t *, int, hipStream_t);
 MP_GEMM_INST(double, 2)

@@ -376,16 +376,17 @@ __global__ __launch_bounds__(256) void k_int8_combine(const int32_t *__restrict_
 // items are ordered by decreasing work.
 template <int CFG>
 __global__ __launch_bounds__(64 * Int8Cfg<CFG>::WM * Int8Cfg<CFG>::WN, 1) void k_gemm_int8_batched(
-    const Int8GemmDesc *__restrict__ descs, const int4 *__restrict__ items, int nitems, int *__restrict__ counter) {
+    const Int8GemmDesc *__restrict__ descs, const int4 *__restrict__ items, const int *__restrict__ bounds,
+    int *__restrict__ counters) {
   __shared__ __attribute__((aligned(16))) int8_t lds[Int8Cfg<CFG>::NS * int8_stage_bytes<CFG>()];
   __shared__ int next;
   constexpr int TB = Int8Cfg<CFG>::TB;
   for (;;) {
-    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    if (threadIdx.x == 0) next = take_item(counters, bounds, blockIdx.x);
     __syncthreads();
     const int it = next;
     __syncthreads();
-    if (it >= nitems) break;
+    if (it < 0) break;
     const int4 w = items[it];
     const Int8GemmDesc &d = descs[w.x];
     const int tiles_m = (int)(d.mbp / TB);
@@ -486,19 +487,20 @@ hipError_t launch_gemm_int8(const void *Apk, const void *Bpk, const int *EA, con
 }
 
 template <int C>
-hipError_t launch_int8_batched(const Int8GemmDesc *descs, const int4 *items, int nitems1, int nitems3, int *counters,
-                               const int *prefix_blocks, int nprod, int64_t blocks, hipStream_t st) {
+hipError_t launch_int8_batched(const Int8GemmDesc *descs, const int4 *items, int nitems1, int nitems3,
+                               const int *bounds, int *counters, const int *prefix_blocks, int nprod, int64_t blocks,
+                               hipStream_t st) {
   // items [0, nitems1): 128 x 128 tiles, two workgroups per CU; then the 256 x 256 ones, one per CU
   if (nitems1 > 0) {
     hipLaunchKernelGGL(k_gemm_int8_batched<1>, dim3(std::min(nitems1, 512)),
-                       dim3(64 * Int8Cfg<1>::WM * Int8Cfg<1>::WN), 0, st, descs, items, nitems1, counters);
+                       dim3(64 * Int8Cfg<1>::WM * Int8Cfg<1>::WN), 0, st, descs, items, bounds, counters);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
   if (nitems3 > 0) {
     hipLaunchKernelGGL(k_gemm_int8_batched<3>, dim3(std::min(nitems3, 256)),
-                       dim3(64 * Int8Cfg<3>::WM * Int8Cfg<3>::WN), 0, st, descs, items + nitems1, nitems3,
-                       counters + 1);
+                       dim3(64 * Int8Cfg<3>::WM * Int8Cfg<3>::WN), 0, st, descs, items + nitems1, bounds + kXcds + 1,
+                       counters + kXcds);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
@@ -528,12 +530,12 @@ MP_INT8_INST(11)
 MP_INT8_INST(12)
 MP_INT8_INST(13)
 MP_INT8_INST(14)
-template hipError_t launch_int8_batched<2>(const Int8GemmDesc *, const int4 *, int, int, int *, const int *, int,
-                                           int64_t, hipStream_t);
-template hipError_t launch_int8_batched<3>(const Int8GemmDesc *, const int4 *, int, int, int *, const int *, int,
-                                           int64_t, hipStream_t);
-template hipError_t launch_int8_batched<4>(const Int8GemmDesc *, const int4 *, int, int, int *, const int *, int,
-                                           int64_t, hipStream_t);
+template hipError_t launch_int8_batched<2>(const Int8GemmDesc *, const int4 *, int, int, const int *, int *,
+                                           const int *, int, int64_t, hipStream_t);
+template hipError_t launch_int8_batched<3>(const Int8GemmDesc *, const int4 *, int, int, const int *, int *,
+                                           const int *, int, int64_t, hipStream_t);
+template hipError_t launch_int8_batched<4>(const Int8GemmDesc *, const int4 *, int, int, const int *, int *,
+                                           const int *, int, int64_t, hipStream_t);
 #undef MP_INT8_INST
 
 }  // namespace mp

@@ -10,6 +10,25 @@ namespace mp {
 
 constexpr int kZeroExp = INT32_MIN;
 
+// Work lists of a persistent launch, one per XCD (each XCD has its own L2).
+// List q holds items [bounds[q], bounds[q + 1]); counters[q] counts the items
+// taken from it (cleared before the launch).  Workgroups are dispatched to the
+// XCDs in turn, so workgroup b runs on XCD b % kXcds: it takes items from its
+// own list first, so that the workgroups sharing an L2 work on the tiles of the
+// same products at the same time, then from the other lists, so that no list
+// waits for one XCD.  Returns -1 once every list is drained.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int take_item(int *counters, const int *bounds, int b) {
+  for (int j = 0; j < kXcds; ++j) {
+    const int q = (b + j) % kXcds;
+    const int size = bounds[q + 1] - bounds[q];
+    if (size <= 0) continue;
+    const int i = atomicAdd(&counters[q], 1);
+    if (i < size) return bounds[q] + i;
+  }
+  return -1;
+}
+
 // One operand of a split: `nvec` vectors (rows of A, or columns of B) of `len`
 // multi-component elements; component r of element (v, p) is at
 // X[r * comp_stride + v * sv + p * sp].  `orient` 0: v is the contiguous
@@ -94,9 +113,10 @@ hipError_t launch_split_plain_batched(const SplitOperand<T> *ops, const int *pre
                                       int strips_fused, int dmax, void *mu_all, int64_t mu_words, hipStream_t st);
 
 // Persistent GEMM over a batch: items (product index, tile index) in device
-// memory, taken in order through *counter (cleared by the caller).
+// memory, in kXcds per-XCD lists (bounds: kXcds + 1 running offsets; counters:
+// kXcds words, cleared by the caller; take_item).
 template <typename T, int C>
-hipError_t launch_gemm_plain_batched(const PlainGemmDesc *descs, const int2 *items, int nitems, int *counter,
+hipError_t launch_gemm_plain_batched(const PlainGemmDesc *descs, const int2 *items, const int *bounds, int *counters,
                                      int grid, int layout, hipStream_t st);
 
 // INT8 digit split of both operands.
@@ -114,12 +134,15 @@ hipError_t launch_split_int8_batched(const SplitOperand<double> *ops, const int 
 // INT8-form batch: persistent GEMMs over items (product, tile, k chunk,
 // diagonal group): items[0, nitems1) in the 128 x 128 configuration (their
 // products' slices padded to 128 rows), then nitems3 in the 256 x 256 one,
-// taken through counters[0] and counters[1] (cleared by the caller); then the
+// each in kXcds per-XCD lists (bounds[0, kXcds] over the first items,
+// bounds[kXcds + 1, 2 kXcds + 1] over the second, relative to their first
+// item; counters: 2 kXcds words, cleared by the caller; take_item); then the
 // combine of every product, prefix_blocks giving the running sums of the
 // 32 x 32 blocks of each product's C.
 template <int C>
-hipError_t launch_int8_batched(const Int8GemmDesc *descs, const int4 *items, int nitems1, int nitems3, int *counters,
-                               const int *prefix_blocks, int nprod, int64_t blocks, hipStream_t st);
+hipError_t launch_int8_batched(const Int8GemmDesc *descs, const int4 *items, int nitems1, int nitems3,
+                               const int *bounds, int *counters, const int *prefix_blocks, int nprod, int64_t blocks,
+                               hipStream_t st);
 
 // Fused slice-product GEMM with error-free accumulation into C (C components).
 // single_pair >= 0 selects debug mode: only pair (a, b) = (single_pair / D,
