@@ -311,11 +311,31 @@ __global__ __launch_bounds__(64 * Int8Cfg<CFG>::WM * Int8Cfg<CFG>::WN, 1) void k
 // (32 bi + l % 32, 32 bj + 8 (r / 4) + 4 (l / 32) + r % 4) at
 // ((bj * mbp + bi) * 64 + l) * 16 + r.  A combine thread takes four
 // consecutive r of one (block, lane): one 16-byte load per diagonal and chunk.
+//
+// Consecutive diagonals differ in weight by 2^7, so a run of L of them is
+// summed exactly in a 64-bit integer, T = sum_j S_(g0 + j) 2^(7 (L - 1 - j)),
+// at the weight of its last diagonal, and enters the accumulator as the two
+// binary64 values hi = RN(T) and lo = T - hi (exact: |lo| < 2^9 while
+// |T| < 2^62).  With digits of at most 64 in magnitude, |S_g| <= g K 2^12 <=
+// D K 2^12 (K the padded k); for 2^B >= D K 2^12, |T| < 2^(B + 7 (L - 1) + 1),
+// so L = 1 + (61 - B) / 7 keeps |T| below 2^62 (L = 5 for QD at k = 4096).
+// Two accumulator additions per run instead of one per diagonal: the combine
+// is bound by its binary64 additions, not by its loads.
+__host__ __device__ inline int combine_run(int D, int64_t kbp) {
+  int64_t x = (int64_t)(D > 0 ? D : 1) * (kbp > 0 ? kbp : 1) * kKBlk8;  // D K
+  int b = 12;
+  while (x > 1) {  // b = 12 + ceil(log2(D K))
+    x = (x + 1) / 2;
+    ++b;
+  }
+  return b <= 61 ? 1 + (61 - b) / 7 : 1;
+}
+
 // Combine thread t (0 <= t < mbp * nbp * 256) of one product: four
 // consecutive accumulator entries r of one (block, lane).
 template <int C>
 __device__ __forceinline__ void combine_one(int64_t t, const int32_t *__restrict__ S, int64_t plane, int nchunks,
-                                            int D, const int *__restrict__ EA, const int *__restrict__ EB,
+                                            int D, int run, const int *__restrict__ EA, const int *__restrict__ EB,
                                             int64_t mbp, int m, int n, double *__restrict__ Cout, int ldc,
                                             int64_t c_stride, int debug_g, int64_t *__restrict__ Sdbg, int lddbg) {
   const int q = (int)(t % 4);
@@ -335,19 +355,30 @@ __device__ __forceinline__ void combine_one(int64_t t, const int32_t *__restrict
 #pragma unroll
     for (int c = 0; c <= C; ++c) acc[e][c] = 0.0;
   }
-  for (int g = 1; g <= D; ++g) {
-    int64_t s[4] = {0, 0, 0, 0};
-    for (int c = 0; c < nchunks; ++c) {
-      const i4v v = *reinterpret_cast<const i4v *>(S + ((int64_t)(g - 1) * nchunks + c) * plane + off);
+  for (int g0 = 1; g0 <= D; g0 += run) {
+    const int g1 = g0 + run <= D + 1 ? g0 + run : D + 1;  // diagonals g0 .. g1 - 1
+    int64_t T[4] = {0, 0, 0, 0};
+    for (int g = g0; g < g1; ++g) {
+      int64_t s[4] = {0, 0, 0, 0};
+      for (int c = 0; c < nchunks; ++c) {
+        const i4v v = *reinterpret_cast<const i4v *>(S + ((int64_t)(g - 1) * nchunks + c) * plane + off);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) s[e] += v[e];
+        for (int e = 0; e < 4; ++e) s[e] += v[e];
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (debug_g == g && j0 + e < n) Sdbg[i + (int64_t)(j0 + e) * lddbg] = s[e];
+        T[e] = T[e] * 128 + s[e];
+      }
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      if (j0 + e >= n) continue;
-      if (debug_g == g) Sdbg[i + (int64_t)(j0 + e) * lddbg] = s[e];
-      if (Ei != kZeroExp && Fj[e] != kZeroExp && s[e] != 0)
-        acc_add<double, C + 1>(acc[e], ldexp((double)s[e], Ei + Fj[e] + 2 - 7 * (g + 1)));
+      if (j0 + e >= n || Ei == kZeroExp || Fj[e] == kZeroExp || T[e] == 0) continue;
+      const double hi = (double)T[e];
+      const double lo = (double)(T[e] - (int64_t)hi);
+      const int w = Ei + Fj[e] + 2 - 7 * g1;  // the weight of diagonal g1 - 1
+      acc_add<double, C + 1>(acc[e], ldexp(hi, w));
+      acc_add<double, C + 1>(acc[e], ldexp(lo, w));
     }
   }
   if (debug_g > 0) return;
@@ -362,13 +393,13 @@ __device__ __forceinline__ void combine_one(int64_t t, const int32_t *__restrict
 
 template <int C>
 __global__ __launch_bounds__(256) void k_int8_combine(const int32_t *__restrict__ S, int64_t plane, int nchunks, int D,
-                                                      const int *__restrict__ EA, const int *__restrict__ EB,
+                                                      int run, const int *__restrict__ EA, const int *__restrict__ EB,
                                                       int64_t mbp, int64_t nbp, int m, int n,
                                                       double *__restrict__ Cout, int ldc, int64_t c_stride,
                                                       int debug_g, int64_t *__restrict__ Sdbg, int lddbg) {
   const int64_t total = mbp * nbp * 64 * 4;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x)
-    combine_one<C>(t, S, plane, nchunks, D, EA, EB, mbp, m, n, Cout, ldc, c_stride, debug_g, Sdbg, lddbg);
+    combine_one<C>(t, S, plane, nchunks, D, run, EA, EB, mbp, m, n, Cout, ldc, c_stride, debug_g, Sdbg, lddbg);
 }
 
 // Persistent INT8 GEMM of a batch in tile configuration CFG: each workgroup
@@ -417,8 +448,8 @@ __global__ __launch_bounds__(256) void k_int8_combine_batched(const Int8GemmDesc
   }
   const Int8GemmDesc &d = descs[lo];
   const int64_t t = ((int64_t)blockIdx.x - prefix[lo]) * 256 + threadIdx.x;
-  combine_one<C>(t, d.S, d.plane, d.nchunks, d.D, d.EA, d.EB, d.mbp, d.m, d.n, d.C, d.ldc, d.c_stride, 0, nullptr,
-                 0);
+  combine_one<C>(t, d.S, d.plane, d.nchunks, d.D, combine_run(d.D, d.kbp), d.EA, d.EB, d.mbp, d.m, d.n, d.C, d.ldc,
+                 d.c_stride, 0, nullptr, 0);
 }
 
 }  // namespace
@@ -482,7 +513,8 @@ hipError_t launch_gemm_int8(const void *Apk, const void *Bpk, const int *EA, con
   if (err != hipSuccess) return err;
   const int64_t blocks = ceil_div(mbp * nbp * 256, 256);
   hipLaunchKernelGGL((k_int8_combine<C>), dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, st, Sws,
-                     plane, nchunks, D, EA, EB, mbp, nbp, m, n, Cout, ldc, c_stride, debug_g, Sdbg, lddbg);
+                     plane, nchunks, D, combine_run(D, kbp), EA, EB, mbp, nbp, m, n, Cout, ldc, c_stride, debug_g,
+                     Sdbg, lddbg);
   return hipGetLastError();
 }
 
