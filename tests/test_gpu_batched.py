@@ -144,6 +144,22 @@ def test_batched_int8_equals_single_calls(mp, orc, fmt):
         assert ok, (i, sh[i], worst)
 
 
+@pytest.mark.parametrize("mode", ["float", "int8"])
+@pytest.mark.parametrize("sh", [[(1, 1, 1)], [(70, 9, 33), (5, 130, 64)], [(64, 64, 64), (3, 3, 300), (129, 65, 2)]])
+def test_batches_with_fewer_items_than_work_lists(mp, mode, sh):
+    """Batches of one to three small products give fewer work items than
+    there are per-XCD lists (and a persistent grid that small): every product
+    still equals its single call bit for bit."""
+    import torch
+    host = make_batch("dd", sh, seed=29)
+    As = [dev(A) for A, _ in host]
+    Bs = [dev(B) for _, B in host]
+    Cs = mp.gemm_batched("dd", As, Bs, mode=mode)
+    torch.cuda.synchronize()
+    for i, (A, B) in enumerate(zip(As, Bs)):
+        assert torch.equal(mp.gemm("dd", A, B, mode=mode), Cs[i]), (i, sh[i])
+
+
 def test_graph_replays_with_new_inputs(mp):
     import torch
     sh = shapes(2, 24, 16, 200)
