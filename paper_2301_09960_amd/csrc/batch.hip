@@ -75,6 +75,7 @@ struct BatchPlan {
   size_t off_ops = 0, off_descs = 0, desc_bytes = 0, off_prefix0 = 0, off_prefixp = 0, off_prefixf = 0,
          off_items = 0, off_bounds = 0, off_counter = 0, off_mu = 0, mu_bytes = 0, off_prefixc = 0, total = 0;
   int nops = 0, tiles0 = 0, tilesp = 0, stripsf = 0, dmax = 0, nitems = 0, nitems3 = 0;
+  int fused_nt = 1024;  // threads of the fused-split workgroups
   int64_t blocks8 = 0, blocksc = 0;  // INT8 form: split blocks, combine blocks
   void *stage = nullptr;
   hipEvent_t stage_done = nullptr;
@@ -172,6 +173,12 @@ int build_plan(BatchPlan &p, hipStream_t st) {
   p.prod.resize(count);
   p.live.clear();
   p.dmax = 0;
+  // one fused-split launch for the batch: 512-thread workgroups when every
+  // product's vectors allow them, else 1024
+  p.fused_nt = 512;
+  for (int g = 0; g < count; ++g)
+    if (p.m[g] > 0 && p.n[g] > 0 && p.k[g] > 0 && fused_threads<T, C>(kblocks_padded(p.k[g]) * kKBlk) == 1024)
+      p.fused_nt = 1024;
   for (int g = 0; g < count; ++g) {
     ProductLayout &L = p.prod[g];
     L.m = p.m[g];
@@ -184,8 +191,8 @@ int build_plan(BatchPlan &p, hipStream_t st) {
     L.mbp = nblocks_padded(L.m);
     L.nbp = nblocks_padded(L.n);
     L.kbp = kblocks_padded(L.k);
-    L.fused_a = p.split_kernel == 0 && fused_strips<T, C>(OperandShape{L.kbp, L.mbp, L.m}) >= 0;
-    L.fused_b = p.split_kernel == 0 && fused_strips<T, C>(OperandShape{L.kbp, L.nbp, L.n}) >= 0;
+    L.fused_a = p.split_kernel == 0 && fused_strips<T, C>(OperandShape{L.kbp, L.mbp, L.m}, p.fused_nt) >= 0;
+    L.fused_b = p.split_kernel == 0 && fused_strips<T, C>(OperandShape{L.kbp, L.nbp, L.n}, p.fused_nt) >= 0;
     L.resid_a = take(L.D > 1 && !L.fused_a ? (size_t)C * L.m * L.k * w : 0);
     L.resid_b = take(L.D > 1 && !L.fused_b ? (size_t)C * L.k * L.n * w : 0);
     L.pack_a = take((size_t)L.D * L.mbp * L.kbp * 256 * w);
@@ -258,7 +265,7 @@ int build_plan(BatchPlan &p, hipStream_t st) {
       const int i = 2 * slot + side;
       const int64_t nvec = side == 0 ? L.m : L.n, nbp = side == 0 ? L.mbp : L.nbp;
       const bool fused = side == 0 ? L.fused_a : L.fused_b;
-      pref[i + 1] = pref[i] + (fused ? fused_strips<T, C>(OperandShape{L.kbp, nbp, nvec}) : 0);
+      pref[i + 1] = pref[i] + (fused ? fused_strips<T, C>(OperandShape{L.kbp, nbp, nvec}, p.fused_nt) : 0);
       pre0[i + 1] = pre0[i] + (fused ? 0 : tiles64(nvec, L.k));
       prep[i + 1] = prep[i] + (fused ? 0 : tiles64(nbp * kBlk, L.kbp * kKBlk));
       if (!fused) dpass = std::max(dpass, L.D);
@@ -285,7 +292,7 @@ int build_plan(BatchPlan &p, hipStream_t st) {
   hipError_t e = launch_split_plain_batched<T, C>(
       reinterpret_cast<const SplitOperand<T> *>(p.ws + p.off_ops), reinterpret_cast<const int *>(p.ws + p.off_prefix0),
       reinterpret_cast<const int *>(p.ws + p.off_prefixp), reinterpret_cast<const int *>(p.ws + p.off_prefixf),
-      p.nops, p.tiles0, p.tilesp, p.stripsf, dpass, p.ws + p.off_mu, (int64_t)(p.mu_bytes / 4), cs);
+      p.nops, p.tiles0, p.tilesp, p.stripsf, p.fused_nt, dpass, p.ws + p.off_mu, (int64_t)(p.mu_bytes / 4), cs);
   if (e == hipSuccess) e = launch_fill32(p.ws + p.off_counter, kXcds, 0u, cs);
   if (e == hipSuccess)
     e = launch_gemm_plain_batched<T, C>(reinterpret_cast<const PlainGemmDesc *>(p.ws + p.off_descs),

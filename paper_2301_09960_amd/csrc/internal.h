@@ -71,25 +71,38 @@ struct PlainGemmDesc {
   int64_t c_stride;
 };
 
-// Fused plain split: a workgroup of kFusedThreads threads holds the residual of
+// Fused plain split: a workgroup of 512 or 1024 threads holds the residual of
 // nv whole vectors in registers, fused_per_thread<T, C>() elements per thread.
-constexpr int kFusedThreads = 1024;
 template <typename T, int C>
 __host__ __device__ constexpr int fused_per_thread() {
   return sizeof(T) == 8 ? (C == 2 ? 16 : C == 3 ? 10 : 8) : 16;
 }
-// Vectors per workgroup (16, 8, 4 or 2; a divisor of the 16 of a packed
-// block) for vectors of padded length len_cover; 0 when not even two fit.
-__host__ __device__ inline int fused_vectors(int64_t len_cover, int per_thread) {
-  for (int nv = kBlk; nv >= 2; nv /= 2)
-    if (nv * len_cover <= (int64_t)kFusedThreads * per_thread) return nv;
+// Vectors per workgroup of `threads` threads (16, 8, 4, 2 or 1; a divisor of
+// the 16 of a packed block) for vectors of padded length len_cover; 0 when not
+// even one fits.
+__host__ __device__ inline int fused_vectors(int64_t len_cover, int per_thread, int threads) {
+  for (int nv = kBlk; nv >= 1; nv /= 2)
+    if (nv * len_cover <= (int64_t)threads * per_thread) return nv;
   return 0;
 }
-// Workgroups of the fused split for one operand; -1 if its vectors are too long.
+// Threads of a fused-split workgroup for vectors of padded length len_cover:
+// 512 while 4 or more vectors fit (two workgroups share a CU, one computing
+// while the other waits for its loads); else 1024 while 2 fit (fewer vectors
+// per workgroup cut the reads of A's rows and the slice stores into short
+// runs); 0 when the vectors are too long to fuse.
+template <typename T, int C>
+inline int fused_threads(int64_t len_cover) {
+  if (fused_vectors(len_cover, fused_per_thread<T, C>(), 512) >= 4) return 512;
+  if (fused_vectors(len_cover, fused_per_thread<T, C>(), 1024) >= 2) return 1024;
+  return 0;
+}
+// Workgroups of `threads` threads of the fused split for one operand; -1 if
+// its vectors do not fit them as fused_threads allows.
 template <typename T, int C, typename Op>
-inline int fused_strips(const Op &op) {
-  const int nv = fused_vectors(op.kbp * kKBlk, fused_per_thread<T, C>());
-  if (nv == 0) return -1;
+inline int fused_strips(const Op &op, int threads) {
+  const int ft = fused_threads<T, C>(op.kbp * kKBlk);
+  if (ft == 0 || ft > threads) return -1;
+  const int nv = fused_vectors(op.kbp * kKBlk, fused_per_thread<T, C>(), threads);
   return op.nvec > 0 ? (int)(op.nbp * kBlk / nv) : 0;
 }
 
@@ -102,7 +115,8 @@ hipError_t launch_split_plain(const SplitOperand<T> &a, const SplitOperand<T> &b
 
 // Plain split of many operands at once: ops[0..nops) in device memory.
 // prefix_fused (nops + 1 entries, device) holds running sums of the fused
-// workgroups of each operand (0 for operands left to the pass kernels);
+// workgroups (of fused_nt threads) of each operand (0 for operands left to the
+// pass kernels);
 // prefix_max0 / prefix_pass the running sums of the 64 x 64 tiles each
 // remaining operand needs in the max and pass kernels (0 for fused operands).
 // Operand i runs ops[i].D passes; pass launches cover dmax passes.  mu_all /
@@ -110,7 +124,8 @@ hipError_t launch_split_plain(const SplitOperand<T> &a, const SplitOperand<T> &b
 template <typename T, int C>
 hipError_t launch_split_plain_batched(const SplitOperand<T> *ops, const int *prefix_max0, const int *prefix_pass,
                                       const int *prefix_fused, int nops, int tiles_max0, int tiles_pass,
-                                      int strips_fused, int dmax, void *mu_all, int64_t mu_words, hipStream_t st);
+                                      int strips_fused, int fused_nt, int dmax, void *mu_all, int64_t mu_words,
+                                      hipStream_t st);
 
 // Persistent GEMM over a batch: items (product index, tile index) in device
 // memory, in kXcds per-XCD lists (bounds: kXcds + 1 running offsets; counters:

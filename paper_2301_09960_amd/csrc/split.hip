@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kThreads) void k_split_pass_batched(const SplitOper
 
 // ---------------------------------------------------------------------------
 // Fused plain split.  While whole vectors fit in one workgroup's registers, a
-// workgroup of kFusedThreads threads takes nv vectors (nv of the 16 of one
+// workgroup of NT threads (512 or 1024) takes nv vectors (nv of the 16 of one
 // packed row/column block) over their full padded length and runs all D
 // passes itself.  The maximum of each pass is reduced inside the workgroup, so
 // the operand is read once and only the slices are written, instead of D + 1
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(kThreads) void k_split_pass_batched(const SplitOper
 // arithmetic of pass_body, step for step, so the slices and exponents are the
 // same as those of the pass kernels.
 //
-// Thread t holds the strip elements t + kFusedThreads j, numbered in packed
+// Thread t holds the strip elements t + NT j, numbered in packed
 // order.  Each slice store is then a run of 2 nv (binary64) or 4 nv (binary32)
 // consecutive elements per group of lanes, and every element of a thread lies
 // in the same vector (that run length divides 64).
@@ -259,14 +259,14 @@ __device__ __forceinline__ int xcd_contiguous(int b, int total) {
   return x * per + (x < rem ? x : rem) + b / 8;
 }
 
-template <typename T, int C>
+template <typename T, int C, int NT>
 __device__ void fused_strip(const SplitOperand<T> &op, int strip, int D, int rho) {
   using U = typename bits_of<T>::type;
   constexpr int kPer = fused_per_thread<T, C>();
   constexpr int kRunPer = sizeof(T) == 8 ? 2 : 4;  // consecutive packed elements of one vector
-  constexpr int kWaves = kFusedThreads / 64;
+  constexpr int kWaves = NT / 64;
   const int64_t len_cover = op.kbp * kKBlk;
-  const int nv = fused_vectors(len_cover, kPer);
+  const int nv = fused_vectors(len_cover, kPer, NT);
   const int run = kRunPer * nv, per_block = kBlk * nv;
   const int v0 = strip * nv, vb = v0 / kBlk, vl0 = v0 % kBlk;
   const int nl = (int)(nv * len_cover);
@@ -282,7 +282,7 @@ __device__ void fused_strip(const SplitOperand<T> &op, int strip, int D, int rho
   U m = 0;
 #pragma unroll
   for (int j = 0; j < kPer; ++j) {
-    const int idx = tid + kFusedThreads * j;
+    const int idx = tid + NT * j;
     off[j] = -1;
     valid[j] = false;
 #pragma unroll
@@ -350,25 +350,24 @@ __device__ void fused_strip(const SplitOperand<T> &op, int strip, int D, int rho
   }
 }
 
-template <typename T, int C>
-__global__ __launch_bounds__(kFusedThreads) void k_split_fused(SplitOperand<T> a, SplitOperand<T> b, int strips_a,
-                                                               int D, int rho) {
+template <typename T, int C, int NT>
+__global__ __launch_bounds__(NT) void k_split_fused(SplitOperand<T> a, SplitOperand<T> b, int strips_a, int D,
+                                                    int rho) {
   const int w = xcd_contiguous(blockIdx.x, gridDim.x);
   if (w < strips_a)
-    fused_strip<T, C>(a, w, D, rho);
+    fused_strip<T, C, NT>(a, w, D, rho);
   else
-    fused_strip<T, C>(b, w - strips_a, D, rho);
+    fused_strip<T, C, NT>(b, w - strips_a, D, rho);
 }
 
 // Batched: workgroup b takes strip b - prefix[i] of operand i (operands split
 // by the pass kernels own no strips).
-template <typename T, int C>
-__global__ __launch_bounds__(kFusedThreads) void k_split_fused_batched(const SplitOperand<T> *ops, const int *prefix,
-                                                                       int nops) {
+template <typename T, int C, int NT>
+__global__ __launch_bounds__(NT) void k_split_fused_batched(const SplitOperand<T> *ops, const int *prefix, int nops) {
   const int w = xcd_contiguous(blockIdx.x, gridDim.x);
   const int i = __builtin_amdgcn_readfirstlane(find_operand(prefix, nops, w));
   const SplitOperand<T> op = ops[i];  // uniform: kept in scalar registers
-  fused_strip<T, C>(op, w - prefix[i], op.D, op.rho);
+  fused_strip<T, C, NT>(op, w - prefix[i], op.D, op.rho);
 }
 
 __global__ void k_fill32(uint32_t *p, int64_t n, uint32_t value) {
@@ -390,10 +389,15 @@ template <typename T, int C>
 hipError_t launch_split_plain(const SplitOperand<T> &a, const SplitOperand<T> &b, int D, int rho, bool fused,
                               hipStream_t st) {
   using U = typename bits_of<T>::type;
-  if (fused && fused_strips<T, C>(a) >= 0 && fused_strips<T, C>(b) >= 0) {
-    const int sa = fused_strips<T, C>(a), sb = fused_strips<T, C>(b);
+  const int ta = fused_threads<T, C>(a.kbp * kKBlk), tb = fused_threads<T, C>(b.kbp * kKBlk);
+  if (fused && ta > 0 && tb > 0) {
+    const int nt = ta > tb ? ta : tb;
+    const int sa = fused_strips<T, C>(a, nt), sb = fused_strips<T, C>(b, nt);
     if (sa + sb > 0 && D > 0) {
-      hipLaunchKernelGGL((k_split_fused<T, C>), dim3(sa + sb), dim3(kFusedThreads), 0, st, a, b, sa, D, rho);
+      if (nt == 512)
+        hipLaunchKernelGGL((k_split_fused<T, C, 512>), dim3(sa + sb), dim3(512), 0, st, a, b, sa, D, rho);
+      else
+        hipLaunchKernelGGL((k_split_fused<T, C, 1024>), dim3(sa + sb), dim3(1024), 0, st, a, b, sa, D, rho);
       return hipGetLastError();
     }
     return hipSuccess;
@@ -422,12 +426,17 @@ hipError_t launch_split_plain(const SplitOperand<T> &a, const SplitOperand<T> &b
 template <typename T, int C>
 hipError_t launch_split_plain_batched(const SplitOperand<T> *ops, const int *prefix_max0, const int *prefix_pass,
                                       const int *prefix_fused, int nops, int tiles_max0, int tiles_pass,
-                                      int strips_fused, int dmax, void *mu_all, int64_t mu_words, hipStream_t st) {
+                                      int strips_fused, int fused_nt, int dmax, void *mu_all, int64_t mu_words,
+                                      hipStream_t st) {
   hipError_t err = hipSuccess;
   if (nops <= 0) return err;
   if (strips_fused > 0) {
-    hipLaunchKernelGGL((k_split_fused_batched<T, C>), dim3(strips_fused), dim3(kFusedThreads), 0, st, ops,
-                       prefix_fused, nops);
+    if (fused_nt == 512)
+      hipLaunchKernelGGL((k_split_fused_batched<T, C, 512>), dim3(strips_fused), dim3(512), 0, st, ops, prefix_fused,
+                         nops);
+    else
+      hipLaunchKernelGGL((k_split_fused_batched<T, C, 1024>), dim3(strips_fused), dim3(1024), 0, st, ops,
+                         prefix_fused, nops);
     if ((err = hipGetLastError()) != hipSuccess) return err;
   }
   if (tiles_max0 <= 0 && tiles_pass <= 0) return hipSuccess;
@@ -446,8 +455,8 @@ hipError_t launch_split_plain_batched(const SplitOperand<T> *ops, const int *pre
 
 #define MP_SPLIT_BATCHED(T, C)                                                                                 \
   template hipError_t launch_split_plain_batched<T, C>(const SplitOperand<T> *, const int *, const int *,         \
-                                                       const int *, int, int, int, int, int, void *, int64_t, \
-                                                       hipStream_t);
+                                                       const int *, int, int, int, int, int, int, void *,     \
+                                                       int64_t, hipStream_t);
 MP_SPLIT_BATCHED(double, 2)
 MP_SPLIT_BATCHED(double, 3)
 MP_SPLIT_BATCHED(double, 4)
