@@ -148,7 +148,18 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
   static_assert(KSB % kKStepBlocks8 == 0 && KSB <= 2 * kKStepBlocks8, "k steps and the k padding unit");
 
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-  const int wm = wave % WM, wn = wave / WM;
+  // wavefront -> (wm, wn).  With 2 x 4 wavefronts (two per SIMD: w and w + 4)
+  // the two of a SIMD differ in both wm and wn, so that a tile padded in m or
+  // in n leaves each SIMD a wavefront with work.
+  int wm, wn;
+  if constexpr (WM == 2 && WN == 4) {
+    const int sw = wave & 3, hw = wave >> 2;
+    wm = (sw & 1) ^ hw;
+    wn = (sw >> 1) + 2 * hw;
+  } else {
+    wm = wave % WM;
+    wn = wave / WM;
+  }
   // diagonals g0 .. g1 - 1 (g pairs each)
   const int64_t total = ((int64_t)(g1 - 1) * g1 / 2 - (int64_t)(g0 - 1) * g0 / 2) * nks;
 
@@ -207,6 +218,34 @@ __device__ __forceinline__ void gemm_int8_tile(const int8_t *__restrict__ Apk, c
       for (int j = 0; j < kL; ++j) load_lds16(src + piece(j, lks), dst + loff[j]);
       advance();
     }
+
+  // A wavefront whose blocks are all padding (rows from m or columns from n
+  // on) has no matrix-core work: it only moves its share of the panels, at the
+  // places and about the pace (64 cycles per two instructions) of the others,
+  // and passes the same barriers.  It leaves its blocks of the S_g planes
+  // unwritten; the combine reads no element outside m x n.
+  if (__builtin_amdgcn_readfirstlane(((int64_t)tm * TB + wm * BI) * 32 >= m || ((int64_t)tn * TB + wn * BJ) * 32 >= n
+                                         ? 1
+                                         : 0)) {
+    for (int64_t step = 0; step < total; ++step) {
+      wait_step<NS, kL>(total - 1 - step);
+      __builtin_amdgcn_s_barrier();
+      const bool more = issued < total;
+      const int8_t *nsrc = more ? panel_base() : Apk;
+      int8_t *ndst = lds + (issued % NS) * int8_stage_bytes<CFG>();
+      const uint32_t next_short = lks == nks - 1 && last < KSB ? 1u : 0u;
+#pragma unroll
+      for (int mma = 0; mma < kMma; ++mma) {
+        if (mma % kEvery == 0 && mma / kEvery < kL && more)
+          load_lds16(nsrc + (goff[mma / kEvery] - next_short * beyond[mma / kEvery]), ndst + loff[mma / kEvery]);
+        if (mma % 2 == 1) __builtin_amdgcn_s_sleep(1);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (more) advance();
+    }
+    __builtin_amdgcn_s_barrier();
+    return;
+  }
 
   int cg = g0, cs = 1, cks = 0;  // compute cursor
   for (int64_t step = 0; step < total; ++step) {
