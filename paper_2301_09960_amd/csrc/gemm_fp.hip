@@ -184,7 +184,18 @@ __device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const
   static_assert(2 * kInstPerPanel % NW == 0, "staging split");
 
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-  const int wm = wave % WM, wn = wave / WM;
+  // wavefront -> (wm, wn).  With 2 x 4 wavefronts (two per SIMD: w and w + 4)
+  // the two of a SIMD differ in both wm and wn, so that a tile padded in m or
+  // in n leaves each SIMD a wavefront with work.
+  int wm, wn;
+  if constexpr (WM == 2 && WN == 4) {
+    const int sw = wave & 3, hw = wave >> 2;
+    wm = (sw & 1) ^ hw;
+    wn = (sw >> 1) + 2 * hw;
+  } else {
+    wm = wave % WM;
+    wn = wave / WM;
+  }
 
   const int nks = (int)(kbp / kKStepBlocks);
   auto lim = [&](int a) -> int {
@@ -276,6 +287,35 @@ __device__ __forceinline__ void gemm_plain_tile(const T *__restrict__ Apk, const
   static_assert(kMma % kL == 0, "one load per fixed number of matrix-core instructions");
   constexpr int kEvery = kMma / kL;
   constexpr bool kSpread = sizeof(T) == 8 && LAYOUT == 1;
+
+  // A wavefront whose blocks are all padding (rows from m or columns from n
+  // on) has no matrix-core work and nothing to store: it only moves its share
+  // of the panels, at the places and about the pace (one 64-cycle sleep per
+  // instruction slot where loads are spread) of the others, and passes the same
+  // barriers.
+  if (__builtin_amdgcn_readfirstlane(tm * 64 + wm * BI * 16 >= m || tn * 64 + wn * BJ * 16 >= n ? 1 : 0)) {
+    for (int64_t step = 0; step < total; ++step) {
+      wait_step<kStages, kL>(total - 1 - step);
+      __builtin_amdgcn_s_barrier();
+      const bool more = issued < total;
+      const char *nsrc = more ? panel_base() : reinterpret_cast<const char *>(Apk);
+      T *ndst = lds + (issued % kStages) * stage_elems<T>();
+      if constexpr (kSpread) {
+#pragma unroll
+        for (int mma = 0; mma < kMma; ++mma) {
+          if (mma % kEvery == 0 && more) load_lds16(nsrc + goff(mma / kEvery) + g0, ndst + l0 + loff(mma / kEvery));
+          __builtin_amdgcn_s_sleep(1);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      } else if (more) {
+#pragma unroll
+        for (int j = 0; j < kL; ++j) load_lds16(nsrc + goff(j) + g0, ndst + l0 + loff(j));
+      }
+      if (more) advance();
+    }
+    __builtin_amdgcn_s_barrier();
+    return;
+  }
 
   int cks = 0;  // k step of the pair being computed
   for (int64_t step = 0; step < total; ++step) {
