@@ -19,10 +19,11 @@
 // stores per lane).  k_gemm_int8_batched runs the same tiles as items of a
 // persistent launch over many products.
 //
-// k_int8_combine: per element, C = sum_g S_g 2^(E_i + F_j + 2 - 7 (g + 1)),
-// every term exact in binary64, added with TwoSum into a (c+1)-term
-// accumulator and renormalized into the c components of C (HBM-bound: it
-// reads D 32-bit sums per element per chunk and writes C once).
+// k_int8_combine: per element, C = sum_g S_g 2^(E_i + F_j + 2 - 7 (g + 1)):
+// runs of consecutive diagonals summed exactly in 64-bit integers, each run
+// split exactly into two binary64 values, added with TwoSum into a (c+1)-term
+// accumulator and renormalized into the c components of C (it reads D 32-bit
+// sums per element per chunk and writes C once).
 #include <algorithm>
 
 #include "internal.h"
