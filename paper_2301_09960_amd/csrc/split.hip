@@ -524,22 +524,21 @@ __device__ __forceinline__ void binary64_parts(double x, int64_t &M, int &q) {
   M = (b >> 63) ? -m : m;
 }
 
-// w += M 2^off over all NW words (two's complement; off >= 0).
+// w += M 2^off over all NW words (two's complement; off >= 0).  With
+// off = 32 q + sh, M 2^sh spans three words x0, x1, x2 (the sign beyond), and
+// word i receives the one of them numbered i - q: selects, no branches.
 template <int NW>
 __device__ __forceinline__ void window_add(uint32_t (&w)[NW], int64_t M, int off) {
+  const int q = off >> 5, sh = off & 31;
+  const uint64_t u = (uint64_t)M << sh;
+  const uint32_t sign = (uint32_t)(M >> 63);
+  const uint32_t x0 = (uint32_t)u, x1 = (uint32_t)(u >> 32);
+  const uint32_t x2 = sh ? (uint32_t)(M >> (64 - sh)) : sign;
   uint32_t carry = 0;
 #pragma unroll
   for (int i = 0; i < NW; ++i) {
-    const int t = 32 * i - off;  // bit of M at bit 0 of word i
-    uint32_t part;
-    if (t >= 64)
-      part = M < 0 ? 0xffffffffu : 0u;
-    else if (t >= 0)
-      part = (uint32_t)(M >> t);
-    else if (t > -32)
-      part = (uint32_t)((uint64_t)M << (-t));
-    else
-      part = 0u;
+    const int d = i - q;
+    const uint32_t part = d < 0 ? 0u : d == 0 ? x0 : d == 1 ? x1 : d == 2 ? x2 : sign;
     const uint64_t sum = (uint64_t)w[i] + part + carry;
     w[i] = (uint32_t)sum;
     carry = (uint32_t)(sum >> 32);
