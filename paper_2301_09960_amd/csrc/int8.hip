@@ -85,7 +85,9 @@ __device__ __forceinline__ void wait_step(int64_t later) {
 
 // Tile configurations (in 32 x 32 blocks): TB x TB tile of C, WM x WN
 // wavefronts, KSB 32-wide k blocks per pipeline step, NS LDS stages.
-//   config 1: 128 x 128 tile, 4 wavefronts of 64 x 64 (small products)
+//   config 1: 128 x 128 tile, 4 wavefronts of 64 x 64 (small products), k
+//             steps of 128 in a 2-stage ring (two workgroups per CU), each
+//             step's loads over its first half
 //   config 2: 256 x 256 tile, 4 wavefronts of 128 x 128 (accumulators in AGPRs;
 //             LDS traffic per instruction halved)
 //   config 4: 256 x 256 tile, 16 wavefronts of 64 x 64 (more wavefronts to
@@ -96,7 +98,7 @@ __device__ __forceinline__ void wait_step(int64_t later) {
 // KSB is 1 or 2 times kKStepBlocks8, the k padding unit of the INT8 slices (64
 // k): with 4-block steps a pair's last step in a k chunk may hold 2 blocks.
 template <int CFG> struct Int8Cfg;
-template <> struct Int8Cfg<1> { static constexpr int TB = 4, WM = 2, WN = 2, KSB = 2, NS = 4, SPACING = 0; };
+template <> struct Int8Cfg<1> { static constexpr int TB = 4, WM = 2, WN = 2, KSB = 4, NS = 2, SPACING = 1; };
 template <> struct Int8Cfg<2> { static constexpr int TB = 8, WM = 2, WN = 2, KSB = 2, NS = 4, SPACING = 0; };
 template <> struct Int8Cfg<3> { static constexpr int TB = 8, WM = 2, WN = 4, KSB = 4, NS = 2, SPACING = 3; };
 template <> struct Int8Cfg<4> { static constexpr int TB = 8, WM = 4, WN = 4, KSB = 4, NS = 2, SPACING = 0; };

@@ -136,11 +136,11 @@ def test_int8_zero_rows_and_chunking(mp, orc):
     assert ok
 
 
-@pytest.mark.parametrize("cfg", [3, 4])
+@pytest.mark.parametrize("cfg", [1, 3, 4])
 @pytest.mark.parametrize("fmt,m,n,k,D", [("dd", 70, 90, 60, 0), ("td", 300, 40, 170, 0), ("qd", 33, 270, 420, 0),
                                          ("dd", 20, 12, 14500, 37)])
 def test_int8_short_last_step(mp, orc, cfg, fmt, m, n, k, D):
-    """k padded to 64: with 128-deep steps (configurations 3 and 4) a pair's
+    """k padded to 64: with 128-deep steps (configurations 1, 3 and 4) a pair's
     last step in a k chunk holds 64 k when the chunk's 32-wide k blocks are 2
     mod 4 (k = 60, 170, 420; and D = 37, whose 32-bit chunks are 442 blocks,
     at k = 14500): diagonal sums bit-exact, C within the bound."""
