@@ -536,19 +536,19 @@ hipError_t launch_gemm_int8(const void *Apk, const void *Bpk, const int *EA, con
   const int groups = wgs >= want ? 1 : (int)std::min<int64_t>(D, ceil_div(want, wgs));
   if (use == 2) {
     const int64_t tiles = (mbp / 8) * (nbp / 8);
-    hipLaunchKernelGGL((k_gemm_int8<2>), dim3((unsigned)tiles, (unsigned)nchunks, (unsigned)groups), dim3(256), 0, st, a, b, mbp, nbp,
+    hipLaunchKernelGGL((k_gemm_int8<2>), dim3((unsigned)tiles, (unsigned)nchunks, (unsigned)groups), dim3(64 * Int8Cfg<2>::WM * Int8Cfg<2>::WN), 0, st, a, b, mbp, nbp,
                        kbp, kbc, D, m, n, Sws, plane);
   } else if (use == 4) {
     const int64_t tiles = (mbp / 8) * (nbp / 8);
-    hipLaunchKernelGGL((k_gemm_int8<4>), dim3((unsigned)tiles, (unsigned)nchunks, (unsigned)groups), dim3(1024), 0, st,
+    hipLaunchKernelGGL((k_gemm_int8<4>), dim3((unsigned)tiles, (unsigned)nchunks, (unsigned)groups), dim3(64 * Int8Cfg<4>::WM * Int8Cfg<4>::WN), 0, st,
                        a, b, mbp, nbp, kbp, kbc, D, m, n, Sws, plane);
   } else if (use == 3) {
     const int64_t tiles = (mbp / 8) * (nbp / 8);
-    hipLaunchKernelGGL((k_gemm_int8<3>), dim3((unsigned)tiles, (unsigned)nchunks, (unsigned)groups), dim3(512), 0, st, a, b, mbp, nbp,
+    hipLaunchKernelGGL((k_gemm_int8<3>), dim3((unsigned)tiles, (unsigned)nchunks, (unsigned)groups), dim3(64 * Int8Cfg<3>::WM * Int8Cfg<3>::WN), 0, st, a, b, mbp, nbp,
                        kbp, kbc, D, m, n, Sws, plane);
   } else {
     const int64_t tiles = (mbp / 4) * (nbp / 4);
-    hipLaunchKernelGGL((k_gemm_int8<1>), dim3((unsigned)tiles, (unsigned)nchunks, (unsigned)groups), dim3(256), 0, st, a, b, mbp, nbp,
+    hipLaunchKernelGGL((k_gemm_int8<1>), dim3((unsigned)tiles, (unsigned)nchunks, (unsigned)groups), dim3(64 * Int8Cfg<1>::WM * Int8Cfg<1>::WN), 0, st, a, b, mbp, nbp,
                        kbp, kbc, D, m, n, Sws, plane);
   }
   hipError_t err = hipGetLastError();
